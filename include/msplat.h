@@ -1,0 +1,280 @@
+/*
+ * msplat.h -- C ABI of the MI355X (gfx950) differentiable Gaussian rasterizer.
+ *
+ * The library implements the data-parallel hot path of Mini-Splatting2-style
+ * scene modelling (arXiv 2411.12788): projection of 3D Gaussians to screen,
+ * tile binning by a (tile | depth) key sort, front-to-back alpha compositing
+ * with rendered argmax index and depth, per-Gaussian importance / area /
+ * max-weight accumulation, and the backward pass restricted to an active mask.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Return value: gs_status (0 = GS_OK).  On error nothing has been enqueued
+ *    (argument errors) or the HIP error text is available via gs_last_error().
+ *  - Ownership: every buffer is allocated and freed by the caller.  Device
+ *    pointers (marked [dev]) must stay valid until the enqueued work on
+ *    `stream` completes; host pointers (marked [host]) are read before the
+ *    call returns.  The library keeps no pointer after return and allocates
+ *    nothing: scratch memory arrives as (ws, ws_bytes), sized by the matching
+ *    *_workspace_size() query, 256-byte aligned.
+ *  - Asynchrony: work is enqueued on `stream` (a hipStream_t; NULL = the null
+ *    stream).  Only gs_bin_count synchronises (it returns the pair count).
+ *  - Reentrancy: no global mutable state; concurrent calls on different
+ *    streams with disjoint buffers are safe.
+ *  - Views: V cameras (1 <= V <= GS_MAX_VIEWS) are rendered in one launch per
+ *    stage.  A record is one (view, Gaussian) pair, index r = v * n + i.
+ *    Per-pixel arrays are indexed by the global pixel id
+ *    g = pixel_base[v] + y * width_v + x, pixel_base = prefix sum of width*height;
+ *    colour-like arrays are channel-planar: color[c * P + g], P = total pixels.
+ *    Tiles are 16x16 pixels; the global tile id is tile_base[v] + ty * tiles_x_v + tx.
+ */
+#ifndef MSPLAT_H
+#define MSPLAT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GS_MAX_VIEWS 32
+#define GS_TILE 16
+#define GS_REC_FLOATS 16 /* floats per projected record */
+#define GS_GRAD2D_FLOATS 9 /* floats per record in the 2D gradient buffer */
+
+typedef enum {
+  GS_OK = 0,
+  GS_ERR_NULL = -1,        /* a required pointer is NULL */
+  GS_ERR_SHAPE = -2,       /* n < 0, V out of range, width/height <= 0 or > 65535, sh_degree not in 0..3 */
+  GS_ERR_CAMERA = -3,      /* a camera value is not finite, or fx/fy <= 0 */
+  GS_ERR_CAPACITY = -4,    /* ws_bytes (or a count) too small; see the call's notes */
+  GS_ERR_DEVICE = -5,      /* HIP reported an error; see gs_last_error() */
+  GS_ERR_UNSUPPORTED = -6  /* option value not supported */
+} gs_status;
+
+/* depth_mode values: which depth the forward pass writes per pixel.
+ * MID     d^mid of the max-weight Gaussian: mid-point of the ray's two
+ *         intersections with its 1-sigma ellipsoid (Eq. (2); Sec. 4.1).
+ *         When the ray misses the ellipsoid the max-density point along the ray
+ *         is written and hit = 0.
+ * CENTER  camera depth of the max-weight Gaussian's centre (Sec. 4.1, d^center).
+ * BLEND   sum_i w_i z_i (Sec. 4.1, d^blend). */
+enum { GS_DEPTH_MID = 0, GS_DEPTH_CENTER = 1, GS_DEPTH_BLEND = 2 };
+
+/* flags */
+enum {
+  GS_ACCUM_IMPORTANCE = 1, /* gs_render_forward also accumulates (importance, wmax, area) */
+  GS_ACCUM_PER_VIEW = 2    /* accumulators are [V][n] instead of [n] summed over views */
+};
+
+/* Scene: structure-of-arrays float32 planes, all [dev].
+ * means[3][n], scales[3][n] (activated, > 0), quats[4][n] ((w, x, y, z), any
+ * non-zero norm; normalised inside), opacity[n] (activated, in [0, 1]),
+ * sh[16][3][n] (real SH coefficients, plane k * 3 + channel; only the first
+ * (sh_degree + 1)^2 coefficient planes are read).  Sec. 3.1: Gaussian with
+ * opacity, centre and covariance Sigma = R(q) diag(s)^2 R(q)^T; colour from SH. */
+typedef struct {
+  const float* means;
+  const float* scales;
+  const float* quats;
+  const float* opacity;
+  const float* sh;
+  int64_t n;
+  int32_t sh_degree;
+} gs_scene_t;
+
+/* Pinhole camera [host]: world -> camera rotation R (row-major) and
+ * translation t (x_cam = R x_world + t; OpenCV axes: x right, y down, z
+ * forward), focal lengths and principal point in pixels; pixel (px, py)
+ * samples the continuous image point (px + 0.5, py + 0.5). */
+typedef struct {
+  float R[9];
+  float t[3];
+  float fx, fy, cx, cy;
+  int32_t width, height;
+} gs_camera_t;
+
+/* Rasterizer constants.  The paper states none of them; gs_default_opts()
+ * gives the 3DGS-lineage values: znear 0.2, low-pass 0.3 (added to the 2D
+ * covariance), alpha_max 0.99 (clamp), alpha_min 1/255 (skip), t_min 1e-4
+ * (stop before a Gaussian that would take transmittance below it), Jacobian
+ * clamp 1.3 x tan(half field of view), black background, MID depth. */
+typedef struct {
+  float znear, lowpass, alpha_max, alpha_min, t_min, jac_clamp;
+  float bg[3];
+  int32_t depth_mode;
+  int32_t flags;
+} gs_opts_t;
+
+/* Projected records [dev], written by gs_project:
+ * rec[V * n][16] float: u_hi, v_hi, u_lo, v_lo (screen mean as a float pair,
+ *   u = u_hi + u_lo), A, B, C, lo (exponent form of the conic: the 2D Gaussian
+ *   times opacity is exp2(lo - A dx^2 - B dx dy - C dy^2), lo = log2 opacity),
+ *   r, g, b, opacity, z (camera depth of the centre), a, b, c (conic
+ *   [[a, b], [b, c]] = inverse of the 2D covariance with low-pass).
+ * bin[V * n][4] int32: x box (x_lo | x_hi << 16), y box (y_lo | y_hi << 16) in
+ *   pixels, clipped to the image; float32 bits of z; tiles_touched (0 = not
+ *   drawn: culled, behind the near plane, off-image, or opacity < alpha_min). */
+typedef struct {
+  float* rec;
+  int32_t* bin;
+} gs_projected_t;
+
+/* Statistics returned by gs_bin_count [host]. */
+typedef struct {
+  int64_t n_isect;     /* number of (tile, record) pairs */
+  int64_t n_visible;   /* records with tiles_touched > 0 */
+  uint32_t zbits_min;  /* min / max float32 bits of z over visible records */
+  uint32_t zbits_max;
+  int32_t tiles_total; /* sum over views of tiles_x * tiles_y */
+  int32_t depth_bits;  /* bits kept of (zbits - zbits_min) in the sort key */
+  int32_t key_bits;    /* significant bits of the sort key: tile bits + depth_bits */
+  int32_t pad;
+} gs_bin_stats_t;
+
+/* Forward outputs [dev], P = total pixels over the V views.  Optional
+ * pointers may be NULL. */
+typedef struct {
+  float* color;        /* [3][P] composited colour incl. T_final * bg (Eq. (1)) */
+  float* depth;        /* [P] per depth_mode; 0 where nothing was drawn */
+  int32_t* imax;       /* [P] Gaussian index of max blend weight (Eq. (2)); -1 if none */
+  float* t_final;      /* [P] transmittance after the last included Gaussian */
+  uint32_t* last;      /* [P] 1 + position in the tile list of the last included Gaussian */
+  uint32_t* n_contrib; /* [P] optional: number of included Gaussians */
+  uint8_t* hit;        /* [P] optional: 1 if the pixel ray meets imax's 1-sigma ellipsoid */
+} gs_fwd_out_t;
+
+/* Per-Gaussian accumulators [dev]; ADDED to (the caller zeroes them).
+ * importance: I_i = sum over pixels of w_i (Sec. 3.2)
+ * wmax:       max over pixels of w_i (the w_{i_max} significance criterion, Sec. 5.1)
+ * area:       S_i = number of pixels whose imax is i (Eq. (3))
+ * Sized [n], or [V][n] with GS_ACCUM_PER_VIEW (per-view visibility, Sec. 5.2).
+ * Any of the three may be NULL. */
+typedef struct {
+  float* importance;
+  float* wmax;
+  uint32_t* area;
+} gs_accum_t;
+
+/* Parameter gradients [dev], same layouts as gs_scene_t (sh is [16][3][n];
+ * planes beyond (sh_degree + 1)^2 are written as 0).  Overwritten. */
+typedef struct {
+  float* means;
+  float* scales;
+  float* quats;
+  float* opacity;
+  float* sh;
+} gs_grads_t;
+
+/* ---------------------------------------------------------------------- */
+const char* gs_last_error(void);      /* thread-local text of the last error */
+int32_t gs_version(void);             /* 10000 * major + 100 * minor + patch */
+void gs_default_opts(gs_opts_t* opts);
+
+/* Per-view layout helpers [host out]: tiles_x/tiles_y/tile_base/pixel_base
+ * arrays of length V (may be NULL), totals returned through the pointers. */
+int32_t gs_view_layout(const gs_camera_t* cams, int32_t V, int32_t* tiles_x, int32_t* tiles_y,
+                       int32_t* tile_base, int64_t* pixel_base, int32_t* tiles_total, int64_t* pixels_total);
+
+/* a1 -- projection (Sec. 3.1): for every record, camera transform, covariance
+ * Sigma = R(q) diag(s^2) R(q)^T, local affine projection
+ * Sigma' = J W Sigma W^T J^T + lowpass I, conic, screen mean, SH colour
+ * max(0, 0.5 + sum_k c_k Y_k(dir)) with dir from the camera centre, and the
+ * pixel box of the ellipse where alpha >= alpha_min.  Computed in double and
+ * stored as float.  cull_mask [dev, u8 n] may be NULL; a 0 entry excludes that
+ * Gaussian from every view "at the preprocessing stage" (Sec. 5.2). */
+int32_t gs_project(const gs_scene_t* scene, const gs_camera_t* cams, int32_t V, const uint8_t* cull_mask,
+                   const gs_opts_t* opts, const gs_projected_t* out, void* stream);
+
+/* a2 -- binning count: exclusive scan of tiles_touched into offsets [dev, u32
+ * V*n] and the statistics above.  Synchronises `stream` to return *stats.
+ * GS_ERR_CAPACITY if the pair count does not fit 32 bits. */
+size_t gs_bin_count_workspace_size(int64_t n_records);
+int32_t gs_bin_count(const gs_projected_t* proj, const gs_camera_t* cams, int32_t V, int64_t n,
+                     uint32_t* offsets, gs_bin_stats_t* stats, void* ws, size_t ws_bytes, void* stream);
+
+/* a2-a4 -- emit one (tile | depth) key per (tile, record) pair, sort them
+ * stably by key (ties keep ascending record order), and find each tile's run.
+ * Sec. 3.1: Gaussians are sorted in an approximate depth order by the depth of
+ * their centres; here per tile.  vals [dev, u32 n_isect] receives the sorted
+ * record indices; ranges [dev, u32 tiles_total][2] receives [start, end) per
+ * tile ([0, 0) if empty); keys [dev, u64 n_isect] may be NULL, else receives the
+ * sorted keys (global tile << 32) | float32 bits of z. */
+size_t gs_bin_sort_workspace_size(int64_t n_isect);
+int32_t gs_bin_sort(const gs_projected_t* proj, const gs_camera_t* cams, int32_t V, int64_t n,
+                    const uint32_t* offsets, const gs_bin_stats_t* stats, uint64_t* keys, uint32_t* vals,
+                    uint32_t* ranges, void* ws, size_t ws_bytes, void* stream);
+
+/* The three stages of gs_bin_sort, exported separately.
+ * gs_emit_keys: key = (global tile << depth_shift) | (zbits - zbits_min) for each pair.
+ * gs_sort_pairs: in-place stable ascending sort of (keys, vals) on key bits
+ *   [0, key_bits) (1..64); ws sized by gs_sort_workspace_size(n).
+ * gs_tile_ranges: ranges from sorted keys whose tile id is key >> depth_shift;
+ *   keys_out (may be NULL) receives (tile << 32) | (low bits + zbits_min). */
+int32_t gs_emit_keys(const gs_projected_t* proj, const gs_camera_t* cams, int32_t V, int64_t n,
+                     const uint32_t* offsets, int32_t depth_shift, uint32_t zbits_min, uint64_t* keys,
+                     uint32_t* vals, void* stream);
+size_t gs_sort_workspace_size(int64_t n);
+int32_t gs_sort_pairs(uint64_t* keys, uint32_t* vals, int64_t n, int32_t key_bits, void* ws, size_t ws_bytes,
+                      void* stream);
+int32_t gs_tile_ranges(const uint64_t* keys, int64_t n, int32_t depth_shift, uint32_t zbits_min,
+                       int32_t tiles_total, uint32_t* ranges, uint64_t* keys_out, void* stream);
+
+/* a5 (+a6) -- forward compositing, Eq. (1): per pixel, front to back over its
+ * tile's list: alpha = min(alpha_max, opacity * G2D); skip when alpha <
+ * alpha_min; stop before a Gaussian whose inclusion would take T below t_min;
+ * w = alpha T; C += w c; imax = argmax w (first wins ties, Eq. (2)); depth per
+ * depth_mode.  With GS_ACCUM_IMPORTANCE, acc (non-NULL) also receives the
+ * importance / wmax / area sums (Sec. 3.2, Eq. (3), Sec. 5.1) of the same pass. */
+int32_t gs_render_forward(const gs_scene_t* scene, const gs_projected_t* proj, const uint32_t* vals,
+                          const uint32_t* ranges, const gs_camera_t* cams, int32_t V, const gs_opts_t* opts,
+                          const gs_fwd_out_t* out, const gs_accum_t* acc, void* stream);
+
+/* a6 -- the accumulations alone (same decisions as gs_render_forward; no
+ * per-pixel outputs): importance I_i (Sec. 3.2), wmax, area S_i (Eq. (3)).
+ * opts->flags may carry GS_ACCUM_PER_VIEW. */
+int32_t gs_accumulate_importance(const gs_projected_t* proj, const uint32_t* vals, const uint32_t* ranges,
+                                 const gs_camera_t* cams, int32_t V, int64_t n, const gs_opts_t* opts,
+                                 const gs_accum_t* acc, void* stream);
+
+/* a7 + a8 -- backward of Eq. (1) and of the projection, restricted to an
+ * active mask (region-prioritized optimisation, Sec. 5.2): per pixel, reverse
+ * order from `last`, recomputing alpha with the forward's decisions; every
+ * Gaussian updates the transmittance and the colour behind it, but only those
+ * with active[i] != 0 (all when active == NULL) receive gradient.  dl_dcolor
+ * [dev, 3][P]; t_final, last from gs_render_forward.  grad2d [dev, V*n][9]
+ * receives d loss / d (u, v, a, b, c, opacity, r, g, b) per record (zeroed
+ * first; rows of inactive Gaussians stay 0); grads receives the parameter
+ * gradients summed over views (inactive rows 0). */
+int32_t gs_render_backward(const gs_scene_t* scene, const gs_projected_t* proj, const uint32_t* vals,
+                           const uint32_t* ranges, const gs_camera_t* cams, int32_t V, const gs_opts_t* opts,
+                           const float* t_final, const uint32_t* last, const float* dl_dcolor,
+                           const uint8_t* active, float* grad2d, const gs_grads_t* grads, void* stream);
+
+/* a7 alone: adds into grad2d (caller zeroes it). */
+int32_t gs_render_backward_pixels(const gs_projected_t* proj, const uint32_t* vals, const uint32_t* ranges,
+                                  const gs_camera_t* cams, int32_t V, int64_t n, const gs_opts_t* opts,
+                                  const float* t_final, const uint32_t* last, const float* dl_dcolor,
+                                  const uint8_t* active, float* grad2d, void* stream);
+
+/* a8 alone: chain rule of gs_project from grad2d to the parameters (written,
+ * summed over views; rows with active[i] == 0 written as 0; records with
+ * tiles_touched == 0 contribute nothing). */
+int32_t gs_project_backward(const gs_scene_t* scene, const gs_projected_t* proj, const gs_camera_t* cams,
+                            int32_t V, const gs_opts_t* opts, const float* grad2d, const uint8_t* active,
+                            const gs_grads_t* grads, void* stream);
+
+/* Mean absolute error loss and its gradient for a training step:
+ * dl_dcolor[k] = sign(color[k] - target[k]) / count; *loss (device float) is
+ * ADDED the mean |color - target| (caller zeroes it). */
+int32_t gs_l1_loss_grad(const float* color, const float* target, int64_t count, float* dl_dcolor, float* loss,
+                        void* stream);
+
+/* Fill `count` 32-bit words with `value` (graph-capture-safe clear). */
+int32_t gs_fill_u32(void* dst, uint32_t value, int64_t count, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MSPLAT_H */

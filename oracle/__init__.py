@@ -166,7 +166,8 @@ def render(params: Params, cam, proj: np.ndarray, ordr: np.ndarray, opts: Opts,
 
     ``pixels``: optional int32 [m, 2] (x, y) list; default every pixel, row-major.
     ``tiles``: optional (vals, ranges) from :func:`bin` to restrict each pixel to
-    its tile's list.
+    its tile's list.  ``margin`` columns: alpha vs skip threshold, transmittance
+    vs stop threshold, top-two weight gap, opacity*G vs clamp (all relative).
     """
     n = params.n
     W, H = int(cam.width), int(cam.height)
@@ -174,7 +175,7 @@ def render(params: Params, cam, proj: np.ndarray, ordr: np.ndarray, opts: Opts,
     npx = W * H if pix is None else pix.shape[0]
     out = dict(color=np.zeros((npx, 3)), depth=np.zeros(npx), imax=np.zeros(npx, dtype=np.int64),
                t_final=np.zeros(npx), n_contrib=np.zeros(npx, dtype=np.int32),
-               hit=np.zeros(npx, dtype=np.uint8), margin=np.zeros((npx, 3)))
+               hit=np.zeros(npx, dtype=np.uint8), margin=np.zeros((npx, 4)))
     if accumulate:
         out.update(importance=np.zeros(max(n, 1)), wmax=np.zeros(max(n, 1)),
                    area=np.zeros(max(n, 1), dtype=np.int64))

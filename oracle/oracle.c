@@ -342,10 +342,10 @@ typedef struct {
  * -1 when cap is too small. */
 static int64_t composite_pixel(const double* proj, const int64_t* list, int64_t nl, double xc, double yc,
                                const oopts_t* opt, ostep_t* steps, int64_t cap, double* T_out,
-                               double* m_dec, double* m_clamp) {
+                               double* m_alpha, double* m_stop, double* m_clamp) {
   double T = 1.0;
   int64_t ns = 0;
-  double md = INFINITY, mc = INFINITY;
+  double ma = INFINITY, mt = INFINITY, mc = INFINITY;
   for (int64_t k = 0; k < nl; k++) {
     const double* P = proj + list[k] * OP_STRIDE;
     if (P[OP_VALID] == 0) continue;
@@ -355,11 +355,11 @@ static int64_t composite_pixel(const double* proj, const int64_t* list, int64_t 
     double oG = P[OP_OPAC] * G;
     double alpha = oG < opt->alpha_max ? oG : opt->alpha_max;
     double m1 = fabs(alpha - opt->alpha_min) / opt->alpha_min;
-    if (m1 < md) md = m1;
+    if (m1 < ma) ma = m1;
     if (alpha < opt->alpha_min) continue;
     double Tn = T * (1 - alpha);
     double m2 = fabs(Tn - opt->t_min) / opt->t_min;
-    if (m2 < md) md = m2;
+    if (m2 < mt) mt = m2;
     if (Tn < opt->t_min) break;
     double m3 = fabs(oG - opt->alpha_max) / opt->alpha_max;
     if (m3 < mc) mc = m3;
@@ -375,7 +375,8 @@ static int64_t composite_pixel(const double* proj, const int64_t* list, int64_t 
     T = Tn;
   }
   *T_out = T;
-  *m_dec = md;
+  *m_alpha = ma;
+  *m_stop = mt;
   *m_clamp = mc;
   return ns;
 }
@@ -418,7 +419,9 @@ static void mid_depth(const ocam_t* cam, const double* means, const double* scal
  * pixel composites only the list of its tile (tile-restricted mode) instead of
  * all records.  Outputs per pixel: colour [3], depth, imax (-1 when nothing is
  * drawn), final transmittance, count of included Gaussians, ray/ellipsoid hit,
- * margins [3] (decision, argmax gap, alpha-clamp).  Accumulators (may be NULL)
+ * margins [4]: relative distance of the nearest evaluated alpha to the skip
+ * threshold, of the nearest transmittance to the stop threshold, the relative
+ * gap between the two largest weights, and the nearest opacity*G to the clamp.  Accumulators (may be NULL)
  * are added to, over the given pixels: importance (sum of w), max w, and area
  * (count of pixels whose imax is the record). */
 int orc_render(int64_t n, const double* proj, const int64_t* order, int64_t n_order, const double* means,
@@ -445,8 +448,8 @@ int orc_render(int64_t n, const double* proj, const int64_t* order, int64_t n_or
       for (uint32_t j = s0; j < s1; j++) tl[nl++] = tile_vals[j];
       list = tl;
     }
-    double T, md, mc;
-    int64_t ns = composite_pixel(proj, list, nl, xc, yc, opt, steps, cap, &T, &md, &mc);
+    double T, ma, mt, mc;
+    int64_t ns = composite_pixel(proj, list, nl, xc, yc, opt, steps, cap, &T, &ma, &mt, &mc);
     if (ns < 0) { free(steps); if (tl) free(tl); return -1; }
     double C[3] = {0, 0, 0};
     double wbest = 0, wsecond = 0, dblend = 0;
@@ -477,9 +480,10 @@ int orc_render(int64_t n, const double* proj, const int64_t* order, int64_t n_or
     if (depth) depth[p] = dep;
     if (hit) hit[p] = (uint8_t)h;
     if (margin) {
-      margin[3 * p + 0] = md;
-      margin[3 * p + 1] = ns >= 2 ? (wbest - wsecond) / wbest : 1.0;
-      margin[3 * p + 2] = mc;
+      margin[4 * p + 0] = ma;
+      margin[4 * p + 1] = mt;
+      margin[4 * p + 2] = ns >= 2 ? (wbest - wsecond) / wbest : 1.0;
+      margin[4 * p + 3] = mc;
     }
   }
   free(steps);
@@ -509,8 +513,8 @@ int orc_render_backward(int64_t n, const double* proj, const int64_t* order, int
     int64_t px = pix ? pix[2 * p] : p % W;
     int64_t py = pix ? pix[2 * p + 1] : p / W;
     double xc = px + 0.5, yc = py + 0.5;
-    double T, md, mc;
-    int64_t ns = composite_pixel(proj, order, n_order, xc, yc, opt, steps, cap, &T, &md, &mc);
+    double T, ma, mt, mc;
+    int64_t ns = composite_pixel(proj, order, n_order, xc, yc, opt, steps, cap, &T, &ma, &mt, &mc);
     if (ns < 0) { free(steps); free(suffix); return -1; }
     /* suffix[k] = sum_{j >= k} w_j c_j + T_final bg */
     for (int ch = 0; ch < 3; ch++) suffix[3 * ns + ch] = T * opt->bg[ch];

@@ -1,0 +1,624 @@
+// a2-a4: tile binning.  Exclusive scan of tiles_touched, emission of one
+// (tile | depth) key per (tile, record) pair, stable LSD radix sort on the
+// significant key bits only, and per-tile [start, end) ranges.
+//
+// Sort keys are compacted before sorting: depth enters as (zbits - zbits_min)
+// on depth_bits = bit length of (zbits_max - zbits_min) bits and the global
+// tile id sits directly above, so a 1920x1080 view (8,160 tiles) with depths
+// spanning a factor of ~4 needs ~38 bits (5 passes of 8) instead of 64.
+// Subtracting a constant keeps the unsigned order of the float bits, which for
+// positive depths is the float order.
+#include "common.hpp"
+
+namespace msplat {
+
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kBlock * kScanItems;  // 4096 elements per block
+constexpr int kSortItems = 16;
+constexpr int kSortTile = kBlock * kSortItems;   // 4096 keys per block
+constexpr int kRadix = 256;
+constexpr int kWaves = kBlock / kWave;
+
+// ---------------------------------------------------------------------------
+// block-wide exclusive scan of one value per thread
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T block_exclusive_scan(T x, T* lds /*kWaves + 1*/, T* total) {
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+  T inc = x;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    T y = __shfl_up(inc, o, kWave);
+    if (lane >= o) inc += y;
+  }
+  if (lane == kWave - 1) lds[w] = inc;
+  __syncthreads();
+  T wpre = 0, tot = 0;
+#pragma unroll
+  for (int k = 0; k < kWaves; ++k) {
+    T v = lds[k];
+    wpre += (k < w) ? v : T(0);
+    tot += v;
+  }
+  __syncthreads();
+  *total = tot;
+  return wpre + inc - x;
+}
+
+// ---------------------------------------------------------------------------
+// count: scan of tiles_touched with visibility statistics
+// ---------------------------------------------------------------------------
+struct CountWs {
+  uint64_t* block_sum;   // [nb]
+  uint32_t* block_zmin;  // [nb]
+  uint32_t* block_zmax;  // [nb]
+  uint32_t* block_vis;   // [nb]
+  uint64_t* stats;       // [4]: n_isect, n_visible, zmin, zmax
+};
+
+__global__ __launch_bounds__(kBlock) void k_count_reduce(const int4* __restrict__ bin, int64_t nrec, CountWs ws) {
+  __shared__ uint64_t lds[kWaves + 1];
+  __shared__ uint32_t lz[2 * kWaves + kWaves];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  uint64_t sum = 0;
+  uint32_t zmin = 0xffffffffu, zmax = 0u, vis = 0;
+#pragma unroll 4
+  for (int k = 0; k < kScanItems; ++k) {
+    const int64_t r = base + k;
+    if (r < nrec) {
+      int4 b = bin[r];
+      if (b.w > 0) {
+        sum += (uint32_t)b.w;
+        uint32_t z = (uint32_t)b.z;
+        zmin = z < zmin ? z : zmin;
+        zmax = z > zmax ? z : zmax;
+        vis++;
+      }
+    }
+  }
+  uint64_t tot;
+  block_exclusive_scan<uint64_t>(sum, lds, &tot);
+  // min / max / count over the block
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    uint32_t a = __shfl_xor(zmin, o, kWave), b = __shfl_xor(zmax, o, kWave), c = __shfl_xor(vis, o, kWave);
+    zmin = a < zmin ? a : zmin;
+    zmax = b > zmax ? b : zmax;
+    vis += c;
+  }
+  const int w = threadIdx.x / kWave;
+  if ((threadIdx.x & (kWave - 1)) == 0) { lz[w] = zmin; lz[kWaves + w] = zmax; lz[2 * kWaves + w] = vis; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t a = lz[0], b = lz[kWaves], c = 0;
+    for (int k = 0; k < kWaves; ++k) {
+      a = lz[k] < a ? lz[k] : a;
+      b = lz[kWaves + k] > b ? lz[kWaves + k] : b;
+      c += lz[2 * kWaves + k];
+    }
+    ws.block_sum[blockIdx.x] = tot;
+    ws.block_zmin[blockIdx.x] = a;
+    ws.block_zmax[blockIdx.x] = b;
+    ws.block_vis[blockIdx.x] = c;
+  }
+}
+
+// one block: exclusive scan of block sums in place, and the global statistics
+__global__ __launch_bounds__(kBlock) void k_count_top(int64_t nb, CountWs ws) {
+  __shared__ uint64_t lds[kWaves + 1];
+  __shared__ uint32_t lz[3 * kWaves];
+  uint64_t carry = 0;
+  uint32_t zmin = 0xffffffffu, zmax = 0u;
+  uint64_t vis = 0;
+  for (int64_t c0 = 0; c0 < nb; c0 += kBlock) {
+    const int64_t k = c0 + threadIdx.x;
+    uint64_t x = k < nb ? ws.block_sum[k] : 0;
+    if (k < nb) {
+      uint32_t a = ws.block_zmin[k], b = ws.block_zmax[k];
+      zmin = a < zmin ? a : zmin;
+      zmax = b > zmax ? b : zmax;
+      vis += ws.block_vis[k];
+    }
+    uint64_t tot;
+    uint64_t ex = block_exclusive_scan<uint64_t>(x, lds, &tot);
+    if (k < nb) ws.block_sum[k] = carry + ex;
+    carry += tot;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    uint32_t a = __shfl_xor(zmin, o, kWave), b = __shfl_xor(zmax, o, kWave);
+    uint64_t c = __shfl_xor(vis, o, kWave);
+    zmin = a < zmin ? a : zmin;
+    zmax = b > zmax ? b : zmax;
+    vis += c;
+  }
+  __shared__ uint64_t lv[kWaves];
+  const int w = threadIdx.x / kWave;
+  if ((threadIdx.x & (kWave - 1)) == 0) { lz[w] = zmin; lz[kWaves + w] = zmax; lv[w] = vis; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t a = lz[0], b = lz[kWaves];
+    uint64_t c = 0;
+    for (int k = 0; k < kWaves; ++k) {
+      a = lz[k] < a ? lz[k] : a;
+      b = lz[kWaves + k] > b ? lz[kWaves + k] : b;
+      c += lv[k];
+    }
+    if (c == 0) { a = 0; b = 0; }
+    ws.stats[0] = carry;
+    ws.stats[1] = c;
+    ws.stats[2] = a;
+    ws.stats[3] = b;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_count_down(const int4* __restrict__ bin, int64_t nrec, CountWs ws,
+                                                       uint32_t* __restrict__ offsets) {
+  __shared__ uint64_t lds[kWaves + 1];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  uint32_t t[kScanItems];
+  uint64_t sum = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const int64_t r = base + k;
+    int32_t w = r < nrec ? bin[r].w : 0;
+    t[k] = w > 0 ? (uint32_t)w : 0u;
+    sum += t[k];
+  }
+  uint64_t tot;
+  uint64_t run = ws.block_sum[blockIdx.x] + block_exclusive_scan<uint64_t>(sum, lds, &tot);
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const int64_t r = base + k;
+    if (r < nrec) offsets[r] = (uint32_t)run;
+    run += t[k];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// generic exclusive scan of a u32 array (sums < 2^32), three launches
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_scan_reduce(const uint32_t* __restrict__ in, int64_t count,
+                                                        uint32_t* __restrict__ block_sum) {
+  __shared__ uint32_t lds[kWaves + 1];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile;
+  uint32_t s = 0;
+#pragma unroll 4
+  for (int k = 0; k < kScanItems; ++k) {
+    const int64_t e = base + (int64_t)k * kBlock + threadIdx.x;
+    s += e < count ? in[e] : 0u;
+  }
+  uint32_t tot;
+  block_exclusive_scan<uint32_t>(s, lds, &tot);
+  if (threadIdx.x == 0) block_sum[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_top(uint32_t* __restrict__ block_sum, int64_t nb) {
+  __shared__ uint32_t lds[kWaves + 1];
+  uint32_t carry = 0;
+  for (int64_t c0 = 0; c0 < nb; c0 += kBlock) {
+    const int64_t k = c0 + threadIdx.x;
+    uint32_t x = k < nb ? block_sum[k] : 0u;
+    uint32_t tot;
+    uint32_t ex = block_exclusive_scan<uint32_t>(x, lds, &tot);
+    if (k < nb) block_sum[k] = carry + ex;
+    carry += tot;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_down(const uint32_t* __restrict__ in, int64_t count,
+                                                      const uint32_t* __restrict__ block_sum,
+                                                      uint32_t* __restrict__ out) {
+  __shared__ uint32_t lds[kWaves + 1];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  uint32_t t[kScanItems];
+  uint32_t s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const int64_t e = base + k;
+    t[k] = e < count ? in[e] : 0u;
+    s += t[k];
+  }
+  uint32_t tot;
+  uint32_t run = block_sum[blockIdx.x] + block_exclusive_scan<uint32_t>(s, lds, &tot);
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const int64_t e = base + k;
+    if (e < count) out[e] = run;
+    run += t[k];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// emission of (tile | depth) keys
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_emit(const int4* __restrict__ bin, const uint32_t* __restrict__ offsets,
+                                                 int64_t n, int64_t nrec, int32_t shift, uint32_t zmin,
+                                                 uint64_t* __restrict__ keys, uint32_t* __restrict__ vals,
+                                                 ViewSet vs) {
+  const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (r >= nrec) return;
+  const int4 b = bin[r];
+  if (b.w <= 0) return;
+  const int32_t v = (int32_t)(r / n);
+  const int32_t tx0 = (b.x & 0xffff) >> 4, tx1 = ((uint32_t)b.x >> 16) >> 4;
+  const int32_t ty0 = (b.y & 0xffff) >> 4, ty1 = ((uint32_t)b.y >> 16) >> 4;
+  const uint64_t low = (uint64_t)((uint32_t)b.z - zmin);
+  const int32_t tbase = vs.v[v].tile_base, tw = vs.v[v].tiles_x;
+  uint32_t o = offsets[r];
+  for (int32_t ty = ty0; ty <= ty1; ++ty)
+    for (int32_t tx = tx0; tx <= tx1; ++tx) {
+      const uint64_t tile = (uint64_t)(tbase + ty * tw + tx);
+      keys[o] = (tile << shift) | low;
+      vals[o] = (uint32_t)r;
+      ++o;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// stable LSD radix sort, 8-bit digits, reduce-then-scan per pass
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_sort_upsweep(const uint64_t* __restrict__ keys, int64_t n, int32_t shift,
+                                                         int64_t nb, uint32_t* __restrict__ hist) {
+  __shared__ uint32_t h[kRadix];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kSortTile;
+#pragma unroll 4
+  for (int k = 0; k < kSortItems; ++k) {
+    const int64_t e = base + (int64_t)k * kBlock + threadIdx.x;
+    if (e < n) atomicAdd(&h[(uint32_t)(keys[e] >> shift) & 0xffu], 1u);
+  }
+  __syncthreads();
+  hist[(int64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
+}
+
+__device__ __forceinline__ uint64_t match_digit(uint32_t d) {
+  uint64_t m = ~0ull;
+#pragma unroll
+  for (int b = 0; b < 8; ++b) {
+    const uint64_t bb = __ballot((d >> b) & 1u);
+    m &= ((d >> b) & 1u) ? bb : ~bb;
+  }
+  return m;
+}
+
+__global__ __launch_bounds__(kBlock) void k_sort_downsweep(const uint64_t* __restrict__ kin,
+                                                           const uint32_t* __restrict__ vin, int64_t n,
+                                                           int32_t shift, int64_t nb,
+                                                           const uint32_t* __restrict__ hist,
+                                                           uint64_t* __restrict__ kout, uint32_t* __restrict__ vout) {
+  __shared__ uint32_t cnt[kWaves][kRadix];
+  __shared__ uint32_t goff[kRadix];
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+#pragma unroll
+  for (int k = 0; k < kWaves; ++k) cnt[k][threadIdx.x] = 0;
+  goff[threadIdx.x] = hist[(int64_t)threadIdx.x * nb + blockIdx.x];
+  __syncthreads();
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
+  const int64_t base = (int64_t)blockIdx.x * kSortTile + (int64_t)w * (kSortItems * kWave);
+  uint64_t key[kSortItems];
+  uint32_t val[kSortItems];
+  uint32_t rank[kSortItems];
+#pragma unroll
+  for (int k = 0; k < kSortItems; ++k) {
+    const int64_t e = base + (int64_t)k * kWave + lane;
+    const bool in = e < n;
+    key[k] = in ? kin[e] : ~0ull;
+    val[k] = in ? vin[e] : 0u;
+    // out-of-range lanes get digit 256 (never matches a real digit)
+    const uint32_t d = in ? ((uint32_t)(key[k] >> shift) & 0xffu) : 256u;
+    uint64_t m = match_digit(d & 0xffu);
+    const uint64_t inm = __ballot(in);
+    m &= in ? inm : ~inm;
+    const uint32_t before = __popcll(m & lt);
+    const uint32_t prev = in ? cnt[w][d & 0xffu] : 0u;
+    rank[k] = prev + before;
+    const bool leader = in && before == 0;
+    if (leader) cnt[w][d] = prev + (uint32_t)__popcll(m);
+  }
+  __syncthreads();
+  // exclusive prefix over waves, per digit
+  {
+    uint32_t run = 0;
+#pragma unroll
+    for (int k = 0; k < kWaves; ++k) {
+      const uint32_t c = cnt[k][threadIdx.x];
+      cnt[k][threadIdx.x] = run;
+      run += c;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kSortItems; ++k) {
+    const int64_t e = base + (int64_t)k * kWave + lane;
+    if (e < n) {
+      const uint32_t d = (uint32_t)(key[k] >> shift) & 0xffu;
+      const uint32_t dst = goff[d] + cnt[w][d] + rank[k];
+      kout[dst] = key[k];
+      vout[dst] = val[k];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// tile ranges
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_ranges(const uint64_t* __restrict__ keys, int64_t n, int32_t shift,
+                                                   uint32_t zmin, int64_t tiles_total, uint32_t* __restrict__ ranges,
+                                                   uint64_t* __restrict__ keys_out) {
+  const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (k >= n) return;
+  const uint64_t key = keys[k];
+  const uint64_t tile = key >> shift;
+  if (tile < (uint64_t)tiles_total) {
+    if (k == 0 || (keys[k - 1] >> shift) != tile) ranges[2 * tile] = (uint32_t)k;
+    if (k == n - 1 || (keys[k + 1] >> shift) != tile) ranges[2 * tile + 1] = (uint32_t)(k + 1);
+  }
+  if (keys_out) {
+    const uint64_t lowmask = shift >= 64 ? ~0ull : ((1ull << shift) - 1ull);
+    keys_out[k] = (tile << 32) | (uint64_t)((uint32_t)(key & lowmask) + zmin);
+  }
+}
+
+__global__ void k_copy_u64(const uint64_t* __restrict__ a, uint64_t* __restrict__ b, int64_t n) {
+  const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (k < n) b[k] = a[k];
+}
+__global__ void k_copy_u32(const uint32_t* __restrict__ a, uint32_t* __restrict__ b, int64_t n) {
+  const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (k < n) b[k] = a[k];
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+static int64_t count_blocks(int64_t nrec) { return (nrec + kScanTile - 1) / kScanTile; }
+
+size_t count_ws_size(int64_t nrec) {
+  const int64_t nb = count_blocks(nrec > 0 ? nrec : 1);
+  return align256(nb * 8) + 3 * align256(nb * 4) + align256(64);
+}
+
+static CountWs carve_count(void* ws, int64_t nrec) {
+  const int64_t nb = count_blocks(nrec > 0 ? nrec : 1);
+  char* p = (char*)ws;
+  CountWs c;
+  c.block_sum = (uint64_t*)p; p += align256(nb * 8);
+  c.block_zmin = (uint32_t*)p; p += align256(nb * 4);
+  c.block_zmax = (uint32_t*)p; p += align256(nb * 4);
+  c.block_vis = (uint32_t*)p; p += align256(nb * 4);
+  c.stats = (uint64_t*)p;
+  return c;
+}
+
+static int64_t sort_blocks(int64_t n) { return (n + kSortTile - 1) / kSortTile; }
+
+// workspace of the radix sort proper: alternate key/val buffers + histograms
+size_t sort_ws_size(int64_t n) {
+  const int64_t nn = n > 0 ? n : 1;
+  const int64_t nb = sort_blocks(nn);
+  const int64_t hist = nb * kRadix;
+  const int64_t hb = (hist + kScanTile - 1) / kScanTile;
+  return align256(nn * 8) + align256(nn * 4) + align256(hist * 4) + align256(hb * 4);
+}
+
+struct SortWs {
+  uint64_t* keys;
+  uint32_t* vals;
+  uint32_t* hist;
+  uint32_t* hsum;
+};
+
+static SortWs carve_sort(void* ws, int64_t n) {
+  const int64_t nn = n > 0 ? n : 1;
+  const int64_t nb = sort_blocks(nn);
+  const int64_t hist = nb * kRadix;
+  char* p = (char*)ws;
+  SortWs s;
+  s.keys = (uint64_t*)p; p += align256(nn * 8);
+  s.vals = (uint32_t*)p; p += align256(nn * 4);
+  s.hist = (uint32_t*)p; p += align256(hist * 4);
+  s.hsum = (uint32_t*)p;
+  return s;
+}
+
+static int32_t scan_u32(uint32_t* data, int64_t count, uint32_t* bsum, hipStream_t st) {
+  const int64_t nb = (count + kScanTile - 1) / kScanTile;
+  hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kBlock), 0, st, data, count, bsum);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kBlock), 0, st, bsum, nb);
+  hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(kBlock), 0, st, data, count, bsum, data);
+  MS_CHECK_LAUNCH("scan");
+  return GS_OK;
+}
+
+// Sorts (k0, v0) by key bits [0, bits).  Passes alternate between (k0, v0)
+// and the workspace pair; the final pass writes vals to `vfinal` (may equal
+// v0) and the function returns the key buffer that holds the sorted keys.
+static int32_t radix_sort(uint64_t* k0, uint32_t* v0, int64_t n, int32_t bits, const SortWs& s,
+                          uint32_t* vfinal, uint64_t** keys_sorted, hipStream_t st) {
+  const int passes = (bits + 7) / 8;
+  *keys_sorted = k0;
+  if (n <= 1 || passes == 0) {
+    if (vfinal != v0 && n > 0) {
+      hipLaunchKernelGGL(k_copy_u32, dim3(grid_1d(n)), dim3(kBlock), 0, st, v0, vfinal, n);
+      MS_CHECK_LAUNCH("copy");
+    }
+    return GS_OK;
+  }
+  const int64_t nb = sort_blocks(n);
+  uint64_t* kin = k0;
+  uint32_t* vin = v0;
+  for (int p = 0; p < passes; ++p) {
+    uint64_t* kout = (kin == k0) ? s.keys : k0;
+    uint32_t* vout = (vin == v0) ? s.vals : v0;
+    if (p == passes - 1) vout = vfinal;
+    if (vout == vin) vout = (vin == v0) ? s.vals : v0;  // never sort in place
+    const int32_t shift = 8 * p;
+    hipLaunchKernelGGL(k_sort_upsweep, dim3((unsigned)nb), dim3(kBlock), 0, st, kin, n, shift, nb, s.hist);
+    int32_t r = scan_u32(s.hist, nb * kRadix, s.hsum, st);
+    if (r != GS_OK) return r;
+    hipLaunchKernelGGL(k_sort_downsweep, dim3((unsigned)nb), dim3(kBlock), 0, st, kin, vin, n, shift, nb, s.hist,
+                       kout, vout);
+    MS_CHECK_LAUNCH("sort pass");
+    kin = kout;
+    vin = vout;
+  }
+  if (vin != vfinal) {
+    hipLaunchKernelGGL(k_copy_u32, dim3(grid_1d(n)), dim3(kBlock), 0, st, vin, vfinal, n);
+    MS_CHECK_LAUNCH("copy");
+  }
+  *keys_sorted = kin;
+  return GS_OK;
+}
+
+static int32_t bits_for(uint64_t maxval) {
+  int32_t b = 0;
+  while (b < 64 && (maxval >> b) != 0) ++b;
+  return b;
+}
+
+int32_t launch_fill(void* dst, uint32_t value, int64_t count, hipStream_t st);
+
+}  // namespace msplat
+
+using namespace msplat;
+
+extern "C" {
+
+size_t gs_bin_count_workspace_size(int64_t n_records) { return count_ws_size(n_records); }
+
+int32_t gs_bin_count(const gs_projected_t* proj, const gs_camera_t* cams, int32_t V, int64_t n, uint32_t* offsets,
+                     gs_bin_stats_t* stats, void* ws, size_t ws_bytes, void* stream) {
+  if (!proj || !stats) { set_error("proj/stats NULL"); return GS_ERR_NULL; }
+  ViewSet vs;
+  int32_t st = build_views(cams, V, &vs);
+  if (st != GS_OK) return st;
+  if (n < 0) { set_error("n < 0"); return GS_ERR_SHAPE; }
+  const int64_t nrec = (int64_t)V * n;
+  std::memset(stats, 0, sizeof(*stats));
+  stats->tiles_total = vs.tiles_total;
+  stats->depth_bits = 0;
+  stats->key_bits = bits_for((uint64_t)(vs.tiles_total - 1));
+  if (nrec == 0) return GS_OK;
+  if (!proj->bin || !offsets || !ws) { set_error("buffer NULL"); return GS_ERR_NULL; }
+  if (ws_bytes < count_ws_size(nrec)) { set_error("count workspace too small"); return GS_ERR_CAPACITY; }
+  hipStream_t s = (hipStream_t)stream;
+  CountWs c = carve_count(ws, nrec);
+  const int64_t nb = count_blocks(nrec);
+  const int4* bin = reinterpret_cast<const int4*>(proj->bin);
+  hipLaunchKernelGGL(k_count_reduce, dim3((unsigned)nb), dim3(kBlock), 0, s, bin, nrec, c);
+  hipLaunchKernelGGL(k_count_top, dim3(1), dim3(kBlock), 0, s, nb, c);
+  hipLaunchKernelGGL(k_count_down, dim3((unsigned)nb), dim3(kBlock), 0, s, bin, nrec, c, offsets);
+  MS_CHECK_LAUNCH("bin_count");
+  uint64_t h[4];
+  st = check_hip(hipMemcpyAsync(h, c.stats, sizeof(h), hipMemcpyDeviceToHost, s), "bin_count copy");
+  if (st != GS_OK) return st;
+  st = check_hip(hipStreamSynchronize(s), "bin_count sync");
+  if (st != GS_OK) return st;
+  stats->n_isect = (int64_t)h[0];
+  stats->n_visible = (int64_t)h[1];
+  stats->zbits_min = (uint32_t)h[2];
+  stats->zbits_max = (uint32_t)h[3];
+  stats->depth_bits = bits_for((uint64_t)(stats->zbits_max - stats->zbits_min));
+  stats->key_bits = stats->depth_bits + bits_for((uint64_t)(vs.tiles_total - 1));
+  if (h[0] >= (uint64_t(1) << 32)) { set_error("pair count exceeds 32 bits"); return GS_ERR_CAPACITY; }
+  return GS_OK;
+}
+
+size_t gs_sort_workspace_size(int64_t n) { return sort_ws_size(n); }
+
+size_t gs_bin_sort_workspace_size(int64_t n_isect) {
+  const int64_t nn = n_isect > 0 ? n_isect : 1;
+  return align256(nn * 8) + align256(nn * 4) + sort_ws_size(n_isect);
+}
+
+int32_t gs_emit_keys(const gs_projected_t* proj, const gs_camera_t* cams, int32_t V, int64_t n,
+                     const uint32_t* offsets, int32_t depth_shift, uint32_t zbits_min, uint64_t* keys, uint32_t* vals,
+                     void* stream) {
+  if (!proj) { set_error("proj NULL"); return GS_ERR_NULL; }
+  ViewSet vs;
+  int32_t st = build_views(cams, V, &vs);
+  if (st != GS_OK) return st;
+  if (depth_shift < 0 || depth_shift > 32) { set_error("depth_shift out of range"); return GS_ERR_SHAPE; }
+  const int64_t nrec = (int64_t)V * n;
+  if (nrec == 0) return GS_OK;
+  if (!proj->bin || !offsets || !keys || !vals) { set_error("buffer NULL"); return GS_ERR_NULL; }
+  hipLaunchKernelGGL(k_emit, dim3(grid_1d(nrec)), dim3(kBlock), 0, (hipStream_t)stream,
+                     reinterpret_cast<const int4*>(proj->bin), offsets, n, nrec, depth_shift, zbits_min, keys, vals,
+                     vs);
+  MS_CHECK_LAUNCH("emit");
+  return GS_OK;
+}
+
+int32_t gs_sort_pairs(uint64_t* keys, uint32_t* vals, int64_t n, int32_t key_bits, void* ws, size_t ws_bytes,
+                      void* stream) {
+  if (n < 0 || key_bits < 1 || key_bits > 64) { set_error("bad n / key_bits"); return GS_ERR_SHAPE; }
+  if (n == 0) return GS_OK;
+  if (!keys || !vals || !ws) { set_error("buffer NULL"); return GS_ERR_NULL; }
+  if (n >= (int64_t(1) << 32)) { set_error("n exceeds 32 bits"); return GS_ERR_CAPACITY; }
+  if (ws_bytes < sort_ws_size(n)) { set_error("sort workspace too small"); return GS_ERR_CAPACITY; }
+  hipStream_t s = (hipStream_t)stream;
+  SortWs sw = carve_sort(ws, n);
+  uint64_t* ks = nullptr;
+  int32_t st = radix_sort(keys, vals, n, key_bits, sw, vals, &ks, s);
+  if (st != GS_OK) return st;
+  if (ks != keys) {
+    hipLaunchKernelGGL(k_copy_u64, dim3(grid_1d(n)), dim3(kBlock), 0, s, ks, keys, n);
+    MS_CHECK_LAUNCH("copy");
+  }
+  return GS_OK;
+}
+
+int32_t gs_tile_ranges(const uint64_t* keys, int64_t n, int32_t depth_shift, uint32_t zbits_min, int32_t tiles_total,
+                       uint32_t* ranges, uint64_t* keys_out, void* stream) {
+  if (n < 0 || tiles_total < 0 || depth_shift < 0 || depth_shift > 63) { set_error("bad args"); return GS_ERR_SHAPE; }
+  hipStream_t s = (hipStream_t)stream;
+  if (tiles_total > 0) {
+    if (!ranges) { set_error("ranges NULL"); return GS_ERR_NULL; }
+    int32_t st = launch_fill(ranges, 0u, 2 * (int64_t)tiles_total, s);
+    if (st != GS_OK) return st;
+  }
+  if (n == 0) return GS_OK;
+  if (!keys) { set_error("keys NULL"); return GS_ERR_NULL; }
+  hipLaunchKernelGGL(k_ranges, dim3(grid_1d(n)), dim3(kBlock), 0, s, keys, n, depth_shift, zbits_min,
+                     (int64_t)tiles_total, ranges, keys_out);
+  MS_CHECK_LAUNCH("ranges");
+  return GS_OK;
+}
+
+int32_t gs_bin_sort(const gs_projected_t* proj, const gs_camera_t* cams, int32_t V, int64_t n,
+                    const uint32_t* offsets, const gs_bin_stats_t* stats, uint64_t* keys, uint32_t* vals,
+                    uint32_t* ranges, void* ws, size_t ws_bytes, void* stream) {
+  if (!proj || !stats) { set_error("proj/stats NULL"); return GS_ERR_NULL; }
+  ViewSet vs;
+  int32_t st = build_views(cams, V, &vs);
+  if (st != GS_OK) return st;
+  if (stats->tiles_total != vs.tiles_total) { set_error("stats do not match cameras"); return GS_ERR_SHAPE; }
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t ni = stats->n_isect;
+  if (!ranges) { set_error("ranges NULL"); return GS_ERR_NULL; }
+  if ((st = launch_fill(ranges, 0u, 2 * (int64_t)vs.tiles_total, s)) != GS_OK) return st;
+  if (ni == 0) return GS_OK;
+  if (!vals || !ws || !offsets) { set_error("buffer NULL"); return GS_ERR_NULL; }
+  if (ws_bytes < gs_bin_sort_workspace_size(ni)) { set_error("bin_sort workspace too small"); return GS_ERR_CAPACITY; }
+  char* p = (char*)ws;
+  uint64_t* k0 = (uint64_t*)p; p += align256(ni * 8);
+  uint32_t* v0 = (uint32_t*)p; p += align256(ni * 4);
+  SortWs sw = carve_sort(p, ni);
+  const int32_t shift = stats->depth_bits;
+  hipLaunchKernelGGL(k_emit, dim3(grid_1d((int64_t)V * n)), dim3(kBlock), 0, s,
+                     reinterpret_cast<const int4*>(proj->bin), offsets, n, (int64_t)V * n, shift, stats->zbits_min,
+                     k0, v0, vs);
+  MS_CHECK_LAUNCH("emit");
+  uint64_t* ks = nullptr;
+  if ((st = radix_sort(k0, v0, ni, stats->key_bits, sw, vals, &ks, s)) != GS_OK) return st;
+  hipLaunchKernelGGL(k_ranges, dim3(grid_1d(ni)), dim3(kBlock), 0, s, ks, ni, shift, stats->zbits_min,
+                     (int64_t)vs.tiles_total, ranges, keys);
+  MS_CHECK_LAUNCH("ranges");
+  return GS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,385 @@
+// a5-a7: per-tile compositing (Eq. (1)), argmax index and depth (Eq. (2),
+// Sec. 4.1), importance / max-weight / area accumulation (Sec. 3.2, Eq. (3),
+// Sec. 5.1), and the reverse-order backward restricted to an active mask
+// (Sec. 5.2).
+//
+// Work mapping: one 256-thread workgroup per 16x16 tile, one wave per 8x8
+// quarter, one pixel per lane.  The tile's sorted list is walked in
+// wave-uniform order: the record index, its pixel box and its 48-byte record
+// are uniform across the wave, so they travel through the scalar cache, and a
+// wave skips (with one uniform branch) every Gaussian whose pixel box misses
+// its 8x8 quarter.  That box bounds exactly the pixels where
+// opacity * G2D >= alpha_min, so the skip never changes a result.  A wave stops
+// as soon as all its lanes have terminated.
+#include <cmath>
+
+#include "common.hpp"
+
+namespace msplat {
+
+struct FwdOut {
+  float* color;
+  float* depth;
+  int32_t* imax;
+  float* t_final;
+  uint32_t* last;
+  uint32_t* n_contrib;
+  uint8_t* hit;
+  float* imp;
+  float* wmax;
+  uint32_t* area;
+};
+
+// Mid-point of the ray's intersections with the 1-sigma ellipsoid (Sec. 4.1),
+// in the ellipsoid's scaled frame: t* = -(o'.d') / (d'.d'); d has unit camera
+// z, so t* is a camera depth.  Double precision: it runs once per pixel.
+__device__ __noinline__ void mid_depth(const KView& cam, const float* __restrict__ means,
+                                       const float* __restrict__ scales, const float* __restrict__ quats, int64_t n,
+                                       int64_t g, float pxc, float pyc, float* depth, uint8_t* hit) {
+  double R[9];
+  for (int k = 0; k < 9; ++k) R[k] = cam.R[k];
+  const double c0 = -(R[0] * cam.t[0] + R[3] * cam.t[1] + R[6] * cam.t[2]);
+  const double c1 = -(R[1] * cam.t[0] + R[4] * cam.t[1] + R[7] * cam.t[2]);
+  const double c2 = -(R[2] * cam.t[0] + R[5] * cam.t[1] + R[8] * cam.t[2]);
+  const double e0 = ((double)pxc - cam.cx) / cam.fx, e1 = ((double)pyc - cam.cy) / cam.fy;
+  const double d0 = R[0] * e0 + R[3] * e1 + R[6];
+  const double d1 = R[1] * e0 + R[4] * e1 + R[7];
+  const double d2 = R[2] * e0 + R[5] * e1 + R[8];
+  const double qw = quats[g], qx = quats[n + g], qy = quats[2 * n + g], qz = quats[3 * n + g];
+  const double iq = 1.0 / sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
+  const double w = qw * iq, x = qx * iq, y = qy * iq, z = qz * iq;
+  const double Q[3][3] = {{1.0 - 2.0 * (y * y + z * z), 2.0 * (x * y - w * z), 2.0 * (x * z + w * y)},
+                          {2.0 * (x * y + w * z), 1.0 - 2.0 * (x * x + z * z), 2.0 * (y * z - w * x)},
+                          {2.0 * (x * z - w * y), 2.0 * (y * z + w * x), 1.0 - 2.0 * (x * x + y * y)}};
+  const double o0 = c0 - means[g], o1 = c1 - means[n + g], o2 = c2 - means[2 * n + g];
+  double od = 0.0, dd = 0.0, oo = 0.0;
+  for (int k = 0; k < 3; ++k) {
+    const double is = 1.0 / (double)scales[k * n + g];
+    const double ok = (Q[0][k] * o0 + Q[1][k] * o1 + Q[2][k] * o2) * is;
+    const double dk = (Q[0][k] * d0 + Q[1][k] * d1 + Q[2][k] * d2) * is;
+    od += ok * dk;
+    dd += dk * dk;
+    oo += ok * ok;
+  }
+  *depth = (float)(-od / dd);
+  *hit = (od * od - dd * (oo - 1.0)) >= 0.0 ? 1 : 0;
+}
+
+template <bool ACC, bool OUT, int DEPTH>
+__global__ __launch_bounds__(kBlock) void k_render_fwd(const float* __restrict__ rec, const int32_t* __restrict__ bin,
+                                                       const uint32_t* __restrict__ vals,
+                                                       const uint32_t* __restrict__ ranges, int64_t n,
+                                                       const float* __restrict__ means,
+                                                       const float* __restrict__ scales,
+                                                       const float* __restrict__ quats, FwdOut o, KOpts op,
+                                                       int32_t per_view, ViewSet vs) {
+  const int32_t tile = xcd_remap((int32_t)blockIdx.x, (int32_t)gridDim.x);
+  const int32_t v = view_of_tile(vs, tile);
+  const KView& cam = vs.v[v];
+  const int32_t lt = tile - cam.tile_base;
+  const int32_t tx = lt % cam.tiles_x, ty = lt / cam.tiles_x;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int32_t sx0 = tx * kTile + (wv & 1) * 8, sy0 = ty * kTile + (wv >> 1) * 8;
+  const int32_t px = sx0 + (lane & 7), py = sy0 + (lane >> 3);
+  const bool inside = px < cam.width && py < cam.height;
+  const float pxc = (float)px + 0.5f, pyc = (float)py + 0.5f;
+  const uint32_t start = uload(ranges + 2 * tile), end = uload(ranges + 2 * tile + 1);
+  const int64_t vbase = (int64_t)v * n;
+  float T = 1.f, c0 = 0.f, c1 = 0.f, c2 = 0.f, wbest = 0.f, dblend = 0.f;
+  int32_t best = -1;
+  uint32_t lastpos = 0, cnt = 0;
+  bool done = !inside;
+  for (uint32_t j = start; j < end; ++j) {
+    if (__all(done)) break;
+    const uint32_t r = uload(vals + j);
+    const int2 bb = uload(reinterpret_cast<const int2*>(bin + 4 * (int64_t)r));
+    const int32_t bx = bb.x, by = bb.y;
+    if ((int32_t)((uint32_t)bx >> 16) < sx0 || (bx & 0xffff) > sx0 + 7 || (int32_t)((uint32_t)by >> 16) < sy0 ||
+        (by & 0xffff) > sy0 + 7)
+      continue;
+    const float4* R4 = reinterpret_cast<const float4*>(rec + (int64_t)r * kRecFloats);
+    const float4 r0 = uload(R4), r1 = uload(R4 + 1), r2 = uload(R4 + 2);
+    float wgt = 0.f;
+    bool inc = false;
+    if (!done) {
+      const float dx = (pxc - r0.x) - r0.z;
+      const float dy = (pyc - r0.y) - r0.w;
+      const float e = r1.w - (r1.x * dx * dx + r1.y * dx * dy + r1.z * dy * dy);
+      if (e >= op.log2_alpha_min) {
+        const float al = fminf(op.alpha_max, __builtin_amdgcn_exp2f(e));
+        const float Tn = T * (1.f - al);
+        if (Tn < op.t_min) {
+          done = true;
+        } else {
+          wgt = al * T;
+          c0 += wgt * r2.x;
+          c1 += wgt * r2.y;
+          c2 += wgt * r2.z;
+          if (DEPTH == GS_DEPTH_BLEND) dblend += wgt * uload(rec + (int64_t)r * kRecFloats + 12);
+          if (wgt > wbest) { wbest = wgt; best = (int32_t)(r - vbase); }
+          T = Tn;
+          lastpos = j - start + 1;
+          ++cnt;
+          inc = true;
+        }
+      }
+    }
+    if (ACC) {
+      if (__any(inc)) {
+        const float ws = wave_sum(wgt);
+        const float wm = wave_max(wgt);
+        if (lane == 0) {
+          const int64_t ai = per_view ? (int64_t)r : (int64_t)r - vbase;
+          if (o.imp) atomicAdd(o.imp + ai, ws);
+          if (o.wmax) atomicMax(reinterpret_cast<unsigned int*>(o.wmax) + ai, __float_as_uint(wm));
+        }
+      }
+    }
+  }
+  if (!inside) return;
+  if (ACC && o.area && best >= 0) atomicAdd(o.area + (per_view ? vbase + best : (int64_t)best), 1u);
+  if (!OUT) return;
+  const int64_t P = vs.pixels_total;
+  const int64_t gp = cam.pixel_base + (int64_t)py * cam.width + px;
+  o.color[gp] = c0 + T * op.bg[0];
+  o.color[P + gp] = c1 + T * op.bg[1];
+  o.color[2 * P + gp] = c2 + T * op.bg[2];
+  o.t_final[gp] = T;
+  o.last[gp] = lastpos;
+  o.imax[gp] = best;
+  if (o.n_contrib) o.n_contrib[gp] = cnt;
+  float dep = 0.f;
+  uint8_t h = 0;
+  if (best >= 0 && (o.depth || o.hit)) {
+    float dm;
+    mid_depth(cam, means, scales, quats, n, best, pxc, pyc, &dm, &h);
+    if (DEPTH == GS_DEPTH_MID) dep = dm;
+    else if (DEPTH == GS_DEPTH_CENTER) dep = rec[(vbase + best) * kRecFloats + 12];
+    else dep = dblend;
+  }
+  if (o.depth) o.depth[gp] = dep;
+  if (o.hit) o.hit[gp] = h;
+}
+
+// ---------------------------------------------------------------------------
+// backward
+// ---------------------------------------------------------------------------
+template <bool MASKED>
+__global__ __launch_bounds__(kBlock) void k_render_bwd(const float* __restrict__ rec, const int32_t* __restrict__ bin,
+                                                       const uint32_t* __restrict__ vals,
+                                                       const uint32_t* __restrict__ ranges, int64_t n,
+                                                       const float* __restrict__ t_final,
+                                                       const uint32_t* __restrict__ last,
+                                                       const float* __restrict__ dldc,
+                                                       const uint8_t* __restrict__ active, float* __restrict__ g2d,
+                                                       KOpts op, ViewSet vs) {
+  const int32_t tile = xcd_remap((int32_t)blockIdx.x, (int32_t)gridDim.x);
+  const int32_t v = view_of_tile(vs, tile);
+  const KView& cam = vs.v[v];
+  const int32_t lt = tile - cam.tile_base;
+  const int32_t tx = lt % cam.tiles_x, ty = lt / cam.tiles_x;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int32_t sx0 = tx * kTile + (wv & 1) * 8, sy0 = ty * kTile + (wv >> 1) * 8;
+  const int32_t px = sx0 + (lane & 7), py = sy0 + (lane >> 3);
+  const bool inside = px < cam.width && py < cam.height;
+  const float pxc = (float)px + 0.5f, pyc = (float)py + 0.5f;
+  const uint32_t start = uload(ranges + 2 * tile), end = uload(ranges + 2 * tile + 1);
+  const int64_t vbase = (int64_t)v * n;
+  const int64_t P = vs.pixels_total;
+  const int64_t gp = cam.pixel_base + (int64_t)py * cam.width + px;
+  float T = 1.f, g0 = 0.f, g1 = 0.f, g2 = 0.f;
+  uint32_t lst = 0;
+  if (inside) {
+    T = t_final[gp];
+    lst = last[gp];
+    g0 = dldc[gp];
+    g1 = dldc[P + gp];
+    g2 = dldc[2 * P + gp];
+  }
+  float s0 = T * op.bg[0], s1 = T * op.bg[1], s2 = T * op.bg[2];
+  uint32_t jmax = uniform_u32(wave_max_u32(lst));
+  jmax = jmax < end - start ? jmax : end - start;  // `last` never exceeds the tile's list
+  for (int64_t j = (int64_t)start + jmax - 1; j >= (int64_t)start; --j) {
+    const uint32_t r = uload(vals + j);
+    const int2 bb = uload(reinterpret_cast<const int2*>(bin + 4 * (int64_t)r));
+    const int32_t bx = bb.x, by = bb.y;
+    if ((int32_t)((uint32_t)bx >> 16) < sx0 || (bx & 0xffff) > sx0 + 7 || (int32_t)((uint32_t)by >> 16) < sy0 ||
+        (by & 0xffff) > sy0 + 7)
+      continue;
+    const float4* R4 = reinterpret_cast<const float4*>(rec + (int64_t)r * kRecFloats);
+    const float4 r0 = uload(R4), r1 = uload(R4 + 1), r2 = uload(R4 + 2), r3 = uload(R4 + 3);
+    const bool act = !MASKED || uload(active + (r - vbase)) != 0;
+    float p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f, p4 = 0.f, p5 = 0.f, p6 = 0.f, p7 = 0.f, p8 = 0.f;
+    bool contrib = false;
+    if ((uint32_t)(j - start) < lst) {
+      const float dx = (pxc - r0.x) - r0.z;
+      const float dy = (pyc - r0.y) - r0.w;
+      const float e = r1.w - (r1.x * dx * dx + r1.y * dx * dy + r1.z * dy * dy);
+      if (e >= op.log2_alpha_min) {
+        const float G2 = __builtin_amdgcn_exp2f(e);
+        const float al = fminf(op.alpha_max, G2);
+        const float om = 1.f - al;
+        const float iom = __builtin_amdgcn_rcpf(om);
+        T = T * iom;  // transmittance in front of this Gaussian
+        const float wgt = al * T;
+        if (act) {
+          const float ga = g0 * (T * r2.x - s0 * iom) + g1 * (T * r2.y - s1 * iom) + g2 * (T * r2.z - s2 * iom);
+          p6 = wgt * g0;
+          p7 = wgt * g1;
+          p8 = wgt * g2;
+          if (G2 < op.alpha_max) {
+            p5 = ga * al * __builtin_amdgcn_rcpf(r2.w);
+            const float gq = -0.5f * ga * al;  // d alpha / d q with q = d^T conic d
+            p2 = gq * dx * dx;
+            p3 = 2.f * gq * dx * dy;
+            p4 = gq * dy * dy;
+            p0 = -2.f * gq * (r3.y * dx + r3.z * dy);
+            p1 = -2.f * gq * (r3.z * dx + r3.w * dy);
+          }
+          contrib = true;
+        }
+        s0 += wgt * r2.x;
+        s1 += wgt * r2.y;
+        s2 += wgt * r2.z;
+      }
+    }
+    if (act && __any(contrib)) {
+      p0 = wave_sum(p0); p1 = wave_sum(p1); p2 = wave_sum(p2);
+      p3 = wave_sum(p3); p4 = wave_sum(p4); p5 = wave_sum(p5);
+      p6 = wave_sum(p6); p7 = wave_sum(p7); p8 = wave_sum(p8);
+      if (lane < kG2d) {
+        float x = p0;
+        x = lane == 1 ? p1 : x; x = lane == 2 ? p2 : x; x = lane == 3 ? p3 : x;
+        x = lane == 4 ? p4 : x; x = lane == 5 ? p5 : x; x = lane == 6 ? p6 : x;
+        x = lane == 7 ? p7 : x; x = lane == 8 ? p8 : x;
+        atomicAdd(g2d + (int64_t)r * kG2d + lane, x);
+      }
+    }
+  }
+}
+
+__global__ void k_zero_f32(float* __restrict__ p, int64_t count) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < count; i += stride) p[i] = 0.f;
+}
+
+template <bool ACC, bool OUT>
+static void launch_fwd(int depth_mode, dim3 grid, hipStream_t s, const gs_projected_t* proj, const uint32_t* vals,
+                       const uint32_t* ranges, int64_t n, const gs_scene_t* scene, const FwdOut& o, const KOpts& op,
+                       int32_t per_view, const ViewSet& vs) {
+  const float* m = scene ? scene->means : nullptr;
+  const float* sc = scene ? scene->scales : nullptr;
+  const float* q = scene ? scene->quats : nullptr;
+  if (depth_mode == GS_DEPTH_CENTER)
+    hipLaunchKernelGGL((k_render_fwd<ACC, OUT, GS_DEPTH_CENTER>), grid, dim3(kBlock), 0, s, proj->rec, proj->bin, vals,
+                       ranges, n, m, sc, q, o, op, per_view, vs);
+  else if (depth_mode == GS_DEPTH_BLEND)
+    hipLaunchKernelGGL((k_render_fwd<ACC, OUT, GS_DEPTH_BLEND>), grid, dim3(kBlock), 0, s, proj->rec, proj->bin, vals,
+                       ranges, n, m, sc, q, o, op, per_view, vs);
+  else
+    hipLaunchKernelGGL((k_render_fwd<ACC, OUT, GS_DEPTH_MID>), grid, dim3(kBlock), 0, s, proj->rec, proj->bin, vals,
+                       ranges, n, m, sc, q, o, op, per_view, vs);
+}
+
+}  // namespace msplat
+
+using namespace msplat;
+
+extern "C" {
+
+int32_t gs_render_forward(const gs_scene_t* scene, const gs_projected_t* proj, const uint32_t* vals,
+                          const uint32_t* ranges, const gs_camera_t* cams, int32_t V, const gs_opts_t* opts,
+                          const gs_fwd_out_t* out, const gs_accum_t* acc, void* stream) {
+  int32_t st = check_scene(scene);
+  if (st != GS_OK) return st;
+  if (!proj || !opts || !out || !ranges) { set_error("proj/opts/out/ranges NULL"); return GS_ERR_NULL; }
+  if (opts->depth_mode < 0 || opts->depth_mode > 2) { set_error("depth_mode"); return GS_ERR_UNSUPPORTED; }
+  ViewSet vs;
+  if ((st = build_views(cams, V, &vs)) != GS_OK) return st;
+  if (!out->color || !out->t_final || !out->last || !out->imax) { set_error("forward output NULL"); return GS_ERR_NULL; }
+  const bool accum = (opts->flags & GS_ACCUM_IMPORTANCE) != 0;
+  if (accum && !acc) { set_error("GS_ACCUM_IMPORTANCE without accumulators"); return GS_ERR_NULL; }
+  if (scene->n > 0 && (!proj->rec || !proj->bin)) { set_error("projected buffers NULL"); return GS_ERR_NULL; }
+  FwdOut o{out->color, out->depth, out->imax, out->t_final, out->last, out->n_contrib, out->hit,
+           accum ? acc->importance : nullptr, accum ? acc->wmax : nullptr, accum ? acc->area : nullptr};
+  const KOpts op = make_kopts(opts);
+  const int32_t per_view = (opts->flags & GS_ACCUM_PER_VIEW) ? 1 : 0;
+  dim3 grid(vs.tiles_total);
+  hipStream_t s = (hipStream_t)stream;
+  if (accum)
+    launch_fwd<true, true>(opts->depth_mode, grid, s, proj, vals, ranges, scene->n, scene, o, op, per_view, vs);
+  else
+    launch_fwd<false, true>(opts->depth_mode, grid, s, proj, vals, ranges, scene->n, scene, o, op, per_view, vs);
+  MS_CHECK_LAUNCH("render_forward");
+  return GS_OK;
+}
+
+int32_t gs_accumulate_importance(const gs_projected_t* proj, const uint32_t* vals, const uint32_t* ranges,
+                                 const gs_camera_t* cams, int32_t V, int64_t n, const gs_opts_t* opts,
+                                 const gs_accum_t* acc, void* stream) {
+  if (!proj || !opts || !acc || !ranges) { set_error("proj/opts/acc/ranges NULL"); return GS_ERR_NULL; }
+  if (n < 0) { set_error("n < 0"); return GS_ERR_SHAPE; }
+  ViewSet vs;
+  int32_t st = build_views(cams, V, &vs);
+  if (st != GS_OK) return st;
+  if (n > 0 && (!proj->rec || !proj->bin)) { set_error("projected buffers NULL"); return GS_ERR_NULL; }
+  FwdOut o{};
+  o.imp = acc->importance;
+  o.wmax = acc->wmax;
+  o.area = acc->area;
+  const KOpts op = make_kopts(opts);
+  const int32_t per_view = (opts->flags & GS_ACCUM_PER_VIEW) ? 1 : 0;
+  hipLaunchKernelGGL((k_render_fwd<true, false, GS_DEPTH_CENTER>), dim3(vs.tiles_total), dim3(kBlock), 0,
+                     (hipStream_t)stream, proj->rec, proj->bin, vals, ranges, n, nullptr, nullptr, nullptr, o, op,
+                     per_view, vs);
+  MS_CHECK_LAUNCH("accumulate_importance");
+  return GS_OK;
+}
+
+int32_t gs_render_backward_pixels(const gs_projected_t* proj, const uint32_t* vals, const uint32_t* ranges,
+                                  const gs_camera_t* cams, int32_t V, int64_t n, const gs_opts_t* opts,
+                                  const float* t_final, const uint32_t* last, const float* dl_dcolor,
+                                  const uint8_t* active, float* grad2d, void* stream) {
+  if (!proj || !opts || !ranges || !t_final || !last || !dl_dcolor) { set_error("argument NULL"); return GS_ERR_NULL; }
+  if (n < 0) { set_error("n < 0"); return GS_ERR_SHAPE; }
+  ViewSet vs;
+  int32_t st = build_views(cams, V, &vs);
+  if (st != GS_OK) return st;
+  if (n == 0) return GS_OK;
+  if (!proj->rec || !proj->bin || !grad2d) { set_error("buffer NULL"); return GS_ERR_NULL; }
+  const KOpts op = make_kopts(opts);
+  hipStream_t s = (hipStream_t)stream;
+  if (active)
+    hipLaunchKernelGGL(k_render_bwd<true>, dim3(vs.tiles_total), dim3(kBlock), 0, s, proj->rec, proj->bin, vals,
+                       ranges, n, t_final, last, dl_dcolor, active, grad2d, op, vs);
+  else
+    hipLaunchKernelGGL(k_render_bwd<false>, dim3(vs.tiles_total), dim3(kBlock), 0, s, proj->rec, proj->bin, vals,
+                       ranges, n, t_final, last, dl_dcolor, active, grad2d, op, vs);
+  MS_CHECK_LAUNCH("render_backward_pixels");
+  return GS_OK;
+}
+
+int32_t gs_render_backward(const gs_scene_t* scene, const gs_projected_t* proj, const uint32_t* vals,
+                           const uint32_t* ranges, const gs_camera_t* cams, int32_t V, const gs_opts_t* opts,
+                           const float* t_final, const uint32_t* last, const float* dl_dcolor, const uint8_t* active,
+                           float* grad2d, const gs_grads_t* grads, void* stream) {
+  int32_t st = check_scene(scene);
+  if (st != GS_OK) return st;
+  if (scene->n > 0) {
+    if (!grad2d) { set_error("grad2d NULL"); return GS_ERR_NULL; }
+    const int64_t count = (int64_t)V * scene->n * kG2d;
+    int64_t blocks = (count + kBlock - 1) / kBlock;
+    if (blocks > 16384) blocks = 16384;
+    if (V >= 1 && V <= GS_MAX_VIEWS) {
+      hipLaunchKernelGGL(k_zero_f32, dim3((unsigned)blocks), dim3(kBlock), 0, (hipStream_t)stream, grad2d, count);
+      MS_CHECK_LAUNCH("zero grad2d");
+    }
+  }
+  st = gs_render_backward_pixels(proj, vals, ranges, cams, V, scene->n, opts, t_final, last, dl_dcolor, active, grad2d,
+                                 stream);
+  if (st != GS_OK) return st;
+  return gs_project_backward(scene, proj, cams, V, opts, grad2d, active, grads, stream);
+}
+
+}  // extern "C"

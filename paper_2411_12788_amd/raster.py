@@ -1,0 +1,288 @@
+"""Thin Python layer over the C ABI: torch tensors in, torch tensors out.
+
+PyTorch only allocates device memory and supplies the stream; every step of
+the rasterizer runs in libmsplat.so.  Function names follow the C entry points.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+from typing import Dict, List, Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+@dataclasses.dataclass
+class RasterOpts:
+    znear: float = 0.2
+    lowpass: float = 0.3
+    alpha_max: float = 0.99
+    alpha_min: float = 1.0 / 255.0
+    t_min: float = 1e-4
+    jac_clamp: float = 1.3
+    bg: Sequence[float] = (0.0, 0.0, 0.0)
+    depth_mode: int = L.GS_DEPTH_MID
+    flags: int = 0
+
+    def c(self, flags: Optional[int] = None) -> L.Opts:
+        o = L.Opts()
+        o.znear, o.lowpass, o.alpha_max, o.alpha_min = self.znear, self.lowpass, self.alpha_max, self.alpha_min
+        o.t_min, o.jac_clamp = self.t_min, self.jac_clamp
+        for k in range(3):
+            o.bg[k] = float(self.bg[k])
+        o.depth_mode = int(self.depth_mode)
+        o.flags = int(self.flags if flags is None else flags)
+        return o
+
+
+@dataclasses.dataclass
+class DeviceScene:
+    """Gaussian parameters as device tensors in the library's SoA layout."""
+    means: torch.Tensor    # [3, n]
+    scales: torch.Tensor   # [3, n]
+    quats: torch.Tensor    # [4, n]
+    opacity: torch.Tensor  # [n]
+    sh: torch.Tensor       # [16, 3, n]
+    sh_degree: int = 3
+
+    @property
+    def n(self) -> int:
+        return int(self.opacity.shape[0])
+
+    @staticmethod
+    def from_numpy(scene, device="cuda") -> "DeviceScene":
+        def t(a):
+            return torch.from_numpy(a).to(device=device, dtype=torch.float32).contiguous()
+        return DeviceScene(t(scene.means), t(scene.scales), t(scene.quats), t(scene.opacity), t(scene.sh),
+                           int(scene.sh_degree))
+
+    def c(self) -> L.Scene:
+        for a in (self.means, self.scales, self.quats, self.opacity, self.sh):
+            assert a.is_contiguous() and a.dtype == torch.float32
+        s = L.Scene()
+        s.means, s.scales, s.quats = _ptr(self.means), _ptr(self.scales), _ptr(self.quats)
+        s.opacity, s.sh = _ptr(self.opacity), _ptr(self.sh)
+        s.n, s.sh_degree = self.n, int(self.sh_degree)
+        return s
+
+    def nbytes(self) -> int:
+        return sum(a.numel() * 4 for a in (self.means, self.scales, self.quats, self.opacity, self.sh))
+
+
+def cameras(cams) -> "ctypes.Array[L.Camera]":
+    arr = (L.Camera * len(cams))()
+    for k, c in enumerate(cams):
+        Rm = np.asarray(c.R, dtype=np.float32).reshape(9)
+        tv = np.asarray(c.t, dtype=np.float32).reshape(3)
+        for i in range(9):
+            arr[k].R[i] = float(Rm[i])
+        for i in range(3):
+            arr[k].t[i] = float(tv[i])
+        arr[k].fx, arr[k].fy, arr[k].cx, arr[k].cy = float(c.fx), float(c.fy), float(c.cx), float(c.cy)
+        arr[k].width, arr[k].height = int(c.width), int(c.height)
+    return arr
+
+
+@dataclasses.dataclass
+class Layout:
+    tiles_x: List[int]
+    tiles_y: List[int]
+    tile_base: List[int]
+    pixel_base: List[int]
+    tiles_total: int
+    pixels_total: int
+
+
+def view_layout(cams) -> Layout:
+    V = len(cams)
+    ca = cameras(cams)
+    tx, ty, tb = (ctypes.c_int32 * V)(), (ctypes.c_int32 * V)(), (ctypes.c_int32 * V)()
+    pb = (ctypes.c_int64 * V)()
+    tt, pt = ctypes.c_int32(), ctypes.c_int64()
+    L.check(L.lib().gs_view_layout(ca, V, tx, ty, tb, pb, ctypes.byref(tt), ctypes.byref(pt)), "gs_view_layout")
+    return Layout(list(tx), list(ty), list(tb), list(pb), tt.value, pt.value)
+
+
+@dataclasses.dataclass
+class Projected:
+    rec: torch.Tensor  # [V*n, 16] float32
+    bin: torch.Tensor  # [V*n, 4] int32
+
+    def c(self) -> L.Projected:
+        p = L.Projected()
+        p.rec, p.bin = _ptr(self.rec), _ptr(self.bin)
+        return p
+
+
+def project(scene: DeviceScene, cams, opts: RasterOpts, cull_mask: Optional[torch.Tensor] = None,
+            stream=None) -> Projected:
+    V, n = len(cams), scene.n
+    dev = scene.opacity.device
+    out = Projected(torch.empty((max(V * n, 1), L.GS_REC_FLOATS), device=dev, dtype=torch.float32),
+                    torch.empty((max(V * n, 1), 4), device=dev, dtype=torch.int32))
+    L.check(L.lib().gs_project(ctypes.byref(scene.c()), cameras(cams), V, _ptr(cull_mask), ctypes.byref(opts.c()),
+                               ctypes.byref(out.c()), _stream(stream)), "gs_project")
+    return out
+
+
+@dataclasses.dataclass
+class Binned:
+    vals: torch.Tensor     # [n_isect] uint32 as int32
+    ranges: torch.Tensor   # [tiles_total, 2] uint32 as int32
+    keys: Optional[torch.Tensor]
+    stats: L.BinStats
+    offsets: torch.Tensor
+
+
+def bin_count(proj: Projected, cams, n: int, stream=None):
+    V = len(cams)
+    dev = proj.rec.device
+    offsets = torch.empty(max(V * n, 1), device=dev, dtype=torch.int32)
+    ws = torch.empty(L.lib().gs_bin_count_workspace_size(V * n), device=dev, dtype=torch.uint8)
+    st = L.BinStats()
+    L.check(L.lib().gs_bin_count(ctypes.byref(proj.c()), cameras(cams), V, n, _ptr(offsets), ctypes.byref(st),
+                                 _ptr(ws), ws.numel(), _stream(stream)), "gs_bin_count")
+    return offsets, st
+
+
+def bin_sort(proj: Projected, cams, n: int, offsets: torch.Tensor, st: L.BinStats, want_keys: bool = False,
+             stream=None) -> Binned:
+    V = len(cams)
+    dev = proj.rec.device
+    ni = int(st.n_isect)
+    vals = torch.empty(max(ni, 1), device=dev, dtype=torch.int32)
+    keys = torch.empty(max(ni, 1), device=dev, dtype=torch.int64) if want_keys else None
+    ranges = torch.empty((max(st.tiles_total, 1), 2), device=dev, dtype=torch.int32)
+    ws = torch.empty(max(L.lib().gs_bin_sort_workspace_size(ni), 1), device=dev, dtype=torch.uint8)
+    L.check(L.lib().gs_bin_sort(ctypes.byref(proj.c()), cameras(cams), V, n, _ptr(offsets), ctypes.byref(st),
+                                _ptr(keys), _ptr(vals), _ptr(ranges), _ptr(ws), ws.numel(), _stream(stream)),
+            "gs_bin_sort")
+    return Binned(vals[:ni], ranges[: st.tiles_total], None if keys is None else keys[:ni], st, offsets)
+
+
+def bin(proj: Projected, cams, n: int, want_keys: bool = False, stream=None) -> Binned:
+    offsets, st = bin_count(proj, cams, n, stream)
+    return bin_sort(proj, cams, n, offsets, st, want_keys, stream)
+
+
+def sort_pairs(keys: torch.Tensor, vals: torch.Tensor, key_bits: int, stream=None) -> None:
+    n = keys.numel()
+    ws = torch.empty(max(L.lib().gs_sort_workspace_size(n), 1), device=keys.device, dtype=torch.uint8)
+    L.check(L.lib().gs_sort_pairs(_ptr(keys), _ptr(vals), n, key_bits, _ptr(ws), ws.numel(), _stream(stream)),
+            "gs_sort_pairs")
+
+
+@dataclasses.dataclass
+class Frame:
+    color: torch.Tensor     # [3, P]
+    depth: torch.Tensor     # [P]
+    imax: torch.Tensor      # [P]
+    t_final: torch.Tensor   # [P]
+    last: torch.Tensor      # [P]
+    n_contrib: Optional[torch.Tensor]
+    hit: Optional[torch.Tensor]
+
+
+def alloc_accum(n: int, V: int = 1, per_view: bool = False, device="cuda"):
+    m = n * (V if per_view else 1)
+    return dict(importance=torch.zeros(max(m, 1), device=device), wmax=torch.zeros(max(m, 1), device=device),
+                area=torch.zeros(max(m, 1), device=device, dtype=torch.int32))
+
+
+def _accum_c(acc: Optional[Dict[str, torch.Tensor]]):
+    a = L.Accum()
+    if acc is not None:
+        a.importance, a.wmax, a.area = _ptr(acc.get("importance")), _ptr(acc.get("wmax")), _ptr(acc.get("area"))
+    return a
+
+
+def render_forward(scene: DeviceScene, proj: Projected, binned: Binned, cams, opts: RasterOpts,
+                   accum: Optional[Dict[str, torch.Tensor]] = None, extras: bool = True, stream=None,
+                   out: Optional[Frame] = None) -> Frame:
+    lay_P = view_layout(cams).pixels_total
+    dev = proj.rec.device
+    if out is None:
+        out = Frame(torch.empty((3, lay_P), device=dev), torch.empty(lay_P, device=dev),
+                    torch.empty(lay_P, device=dev, dtype=torch.int32), torch.empty(lay_P, device=dev),
+                    torch.empty(lay_P, device=dev, dtype=torch.int32),
+                    torch.empty(lay_P, device=dev, dtype=torch.int32) if extras else None,
+                    torch.empty(lay_P, device=dev, dtype=torch.uint8) if extras else None)
+    fo = L.FwdOut()
+    fo.color, fo.depth, fo.imax, fo.t_final = _ptr(out.color), _ptr(out.depth), _ptr(out.imax), _ptr(out.t_final)
+    fo.last, fo.n_contrib, fo.hit = _ptr(out.last), _ptr(out.n_contrib), _ptr(out.hit)
+    flags = opts.flags | (L.GS_ACCUM_IMPORTANCE if accum is not None else 0)
+    a = _accum_c(accum)
+    L.check(L.lib().gs_render_forward(ctypes.byref(scene.c()), ctypes.byref(proj.c()), _ptr(binned.vals),
+                                      _ptr(binned.ranges), cameras(cams), len(cams), ctypes.byref(opts.c(flags)),
+                                      ctypes.byref(fo), ctypes.byref(a) if accum is not None else None,
+                                      _stream(stream)), "gs_render_forward")
+    return out
+
+
+def accumulate_importance(proj: Projected, binned: Binned, cams, n: int, opts: RasterOpts,
+                          accum: Dict[str, torch.Tensor], stream=None) -> None:
+    a = _accum_c(accum)
+    L.check(L.lib().gs_accumulate_importance(ctypes.byref(proj.c()), _ptr(binned.vals), _ptr(binned.ranges),
+                                             cameras(cams), len(cams), n, ctypes.byref(opts.c()), ctypes.byref(a),
+                                             _stream(stream)), "gs_accumulate_importance")
+
+
+def alloc_grads(n: int, device="cuda") -> Dict[str, torch.Tensor]:
+    return dict(means=torch.empty((3, n), device=device), scales=torch.empty((3, n), device=device),
+                quats=torch.empty((4, n), device=device), opacity=torch.empty(n, device=device),
+                sh=torch.empty((16, 3, n), device=device))
+
+
+def _grads_c(g):
+    c = L.Grads()
+    c.means, c.scales, c.quats, c.opacity, c.sh = (_ptr(g["means"]), _ptr(g["scales"]), _ptr(g["quats"]),
+                                                   _ptr(g["opacity"]), _ptr(g["sh"]))
+    return c
+
+
+def render_backward(scene: DeviceScene, proj: Projected, binned: Binned, cams, opts: RasterOpts, frame: Frame,
+                    dl_dcolor: torch.Tensor, active: Optional[torch.Tensor] = None,
+                    grads: Optional[Dict[str, torch.Tensor]] = None, grad2d: Optional[torch.Tensor] = None,
+                    stream=None):
+    V, n = len(cams), scene.n
+    dev = proj.rec.device
+    if grads is None:
+        grads = alloc_grads(max(n, 1), dev)
+    if grad2d is None:
+        grad2d = torch.empty((max(V * n, 1), L.GS_GRAD2D_FLOATS), device=dev)
+    L.check(L.lib().gs_render_backward(ctypes.byref(scene.c()), ctypes.byref(proj.c()), _ptr(binned.vals),
+                                       _ptr(binned.ranges), cameras(cams), V, ctypes.byref(opts.c()),
+                                       _ptr(frame.t_final), _ptr(frame.last), _ptr(dl_dcolor.contiguous()),
+                                       _ptr(active), _ptr(grad2d), ctypes.byref(_grads_c(grads)), _stream(stream)),
+            "gs_render_backward")
+    return grads, grad2d
+
+
+def render_backward_pixels(proj: Projected, binned: Binned, cams, n: int, opts: RasterOpts, frame: Frame,
+                           dl_dcolor: torch.Tensor, active=None, grad2d=None, stream=None) -> torch.Tensor:
+    V = len(cams)
+    if grad2d is None:
+        grad2d = torch.zeros((max(V * n, 1), L.GS_GRAD2D_FLOATS), device=proj.rec.device)
+    L.check(L.lib().gs_render_backward_pixels(ctypes.byref(proj.c()), _ptr(binned.vals), _ptr(binned.ranges),
+                                              cameras(cams), V, n, ctypes.byref(opts.c()), _ptr(frame.t_final),
+                                              _ptr(frame.last), _ptr(dl_dcolor.contiguous()), _ptr(active),
+                                              _ptr(grad2d), _stream(stream)), "gs_render_backward_pixels")
+    return grad2d
+
+
+def l1_loss_grad(color: torch.Tensor, target: torch.Tensor, dl_dcolor: torch.Tensor, loss: Optional[torch.Tensor],
+                 stream=None) -> None:
+    L.check(L.lib().gs_l1_loss_grad(_ptr(color), _ptr(target), color.numel(), _ptr(dl_dcolor), _ptr(loss),
+                                    _stream(stream)), "gs_l1_loss_grad")

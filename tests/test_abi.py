@@ -1,0 +1,80 @@
+"""C-ABI contract checks that need no GPU: the library loads, exports every
+function include/msplat.h declares, and rejects bad arguments on the host
+before any device work."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import gs_inputs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "msplat.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(gs_[a-z0-9_]+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2411_12788_amd import _lib
+    _lib.lib()
+    return _lib
+
+
+def test_library_exports_every_declared_symbol(L):
+    names = _declared()
+    assert len(names) >= 20
+    lib = L.lib()
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(L.exported_names())
+
+
+def test_default_opts_and_version(L):
+    o = L.Opts()
+    L.lib().gs_default_opts(ctypes.byref(o))
+    assert o.alpha_max == pytest.approx(0.99) and o.alpha_min == pytest.approx(1 / 255)
+    assert o.t_min == pytest.approx(1e-4) and o.lowpass == pytest.approx(0.3) and o.znear == pytest.approx(0.2)
+    assert o.depth_mode == 0 and o.flags == 0
+    assert L.lib().gs_version() >= 100
+
+
+def test_view_layout_host_only(L):
+    from paper_2411_12788_amd import raster as R
+    cams = [gs_inputs.look_at((0, 0, 4), (0, 0, 0), w, h) for (w, h) in [(1920, 1080), (37, 23), (16, 16)]]
+    lay = R.view_layout(cams)
+    assert lay.tiles_x == [120, 3, 1] and lay.tiles_y == [68, 2, 1]
+    assert lay.tile_base == [0, 8160, 8166] and lay.tiles_total == 8167
+    assert lay.pixel_base == [0, 1920 * 1080, 1920 * 1080 + 37 * 23]
+
+
+def test_argument_errors_on_host(L):
+    from paper_2411_12788_amd import raster as R
+    lib = L.lib()
+    cams = R.cameras([gs_inputs.look_at((0, 0, 4), (0, 0, 0), 16, 16)])
+    o = R.RasterOpts().c()
+    out = L.Projected()
+    assert lib.gs_project(None, cams, 1, None, ctypes.byref(o), ctypes.byref(out), None) == L.GS_ERR_NULL
+    s = L.Scene()
+    s.n, s.sh_degree = 4, 3
+    assert lib.gs_project(ctypes.byref(s), cams, 1, None, ctypes.byref(o), ctypes.byref(out), None) == L.GS_ERR_NULL
+    s.n, s.sh_degree = 0, 5
+    assert lib.gs_project(ctypes.byref(s), cams, 1, None, ctypes.byref(o), ctypes.byref(out), None) == L.GS_ERR_SHAPE
+    s.sh_degree = 3
+    assert lib.gs_project(ctypes.byref(s), cams, 0, None, ctypes.byref(o), ctypes.byref(out), None) == L.GS_ERR_SHAPE
+    assert lib.gs_project(ctypes.byref(s), cams, 33, None, ctypes.byref(o), ctypes.byref(out), None) == L.GS_ERR_SHAPE
+    cams[0].fy = -1.0
+    assert lib.gs_project(ctypes.byref(s), cams, 1, None, ctypes.byref(o), ctypes.byref(out), None) == L.GS_ERR_CAMERA
+    cams[0].fy = 10.0
+    cams[0].width = 0
+    assert lib.gs_project(ctypes.byref(s), cams, 1, None, ctypes.byref(o), ctypes.byref(out), None) == L.GS_ERR_SHAPE
+    assert b"size" in lib.gs_last_error()
+    assert lib.gs_sort_pairs(None, None, 10, 0, None, 0, None) == L.GS_ERR_SHAPE
+    assert lib.gs_sort_pairs(None, None, 0, 8, None, 0, None) == L.GS_OK
+    assert lib.gs_fill_u32(None, 0, 0, None) == L.GS_OK
+    assert lib.gs_bin_count_workspace_size(10 ** 6) > 0 and lib.gs_bin_sort_workspace_size(10 ** 6) > 12 * 10 ** 6

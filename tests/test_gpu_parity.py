@@ -1,0 +1,231 @@
+"""GPU (HIP, gfx950) parity against the FP64 oracle, through the C ABI.
+
+Bit-exact: rectangles, tile keys, sorted order, per-tile ranges, sort of
+synthetic pairs.  Colour, depth, transmittance: <= 1e-4 max abs on pixels
+without an ambiguous float32-vs-float64 decision (count bounded).  Gradients:
+<= 1e-3 relative L2 per parameter group.
+"""
+import numpy as np
+import pytest
+import torch
+
+import gs_inputs
+import oracle
+from oracle import F
+from tests import gpu_helpers as H
+
+pytestmark = pytest.mark.gpu
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _oracle_view(scene, cam, opts=None, cull=None, pixels=None):
+    p = oracle.Params.of(scene)
+    return p, oracle.forward_view(p, cam, opts or oracle.Opts(), cull_mask=cull, pixels=pixels)
+
+
+def _small(seed=0, n=4096, W=128, H=128):
+    return gs_inputs.small_cube(seed, n, W, H)
+
+
+# ---------------------------------------------------------------------------
+def test_project_matches_oracle(gpu_lib):
+    wl = _small()
+    out = H.run_gpu_forward(wl.scene, wl.cameras, accumulate=False)
+    rec, binr = _np(out["proj"].rec).astype(np.float64), _np(out["proj"].bin)
+    _, orc = _oracle_view(wl.scene, wl.cameras[0])
+    P = orc["proj"]
+    vis_o = (P[:, F["VALID"]] == 1) & (P[:, F["TILES"]] > 0)
+    vis_g = binr[:, 3] > 0
+    assert np.array_equal(vis_o, vis_g)
+    v = vis_o
+    u = rec[:, 0] + rec[:, 2]
+    vv = rec[:, 1] + rec[:, 3]
+    assert np.abs(u[v] - P[v, F["U"]]).max() < 1e-6 and np.abs(vv[v] - P[v, F["V"]]).max() < 1e-6
+    for k, f in ((13, "CA"), (14, "CB"), (15, "CC")):
+        scale = np.abs(P[v, F["CA"]]) + np.abs(P[v, F["CC"]])
+        assert (np.abs(rec[v, k] - P[v, F[f]]) / scale).max() < 1e-6
+    for k, f in ((8, "R"), (9, "G"), (10, "B")):
+        assert np.abs(rec[v, k] - P[v, F[f]]).max() < 1e-6
+    assert np.array_equal(rec[v, 12].astype(np.float32), P[v, F["Z"]].astype(np.float32))
+    box = np.stack([binr[:, 0] & 0xFFFF, binr[:, 0] >> 16, binr[:, 1] & 0xFFFF, binr[:, 1] >> 16], 1)
+    obox = P[:, [F["XLO"], F["XHI"], F["YLO"], F["YHI"]]].astype(np.int64)
+    assert np.array_equal(box[v], obox[v])
+    assert np.array_equal(binr[v, 3], P[v, F["TILES"]].astype(np.int64))
+    assert np.array_equal(binr[v, 2].view(np.uint32), P[v, F["Z"]].astype(np.float32).view(np.uint32))
+
+
+def test_binning_bit_exact(gpu_lib):
+    wl = _small(seed=1)
+    out = H.run_gpu_forward(wl.scene, wl.cameras, accumulate=False, want_keys=True)
+    b = out["binned"]
+    _, orc = _oracle_view(wl.scene, wl.cameras[0])
+    P = orc["proj"]
+    tx, ty, base, total = oracle.view_layout(wl.cameras)
+    keys, vals, ranges = oracle.bin(oracle.tile_rects(P), oracle.zbits(P), 1, wl.scene.n, base, tx, total)
+    assert b.stats.n_isect == len(keys)
+    assert np.array_equal(_np(b.keys).view(np.uint64), keys)
+    assert np.array_equal(_np(b.vals).view(np.uint32), vals)
+    assert np.array_equal(_np(b.ranges).view(np.uint32), ranges)
+
+
+@pytest.mark.parametrize("n,bits,spread", [(1, 8, 2), (1000, 20, 16), (3 * 4096 + 17, 45, 1 << 40),
+                                           (100_003, 64, 1 << 62), (50_000, 33, 7)])
+def test_sort_pairs_matches_lexsort(gpu_lib, n, bits, spread):
+    R = H.raster()
+    g = gs_inputs.rng(n + bits)
+    hi = min(spread, (1 << bits) - 1) if bits < 64 else spread
+    keys = g.integers(0, hi, size=n, dtype=np.uint64, endpoint=True)
+    if bits < 64:
+        keys &= np.uint64((1 << bits) - 1)
+    vals = np.arange(n, dtype=np.uint32)
+    kt = torch.from_numpy(keys.view(np.int64)).cuda()
+    vt = torch.from_numpy(vals.view(np.int32)).cuda()
+    R.sort_pairs(kt, vt, bits)
+    perm = np.lexsort((vals, keys))
+    assert np.array_equal(_np(kt).view(np.uint64), keys[perm])
+    assert np.array_equal(_np(vt).view(np.uint32), vals[perm])
+
+
+def _check_accum(acc_g, orc, amb_arg, n, tol_abs=5e-3):
+    imp_g, wm_g, ar_g = _np(acc_g["importance"])[:n], _np(acc_g["wmax"])[:n], _np(acc_g["area"])[:n]
+    di = np.abs(imp_g - orc["importance"])
+    # a decision flip at an ambiguous pixel moves one weight by ~alpha_min
+    assert (di <= 1e-4 * orc["importance"] + 1e-6).mean() >= 0.999
+    assert di.max() <= tol_abs
+    dw = np.abs(wm_g - orc["wmax"])
+    assert (dw <= 1e-5 * orc["wmax"] + 1e-7).mean() >= 0.999 and dw.max() <= tol_abs
+    assert np.abs(ar_g.astype(np.int64) - orc["area"]).sum() <= 2 * amb_arg.sum()
+
+
+def test_forward_and_accumulations_small_cube(gpu_lib):
+    wl = _small(seed=2)
+    out = H.run_gpu_forward(wl.scene, wl.cameras, accumulate=True)
+    _, orc = _oracle_view(wl.scene, wl.cameras[0])
+    amb, amb_arg = H.compare_forward(out["frame"], orc, slice(0, 128 * 128), "small cube")
+    _check_accum(out["acc"], orc, amb_arg, wl.scene.n)
+    # invariants on the GPU's own outputs
+    imp = _np(out["acc"]["importance"]).astype(np.float64)
+    tf = _np(out["frame"].t_final).astype(np.float64)
+    assert imp.sum() == pytest.approx((1 - tf).sum(), rel=1e-5)
+    assert int(_np(out["acc"]["area"]).sum()) == int((_np(out["frame"].imax) >= 0).sum())
+
+
+def test_accumulate_importance_equals_fused(gpu_lib):
+    R = H.raster()
+    wl = _small(seed=3)
+    out = H.run_gpu_forward(wl.scene, wl.cameras, accumulate=True)
+    acc2 = R.alloc_accum(wl.scene.n)
+    R.accumulate_importance(out["proj"], out["binned"], wl.cameras, wl.scene.n, R.RasterOpts(), acc2)
+    torch.cuda.synchronize()
+    assert np.array_equal(_np(acc2["area"]), _np(out["acc"]["area"]))
+    assert np.array_equal(_np(acc2["wmax"]), _np(out["acc"]["wmax"]))
+    assert np.allclose(_np(acc2["importance"]), _np(out["acc"]["importance"]), rtol=1e-5, atol=1e-7)
+
+
+@pytest.mark.parametrize("depth_mode", [1, 2])
+def test_depth_modes(gpu_lib, depth_mode):
+    R = H.raster()
+    wl = _small(seed=4, n=2048, W=96, H=80)
+    out = H.run_gpu_forward(wl.scene, wl.cameras, opts=R.RasterOpts(depth_mode=depth_mode), accumulate=False)
+    _, orc = _oracle_view(wl.scene, wl.cameras[0], oracle.Opts(depth_mode=depth_mode))
+    H.compare_forward(out["frame"], orc, slice(0, 96 * 80), f"depth mode {depth_mode}")
+
+
+def _grads_np(g, n):
+    return {k: _np(v)[..., :n].astype(np.float64) for k, v in g.items()}
+
+
+@pytest.mark.parametrize("masked", [False, True])
+def test_backward_small_cube(gpu_lib, masked):
+    R = H.raster()
+    wl = _small(seed=5, n=3000, W=112, H=96)
+    cam = wl.cameras[0]
+    out = H.run_gpu_forward(wl.scene, wl.cameras, accumulate=False)
+    Pn = cam.width * cam.height
+    dldc = gs_inputs.normal_image(3, Pn, 77, scale=1.0 / Pn)
+    active = gs_inputs.bernoulli_mask(wl.scene.n, 0.25, 78) if masked else None
+    grads, g2d = R.render_backward(out["scene"], out["proj"], out["binned"], wl.cameras, R.RasterOpts(),
+                                   out["frame"], torch.from_numpy(dldc).cuda(),
+                                   None if active is None else torch.from_numpy(active).cuda())
+    torch.cuda.synchronize()
+    p = oracle.Params.of(wl.scene)
+    og, og2d = oracle.backward_views(p, wl.cameras, oracle.Opts(), [dldc.T.astype(np.float64)], active=active)
+    gg = _grads_np(grads, wl.scene.n)
+    for k in ("means", "scales", "quats", "opacity", "sh"):
+        err = H.rel_l2(gg[k], og[k])
+        assert err <= H.GRAD_REL_L2, (k, err)
+        if masked:
+            assert np.all(gg[k][..., active == 0] == 0), k
+    g2 = _np(g2d).astype(np.float64)[: wl.scene.n]
+    ref = og2d[0] if not masked else og2d[0] * active[:, None]
+    assert H.rel_l2(g2, ref) <= H.GRAD_REL_L2
+    if masked:
+        assert np.all(g2[active == 0] == 0)
+
+
+def test_multiview_mixed_resolution(gpu_lib):
+    R = H.raster()
+    sc = gs_inputs.uniform_cube_scene(2500, 9)
+    cams = [gs_inputs.look_at((0, 0, 4), (0, 0, 0), 96, 64), gs_inputs.look_at((2.5, 1, 3), (0, 0, 0), 50, 37),
+            gs_inputs.look_at((-3, 0.5, 2.5), (0, 0, 0), 128, 80)]
+    out = H.run_gpu_forward(sc, cams, accumulate=True, per_view=True)
+    lay = R.view_layout(cams)
+    p = oracle.Params.of(sc)
+    dls = []
+    n = sc.n
+    for v, cam in enumerate(cams):
+        orc = oracle.forward_view(p, cam, oracle.Opts())
+        sl = slice(lay.pixel_base[v], lay.pixel_base[v] + cam.width * cam.height)
+        amb, amb_arg = H.compare_forward(out["frame"], orc, sl, f"view {v}")
+        accv = {k: t[v * n:(v + 1) * n] for k, t in out["acc"].items()}
+        _check_accum(accv, orc, amb_arg, n)
+        dls.append(gs_inputs.normal_image(3, cam.width * cam.height, 100 + v, scale=1e-3))
+    dl = torch.from_numpy(np.concatenate(dls, axis=1)).cuda()
+    grads, _ = R.render_backward(out["scene"], out["proj"], out["binned"], cams, R.RasterOpts(), out["frame"], dl)
+    torch.cuda.synchronize()
+    og, _ = oracle.backward_views(p, cams, oracle.Opts(), [d.T.astype(np.float64) for d in dls])
+    gg = _grads_np(grads, n)
+    for k in og:
+        assert H.rel_l2(gg[k], og[k]) <= H.GRAD_REL_L2, k
+
+
+def test_edge_cases(gpu_lib):
+    R = H.raster()
+    cam = gs_inputs.look_at((0, 0, 4), (0, 0, 0), 37, 23)
+    # empty scene: background everywhere
+    empty = gs_inputs.uniform_cube_scene(0, 0)
+    opts = R.RasterOpts(bg=(0.25, 0.5, 0.75))
+    out = H.run_gpu_forward(empty, [cam], opts=opts)
+    assert np.allclose(_np(out["frame"].color).T, [0.25, 0.5, 0.75]) and np.all(_np(out["frame"].imax) == -1)
+    # all culled by the mask
+    sc = gs_inputs.uniform_cube_scene(500, 3)
+    out = H.run_gpu_forward(sc, [cam], opts=opts, cull=np.zeros(500, np.uint8))
+    assert out["binned"].stats.n_isect == 0 and np.all(_np(out["frame"].t_final) == 1)
+    # partial cull mask and lower SH degrees against the oracle
+    cull = gs_inputs.bernoulli_mask(500, 0.6, 4)
+    for deg in (0, 1, 2):
+        sc.sh_degree = deg
+        out = H.run_gpu_forward(sc, [cam], opts=opts, cull=cull)
+        _, orc = _oracle_view(sc, cam, oracle.Opts(bg=(0.25, 0.5, 0.75)), cull=cull)
+        H.compare_forward(out["frame"], orc, slice(0, 37 * 23), f"deg {deg}")
+    sc.sh_degree = 3
+
+
+def test_argument_errors(gpu_lib):
+    import ctypes
+    from paper_2411_12788_amd import _lib as L
+    lib = L.lib()
+    R = H.raster()
+    cams = R.cameras([gs_inputs.look_at((0, 0, 4), (0, 0, 0), 16, 16)])
+    o = R.RasterOpts().c()
+    outp = L.Projected()
+    assert lib.gs_project(None, cams, 1, None, ctypes.byref(o), ctypes.byref(outp), None) == L.GS_ERR_NULL
+    ds = R.DeviceScene.from_numpy(gs_inputs.uniform_cube_scene(8, 0))
+    assert lib.gs_project(ctypes.byref(ds.c()), cams, 0, None, ctypes.byref(o), ctypes.byref(outp), None) == \
+        L.GS_ERR_SHAPE
+    cams[0].fx = float("nan")
+    assert lib.gs_project(ctypes.byref(ds.c()), cams, 1, None, ctypes.byref(o), ctypes.byref(outp), None) == \
+        L.GS_ERR_CAMERA

@@ -30,7 +30,7 @@ def _margins_ok(params, cam, out, opts=OPTS):
     limy = opts.jac_clamp * cam.height / (2 * cam.fy)
     jm = min(np.abs(np.abs(P[v, F["TXTZ"]]) - limx).min(), np.abs(np.abs(P[v, F["TYTZ"]]) - limy).min())
     m = out["margin"]
-    return dict(decision=m[:, 0].min(), clamp=m[:, 2].min(), zgap=zgap, raw=raw, jac=jm)
+    return dict(decision=min(m[:, 0].min(), m[:, 1].min()), clamp=m[:, 3].min(), zgap=zgap, raw=raw, jac=jm)
 
 
 def _fd(params, cam, dldc, name, idx, h_rel=1e-6, cull=None):
@@ -108,7 +108,7 @@ def test_render_backward_matches_differences_of_record_fields(seed):
     ordr = oracle.order(proj)
     dldc = gs_inputs.rng(seed + 9).normal(size=(30 * 26, 3))
     base = oracle.render(p, cam, proj, ordr, OPTS, accumulate=False)
-    assert base["margin"][:, 0].min() > 1e-3 and base["margin"][:, 2].min() > 1e-3
+    assert base["margin"][:, :2].min() > 1e-3 and base["margin"][:, 3].min() > 1e-3
     g2d = oracle.render_backward(p, cam, proj, ordr, OPTS, dldc)
     fields = [F["U"], F["V"], F["CA"], F["CB"], F["CC"], F["OPAC"], F["R"], F["G"], F["B"]]
     fd = np.zeros_like(g2d)
