@@ -72,6 +72,14 @@ int32_t check_scene(const gs_scene_t* s) {
   return GS_OK;
 }
 
+int32_t check_records(int32_t V, int64_t n) {
+  if (n < 0 || (int64_t)V * n >= (int64_t(1) << 31)) {
+    set_error("V * n must be below 2^31 records");
+    return GS_ERR_SHAPE;
+  }
+  return GS_OK;
+}
+
 __global__ void k_fill_u32(uint32_t* __restrict__ dst, uint32_t value, int64_t count) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int64_t stride = (int64_t)gridDim.x * blockDim.x;

@@ -496,7 +496,7 @@ int32_t gs_bin_count(const gs_projected_t* proj, const gs_camera_t* cams, int32_
   ViewSet vs;
   int32_t st = build_views(cams, V, &vs);
   if (st != GS_OK) return st;
-  if (n < 0) { set_error("n < 0"); return GS_ERR_SHAPE; }
+  if ((st = check_records(V, n)) != GS_OK) return st;
   const int64_t nrec = (int64_t)V * n;
   std::memset(stats, 0, sizeof(*stats));
   stats->tiles_total = vs.tiles_total;

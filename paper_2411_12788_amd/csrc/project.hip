@@ -403,6 +403,7 @@ extern "C" int32_t gs_project(const gs_scene_t* scene, const gs_camera_t* cams, 
   if (!opts || !out) { set_error("opts/out is NULL"); return GS_ERR_NULL; }
   ViewSet vs;
   if ((st = build_views(cams, V, &vs)) != GS_OK) return st;
+  if ((st = check_records(V, scene->n)) != GS_OK) return st;
   if (scene->n == 0) return GS_OK;
   if (!out->rec || !out->bin) { set_error("projected buffers NULL"); return GS_ERR_NULL; }
   ProjArgs pa;

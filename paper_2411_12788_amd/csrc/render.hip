@@ -65,6 +65,37 @@ __device__ __noinline__ void mid_depth(const KView& cam, const float* __restrict
   *hit = (od * od - dd * (oo - 1.0)) >= 0.0 ? 1 : 0;
 }
 
+// Wave-wide sum / max of one float, result uniform (read from lane 63).
+// Butterfly inside each 16-lane row through DPP (quad xor 1, quad xor 2,
+// half-row mirror, row mirror), then rows combined with the row broadcasts.
+template <bool MAX>
+__device__ __forceinline__ float dpp_combine(float a, float b) { return MAX ? fmaxf(a, b) : a + b; }
+
+template <bool MAX>
+__device__ __forceinline__ float wave_reduce_dpp(float x) {
+  const int ident = MAX ? 0 : 0;  // inputs are >= 0 for MAX, so 0 is an identity for both
+  x = dpp_combine<MAX>(x, __int_as_float(__builtin_amdgcn_update_dpp(ident, __float_as_int(x), 0xB1, 0xF, 0xF, false)));
+  x = dpp_combine<MAX>(x, __int_as_float(__builtin_amdgcn_update_dpp(ident, __float_as_int(x), 0x4E, 0xF, 0xF, false)));
+  x = dpp_combine<MAX>(x, __int_as_float(__builtin_amdgcn_update_dpp(ident, __float_as_int(x), 0x141, 0xF, 0xF, false)));
+  x = dpp_combine<MAX>(x, __int_as_float(__builtin_amdgcn_update_dpp(ident, __float_as_int(x), 0x140, 0xF, 0xF, false)));
+  x = dpp_combine<MAX>(x, __int_as_float(__builtin_amdgcn_update_dpp(ident, __float_as_int(x), 0x142, 0xA, 0xF, false)));
+  x = dpp_combine<MAX>(x, __int_as_float(__builtin_amdgcn_update_dpp(ident, __float_as_int(x), 0x143, 0xC, 0xF, false)));
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
+}
+
+__device__ __forceinline__ bool box_meets(int2 b, int32_t sx0, int32_t sy0) {
+  // pixel box (lo | hi << 16) against the 8x8 quarter starting at (sx0, sy0)
+  return (int32_t)((uint32_t)b.x >> 16) >= sx0 && (b.x & 0xffff) <= sx0 + 7 && (int32_t)((uint32_t)b.y >> 16) >= sy0 &&
+         (b.y & 0xffff) <= sy0 + 7;
+}
+
+constexpr int kBatch = kBlock;  // list entries staged per workgroup round
+
+// Forward.  Per round the workgroup gathers up to 256 consecutive list entries
+// (index, pixel box, 48-byte record) into LDS with one load per thread, so the
+// latency of the random record gathers is paid once per 256 entries.  Each wave
+// then ballots which staged entries touch its 8x8 quarter and walks only
+// those, reading the record with broadcast LDS loads.
 template <bool ACC, bool OUT, int DEPTH>
 __global__ __launch_bounds__(kBlock) void k_render_fwd(const float* __restrict__ rec, const int32_t* __restrict__ bin,
                                                        const uint32_t* __restrict__ vals,
@@ -73,6 +104,10 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(const float* __restrict__
                                                        const float* __restrict__ scales,
                                                        const float* __restrict__ quats, FwdOut o, KOpts op,
                                                        int32_t per_view, ViewSet vs) {
+  __shared__ float4 s_r0[kBatch], s_r1[kBatch], s_r2[kBatch];
+  __shared__ int2 s_box[kBatch];
+  __shared__ uint32_t s_idx[kBatch];
+  __shared__ float s_z[DEPTH == GS_DEPTH_BLEND ? kBatch : 1];
   const int32_t tile = xcd_remap((int32_t)blockIdx.x, (int32_t)gridDim.x);
   const int32_t v = view_of_tile(vs, tile);
   const KView& cam = vs.v[v];
@@ -89,49 +124,68 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(const float* __restrict__
   int32_t best = -1;
   uint32_t lastpos = 0, cnt = 0;
   bool done = !inside;
-  for (uint32_t j = start; j < end; ++j) {
-    if (__all(done)) break;
-    const uint32_t r = uload(vals + j);
-    const int2 bb = uload(reinterpret_cast<const int2*>(bin + 4 * (int64_t)r));
-    const int32_t bx = bb.x, by = bb.y;
-    if ((int32_t)((uint32_t)bx >> 16) < sx0 || (bx & 0xffff) > sx0 + 7 || (int32_t)((uint32_t)by >> 16) < sy0 ||
-        (by & 0xffff) > sy0 + 7)
-      continue;
-    const float4* R4 = reinterpret_cast<const float4*>(rec + (int64_t)r * kRecFloats);
-    const float4 r0 = uload(R4), r1 = uload(R4 + 1), r2 = uload(R4 + 2);
-    float wgt = 0.f;
-    bool inc = false;
-    if (!done) {
-      const float dx = (pxc - r0.x) - r0.z;
-      const float dy = (pyc - r0.y) - r0.w;
-      const float e = r1.w - (r1.x * dx * dx + r1.y * dx * dy + r1.z * dy * dy);
-      if (e >= op.log2_alpha_min) {
-        const float al = fminf(op.alpha_max, __builtin_amdgcn_exp2f(e));
-        const float Tn = T * (1.f - al);
-        if (Tn < op.t_min) {
-          done = true;
-        } else {
-          wgt = al * T;
-          c0 += wgt * r2.x;
-          c1 += wgt * r2.y;
-          c2 += wgt * r2.z;
-          if (DEPTH == GS_DEPTH_BLEND) dblend += wgt * uload(rec + (int64_t)r * kRecFloats + 12);
-          if (wgt > wbest) { wbest = wgt; best = (int32_t)(r - vbase); }
-          T = Tn;
-          lastpos = j - start + 1;
-          ++cnt;
-          inc = true;
-        }
-      }
+  for (uint32_t base = start; base < end; base += kBatch) {
+    if (__syncthreads_and(done)) break;  // also orders this round's LDS writes after the last round's reads
+    const uint32_t j = base + threadIdx.x;
+    if (j < end) {
+      const uint32_t r = vals[j];
+      s_idx[threadIdx.x] = r;
+      s_box[threadIdx.x] = *reinterpret_cast<const int2*>(bin + 4 * (int64_t)r);
+      const float4* R4 = reinterpret_cast<const float4*>(rec + (int64_t)r * kRecFloats);
+      s_r0[threadIdx.x] = R4[0];
+      s_r1[threadIdx.x] = R4[1];
+      s_r2[threadIdx.x] = R4[2];
+      if (DEPTH == GS_DEPTH_BLEND) s_z[threadIdx.x] = rec[(int64_t)r * kRecFloats + 12];
     }
-    if (ACC) {
-      if (__any(inc)) {
-        const float ws = wave_sum(wgt);
-        const float wm = wave_max(wgt);
-        if (lane == 0) {
-          const int64_t ai = per_view ? (int64_t)r : (int64_t)r - vbase;
-          if (o.imp) atomicAdd(o.imp + ai, ws);
-          if (o.wmax) atomicMax(reinterpret_cast<unsigned int*>(o.wmax) + ai, __float_as_uint(wm));
+    __syncthreads();
+    const uint32_t count = (end - base) < (uint32_t)kBatch ? (end - base) : (uint32_t)kBatch;
+    bool wave_done = __all(done);
+    for (int c = 0; c < kBatch / kWave && !wave_done; ++c) {
+      const int k = c * kWave + lane;
+      const bool rel = (uint32_t)k < count && box_meets(s_box[k < kBatch ? k : 0], sx0, sy0);
+      uint64_t mask = __ballot(rel);
+      while (mask != 0) {
+        const int kk = c * kWave + (int)__builtin_ctzll(mask);
+        mask &= mask - 1;
+        const float4 r0 = s_r0[kk], r1 = s_r1[kk], r2 = s_r2[kk];
+        float wgt = 0.f;
+        bool inc = false;
+        if (!done) {
+          const float dx = (pxc - r0.x) - r0.z;
+          const float dy = (pyc - r0.y) - r0.w;
+          const float e = r1.w - (r1.x * dx * dx + r1.y * dx * dy + r1.z * dy * dy);
+          if (e >= op.log2_alpha_min) {
+            const float al = fminf(op.alpha_max, __builtin_amdgcn_exp2f(e));
+            const float Tn = T * (1.f - al);
+            if (Tn < op.t_min) {
+              done = true;
+            } else {
+              wgt = al * T;
+              c0 += wgt * r2.x;
+              c1 += wgt * r2.y;
+              c2 += wgt * r2.z;
+              if (DEPTH == GS_DEPTH_BLEND) dblend += wgt * s_z[kk];
+              if (wgt > wbest) { wbest = wgt; best = (int32_t)((int64_t)s_idx[kk] - vbase); }
+              T = Tn;
+              lastpos = base + (uint32_t)kk - start + 1;
+              ++cnt;
+              inc = true;
+            }
+          }
+        }
+        if (ACC && __any(inc)) {
+          const float ws = wave_reduce_dpp<false>(wgt);
+          const float wm = wave_reduce_dpp<true>(wgt);
+          if (lane == 0) {
+            const uint32_t r = s_idx[kk];
+            const int64_t ai = per_view ? (int64_t)r : (int64_t)r - vbase;
+            if (o.imp) atomicAdd(o.imp + ai, ws);
+            if (o.wmax) atomicMax(reinterpret_cast<unsigned int*>(o.wmax) + ai, __float_as_uint(wm));
+          }
+        }
+        if (__all(done)) {
+          wave_done = true;
+          break;
         }
       }
     }
@@ -164,6 +218,13 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(const float* __restrict__
 // ---------------------------------------------------------------------------
 // backward
 // ---------------------------------------------------------------------------
+// Same staging as the forward, walking rounds and entries back to front from
+// the largest `last` of the workgroup.  Per pixel: restore the transmittance
+// in front of the Gaussian (T /= 1 - alpha), form dL/dalpha from the colour
+// composited behind it, and add the Gaussian's own weighted colour to that
+// suffix.  Entries of inactive Gaussians update the per-pixel state but emit
+// no gradient.  The nine partials of an entry are summed over the wave with
+// DPP and added by one lane to the record's 2D gradient.
 template <bool MASKED>
 __global__ __launch_bounds__(kBlock) void k_render_bwd(const float* __restrict__ rec, const int32_t* __restrict__ bin,
                                                        const uint32_t* __restrict__ vals,
@@ -173,6 +234,10 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(const float* __restrict__
                                                        const float* __restrict__ dldc,
                                                        const uint8_t* __restrict__ active, float* __restrict__ g2d,
                                                        KOpts op, ViewSet vs) {
+  __shared__ float4 s_r0[kBatch], s_r1[kBatch], s_r2[kBatch], s_r3[kBatch];
+  __shared__ int2 s_box[kBatch];
+  __shared__ uint32_t s_idx[kBatch];  // record index | active << 31
+  __shared__ uint32_t s_jmax[kBlock / kWave];
   const int32_t tile = xcd_remap((int32_t)blockIdx.x, (int32_t)gridDim.x);
   const int32_t v = view_of_tile(vs, tile);
   const KView& cam = vs.v[v];
@@ -196,65 +261,98 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(const float* __restrict__
     g1 = dldc[P + gp];
     g2 = dldc[2 * P + gp];
   }
+  lst = lst < end - start ? lst : end - start;  // `last` never exceeds the tile's list
   float s0 = T * op.bg[0], s1 = T * op.bg[1], s2 = T * op.bg[2];
-  uint32_t jmax = uniform_u32(wave_max_u32(lst));
-  jmax = jmax < end - start ? jmax : end - start;  // `last` never exceeds the tile's list
-  for (int64_t j = (int64_t)start + jmax - 1; j >= (int64_t)start; --j) {
-    const uint32_t r = uload(vals + j);
-    const int2 bb = uload(reinterpret_cast<const int2*>(bin + 4 * (int64_t)r));
-    const int32_t bx = bb.x, by = bb.y;
-    if ((int32_t)((uint32_t)bx >> 16) < sx0 || (bx & 0xffff) > sx0 + 7 || (int32_t)((uint32_t)by >> 16) < sy0 ||
-        (by & 0xffff) > sy0 + 7)
-      continue;
-    const float4* R4 = reinterpret_cast<const float4*>(rec + (int64_t)r * kRecFloats);
-    const float4 r0 = uload(R4), r1 = uload(R4 + 1), r2 = uload(R4 + 2), r3 = uload(R4 + 3);
-    const bool act = !MASKED || uload(active + (r - vbase)) != 0;
-    float p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f, p4 = 0.f, p5 = 0.f, p6 = 0.f, p7 = 0.f, p8 = 0.f;
-    bool contrib = false;
-    if ((uint32_t)(j - start) < lst) {
-      const float dx = (pxc - r0.x) - r0.z;
-      const float dy = (pyc - r0.y) - r0.w;
-      const float e = r1.w - (r1.x * dx * dx + r1.y * dx * dy + r1.z * dy * dy);
-      if (e >= op.log2_alpha_min) {
-        const float G2 = __builtin_amdgcn_exp2f(e);
-        const float al = fminf(op.alpha_max, G2);
-        const float om = 1.f - al;
-        const float iom = __builtin_amdgcn_rcpf(om);
-        T = T * iom;  // transmittance in front of this Gaussian
-        const float wgt = al * T;
-        if (act) {
-          const float ga = g0 * (T * r2.x - s0 * iom) + g1 * (T * r2.y - s1 * iom) + g2 * (T * r2.z - s2 * iom);
-          p6 = wgt * g0;
-          p7 = wgt * g1;
-          p8 = wgt * g2;
-          if (G2 < op.alpha_max) {
-            p5 = ga * al * __builtin_amdgcn_rcpf(r2.w);
-            const float gq = -0.5f * ga * al;  // d alpha / d q with q = d^T conic d
-            p2 = gq * dx * dx;
-            p3 = 2.f * gq * dx * dy;
-            p4 = gq * dy * dy;
-            p0 = -2.f * gq * (r3.y * dx + r3.z * dy);
-            p1 = -2.f * gq * (r3.z * dx + r3.w * dy);
+  const uint32_t wjmax = uniform_u32(wave_max_u32(lst));
+  if (lane == 0) s_jmax[wv] = wjmax;
+  __syncthreads();
+  uint32_t bjmax = 0;
+#pragma unroll
+  for (int k = 0; k < kBlock / kWave; ++k) bjmax = s_jmax[k] > bjmax ? s_jmax[k] : bjmax;
+  for (uint32_t top = start + bjmax; top > start;) {
+    const uint32_t base = top - start > (uint32_t)kBatch ? top - kBatch : start;
+    const uint32_t count = top - base;
+    __syncthreads();  // the previous round's entries are consumed
+    if ((uint32_t)threadIdx.x < count) {
+      const uint32_t r = vals[base + threadIdx.x];
+      const uint32_t act = (!MASKED || active[(int64_t)r - vbase] != 0) ? 1u : 0u;
+      s_idx[threadIdx.x] = r | (act << 31);
+      s_box[threadIdx.x] = *reinterpret_cast<const int2*>(bin + 4 * (int64_t)r);
+      const float4* R4 = reinterpret_cast<const float4*>(rec + (int64_t)r * kRecFloats);
+      s_r0[threadIdx.x] = R4[0];
+      s_r1[threadIdx.x] = R4[1];
+      s_r2[threadIdx.x] = R4[2];
+      s_r3[threadIdx.x] = R4[3];
+    }
+    __syncthreads();
+    for (int c = kBatch / kWave - 1; c >= 0; --c) {
+      const int k = c * kWave + lane;
+      const bool rel = (uint32_t)k < count && base + (uint32_t)k < start + wjmax &&
+                       box_meets(s_box[k], sx0, sy0);
+      uint64_t mask = __ballot(rel);
+      while (mask != 0) {
+        const int hb = 63 - (int)__builtin_clzll(mask);
+        mask &= ~(1ull << hb);
+        const int kk = c * kWave + hb;
+        const uint32_t j = base + (uint32_t)kk;
+        const uint32_t tag = s_idx[kk];
+        const bool act = (tag >> 31) != 0;
+        const float4 r0 = s_r0[kk], r1 = s_r1[kk], r2 = s_r2[kk];
+        float p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f, p4 = 0.f, p5 = 0.f, p6 = 0.f, p7 = 0.f, p8 = 0.f;
+        bool contrib = false;
+        if (j - start < lst) {
+          const float dx = (pxc - r0.x) - r0.z;
+          const float dy = (pyc - r0.y) - r0.w;
+          const float e = r1.w - (r1.x * dx * dx + r1.y * dx * dy + r1.z * dy * dy);
+          if (e >= op.log2_alpha_min) {
+            const float G2 = __builtin_amdgcn_exp2f(e);
+            const float al = fminf(op.alpha_max, G2);
+            const float iom = __builtin_amdgcn_rcpf(1.f - al);
+            T = T * iom;  // transmittance in front of this Gaussian
+            const float wgt = al * T;
+            if (act) {
+              const float ga = g0 * (T * r2.x - s0 * iom) + g1 * (T * r2.y - s1 * iom) + g2 * (T * r2.z - s2 * iom);
+              p6 = wgt * g0;
+              p7 = wgt * g1;
+              p8 = wgt * g2;
+              if (G2 < op.alpha_max) {
+                const float4 r3 = s_r3[kk];
+                p5 = ga * al * __builtin_amdgcn_rcpf(r2.w);
+                const float gq = -0.5f * ga * al;  // d alpha / d q with q = d^T conic d
+                p2 = gq * dx * dx;
+                p3 = 2.f * gq * dx * dy;
+                p4 = gq * dy * dy;
+                p0 = -2.f * gq * (r3.y * dx + r3.z * dy);
+                p1 = -2.f * gq * (r3.z * dx + r3.w * dy);
+              }
+              contrib = true;
+            }
+            s0 += wgt * r2.x;
+            s1 += wgt * r2.y;
+            s2 += wgt * r2.z;
           }
-          contrib = true;
         }
-        s0 += wgt * r2.x;
-        s1 += wgt * r2.y;
-        s2 += wgt * r2.z;
+        if (act && __any(contrib)) {
+          p0 = wave_reduce_dpp<false>(p0);
+          p1 = wave_reduce_dpp<false>(p1);
+          p2 = wave_reduce_dpp<false>(p2);
+          p3 = wave_reduce_dpp<false>(p3);
+          p4 = wave_reduce_dpp<false>(p4);
+          p5 = wave_reduce_dpp<false>(p5);
+          p6 = wave_reduce_dpp<false>(p6);
+          p7 = wave_reduce_dpp<false>(p7);
+          p8 = wave_reduce_dpp<false>(p8);
+          if (lane < kG2d) {
+            float x = p0;
+            x = lane == 1 ? p1 : x; x = lane == 2 ? p2 : x; x = lane == 3 ? p3 : x;
+            x = lane == 4 ? p4 : x; x = lane == 5 ? p5 : x; x = lane == 6 ? p6 : x;
+            x = lane == 7 ? p7 : x; x = lane == 8 ? p8 : x;
+            atomicAdd(g2d + (int64_t)(tag & 0x7fffffffu) * kG2d + lane, x);
+          }
+        }
       }
     }
-    if (act && __any(contrib)) {
-      p0 = wave_sum(p0); p1 = wave_sum(p1); p2 = wave_sum(p2);
-      p3 = wave_sum(p3); p4 = wave_sum(p4); p5 = wave_sum(p5);
-      p6 = wave_sum(p6); p7 = wave_sum(p7); p8 = wave_sum(p8);
-      if (lane < kG2d) {
-        float x = p0;
-        x = lane == 1 ? p1 : x; x = lane == 2 ? p2 : x; x = lane == 3 ? p3 : x;
-        x = lane == 4 ? p4 : x; x = lane == 5 ? p5 : x; x = lane == 6 ? p6 : x;
-        x = lane == 7 ? p7 : x; x = lane == 8 ? p8 : x;
-        atomicAdd(g2d + (int64_t)r * kG2d + lane, x);
-      }
-    }
+    top = base;
   }
 }
 
@@ -297,6 +395,7 @@ int32_t gs_render_forward(const gs_scene_t* scene, const gs_projected_t* proj, c
   if (opts->depth_mode < 0 || opts->depth_mode > 2) { set_error("depth_mode"); return GS_ERR_UNSUPPORTED; }
   ViewSet vs;
   if ((st = build_views(cams, V, &vs)) != GS_OK) return st;
+  if ((st = check_records(V, scene->n)) != GS_OK) return st;
   if (!out->color || !out->t_final || !out->last || !out->imax) { set_error("forward output NULL"); return GS_ERR_NULL; }
   const bool accum = (opts->flags & GS_ACCUM_IMPORTANCE) != 0;
   if (accum && !acc) { set_error("GS_ACCUM_IMPORTANCE without accumulators"); return GS_ERR_NULL; }
@@ -323,6 +422,7 @@ int32_t gs_accumulate_importance(const gs_projected_t* proj, const uint32_t* val
   ViewSet vs;
   int32_t st = build_views(cams, V, &vs);
   if (st != GS_OK) return st;
+  if ((st = check_records(V, n)) != GS_OK) return st;
   if (n > 0 && (!proj->rec || !proj->bin)) { set_error("projected buffers NULL"); return GS_ERR_NULL; }
   FwdOut o{};
   o.imp = acc->importance;
@@ -346,6 +446,7 @@ int32_t gs_render_backward_pixels(const gs_projected_t* proj, const uint32_t* va
   ViewSet vs;
   int32_t st = build_views(cams, V, &vs);
   if (st != GS_OK) return st;
+  if ((st = check_records(V, n)) != GS_OK) return st;
   if (n == 0) return GS_OK;
   if (!proj->rec || !proj->bin || !grad2d) { set_error("buffer NULL"); return GS_ERR_NULL; }
   const KOpts op = make_kopts(opts);

@@ -1,0 +1,105 @@
+"""Serving scheduler policy on the CPU with a simulated executor: overlap,
+HBM-footprint admission, scene-grouped batching, two-phase reservations,
+failure of requests that can never fit, deterministic Poisson load."""
+import threading
+
+import pytest
+
+from paper_2411_12788_amd.serve import AdmissionError, FakeExecutor, Server, drive, poisson_arrivals
+
+SIZES = {"a": 1000, "b": 2000, "c": 500}
+
+
+def _reqs(n, seed=0):
+    import numpy as np
+    g = np.random.Generator(np.random.PCG64(seed))
+    keys = list(SIZES)
+    return [(keys[int(g.integers(0, len(keys)))], ("cam", k)) for k in range(n)]
+
+
+def test_requests_overlap_when_memory_allows():
+    ex = FakeExecutor(SIZES, per_view_s=0.004, per_batch_s=0.004)
+    srv = Server(ex, hbm_budget=10 ** 9, slots=4, max_batch=1)
+    st = drive(srv, _reqs(40), [0.0] * 40)
+    srv.close()
+    assert st["completed"] == 40
+    assert ex.max_concurrency >= 3
+
+
+def test_admission_by_footprint_limits_concurrency():
+    ex = FakeExecutor(SIZES, per_view_s=0.003, per_batch_s=0.002, bytes_per_gaussian=100)
+    budget = 2000 * 100  # exactly one batch of scene "b", or two of "a"
+    srv = Server(ex, hbm_budget=budget, slots=4, max_batch=1)
+    st = drive(srv, _reqs(30, 1), [0.0] * 30)
+    srv.close()
+    assert st["completed"] == 30
+    assert srv.peak_reserved <= budget
+    assert ex.max_concurrency <= 4
+
+
+def test_same_scene_requests_are_batched_and_fifo_head_first():
+    ex = FakeExecutor({"a": 10}, per_view_s=0.001, per_batch_s=0.01)
+    srv = Server(ex, hbm_budget=10 ** 9, slots=1, max_batch=5)
+    futs = [srv.submit("a", ("cam", k)) for k in range(16)]
+    for f in futs:
+        f.result(timeout=30)
+    srv.close()
+    sizes = [len(b) for b in ex.batches]
+    assert max(sizes) <= 5 and sum(sizes) == 16 and max(sizes) > 1
+    heads = [b[0] for b in ex.batches]
+    assert heads == sorted(heads)
+    # every result carries its own camera back (nothing swapped inside a batch)
+    for k, f in enumerate(futs):
+        assert f.result().color == ("a", ("cam", k))
+
+
+def test_batches_only_merge_one_scene():
+    ex = FakeExecutor(SIZES, per_view_s=0.001, per_batch_s=0.01)
+    srv = Server(ex, hbm_budget=10 ** 9, slots=1, max_batch=8)
+    reqs = _reqs(24, 3)
+    futs = [srv.submit(s, c) for s, c in reqs]
+    for f in futs:
+        f.result(timeout=30)
+    srv.close()
+    for b in ex.batches:
+        scenes = {reqs[i][0] for i in b}
+        assert len(scenes) == 1
+
+
+def test_request_that_can_never_fit_fails_and_others_proceed():
+    ex = FakeExecutor({"small": 10, "huge": 10 ** 9}, per_view_s=0.001)
+    srv = Server(ex, hbm_budget=10 ** 6, slots=2, max_batch=1)
+    f1 = srv.submit("small", 1)
+    f2 = srv.submit("huge", 2)
+    f3 = srv.submit("small", 3)
+    assert f1.result(timeout=10).color == ("small", 1)
+    with pytest.raises(AdmissionError):
+        f2.result(timeout=10)
+    assert f3.result(timeout=10).color == ("small", 3)
+    srv.close()
+
+
+def test_two_phase_growth_does_not_deadlock():
+    ex = FakeExecutor(SIZES, per_view_s=0.002, per_batch_s=0.002, realised_factor=1.8)
+    budget = 2000 * 100 * 2
+    srv = Server(ex, hbm_budget=budget, slots=4, max_batch=2)
+    st = drive(srv, _reqs(40, 4), [0.0] * 40)
+    srv.close()
+    assert st["completed"] == 40
+    assert srv.reserved == 0
+
+
+def test_poisson_arrivals_are_seeded():
+    a = poisson_arrivals(100.0, 50, 7)
+    b = poisson_arrivals(100.0, 50, 7)
+    c = poisson_arrivals(100.0, 50, 8)
+    assert a == b and a != c
+    assert all(x < y for x, y in zip(a, a[1:]))
+
+
+def test_latency_percentiles_reported():
+    ex = FakeExecutor(SIZES, per_view_s=0.001, per_batch_s=0.001)
+    srv = Server(ex, hbm_budget=10 ** 9, slots=2, max_batch=4)
+    st = drive(srv, _reqs(60, 5), poisson_arrivals(400.0, 60, 5))
+    srv.close()
+    assert st["completed"] == 60 and 0 < st["p50_ms"] <= st["p99_ms"] and st["views_per_s"] > 0
