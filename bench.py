@@ -14,9 +14,12 @@ measured with HIP events on the launch stream, CPU-oracle baseline).
 from __future__ import annotations
 
 import argparse
+import glob
+import hashlib
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -47,6 +50,13 @@ def parse():
     ap.add_argument("--workload", default="large", choices=["large", "training", "small"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-pixels", type=int, default=48)
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=240)
+    ap.add_argument("--no-multiview", action="store_true")
+    ap.add_argument("--profile", action="store_true",
+                    help="short run for rocprofv3: a few steps plus a 1 GiB copy kernel for counter calibration")
+    ap.add_argument("--summarize", metavar="DIR",
+                    help="write profiles/ summaries from rocprofv3 output in DIR (kt/, fetch/, write/ sub-folders)")
     return ap.parse_args()
 
 
@@ -164,14 +174,212 @@ def cpu_baseline(wl, sample_pixels: int):
                        f"time scaled to the {P} pixels of the view; measured {t4 - t0:.1f} s")}
 
 
+def serving_bench(n_requests: int):
+    """Eight resident scenes (0.2M..3M Gaussians), Poisson arrivals of
+    forward-only renders at 800x800 / 1280x720 / 1920x1080 from random cameras
+    on a radius-6 sphere.  One-at-a-time capacity mu1 is measured first; the
+    continuous-batching server then runs at 0.8 and 1.5 x mu1, and the
+    one-at-a-time server at 0.8 x mu1 for comparison."""
+    from paper_2411_12788_amd import raster as R
+    from paper_2411_12788_amd.serve import GpuExecutor, Server, drive, poisson_arrivals
+    t_gen = time.perf_counter()
+    scenes = {}
+    for k, n in enumerate(gs_inputs.SERVING_SCENE_SIZES):
+        scenes[k] = R.DeviceScene.from_numpy(gs_inputs.surface_scene(n, 500 + k))
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t_gen
+    resident = sum(s.nbytes() for s in scenes.values())
+
+    def requests(count, seed):
+        g = gs_inputs.rng(seed)
+        out = []
+        for _ in range(count):
+            sid = int(g.integers(0, len(scenes)))
+            w, h = gs_inputs.SERVING_RESOLUTIONS[int(g.integers(0, 3))]
+            d = g.normal(size=3)
+            d /= np.linalg.norm(d)
+            out.append((sid, gs_inputs.look_at(6.0 * d, (0, 0, 0), w, h)))
+        return out
+
+    budget = 24 << 30
+    # warm-up and one-at-a-time capacity (back-to-back submissions)
+    ex1 = GpuExecutor(scenes, slots=1)
+    srv = Server(ex1, budget, slots=1, max_batch=1)
+    drive(srv, requests(24, 1), [0.0] * 24)
+    srv.close()
+    srv = Server(ex1, budget, slots=1, max_batch=1)
+    cap = drive(srv, requests(max(40, n_requests // 4), 2), [0.0] * max(40, n_requests // 4))
+    srv.close()
+    mu1 = cap["views_per_s"]
+    out = {"workload": "8 resident scenes 0.2M-3M Gaussians (13.7M total), resolutions "
+                       "800x800/1280x720/1920x1080, Poisson arrivals",
+           "resident_gb": round(resident / 1e9, 3), "one_at_a_time_capacity_views_per_s": round(mu1, 2),
+           "runs": []}
+    for mode, slots, mb, factor in (("one_at_a_time", 1, 1, 0.8), ("continuous_batching", 4, 8, 0.8),
+                                    ("continuous_batching", 4, 8, 1.5)):
+        ex = GpuExecutor(scenes, slots=slots)
+        srv = Server(ex, budget, slots=slots, max_batch=mb)
+        qps = factor * mu1
+        st = drive(srv, requests(n_requests, 10 + slots), poisson_arrivals(qps, n_requests, 20 + slots))
+        srv.close()
+        out["runs"].append({"mode": mode, "offered_qps": round(qps, 2), "views_per_s": round(st["views_per_s"], 2),
+                            "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3),
+                            "mean_batch": round(st["mean_batch"], 2),
+                            "peak_reserved_gb": round(st["peak_reserved_gb"], 3), "requests": st["completed"]})
+    return out
+
+
+def multiview_bench(steps: int, warmup: int):
+    """Batched differentiation: one launch per stage for 16 views of a 1M-Gaussian
+    scene at mixed resolutions (640x480 .. 1600x1200), forward + backward
+    through the autograd Function with recompute-in-backward, L1 loss."""
+    from paper_2411_12788_amd import raster as R
+    from paper_2411_12788_amd.autograd import rasterize
+    wl = gs_inputs.multiview()
+    sc = R.DeviceScene.from_numpy(wl.scene)
+    leaves = [t.clone().requires_grad_(True) for t in (sc.means, sc.scales, sc.quats, sc.opacity, sc.sh)]
+    lay = R.view_layout(wl.cameras)
+    target = torch.from_numpy(gs_inputs.uniform_image(3, lay.pixels_total, 777)).cuda()
+
+    def one():
+        for x in leaves:
+            x.grad = None
+        color, depth, imax = rasterize(*leaves, wl.cameras)
+        (color - target).abs().mean().backward()
+
+    for _ in range(warmup):
+        one()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        one()
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / steps
+    return {"workload": wl.name, "gaussians": wl.scene.n, "views": len(wl.cameras),
+            "pixels": lay.pixels_total, "ms_per_step": round(ms, 3), "views_per_s": round(1e3 * len(wl.cameras) / ms, 2),
+            "mode": "autograd, recompute in backward"}
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2411_12788_amd", "csrc", "*"))):
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or
+    None when there is none or the kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_counters.md")
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    m = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    h = re.search(r"source_sha256:\s*([0-9a-f]+)", txt)
+    if not m or not h or h.group(1) != source_hash():
+        return None
+    return float(m.group(1))
+
+
+def profile_run(steps: int):
+    wl = workload("large")
+    step = Step(wl)
+    for _ in range(steps):
+        step.run(record=False)
+    torch.cuda.synchronize()
+    a = torch.empty(1 << 28, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)  # 1 GiB read + 1 GiB written: calibration for the HBM counters
+    torch.cuda.synchronize()
+    print(json.dumps({"profile_steps": steps, "copy_bytes_each_way": a.numel() * 4, "source_sha256": source_hash()}),
+          flush=True)
+
+
+STAGE_KERNELS = {"render_fwd": "k_render_fwd", "render_bwd": "k_render_bwd", "project": "k_project",
+                 "project_bwd": "k_project_bwd", "sort_pass": "k_os_pass"}
+PROFILE_CMDS = {
+    "kt": "rocprofv3 --kernel-trace --stats -d {d}/kt -o kt --output-format csv -- python3 bench.py --profile --steps 3",
+    "fetch": "rocprofv3 --pmc FETCH_SIZE -d {d}/fetch -o fetch --output-format csv -- python3 bench.py --profile --steps 2",
+    "write": "rocprofv3 --pmc WRITE_SIZE -d {d}/write -o write --output-format csv -- python3 bench.py --profile --steps 2",
+}
+
+
+def _short(name: str) -> str:
+    m = re.search(r"msplat::(k_[a-z0-9_]+)", name)
+    if m:
+        return m.group(1)
+    if "copyBuffer" in name:
+        return "copyBuffer (hipMemcpy D2D)"
+    return name.split("(")[0][:60]
+
+
+def summarize(d: str) -> None:
+    """Turn the three rocprofv3 runs of `bench.py --profile` into the text
+    summaries kept under profiles/ (kernel times; HBM bytes per launch from
+    FETCH_SIZE / WRITE_SIZE scaled by what the counters read for a 1 GiB copy)."""
+    import csv
+    stats = list(csv.DictReader(open(os.path.join(d, "kt", "kt_kernel_stats.csv"))))
+    lines = ["# Kernel times: 3M Gaussians, one 1920x1080 view, fwd+bwd step", "",
+             "Command (from the repository root): `" + PROFILE_CMDS["kt"].format(d="gpurun_out/prof") + "`", "",
+             f"source_sha256: {source_hash()}", "",
+             "| kernel | calls | avg us | min us | max us | share % |", "|---|---|---|---|---|---|"]
+    for r in stats:
+        lines.append(f"| {_short(r['Name'])} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                     f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.2f} |")
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    open(os.path.join(ROOT, "profiles", "kernels_surfaces_3M_1920x1080.md"), "w").write("\n".join(lines) + "\n")
+
+    def counter(kind):
+        rows = list(csv.DictReader(open(os.path.join(d, kind, f"{kind}_counter_collection.csv"))))
+        per = {}
+        for r in rows:
+            per.setdefault(_short(r["Kernel_Name"]), []).append(float(r["Counter_Value"]))
+        return per
+
+    fetch, write = counter("fetch"), counter("write")
+    copy = "copyBuffer (hipMemcpy D2D)"
+    gib_kib = float(1 << 20)
+    f_fac = max(fetch.get(copy, [gib_kib])) / gib_kib
+    w_fac = max(write.get(copy, [gib_kib])) / gib_kib
+    avg_us = {_short(r["Name"]): float(r["AverageNs"]) / 1e3 for r in stats}
+    for stage, k in STAGE_KERNELS.items():
+        if k not in fetch or k not in write:
+            continue
+        fk = sum(fetch[k]) / len(fetch[k])
+        wk = sum(write[k]) / len(write[k])
+        traffic = 1024.0 * (fk / f_fac + wk / w_fac)
+        txt = [f"# HBM traffic of {k}: 3M Gaussians, one 1920x1080 view", "",
+               "Commands (from the repository root):", "",
+               "- `" + PROFILE_CMDS["fetch"].format(d="gpurun_out/prof") + "`",
+               "- `" + PROFILE_CMDS["write"].format(d="gpurun_out/prof") + "`",
+               "- `" + PROFILE_CMDS["kt"].format(d="gpurun_out/prof") + "` (durations)", "",
+               f"- FETCH_SIZE per dispatch: {fk:.1f} KiB (mean of {len(fetch[k])} dispatches)",
+               f"- WRITE_SIZE per dispatch: {wk:.1f} KiB",
+               f"- calibration: a 1 GiB device copy reads {f_fac:.4f} GiB by FETCH_SIZE and writes "
+               f"{w_fac:.4f} GiB by WRITE_SIZE; the counters are divided by these factors",
+               f"- average duration: {avg_us.get(k, float('nan')):.1f} us",
+               f"- measured HBM rate: {traffic / (avg_us.get(k, float('nan')) * 1e-6) / 1e9:.1f} GB/s", "",
+               f"traffic_bytes_per_launch: {traffic:.6e}",
+               f"source_sha256: {source_hash()}", ""]
+        open(os.path.join(ROOT, "profiles", f"{stage}_counters.md"), "w").write("\n".join(txt))
+    print(f"wrote profiles/ from {d}")
+
+
 def main():
     args = parse()
+    if args.summarize:
+        summarize(args.summarize)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU only; multi-GPU scaling is not implemented "
                                    "(the path would shard by view with a gradient all-reduce)",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     torch.cuda.set_device(0)
+    if args.profile:
+        profile_run(max(2, args.steps))
+        return
     wl = workload(args.workload)
     step = Step(wl)
     for _ in range(args.warmup):
@@ -208,7 +416,7 @@ def main():
         a = u / (avg[k] * 1e-3)
         stages[k].update({"bound": b, "achieved": round(a, 3), "unit": un, "frac": round(a / pk, 4)})
     out = {
-        "metric": "fwd+bwd ms/step @3M Gaussians 1080p",
+        "metric": "fwd+bwd ms/step @3M Gaussians 1080p; served views/s + p50/p99 latency",
         "value": round(ms_step, 4),
         "unit": "ms/step",
         "n_gpus": 1,
@@ -225,9 +433,13 @@ def main():
                    "n_visible": n_vis, "n_isect": int(st.n_isect), "key_bits": int(st.key_bits),
                    "included_pairs": int(nc)},
         "roofline": {"bound": bound, "kernel": dom, "achieved": round(achieved, 3), "peak": peak, "unit": unit,
-                     "frac": round(achieved / peak, 5), "traffic": None},
+                     "frac": round(achieved / peak, 5), "traffic": traffic_from_profiles(dom)},
         "stages": stages,
     }
+    if not args.no_multiview:
+        out["multiview"] = multiview_bench(5, 2)
+    if not args.no_serving:
+        out["serving"] = serving_bench(args.serving_requests)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample_pixels)
     print(json.dumps(out), flush=True)

@@ -200,11 +200,23 @@ int32_t gs_bin_count(const gs_projected_t* proj, const gs_camera_t* cams, int32_
  * their centres; here per tile.  vals [dev, u32 n_isect] receives the sorted
  * record indices; ranges [dev, u32 tiles_total][2] receives [start, end) per
  * tile ([0, 0) if empty); keys [dev, u64 n_isect] may be NULL, else receives the
- * sorted keys (global tile << 32) | float32 bits of z. */
+ * sorted keys (global tile << 32) | float32 bits of z; tile_order [dev, u32
+ * tiles_total] may be NULL, else receives the processing order described at
+ * gs_tile_order. */
 size_t gs_bin_sort_workspace_size(int64_t n_isect);
 int32_t gs_bin_sort(const gs_projected_t* proj, const gs_camera_t* cams, int32_t V, int64_t n,
                     const uint32_t* offsets, const gs_bin_stats_t* stats, uint64_t* keys, uint32_t* vals,
-                    uint32_t* ranges, void* ws, size_t ws_bytes, void* stream);
+                    uint32_t* ranges, uint32_t* tile_order, void* ws, size_t ws_bytes, void* stream);
+
+/* Processing order of the tiles for the compositing kernels: tile ids
+ * [dev, u32 tiles_total] grouped by the bit length of their list length,
+ * longest lists first (order inside a group unspecified).  Work per tile
+ * varies by orders of magnitude; starting the long lists first keeps them off
+ * the critical path and spreads them over all XCDs.  Results do not depend on
+ * the order.  Also produced by gs_bin_sort when tile_order is non-NULL. */
+size_t gs_tile_order_workspace_size(void);
+int32_t gs_tile_order(const uint32_t* ranges, int32_t tiles_total, uint32_t* tile_order, void* ws, size_t ws_bytes,
+                      void* stream);
 
 /* The three stages of gs_bin_sort, exported separately.
  * gs_emit_keys: key = (global tile << depth_shift) | (zbits - zbits_min) for each pair.
@@ -226,17 +238,19 @@ int32_t gs_tile_ranges(const uint64_t* keys, int64_t n, int32_t depth_shift, uin
  * alpha_min; stop before a Gaussian whose inclusion would take T below t_min;
  * w = alpha T; C += w c; imax = argmax w (first wins ties, Eq. (2)); depth per
  * depth_mode.  With GS_ACCUM_IMPORTANCE, acc (non-NULL) also receives the
- * importance / wmax / area sums (Sec. 3.2, Eq. (3), Sec. 5.1) of the same pass. */
+ * importance / wmax / area sums (Sec. 3.2, Eq. (3), Sec. 5.1) of the same pass.
+ * tile_order (from gs_bin_sort / gs_tile_order) may be NULL for natural order;
+ * the same holds for the other compositing calls below. */
 int32_t gs_render_forward(const gs_scene_t* scene, const gs_projected_t* proj, const uint32_t* vals,
-                          const uint32_t* ranges, const gs_camera_t* cams, int32_t V, const gs_opts_t* opts,
-                          const gs_fwd_out_t* out, const gs_accum_t* acc, void* stream);
+                          const uint32_t* ranges, const uint32_t* tile_order, const gs_camera_t* cams, int32_t V,
+                          const gs_opts_t* opts, const gs_fwd_out_t* out, const gs_accum_t* acc, void* stream);
 
 /* a6 -- the accumulations alone (same decisions as gs_render_forward; no
  * per-pixel outputs): importance I_i (Sec. 3.2), wmax, area S_i (Eq. (3)).
  * opts->flags may carry GS_ACCUM_PER_VIEW. */
 int32_t gs_accumulate_importance(const gs_projected_t* proj, const uint32_t* vals, const uint32_t* ranges,
-                                 const gs_camera_t* cams, int32_t V, int64_t n, const gs_opts_t* opts,
-                                 const gs_accum_t* acc, void* stream);
+                                 const uint32_t* tile_order, const gs_camera_t* cams, int32_t V, int64_t n,
+                                 const gs_opts_t* opts, const gs_accum_t* acc, void* stream);
 
 /* a7 + a8 -- backward of Eq. (1) and of the projection, restricted to an
  * active mask (region-prioritized optimisation, Sec. 5.2): per pixel, reverse
@@ -248,15 +262,16 @@ int32_t gs_accumulate_importance(const gs_projected_t* proj, const uint32_t* val
  * first; rows of inactive Gaussians stay 0); grads receives the parameter
  * gradients summed over views (inactive rows 0). */
 int32_t gs_render_backward(const gs_scene_t* scene, const gs_projected_t* proj, const uint32_t* vals,
-                           const uint32_t* ranges, const gs_camera_t* cams, int32_t V, const gs_opts_t* opts,
-                           const float* t_final, const uint32_t* last, const float* dl_dcolor,
-                           const uint8_t* active, float* grad2d, const gs_grads_t* grads, void* stream);
+                           const uint32_t* ranges, const uint32_t* tile_order, const gs_camera_t* cams, int32_t V,
+                           const gs_opts_t* opts, const float* t_final, const uint32_t* last,
+                           const float* dl_dcolor, const uint8_t* active, float* grad2d, const gs_grads_t* grads,
+                           void* stream);
 
 /* a7 alone: adds into grad2d (caller zeroes it). */
 int32_t gs_render_backward_pixels(const gs_projected_t* proj, const uint32_t* vals, const uint32_t* ranges,
-                                  const gs_camera_t* cams, int32_t V, int64_t n, const gs_opts_t* opts,
-                                  const float* t_final, const uint32_t* last, const float* dl_dcolor,
-                                  const uint8_t* active, float* grad2d, void* stream);
+                                  const uint32_t* tile_order, const gs_camera_t* cams, int32_t V, int64_t n,
+                                  const gs_opts_t* opts, const float* t_final, const uint32_t* last,
+                                  const float* dl_dcolor, const uint8_t* active, float* grad2d, void* stream);
 
 /* a8 alone: chain rule of gs_project from grad2d to the parameters (written,
  * summed over views; rows with active[i] == 0 written as 0; records with

@@ -74,18 +74,22 @@ _SIGS = {
     "gs_bin_count_workspace_size": (c_sz, [c_i64]),
     "gs_bin_count": (c_i32, [P(Projected), P(Camera), c_i32, c_i64, c_p, P(BinStats), c_p, c_sz, c_p]),
     "gs_bin_sort_workspace_size": (c_sz, [c_i64]),
-    "gs_bin_sort": (c_i32, [P(Projected), P(Camera), c_i32, c_i64, c_p, P(BinStats), c_p, c_p, c_p, c_p, c_sz, c_p]),
+    "gs_bin_sort": (c_i32, [P(Projected), P(Camera), c_i32, c_i64, c_p, P(BinStats), c_p, c_p, c_p, c_p, c_p, c_sz,
+                            c_p]),
+    "gs_tile_order_workspace_size": (c_sz, []),
+    "gs_tile_order": (c_i32, [c_p, c_i32, c_p, c_p, c_sz, c_p]),
     "gs_emit_keys": (c_i32, [P(Projected), P(Camera), c_i32, c_i64, c_p, c_i32, c_u32, c_p, c_p, c_p]),
     "gs_sort_workspace_size": (c_sz, [c_i64]),
     "gs_sort_pairs": (c_i32, [c_p, c_p, c_i64, c_i32, c_p, c_sz, c_p]),
     "gs_tile_ranges": (c_i32, [c_p, c_i64, c_i32, c_u32, c_i32, c_p, c_p, c_p]),
-    "gs_render_forward": (c_i32, [P(Scene), P(Projected), c_p, c_p, P(Camera), c_i32, P(Opts), P(FwdOut), P(Accum),
-                                  c_p]),
-    "gs_accumulate_importance": (c_i32, [P(Projected), c_p, c_p, P(Camera), c_i32, c_i64, P(Opts), P(Accum), c_p]),
-    "gs_render_backward": (c_i32, [P(Scene), P(Projected), c_p, c_p, P(Camera), c_i32, P(Opts), c_p, c_p, c_p, c_p,
-                                   c_p, P(Grads), c_p]),
-    "gs_render_backward_pixels": (c_i32, [P(Projected), c_p, c_p, P(Camera), c_i32, c_i64, P(Opts), c_p, c_p, c_p,
-                                          c_p, c_p, c_p]),
+    "gs_render_forward": (c_i32, [P(Scene), P(Projected), c_p, c_p, c_p, P(Camera), c_i32, P(Opts), P(FwdOut),
+                                  P(Accum), c_p]),
+    "gs_accumulate_importance": (c_i32, [P(Projected), c_p, c_p, c_p, P(Camera), c_i32, c_i64, P(Opts), P(Accum),
+                                         c_p]),
+    "gs_render_backward": (c_i32, [P(Scene), P(Projected), c_p, c_p, c_p, P(Camera), c_i32, P(Opts), c_p, c_p, c_p,
+                                   c_p, c_p, P(Grads), c_p]),
+    "gs_render_backward_pixels": (c_i32, [P(Projected), c_p, c_p, c_p, P(Camera), c_i32, c_i64, P(Opts), c_p, c_p,
+                                          c_p, c_p, c_p, c_p]),
     "gs_project_backward": (c_i32, [P(Scene), P(Projected), P(Camera), c_i32, P(Opts), c_p, c_p, P(Grads), c_p]),
     "gs_l1_loss_grad": (c_i32, [c_p, c_p, c_i64, c_p, c_p, c_p]),
     "gs_fill_u32": (c_i32, [c_p, c_u32, c_i64, c_p]),

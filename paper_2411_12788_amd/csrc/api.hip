@@ -86,18 +86,46 @@ __global__ void k_fill_u32(uint32_t* __restrict__ dst, uint32_t value, int64_t c
   for (; i < count; i += stride) dst[i] = value;
 }
 
-__global__ void k_l1_loss_grad(const float* __restrict__ color, const float* __restrict__ target, int64_t count,
-                               float inv_count, float* __restrict__ grad, float* __restrict__ loss) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+// Streaming L1 gradient: float4 loads and stores, the loss reduced per
+// workgroup (DPP-free shuffles, then LDS) with one atomic per workgroup.
+__global__ __launch_bounds__(kBlock) void k_l1_loss_grad(const float* __restrict__ color,
+                                                         const float* __restrict__ target, int64_t count,
+                                                         float inv_count, float* __restrict__ grad,
+                                                         float* __restrict__ loss) {
+  __shared__ float part[kBlock / kWave];
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const bool aligned = ((reinterpret_cast<uintptr_t>(color) | reinterpret_cast<uintptr_t>(target) |
+                         reinterpret_cast<uintptr_t>(grad)) & 15) == 0;
   float acc = 0.f;
-  for (; i < count; i += stride) {
-    float d = color[i] - target[i];
-    grad[i] = d > 0.f ? inv_count : (d < 0.f ? -inv_count : 0.f);
+  auto sgn = [inv_count](float d) { return d > 0.f ? inv_count : (d < 0.f ? -inv_count : 0.f); };
+  int64_t done = 0;
+  if (aligned) {
+    const int64_t n4 = count / 4;
+    const float4* c4 = reinterpret_cast<const float4*>(color);
+    const float4* t4 = reinterpret_cast<const float4*>(target);
+    float4* g4 = reinterpret_cast<float4*>(grad);
+    for (int64_t i = tid; i < n4; i += stride) {
+      const float4 c = c4[i], t = t4[i];
+      const float d0 = c.x - t.x, d1 = c.y - t.y, d2 = c.z - t.z, d3 = c.w - t.w;
+      g4[i] = make_float4(sgn(d0), sgn(d1), sgn(d2), sgn(d3));
+      acc += fabsf(d0) + fabsf(d1) + fabsf(d2) + fabsf(d3);
+    }
+    done = n4 * 4;
+  }
+  for (int64_t i = done + tid; i < count; i += stride) {
+    const float d = color[i] - target[i];
+    grad[i] = sgn(d);
     acc += fabsf(d);
   }
   acc = wave_sum(acc);
-  if (loss && lane_id() == 0) atomicAdd(loss, acc * inv_count);
+  if (lane_id() == 0) part[threadIdx.x / kWave] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0 && loss) {
+    float s = 0.f;
+    for (int k = 0; k < kBlock / kWave; ++k) s += part[k];
+    atomicAdd(loss, s * inv_count);
+  }
 }
 
 int32_t launch_fill(void* dst, uint32_t value, int64_t count, hipStream_t st) {
@@ -159,8 +187,8 @@ int32_t gs_l1_loss_grad(const float* color, const float* target, int64_t count, 
   if (count < 0) { set_error("count < 0"); return GS_ERR_SHAPE; }
   if (count == 0) return GS_OK;
   if (!color || !target || !dl_dcolor) { set_error("NULL buffer"); return GS_ERR_NULL; }
-  int64_t blocks = (count + kBlock - 1) / kBlock;
-  if (blocks > 4096) blocks = 4096;
+  int64_t blocks = (count / 4 + kBlock - 1) / kBlock + 1;
+  if (blocks > 1024) blocks = 1024;
   hipLaunchKernelGGL(k_l1_loss_grad, dim3((unsigned)blocks), dim3(kBlock), 0, (hipStream_t)stream, color, target,
                      count, (float)(1.0 / (double)count), dl_dcolor, loss);
   MS_CHECK_LAUNCH("l1_loss_grad");

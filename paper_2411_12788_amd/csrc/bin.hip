@@ -1,6 +1,6 @@
 // a2-a4: tile binning.  Exclusive scan of tiles_touched, emission of one
 // (tile | depth) key per (tile, record) pair, stable LSD radix sort on the
-// significant key bits only, and per-tile [start, end) ranges.
+// significant key bits only (sort.hip), and per-tile [start, end) ranges.
 //
 // Sort keys are compacted before sorting: depth enters as (zbits - zbits_min)
 // on depth_bits = bit length of (zbits_max - zbits_min) bits and the global
@@ -14,9 +14,6 @@ namespace msplat {
 
 constexpr int kScanItems = 16;
 constexpr int kScanTile = kBlock * kScanItems;  // 4096 elements per block
-constexpr int kSortItems = 16;
-constexpr int kSortTile = kBlock * kSortItems;   // 4096 keys per block
-constexpr int kRadix = 256;
 constexpr int kWaves = kBlock / kWave;
 
 // ---------------------------------------------------------------------------
@@ -176,60 +173,6 @@ __global__ __launch_bounds__(kBlock) void k_count_down(const int4* __restrict__ 
 }
 
 // ---------------------------------------------------------------------------
-// generic exclusive scan of a u32 array (sums < 2^32), three launches
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_scan_reduce(const uint32_t* __restrict__ in, int64_t count,
-                                                        uint32_t* __restrict__ block_sum) {
-  __shared__ uint32_t lds[kWaves + 1];
-  const int64_t base = (int64_t)blockIdx.x * kScanTile;
-  uint32_t s = 0;
-#pragma unroll 4
-  for (int k = 0; k < kScanItems; ++k) {
-    const int64_t e = base + (int64_t)k * kBlock + threadIdx.x;
-    s += e < count ? in[e] : 0u;
-  }
-  uint32_t tot;
-  block_exclusive_scan<uint32_t>(s, lds, &tot);
-  if (threadIdx.x == 0) block_sum[blockIdx.x] = tot;
-}
-
-__global__ __launch_bounds__(kBlock) void k_scan_top(uint32_t* __restrict__ block_sum, int64_t nb) {
-  __shared__ uint32_t lds[kWaves + 1];
-  uint32_t carry = 0;
-  for (int64_t c0 = 0; c0 < nb; c0 += kBlock) {
-    const int64_t k = c0 + threadIdx.x;
-    uint32_t x = k < nb ? block_sum[k] : 0u;
-    uint32_t tot;
-    uint32_t ex = block_exclusive_scan<uint32_t>(x, lds, &tot);
-    if (k < nb) block_sum[k] = carry + ex;
-    carry += tot;
-  }
-}
-
-__global__ __launch_bounds__(kBlock) void k_scan_down(const uint32_t* __restrict__ in, int64_t count,
-                                                      const uint32_t* __restrict__ block_sum,
-                                                      uint32_t* __restrict__ out) {
-  __shared__ uint32_t lds[kWaves + 1];
-  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
-  uint32_t t[kScanItems];
-  uint32_t s = 0;
-#pragma unroll
-  for (int k = 0; k < kScanItems; ++k) {
-    const int64_t e = base + k;
-    t[k] = e < count ? in[e] : 0u;
-    s += t[k];
-  }
-  uint32_t tot;
-  uint32_t run = block_sum[blockIdx.x] + block_exclusive_scan<uint32_t>(s, lds, &tot);
-#pragma unroll
-  for (int k = 0; k < kScanItems; ++k) {
-    const int64_t e = base + k;
-    if (e < count) out[e] = run;
-    run += t[k];
-  }
-}
-
-// ---------------------------------------------------------------------------
 // emission of (tile | depth) keys
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_emit(const int4* __restrict__ bin, const uint32_t* __restrict__ offsets,
@@ -256,92 +199,6 @@ __global__ __launch_bounds__(kBlock) void k_emit(const int4* __restrict__ bin, c
 }
 
 // ---------------------------------------------------------------------------
-// stable LSD radix sort, 8-bit digits, reduce-then-scan per pass
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_sort_upsweep(const uint64_t* __restrict__ keys, int64_t n, int32_t shift,
-                                                         int64_t nb, uint32_t* __restrict__ hist) {
-  __shared__ uint32_t h[kRadix];
-  h[threadIdx.x] = 0;
-  __syncthreads();
-  const int64_t base = (int64_t)blockIdx.x * kSortTile;
-#pragma unroll 4
-  for (int k = 0; k < kSortItems; ++k) {
-    const int64_t e = base + (int64_t)k * kBlock + threadIdx.x;
-    if (e < n) atomicAdd(&h[(uint32_t)(keys[e] >> shift) & 0xffu], 1u);
-  }
-  __syncthreads();
-  hist[(int64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
-}
-
-__device__ __forceinline__ uint64_t match_digit(uint32_t d) {
-  uint64_t m = ~0ull;
-#pragma unroll
-  for (int b = 0; b < 8; ++b) {
-    const uint64_t bb = __ballot((d >> b) & 1u);
-    m &= ((d >> b) & 1u) ? bb : ~bb;
-  }
-  return m;
-}
-
-__global__ __launch_bounds__(kBlock) void k_sort_downsweep(const uint64_t* __restrict__ kin,
-                                                           const uint32_t* __restrict__ vin, int64_t n,
-                                                           int32_t shift, int64_t nb,
-                                                           const uint32_t* __restrict__ hist,
-                                                           uint64_t* __restrict__ kout, uint32_t* __restrict__ vout) {
-  __shared__ uint32_t cnt[kWaves][kRadix];
-  __shared__ uint32_t goff[kRadix];
-  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-#pragma unroll
-  for (int k = 0; k < kWaves; ++k) cnt[k][threadIdx.x] = 0;
-  goff[threadIdx.x] = hist[(int64_t)threadIdx.x * nb + blockIdx.x];
-  __syncthreads();
-  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
-  const int64_t base = (int64_t)blockIdx.x * kSortTile + (int64_t)w * (kSortItems * kWave);
-  uint64_t key[kSortItems];
-  uint32_t val[kSortItems];
-  uint32_t rank[kSortItems];
-#pragma unroll
-  for (int k = 0; k < kSortItems; ++k) {
-    const int64_t e = base + (int64_t)k * kWave + lane;
-    const bool in = e < n;
-    key[k] = in ? kin[e] : ~0ull;
-    val[k] = in ? vin[e] : 0u;
-    // out-of-range lanes get digit 256 (never matches a real digit)
-    const uint32_t d = in ? ((uint32_t)(key[k] >> shift) & 0xffu) : 256u;
-    uint64_t m = match_digit(d & 0xffu);
-    const uint64_t inm = __ballot(in);
-    m &= in ? inm : ~inm;
-    const uint32_t before = __popcll(m & lt);
-    const uint32_t prev = in ? cnt[w][d & 0xffu] : 0u;
-    rank[k] = prev + before;
-    const bool leader = in && before == 0;
-    if (leader) cnt[w][d] = prev + (uint32_t)__popcll(m);
-  }
-  __syncthreads();
-  // exclusive prefix over waves, per digit
-  {
-    uint32_t run = 0;
-#pragma unroll
-    for (int k = 0; k < kWaves; ++k) {
-      const uint32_t c = cnt[k][threadIdx.x];
-      cnt[k][threadIdx.x] = run;
-      run += c;
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int k = 0; k < kSortItems; ++k) {
-    const int64_t e = base + (int64_t)k * kWave + lane;
-    if (e < n) {
-      const uint32_t d = (uint32_t)(key[k] >> shift) & 0xffu;
-      const uint32_t dst = goff[d] + cnt[w][d] + rank[k];
-      kout[dst] = key[k];
-      vout[dst] = val[k];
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------
 // tile ranges
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_ranges(const uint64_t* __restrict__ keys, int64_t n, int32_t shift,
@@ -359,6 +216,48 @@ __global__ __launch_bounds__(kBlock) void k_ranges(const uint64_t* __restrict__ 
     const uint64_t lowmask = shift >= 64 ? ~0ull : ((1ull << shift) - 1ull);
     keys_out[k] = (tile << 32) | (uint64_t)((uint32_t)(key & lowmask) + zmin);
   }
+}
+
+// ---------------------------------------------------------------------------
+// tile processing order: counting sort of tiles by the bit length of their
+// list length, longest first (bucket 0 = lists of 2^31.. entries, bucket 32 =
+// empty tiles)
+// ---------------------------------------------------------------------------
+constexpr int kOrderBuckets = 33;
+
+__device__ __forceinline__ int order_bucket(const uint32_t* ranges, int32_t t) {
+  const uint32_t c = ranges[2 * t + 1] - ranges[2 * t];
+  return c == 0 ? 32 : __clz((int)c);
+}
+
+__global__ __launch_bounds__(kBlock) void k_order_hist(const uint32_t* __restrict__ ranges, int32_t tiles,
+                                                       uint32_t* __restrict__ hist) {
+  __shared__ uint32_t h[kOrderBuckets];
+  if (threadIdx.x < kOrderBuckets) h[threadIdx.x] = 0;
+  __syncthreads();
+  const int32_t t = blockIdx.x * kBlock + threadIdx.x;
+  if (t < tiles) atomicAdd(&h[order_bucket(ranges, t)], 1u);
+  __syncthreads();
+  if (threadIdx.x < kOrderBuckets && h[threadIdx.x]) atomicAdd(hist + threadIdx.x, h[threadIdx.x]);
+}
+
+__global__ void k_order_scan(uint32_t* __restrict__ hist) {
+  if (threadIdx.x == 0) {
+    uint32_t run = 0;
+    for (int b = 0; b < kOrderBuckets; ++b) {
+      const uint32_t c = hist[b];
+      hist[b] = run;
+      run += c;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_order_scatter(const uint32_t* __restrict__ ranges, int32_t tiles,
+                                                          uint32_t* __restrict__ cursor, uint32_t* __restrict__ order) {
+  const int32_t t = blockIdx.x * kBlock + threadIdx.x;
+  if (t >= tiles) return;
+  const uint32_t pos = atomicAdd(cursor + order_bucket(ranges, t), 1u);
+  if (pos < (uint32_t)tiles) order[pos] = (uint32_t)t;
 }
 
 __global__ void k_copy_u64(const uint64_t* __restrict__ a, uint64_t* __restrict__ b, int64_t n) {
@@ -394,85 +293,11 @@ static CountWs carve_count(void* ws, int64_t nrec) {
   return c;
 }
 
-static int64_t sort_blocks(int64_t n) { return (n + kSortTile - 1) / kSortTile; }
+size_t onesweep_ws_size(int64_t n, int32_t passes);
+int32_t onesweep_sort(uint64_t* k0, uint32_t* v0, int64_t n, int32_t bits, void* ws, uint32_t* vfinal,
+                      uint64_t** keys_sorted, hipStream_t st);
 
-// workspace of the radix sort proper: alternate key/val buffers + histograms
-size_t sort_ws_size(int64_t n) {
-  const int64_t nn = n > 0 ? n : 1;
-  const int64_t nb = sort_blocks(nn);
-  const int64_t hist = nb * kRadix;
-  const int64_t hb = (hist + kScanTile - 1) / kScanTile;
-  return align256(nn * 8) + align256(nn * 4) + align256(hist * 4) + align256(hb * 4);
-}
-
-struct SortWs {
-  uint64_t* keys;
-  uint32_t* vals;
-  uint32_t* hist;
-  uint32_t* hsum;
-};
-
-static SortWs carve_sort(void* ws, int64_t n) {
-  const int64_t nn = n > 0 ? n : 1;
-  const int64_t nb = sort_blocks(nn);
-  const int64_t hist = nb * kRadix;
-  char* p = (char*)ws;
-  SortWs s;
-  s.keys = (uint64_t*)p; p += align256(nn * 8);
-  s.vals = (uint32_t*)p; p += align256(nn * 4);
-  s.hist = (uint32_t*)p; p += align256(hist * 4);
-  s.hsum = (uint32_t*)p;
-  return s;
-}
-
-static int32_t scan_u32(uint32_t* data, int64_t count, uint32_t* bsum, hipStream_t st) {
-  const int64_t nb = (count + kScanTile - 1) / kScanTile;
-  hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kBlock), 0, st, data, count, bsum);
-  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kBlock), 0, st, bsum, nb);
-  hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(kBlock), 0, st, data, count, bsum, data);
-  MS_CHECK_LAUNCH("scan");
-  return GS_OK;
-}
-
-// Sorts (k0, v0) by key bits [0, bits).  Passes alternate between (k0, v0)
-// and the workspace pair; the final pass writes vals to `vfinal` (may equal
-// v0) and the function returns the key buffer that holds the sorted keys.
-static int32_t radix_sort(uint64_t* k0, uint32_t* v0, int64_t n, int32_t bits, const SortWs& s,
-                          uint32_t* vfinal, uint64_t** keys_sorted, hipStream_t st) {
-  const int passes = (bits + 7) / 8;
-  *keys_sorted = k0;
-  if (n <= 1 || passes == 0) {
-    if (vfinal != v0 && n > 0) {
-      hipLaunchKernelGGL(k_copy_u32, dim3(grid_1d(n)), dim3(kBlock), 0, st, v0, vfinal, n);
-      MS_CHECK_LAUNCH("copy");
-    }
-    return GS_OK;
-  }
-  const int64_t nb = sort_blocks(n);
-  uint64_t* kin = k0;
-  uint32_t* vin = v0;
-  for (int p = 0; p < passes; ++p) {
-    uint64_t* kout = (kin == k0) ? s.keys : k0;
-    uint32_t* vout = (vin == v0) ? s.vals : v0;
-    if (p == passes - 1) vout = vfinal;
-    if (vout == vin) vout = (vin == v0) ? s.vals : v0;  // never sort in place
-    const int32_t shift = 8 * p;
-    hipLaunchKernelGGL(k_sort_upsweep, dim3((unsigned)nb), dim3(kBlock), 0, st, kin, n, shift, nb, s.hist);
-    int32_t r = scan_u32(s.hist, nb * kRadix, s.hsum, st);
-    if (r != GS_OK) return r;
-    hipLaunchKernelGGL(k_sort_downsweep, dim3((unsigned)nb), dim3(kBlock), 0, st, kin, vin, n, shift, nb, s.hist,
-                       kout, vout);
-    MS_CHECK_LAUNCH("sort pass");
-    kin = kout;
-    vin = vout;
-  }
-  if (vin != vfinal) {
-    hipLaunchKernelGGL(k_copy_u32, dim3(grid_1d(n)), dim3(kBlock), 0, st, vin, vfinal, n);
-    MS_CHECK_LAUNCH("copy");
-  }
-  *keys_sorted = kin;
-  return GS_OK;
-}
+size_t sort_ws_size(int64_t n) { return onesweep_ws_size(n, 8); }
 
 static int32_t bits_for(uint64_t maxval) {
   int32_t b = 0;
@@ -481,6 +306,18 @@ static int32_t bits_for(uint64_t maxval) {
 }
 
 int32_t launch_fill(void* dst, uint32_t value, int64_t count, hipStream_t st);
+
+static int32_t launch_tile_order(const uint32_t* ranges, int32_t tiles, uint32_t* order, uint32_t* hist,
+                                 hipStream_t st) {
+  if (tiles <= 0) return GS_OK;
+  int32_t r = launch_fill(hist, 0u, kOrderBuckets, st);
+  if (r != GS_OK) return r;
+  hipLaunchKernelGGL(k_order_hist, dim3(grid_1d(tiles)), dim3(kBlock), 0, st, ranges, tiles, hist);
+  hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(64), 0, st, hist);
+  hipLaunchKernelGGL(k_order_scatter, dim3(grid_1d(tiles)), dim3(kBlock), 0, st, ranges, tiles, hist, order);
+  MS_CHECK_LAUNCH("tile_order");
+  return GS_OK;
+}
 
 }  // namespace msplat
 
@@ -532,7 +369,7 @@ size_t gs_sort_workspace_size(int64_t n) { return sort_ws_size(n); }
 
 size_t gs_bin_sort_workspace_size(int64_t n_isect) {
   const int64_t nn = n_isect > 0 ? n_isect : 1;
-  return align256(nn * 8) + align256(nn * 4) + sort_ws_size(n_isect);
+  return align256(nn * 8) + align256(nn * 4) + sort_ws_size(n_isect) + 256;  // + tile-order histogram
 }
 
 int32_t gs_emit_keys(const gs_projected_t* proj, const gs_camera_t* cams, int32_t V, int64_t n,
@@ -561,9 +398,8 @@ int32_t gs_sort_pairs(uint64_t* keys, uint32_t* vals, int64_t n, int32_t key_bit
   if (n >= (int64_t(1) << 32)) { set_error("n exceeds 32 bits"); return GS_ERR_CAPACITY; }
   if (ws_bytes < sort_ws_size(n)) { set_error("sort workspace too small"); return GS_ERR_CAPACITY; }
   hipStream_t s = (hipStream_t)stream;
-  SortWs sw = carve_sort(ws, n);
   uint64_t* ks = nullptr;
-  int32_t st = radix_sort(keys, vals, n, key_bits, sw, vals, &ks, s);
+  int32_t st = onesweep_sort(keys, vals, n, key_bits, ws, vals, &ks, s);
   if (st != GS_OK) return st;
   if (ks != keys) {
     hipLaunchKernelGGL(k_copy_u64, dim3(grid_1d(n)), dim3(kBlock), 0, s, ks, keys, n);
@@ -591,7 +427,7 @@ int32_t gs_tile_ranges(const uint64_t* keys, int64_t n, int32_t depth_shift, uin
 
 int32_t gs_bin_sort(const gs_projected_t* proj, const gs_camera_t* cams, int32_t V, int64_t n,
                     const uint32_t* offsets, const gs_bin_stats_t* stats, uint64_t* keys, uint32_t* vals,
-                    uint32_t* ranges, void* ws, size_t ws_bytes, void* stream) {
+                    uint32_t* ranges, uint32_t* tile_order, void* ws, size_t ws_bytes, void* stream) {
   if (!proj || !stats) { set_error("proj/stats NULL"); return GS_ERR_NULL; }
   ViewSet vs;
   int32_t st = build_views(cams, V, &vs);
@@ -600,25 +436,38 @@ int32_t gs_bin_sort(const gs_projected_t* proj, const gs_camera_t* cams, int32_t
   hipStream_t s = (hipStream_t)stream;
   const int64_t ni = stats->n_isect;
   if (!ranges) { set_error("ranges NULL"); return GS_ERR_NULL; }
-  if ((st = launch_fill(ranges, 0u, 2 * (int64_t)vs.tiles_total, s)) != GS_OK) return st;
-  if (ni == 0) return GS_OK;
-  if (!vals || !ws || !offsets) { set_error("buffer NULL"); return GS_ERR_NULL; }
+  if (!ws) { set_error("workspace NULL"); return GS_ERR_NULL; }
   if (ws_bytes < gs_bin_sort_workspace_size(ni)) { set_error("bin_sort workspace too small"); return GS_ERR_CAPACITY; }
+  if ((st = launch_fill(ranges, 0u, 2 * (int64_t)vs.tiles_total, s)) != GS_OK) return st;
+  uint32_t* order_hist = (uint32_t*)((char*)ws + gs_bin_sort_workspace_size(ni) - 256);
+  if (ni == 0) return tile_order ? launch_tile_order(ranges, vs.tiles_total, tile_order, order_hist, s) : GS_OK;
+  if (!vals || !offsets) { set_error("buffer NULL"); return GS_ERR_NULL; }
   char* p = (char*)ws;
   uint64_t* k0 = (uint64_t*)p; p += align256(ni * 8);
   uint32_t* v0 = (uint32_t*)p; p += align256(ni * 4);
-  SortWs sw = carve_sort(p, ni);
   const int32_t shift = stats->depth_bits;
   hipLaunchKernelGGL(k_emit, dim3(grid_1d((int64_t)V * n)), dim3(kBlock), 0, s,
                      reinterpret_cast<const int4*>(proj->bin), offsets, n, (int64_t)V * n, shift, stats->zbits_min,
                      k0, v0, vs);
   MS_CHECK_LAUNCH("emit");
   uint64_t* ks = nullptr;
-  if ((st = radix_sort(k0, v0, ni, stats->key_bits, sw, vals, &ks, s)) != GS_OK) return st;
+  if ((st = onesweep_sort(k0, v0, ni, stats->key_bits, p, vals, &ks, s)) != GS_OK) return st;
   hipLaunchKernelGGL(k_ranges, dim3(grid_1d(ni)), dim3(kBlock), 0, s, ks, ni, shift, stats->zbits_min,
                      (int64_t)vs.tiles_total, ranges, keys);
   MS_CHECK_LAUNCH("ranges");
+  if (tile_order) return launch_tile_order(ranges, vs.tiles_total, tile_order, order_hist, s);
   return GS_OK;
+}
+
+size_t gs_tile_order_workspace_size(void) { return 256; }
+
+int32_t gs_tile_order(const uint32_t* ranges, int32_t tiles_total, uint32_t* tile_order, void* ws, size_t ws_bytes,
+                      void* stream) {
+  if (tiles_total < 0) { set_error("tiles_total < 0"); return GS_ERR_SHAPE; }
+  if (tiles_total == 0) return GS_OK;
+  if (!ranges || !tile_order || !ws) { set_error("buffer NULL"); return GS_ERR_NULL; }
+  if (ws_bytes < gs_tile_order_workspace_size()) { set_error("workspace too small"); return GS_ERR_CAPACITY; }
+  return launch_tile_order(ranges, tiles_total, tile_order, (uint32_t*)ws, (hipStream_t)stream);
 }
 
 }  // extern "C"

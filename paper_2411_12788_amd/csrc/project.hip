@@ -20,60 +20,39 @@ struct SceneArgs {
 
 // Real orthonormal spherical harmonics (no Condon-Shortley phase), written as
 // homogeneous harmonic polynomials of the unit direction (x, y, z); index
-// k = l^2 + l + m, m = -l..l.
-template <int DEG>
-__device__ __forceinline__ void sh_eval(double x, double y, double z, double* Y) {
-  Y[0] = 0.28209479177387814;
+// k = l^2 + l + m, m = -l..l.  f(k, Y_k, dY_k/dx, dY_k/dy, dY_k/dz) is called
+// once per basis function, so callers never hold all 16 values (and their 48
+// derivatives) in registers at once; unused derivatives fold away.
+template <int DEG, typename F>
+__device__ __forceinline__ void sh_terms(double x, double y, double z, F&& f) {
+  f(0, 0.28209479177387814, 0.0, 0.0, 0.0);
   if (DEG >= 1) {
-    Y[1] = 0.4886025119029199 * y;
-    Y[2] = 0.4886025119029199 * z;
-    Y[3] = 0.4886025119029199 * x;
-  }
-  if (DEG >= 2) {
-    Y[4] = 1.0925484305920792 * x * y;
-    Y[5] = 1.0925484305920792 * y * z;
-    Y[6] = 0.31539156525252005 * (2.0 * z * z - x * x - y * y);
-    Y[7] = 1.0925484305920792 * x * z;
-    Y[8] = 0.5462742152960396 * (x * x - y * y);
-  }
-  if (DEG >= 3) {
-    Y[9] = 0.5900435899266435 * y * (3.0 * x * x - y * y);
-    Y[10] = 2.890611442640554 * x * y * z;
-    Y[11] = 0.4570457994644658 * y * (4.0 * z * z - x * x - y * y);
-    Y[12] = 0.3731763325901154 * z * (2.0 * z * z - 3.0 * x * x - 3.0 * y * y);
-    Y[13] = 0.4570457994644658 * x * (4.0 * z * z - x * x - y * y);
-    Y[14] = 1.445305721320277 * z * (x * x - y * y);
-    Y[15] = 0.5900435899266435 * x * (x * x - 3.0 * y * y);
-  }
-}
-
-// Gradient of each polynomial above w.r.t. (x, y, z); dY[k][3].
-template <int DEG>
-__device__ __forceinline__ void sh_grad(double x, double y, double z, double (*dY)[3]) {
-  for (int k = 0; k < 16; ++k) dY[k][0] = dY[k][1] = dY[k][2] = 0.0;
-  if (DEG >= 1) {
-    dY[1][1] = 0.4886025119029199;
-    dY[2][2] = 0.4886025119029199;
-    dY[3][0] = 0.4886025119029199;
+    const double c = 0.4886025119029199;
+    f(1, c * y, 0.0, c, 0.0);
+    f(2, c * z, 0.0, 0.0, c);
+    f(3, c * x, c, 0.0, 0.0);
   }
   if (DEG >= 2) {
     const double a = 1.0925484305920792, b = 0.31539156525252005, c = 0.5462742152960396;
-    dY[4][0] = a * y; dY[4][1] = a * x;
-    dY[5][1] = a * z; dY[5][2] = a * y;
-    dY[6][0] = -2.0 * b * x; dY[6][1] = -2.0 * b * y; dY[6][2] = 4.0 * b * z;
-    dY[7][0] = a * z; dY[7][2] = a * x;
-    dY[8][0] = 2.0 * c * x; dY[8][1] = -2.0 * c * y;
+    f(4, a * x * y, a * y, a * x, 0.0);
+    f(5, a * y * z, 0.0, a * z, a * y);
+    f(6, b * (2.0 * z * z - x * x - y * y), -2.0 * b * x, -2.0 * b * y, 4.0 * b * z);
+    f(7, a * x * z, a * z, 0.0, a * x);
+    f(8, c * (x * x - y * y), 2.0 * c * x, -2.0 * c * y, 0.0);
   }
   if (DEG >= 3) {
     const double a = 0.5900435899266435, b = 2.890611442640554, c = 0.4570457994644658;
     const double d = 0.3731763325901154, e = 1.445305721320277;
-    dY[9][0] = 6.0 * a * x * y; dY[9][1] = a * (3.0 * x * x - 3.0 * y * y);
-    dY[10][0] = b * y * z; dY[10][1] = b * x * z; dY[10][2] = b * x * y;
-    dY[11][0] = -2.0 * c * x * y; dY[11][1] = c * (4.0 * z * z - x * x - 3.0 * y * y); dY[11][2] = 8.0 * c * y * z;
-    dY[12][0] = -6.0 * d * x * z; dY[12][1] = -6.0 * d * y * z; dY[12][2] = d * (6.0 * z * z - 3.0 * x * x - 3.0 * y * y);
-    dY[13][0] = c * (4.0 * z * z - 3.0 * x * x - y * y); dY[13][1] = -2.0 * c * x * y; dY[13][2] = 8.0 * c * x * z;
-    dY[14][0] = 2.0 * e * x * z; dY[14][1] = -2.0 * e * y * z; dY[14][2] = e * (x * x - y * y);
-    dY[15][0] = a * (3.0 * x * x - 3.0 * y * y); dY[15][1] = -6.0 * a * x * y;
+    f(9, a * y * (3.0 * x * x - y * y), 6.0 * a * x * y, a * (3.0 * x * x - 3.0 * y * y), 0.0);
+    f(10, b * x * y * z, b * y * z, b * x * z, b * x * y);
+    f(11, c * y * (4.0 * z * z - x * x - y * y), -2.0 * c * x * y, c * (4.0 * z * z - x * x - 3.0 * y * y),
+      8.0 * c * y * z);
+    f(12, d * z * (2.0 * z * z - 3.0 * x * x - 3.0 * y * y), -6.0 * d * x * z, -6.0 * d * y * z,
+      d * (6.0 * z * z - 3.0 * x * x - 3.0 * y * y));
+    f(13, c * x * (4.0 * z * z - x * x - y * y), c * (4.0 * z * z - 3.0 * x * x - y * y), -2.0 * c * x * y,
+      8.0 * c * x * z);
+    f(14, e * z * (x * x - y * y), 2.0 * e * x * z, -2.0 * e * y * z, e * (x * x - y * y));
+    f(15, a * x * (x * x - 3.0 * y * y), a * (3.0 * x * x - 3.0 * y * y), -6.0 * a * x * y, 0.0);
   }
 }
 
@@ -178,17 +157,14 @@ __global__ __launch_bounds__(kBlock) void k_project(ProjArgs pa, ViewSet vs) {
   double dx = pa.sc.means[i] - cc[0], dy = pa.sc.means[n + i] - cc[1], dz = pa.sc.means[2 * n + i] - cc[2];
   const double il = 1.0 / sqrt(dx * dx + dy * dy + dz * dz);
   dx *= il; dy *= il; dz *= il;
-  double Y[16];
-  sh_eval<DEG>(dx, dy, dz, Y);
-  constexpr int K = (DEG + 1) * (DEG + 1);
-  double rgb[3];
+  double rgb[3] = {0.5, 0.5, 0.5};
+  const float* shp = pa.sc.sh;
+  sh_terms<DEG>(dx, dy, dz, [&](int k, double Yk, double, double, double) {
 #pragma unroll
-  for (int ch = 0; ch < 3; ++ch) {
-    double acc = 0.5;
+    for (int ch = 0; ch < 3; ++ch) rgb[ch] += (double)shp[(int64_t)(k * 3 + ch) * n + i] * Yk;
+  });
 #pragma unroll
-    for (int k = 0; k < K; ++k) acc += (double)pa.sc.sh[(int64_t)(k * 3 + ch) * n + i] * Y[k];
-    rgb[ch] = acc > 0.0 ? acc : 0.0;
-  }
+  for (int ch = 0; ch < 3; ++ch) rgb[ch] = rgb[ch] > 0.0 ? rgb[ch] : 0.0;
   // extent of the ellipse where opacity * G2D >= alpha_min
   const double kk = 2.0 * log(o / (double)op.alpha_min);
   const double ex = sqrt(kk * g.S00), ey = sqrt(kk * g.S11);
@@ -241,6 +217,85 @@ struct ProjBwdArgs {
   KOpts op;
 };
 
+// Geometry part of the chain rule for one view, accumulated into gm (means),
+// gs (scales), gq (raw quaternion).  Worked in the camera frame: with A = W R
+// diag(s) (camera-frame ellipsoid axes a_k s_k), Sigma_c = A A^T and
+// Sigma' = J Sigma_c J^T + lowpass, the gradient dL/dSigma_c = J^T G J is never
+// formed; only its products with the axes, h_k = J^T G (J a_k), are.
+__device__ __forceinline__ void geometry_backward(const KView& cam, const KOpts& op, const SceneArgs& sc, int64_t i,
+                                                  const float* gr, double* gm, double* gs, double* gq) {
+  Geo g;
+  geometry(cam, op, sc, i, g);
+  const double gu = gr[0], gv = gr[1], ga = gr[2], gb = gr[3], gc = gr[4];
+  // conic -> 2D covariance (per-entry gradient G of the symmetric matrix)
+  const double a = g.a, b = g.b, c = g.c;
+  const double g00 = -(a * a * ga + a * b * gb + b * b * gc);
+  const double g11 = -(b * b * ga + b * c * gb + c * c * gc);
+  const double g01 = -(a * b * ga + 0.5 * (a * c + b * b) * gb + b * c * gc);
+  double W[9];
+  for (int k = 0; k < 9; ++k) W[k] = cam.R[k];
+  // camera-frame unit axes u_k = W r_k (r_k = column k of R(q))
+  double ax[3][3];  // ax[k][row]
+  for (int k = 0; k < 3; ++k)
+    for (int r = 0; r < 3; ++r)
+      ax[k][r] = W[3 * r + 0] * g.Rq[0][k] + W[3 * r + 1] * g.Rq[1][k] + W[3 * r + 2] * g.Rq[2][k];
+  // J u_k (2-vectors) and G J u_k
+  double gJ00 = 0.0, gJ02 = 0.0, gJ11 = 0.0, gJ12 = 0.0;
+  double GR[3][3];  // dL/dR(q), row p, column k
+  for (int k = 0; k < 3; ++k) {
+    const double j0 = g.J00 * ax[k][0] + g.J02 * ax[k][2];
+    const double j1 = g.J11 * ax[k][1] + g.J12 * ax[k][2];
+    const double m0 = g00 * j0 + g01 * j1, m1 = g01 * j0 + g11 * j1;
+    // h = J^T m: the camera-frame gradient applied to u_k
+    const double h0 = g.J00 * m0, h1 = g.J11 * m1, h2 = g.J02 * m0 + g.J12 * m1;
+    const double sk = g.s[k], s2 = sk * sk;
+    // Sigma_c = sum_k s_k^2 u_k u_k^T:  dL/ds_k = 2 s_k u_k^T G_c u_k,  dL/du_k = 2 s_k^2 G_c u_k
+    gs[k] += 2.0 * sk * (ax[k][0] * h0 + ax[k][1] * h1 + ax[k][2] * h2);
+    for (int pr = 0; pr < 3; ++pr) GR[pr][k] = 2.0 * s2 * (W[0 + pr] * h0 + W[3 + pr] * h1 + W[6 + pr] * h2);
+    // dL/dJ = 2 G J Sigma_c, with J Sigma_c = sum_k s_k^2 (J u_k) u_k^T
+    gJ00 += 2.0 * s2 * m0 * ax[k][0];
+    gJ02 += 2.0 * s2 * m0 * ax[k][2];
+    gJ11 += 2.0 * s2 * m1 * ax[k][1];
+    gJ12 += 2.0 * s2 * m1 * ax[k][2];
+  }
+  const double tx = g.t[0], ty = g.t[1], tz = g.t[2];
+  const double fx = cam.fx, fy = cam.fy;
+  double gt0 = gu * fx / tz, gt1 = gv * fy / tz;
+  double gt2 = -(gu * fx * tx + gv * fy * ty) / (tz * tz);
+  gt2 += -(gJ00 * g.J00 + gJ11 * g.J11) / tz;
+  if (g.clx) {
+    gt2 += gJ02 * (fx * g.xr / (tz * tz));
+  } else {
+    gt0 += -gJ02 * fx / (tz * tz);
+    gt2 += gJ02 * 2.0 * fx * tx / (tz * tz * tz);
+  }
+  if (g.cly) {
+    gt2 += gJ12 * (fy * g.yr / (tz * tz));
+  } else {
+    gt1 += -gJ12 * fy / (tz * tz);
+    gt2 += gJ12 * 2.0 * fy * ty / (tz * tz * tz);
+  }
+  // t = W p + tau
+  gm[0] += W[0] * gt0 + W[3] * gt1 + W[6] * gt2;
+  gm[1] += W[1] * gt0 + W[4] * gt1 + W[7] * gt2;
+  gm[2] += W[2] * gt0 + W[5] * gt1 + W[8] * gt2;
+  // rotation -> normalised quaternion (w, x, y, z) -> raw quaternion
+  const double w = g.qh[0], x = g.qh[1], y = g.qh[2], z = g.qh[3];
+  const double dw = 2.0 * (z * (GR[1][0] - GR[0][1]) + y * (GR[0][2] - GR[2][0]) + x * (GR[2][1] - GR[1][2]));
+  const double dx = 2.0 * (y * (GR[0][1] + GR[1][0]) + z * (GR[0][2] + GR[2][0]) + w * (GR[2][1] - GR[1][2])) -
+                    4.0 * x * (GR[1][1] + GR[2][2]);
+  const double dy = 2.0 * (x * (GR[0][1] + GR[1][0]) + w * (GR[0][2] - GR[2][0]) + z * (GR[1][2] + GR[2][1])) -
+                    4.0 * y * (GR[0][0] + GR[2][2]);
+  const double dz = 2.0 * (w * (GR[1][0] - GR[0][1]) + x * (GR[0][2] + GR[2][0]) + y * (GR[1][2] + GR[2][1])) -
+                    4.0 * z * (GR[0][0] + GR[1][1]);
+  const double proj = dw * w + dx * x + dy * y + dz * z;
+  const double iq = 1.0 / g.qnorm;
+  gq[0] += (dw - w * proj) * iq;
+  gq[1] += (dx - x * proj) * iq;
+  gq[2] += (dy - y * proj) * iq;
+  gq[3] += (dz - z * proj) * iq;
+}
+
 template <int DEG>
 __global__ __launch_bounds__(kBlock) void k_project_bwd(ProjBwdArgs pa, ViewSet vs) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -248,148 +303,75 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd(ProjBwdArgs pa, ViewSet 
   if (i >= n) return;
   constexpr int K = (DEG + 1) * (DEG + 1);
   double gm[3] = {0, 0, 0}, gs[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, go = 0.0;
-  double gsh[K][3];
-#pragma unroll
-  for (int k = 0; k < K; ++k) gsh[k][0] = gsh[k][1] = gsh[k][2] = 0.0;
   const bool act = pa.active == nullptr || pa.active[i] != 0;
+  auto live = [&](int v) {
+    const int64_t r = (int64_t)v * n + i;
+    if (pa.bin[4 * r + 3] == 0) return false;
+    const float* gr = pa.g2d + r * kG2d;
+    bool nz = false;
+#pragma unroll
+    for (int k = 0; k < kG2d; ++k) nz = nz || gr[k] != 0.f;
+    return nz;
+  };
+  // pass 1: geometry (mean through u, v and J; covariance; opacity)
   if (act) {
     for (int v = 0; v < vs.count; ++v) {
-      const int64_t r = (int64_t)v * n + i;
-      if (pa.bin[4 * r + 3] == 0) continue;
-      const float* gr = pa.g2d + r * kG2d;
-      double gu = gr[0], gv = gr[1], ga = gr[2], gb = gr[3], gc = gr[4];
-      const double gop = gr[5], gR = gr[6], gG = gr[7], gB = gr[8];
-      if (gu == 0.0 && gv == 0.0 && ga == 0.0 && gb == 0.0 && gc == 0.0 && gop == 0.0 && gR == 0.0 && gG == 0.0 &&
-          gB == 0.0)
-        continue;
-      const KView& cam = vs.v[v];
-      Geo g;
-      geometry(cam, pa.op, pa.sc, i, g);
-      go += gop;
-      // conic -> 2D covariance: dK = -K dS K with the symmetric gradient
-      // [[ga, gb/2], [gb/2, gc]]; per-entry gradient of S below.
-      const double a = g.a, b = g.b, c = g.c;
-      const double g00 = -(a * a * ga + a * b * gb + b * b * gc);
-      const double g11 = -(b * b * ga + b * c * gb + c * c * gc);
-      const double g01 = -(a * b * ga + 0.5 * (a * c + b * b) * gb + b * c * gc);
-      // S = J Sc J^T: G_Sc = J^T G_S J with J columns j0 = (J00, 0), j1 = (0, J11), j2 = (J02, J12)
-      const double jc[3][2] = {{g.J00, 0.0}, {0.0, g.J11}, {g.J02, g.J12}};
-      double GSc[3][3];
-      for (int k = 0; k < 3; ++k)
-        for (int l = 0; l < 3; ++l) {
-          const double h0 = g00 * jc[l][0] + g01 * jc[l][1];
-          const double h1 = g01 * jc[l][0] + g11 * jc[l][1];
-          GSc[k][l] = jc[k][0] * h0 + jc[k][1] * h1;
-        }
-      // G_J = 2 G_S (J Sc), needed at (0,0), (0,2), (1,1), (1,2)
-      double JS[2][3];
-      for (int k = 0; k < 3; ++k) {
-        JS[0][k] = g.J00 * g.Sc[0][k] + g.J02 * g.Sc[2][k];
-        JS[1][k] = g.J11 * g.Sc[1][k] + g.J12 * g.Sc[2][k];
-      }
-      const double gJ00 = 2.0 * (g00 * JS[0][0] + g01 * JS[1][0]);
-      const double gJ02 = 2.0 * (g00 * JS[0][2] + g01 * JS[1][2]);
-      const double gJ11 = 2.0 * (g01 * JS[0][1] + g11 * JS[1][1]);
-      const double gJ12 = 2.0 * (g01 * JS[0][2] + g11 * JS[1][2]);
-      const double tx = g.t[0], ty = g.t[1], tz = g.t[2];
-      const double fx = cam.fx, fy = cam.fy;
-      double gt0 = gu * fx / tz, gt1 = gv * fy / tz;
-      double gt2 = -(gu * fx * tx + gv * fy * ty) / (tz * tz);
-      gt2 += -(gJ00 * g.J00 + gJ11 * g.J11) / tz;
-      if (g.clx) {
-        gt2 += gJ02 * (fx * g.xr / (tz * tz));
-      } else {
-        gt0 += -gJ02 * fx / (tz * tz);
-        gt2 += gJ02 * 2.0 * fx * tx / (tz * tz * tz);
-      }
-      if (g.cly) {
-        gt2 += gJ12 * (fy * g.yr / (tz * tz));
-      } else {
-        gt1 += -gJ12 * fy / (tz * tz);
-        gt2 += gJ12 * 2.0 * fy * ty / (tz * tz * tz);
-      }
-      // t = W p + tau
-      double W[9];
-      for (int k = 0; k < 9; ++k) W[k] = cam.R[k];
-      double gp0 = W[0] * gt0 + W[3] * gt1 + W[6] * gt2;
-      double gp1 = W[1] * gt0 + W[4] * gt1 + W[7] * gt2;
-      double gp2 = W[2] * gt0 + W[5] * gt1 + W[8] * gt2;
-      // Sc = W Sigma W^T: G_Sigma = W^T G_Sc W
-      double GS[3][3];
-      for (int p = 0; p < 3; ++p)
-        for (int q = 0; q < 3; ++q) {
-          double acc = 0.0;
-          for (int k = 0; k < 3; ++k)
-            for (int l = 0; l < 3; ++l) acc += W[3 * k + p] * GSc[k][l] * W[3 * l + q];
-          GS[p][q] = acc;
-        }
-      // Sigma = sum_k s_k^2 r_k r_k^T (r_k = column k of Rq)
-      double GR[3][3];
-      for (int k = 0; k < 3; ++k) {
-        double Gr[3];
-        for (int p = 0; p < 3; ++p) Gr[p] = GS[p][0] * g.Rq[0][k] + GS[p][1] * g.Rq[1][k] + GS[p][2] * g.Rq[2][k];
-        const double rGr = g.Rq[0][k] * Gr[0] + g.Rq[1][k] * Gr[1] + g.Rq[2][k] * Gr[2];
-        gs[k] += 2.0 * g.s[k] * rGr;
-        for (int p = 0; p < 3; ++p) GR[p][k] = 2.0 * g.s[k] * g.s[k] * Gr[p];
-      }
-      // rotation -> normalised quaternion (w, x, y, z)
-      const double w = g.qh[0], x = g.qh[1], y = g.qh[2], z = g.qh[3];
-      double dw = 2.0 * (z * (GR[1][0] - GR[0][1]) + y * (GR[0][2] - GR[2][0]) + x * (GR[2][1] - GR[1][2]));
-      double dx = 2.0 * (y * (GR[0][1] + GR[1][0]) + z * (GR[0][2] + GR[2][0]) + w * (GR[2][1] - GR[1][2])) -
-                  4.0 * x * (GR[1][1] + GR[2][2]);
-      double dy = 2.0 * (x * (GR[0][1] + GR[1][0]) + w * (GR[0][2] - GR[2][0]) + z * (GR[1][2] + GR[2][1])) -
-                  4.0 * y * (GR[0][0] + GR[2][2]);
-      double dz = 2.0 * (w * (GR[1][0] - GR[0][1]) + x * (GR[0][2] + GR[2][0]) + y * (GR[1][2] + GR[2][1])) -
-                  4.0 * z * (GR[0][0] + GR[1][1]);
-      const double proj = dw * w + dx * x + dy * y + dz * z;
-      const double iq = 1.0 / g.qnorm;
-      gq[0] += (dw - w * proj) * iq;
-      gq[1] += (dx - x * proj) * iq;
-      gq[2] += (dy - y * proj) * iq;
-      gq[3] += (dz - z * proj) * iq;
-      // colour: raw = 0.5 + sum_k sh_k Y_k(dir), clamped at 0 (no gradient when raw < 0)
-      double cc[3];
-      camera_centre(cam, cc);
-      double e0 = pa.sc.means[i] - cc[0], e1 = pa.sc.means[n + i] - cc[1], e2 = pa.sc.means[2 * n + i] - cc[2];
-      const double len = sqrt(e0 * e0 + e1 * e1 + e2 * e2);
-      const double il = 1.0 / len;
-      const double d0 = e0 * il, d1 = e1 * il, d2 = e2 * il;
-      double Y[16], dY[16][3];
-      sh_eval<DEG>(d0, d1, d2, Y);
-      sh_grad<DEG>(d0, d1, d2, dY);
-      const double grgb[3] = {gR, gG, gB};
-      double gd0 = 0.0, gd1 = 0.0, gd2 = 0.0;
-#pragma unroll
-      for (int ch = 0; ch < 3; ++ch) {
-        double raw = 0.5;
-        for (int k = 0; k < K; ++k) raw += (double)pa.sc.sh[(int64_t)(k * 3 + ch) * n + i] * Y[k];
-        if (raw < 0.0) continue;
-        const double gch = grgb[ch];
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-          gsh[k][ch] += gch * Y[k];
-          const double coef = pa.sc.sh[(int64_t)(k * 3 + ch) * n + i];
-          gd0 += gch * coef * dY[k][0];
-          gd1 += gch * coef * dY[k][1];
-          gd2 += gch * coef * dY[k][2];
-        }
-      }
-      const double dd = gd0 * d0 + gd1 * d1 + gd2 * d2;
-      gp0 += (gd0 - d0 * dd) * il;
-      gp1 += (gd1 - d1 * dd) * il;
-      gp2 += (gd2 - d2 * dd) * il;
-      gm[0] += gp0; gm[1] += gp1; gm[2] += gp2;
+      if (!live(v)) continue;
+      const float* gr = pa.g2d + ((int64_t)v * n + i) * kG2d;
+      go += gr[5];
+      geometry_backward(vs.v[v], pa.op, pa.sc, i, gr, gm, gs, gq);
     }
   }
-  pa.gmeans[i] = (float)gm[0]; pa.gmeans[n + i] = (float)gm[1]; pa.gmeans[2 * n + i] = (float)gm[2];
   pa.gscales[i] = (float)gs[0]; pa.gscales[n + i] = (float)gs[1]; pa.gscales[2 * n + i] = (float)gs[2];
   for (int k = 0; k < 4; ++k) pa.gquats[(int64_t)k * n + i] = (float)gq[k];
   pa.gopac[i] = (float)go;
+  // pass 2: colour (SH coefficients, and the mean through the viewing direction)
+  float gsh[K][3];
+#pragma unroll
+  for (int k = 0; k < K; ++k) gsh[k][0] = gsh[k][1] = gsh[k][2] = 0.f;
+  if (act) {
+    const float* shp = pa.sc.sh;
+    for (int v = 0; v < vs.count; ++v) {
+      if (!live(v)) continue;
+      const float* gr = pa.g2d + ((int64_t)v * n + i) * kG2d;
+      const KView& cam = vs.v[v];
+      double cc[3];
+      camera_centre(cam, cc);
+      const double e0 = pa.sc.means[i] - cc[0], e1 = pa.sc.means[n + i] - cc[1], e2 = pa.sc.means[2 * n + i] - cc[2];
+      const double il = 1.0 / sqrt(e0 * e0 + e1 * e1 + e2 * e2);
+      const double d0 = e0 * il, d1 = e1 * il, d2 = e2 * il;
+      // raw colour per channel decides the clamp at 0
+      double raw[3] = {0.5, 0.5, 0.5};
+      sh_terms<DEG>(d0, d1, d2, [&](int k, double Yk, double, double, double) {
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) raw[ch] += (double)shp[(int64_t)(k * 3 + ch) * n + i] * Yk;
+      });
+      const double gc0 = raw[0] < 0.0 ? 0.0 : gr[6], gc1 = raw[1] < 0.0 ? 0.0 : gr[7];
+      const double gc2 = raw[2] < 0.0 ? 0.0 : gr[8];
+      double gd0 = 0.0, gd1 = 0.0, gd2 = 0.0;
+      sh_terms<DEG>(d0, d1, d2, [&](int k, double Yk, double Gx, double Gy, double Gz) {
+        gsh[k][0] += (float)(gc0 * Yk);
+        gsh[k][1] += (float)(gc1 * Yk);
+        gsh[k][2] += (float)(gc2 * Yk);
+        const double vk = gc0 * shp[(int64_t)(k * 3 + 0) * n + i] + gc1 * shp[(int64_t)(k * 3 + 1) * n + i] +
+                          gc2 * shp[(int64_t)(k * 3 + 2) * n + i];
+        gd0 += vk * Gx;
+        gd1 += vk * Gy;
+        gd2 += vk * Gz;
+      });
+      // dir = e / |e|: project out the radial part
+      const double dd = gd0 * d0 + gd1 * d1 + gd2 * d2;
+      gm[0] += (gd0 - d0 * dd) * il;
+      gm[1] += (gd1 - d1 * dd) * il;
+      gm[2] += (gd2 - d2 * dd) * il;
+    }
+  }
+  pa.gmeans[i] = (float)gm[0]; pa.gmeans[n + i] = (float)gm[1]; pa.gmeans[2 * n + i] = (float)gm[2];
 #pragma unroll
   for (int k = 0; k < 16; ++k)
 #pragma unroll
     for (int ch = 0; ch < 3; ++ch)
-      pa.gsh[(int64_t)(k * 3 + ch) * n + i] = k < K ? (float)gsh[k < K ? k : 0][ch] : 0.f;
+      pa.gsh[(int64_t)(k * 3 + ch) * n + i] = k < K ? gsh[k < K ? k : 0][ch] : 0.f;
 }
 
 }  // namespace msplat

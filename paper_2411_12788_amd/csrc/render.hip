@@ -33,9 +33,23 @@ struct FwdOut {
 // Mid-point of the ray's intersections with the 1-sigma ellipsoid (Sec. 4.1),
 // in the ellipsoid's scaled frame: t* = -(o'.d') / (d'.d'); d has unit camera
 // z, so t* is a camera depth.  Double precision: it runs once per pixel.
-__device__ __noinline__ void mid_depth(const KView& cam, const float* __restrict__ means,
-                                       const float* __restrict__ scales, const float* __restrict__ quats, int64_t n,
-                                       int64_t g, float pxc, float pyc, float* depth, uint8_t* hit) {
+// The camera travels by value: handing a reference into the kernel-argument
+// view table to a call would make the compiler copy the whole table to
+// per-thread scratch.
+struct RayCam {
+  float R[9];
+  float t[3];
+  float fx, fy, cx, cy;
+};
+
+struct MidDepth {
+  float depth;
+  uint32_t hit;
+};
+
+__device__ __noinline__ MidDepth mid_depth(const RayCam cam, const float* __restrict__ means,
+                                           const float* __restrict__ scales, const float* __restrict__ quats,
+                                           int64_t n, int64_t g, float pxc, float pyc) {
   double R[9];
   for (int k = 0; k < 9; ++k) R[k] = cam.R[k];
   const double c0 = -(R[0] * cam.t[0] + R[3] * cam.t[1] + R[6] * cam.t[2]);
@@ -61,8 +75,10 @@ __device__ __noinline__ void mid_depth(const KView& cam, const float* __restrict
     dd += dk * dk;
     oo += ok * ok;
   }
-  *depth = (float)(-od / dd);
-  *hit = (od * od - dd * (oo - 1.0)) >= 0.0 ? 1 : 0;
+  MidDepth r;
+  r.depth = (float)(-od / dd);
+  r.hit = (od * od - dd * (oo - 1.0)) >= 0.0 ? 1u : 0u;
+  return r;
 }
 
 // Wave-wide sum / max of one float, result uniform (read from lane 63).
@@ -91,6 +107,15 @@ __device__ __forceinline__ bool box_meets(int2 b, int32_t sx0, int32_t sy0) {
 
 constexpr int kBatch = kBlock;  // list entries staged per workgroup round
 
+// Work per tile spans four orders of magnitude and a wave's list is walked in
+// order, so the longest lists set the kernel's length.  Waves of long lists
+// get a higher issue priority than the waves sharing their SIMD.
+__device__ __forceinline__ void set_wave_priority(uint32_t list_len) {
+  if (list_len >= 2048) __builtin_amdgcn_s_setprio(3);
+  else if (list_len >= 1024) __builtin_amdgcn_s_setprio(2);
+  else if (list_len >= 512) __builtin_amdgcn_s_setprio(1);
+}
+
 // Forward.  Per round the workgroup gathers up to 256 consecutive list entries
 // (index, pixel box, 48-byte record) into LDS with one load per thread, so the
 // latency of the random record gathers is paid once per 256 entries.  Each wave
@@ -99,7 +124,8 @@ constexpr int kBatch = kBlock;  // list entries staged per workgroup round
 template <bool ACC, bool OUT, int DEPTH>
 __global__ __launch_bounds__(kBlock) void k_render_fwd(const float* __restrict__ rec, const int32_t* __restrict__ bin,
                                                        const uint32_t* __restrict__ vals,
-                                                       const uint32_t* __restrict__ ranges, int64_t n,
+                                                       const uint32_t* __restrict__ ranges,
+                                                       const uint32_t* __restrict__ order, int64_t n,
                                                        const float* __restrict__ means,
                                                        const float* __restrict__ scales,
                                                        const float* __restrict__ quats, FwdOut o, KOpts op,
@@ -108,7 +134,11 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(const float* __restrict__
   __shared__ int2 s_box[kBatch];
   __shared__ uint32_t s_idx[kBatch];
   __shared__ float s_z[DEPTH == GS_DEPTH_BLEND ? kBatch : 1];
-  const int32_t tile = xcd_remap((int32_t)blockIdx.x, (int32_t)gridDim.x);
+  // per staged entry: importance and max weight gathered from the whole
+  // workgroup with LDS atomics, flushed with one global atomic per entry
+  __shared__ float s_acc_w[ACC ? kBatch : 1];
+  __shared__ uint32_t s_acc_m[ACC ? kBatch : 1];
+  const int32_t tile = order ? (int32_t)uload(order + blockIdx.x) : (int32_t)blockIdx.x;
   const int32_t v = view_of_tile(vs, tile);
   const KView& cam = vs.v[v];
   const int32_t lt = tile - cam.tile_base;
@@ -120,6 +150,8 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(const float* __restrict__
   const float pxc = (float)px + 0.5f, pyc = (float)py + 0.5f;
   const uint32_t start = uload(ranges + 2 * tile), end = uload(ranges + 2 * tile + 1);
   const int64_t vbase = (int64_t)v * n;
+  const int64_t nrec = (int64_t)vs.count * n;
+  set_wave_priority(end - start);
   float T = 1.f, c0 = 0.f, c1 = 0.f, c2 = 0.f, wbest = 0.f, dblend = 0.f;
   int32_t best = -1;
   uint32_t lastpos = 0, cnt = 0;
@@ -128,14 +160,20 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(const float* __restrict__
     if (__syncthreads_and(done)) break;  // also orders this round's LDS writes after the last round's reads
     const uint32_t j = base + threadIdx.x;
     if (j < end) {
-      const uint32_t r = vals[j];
+      uint32_t r = vals[j];
+      const bool valid = (int64_t)r < nrec;  // a corrupt list entry is dropped, never dereferenced
+      r = valid ? r : 0u;
       s_idx[threadIdx.x] = r;
-      s_box[threadIdx.x] = *reinterpret_cast<const int2*>(bin + 4 * (int64_t)r);
+      s_box[threadIdx.x] = valid ? *reinterpret_cast<const int2*>(bin + 4 * (int64_t)r) : make_int2(0xffff, 0xffff);
       const float4* R4 = reinterpret_cast<const float4*>(rec + (int64_t)r * kRecFloats);
       s_r0[threadIdx.x] = R4[0];
       s_r1[threadIdx.x] = R4[1];
       s_r2[threadIdx.x] = R4[2];
       if (DEPTH == GS_DEPTH_BLEND) s_z[threadIdx.x] = rec[(int64_t)r * kRecFloats + 12];
+    }
+    if (ACC) {
+      s_acc_w[threadIdx.x] = 0.f;
+      s_acc_m[threadIdx.x] = 0u;
     }
     __syncthreads();
     const uint32_t count = (end - base) < (uint32_t)kBatch ? (end - base) : (uint32_t)kBatch;
@@ -173,20 +211,23 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(const float* __restrict__
             }
           }
         }
-        if (ACC && __any(inc)) {
-          const float ws = wave_reduce_dpp<false>(wgt);
-          const float wm = wave_reduce_dpp<true>(wgt);
-          if (lane == 0) {
-            const uint32_t r = s_idx[kk];
-            const int64_t ai = per_view ? (int64_t)r : (int64_t)r - vbase;
-            if (o.imp) atomicAdd(o.imp + ai, ws);
-            if (o.wmax) atomicMax(reinterpret_cast<unsigned int*>(o.wmax) + ai, __float_as_uint(wm));
-          }
+        if (ACC && inc) {
+          atomicAdd(&s_acc_w[kk], wgt);
+          atomicMax(&s_acc_m[kk], __float_as_uint(wgt));  // weights are >= 0: bit order is value order
         }
         if (__all(done)) {
           wave_done = true;
           break;
         }
+      }
+    }
+    if (ACC) {
+      __syncthreads();
+      if ((uint32_t)threadIdx.x < count && s_acc_m[threadIdx.x] != 0u) {
+        const uint32_t r = s_idx[threadIdx.x];
+        const int64_t ai = per_view ? (int64_t)r : (int64_t)r - vbase;
+        if (o.imp) atomicAdd(o.imp + ai, s_acc_w[threadIdx.x]);
+        if (o.wmax) atomicMax(reinterpret_cast<unsigned int*>(o.wmax) + ai, s_acc_m[threadIdx.x]);
       }
     }
   }
@@ -205,8 +246,13 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(const float* __restrict__
   float dep = 0.f;
   uint8_t h = 0;
   if (best >= 0 && (o.depth || o.hit)) {
-    float dm;
-    mid_depth(cam, means, scales, quats, n, best, pxc, pyc, &dm, &h);
+    RayCam rc;
+    for (int k = 0; k < 9; ++k) rc.R[k] = cam.R[k];
+    for (int k = 0; k < 3; ++k) rc.t[k] = cam.t[k];
+    rc.fx = cam.fx; rc.fy = cam.fy; rc.cx = cam.cx; rc.cy = cam.cy;
+    const MidDepth md = mid_depth(rc, means, scales, quats, n, best, pxc, pyc);
+    const float dm = md.depth;
+    h = (uint8_t)md.hit;
     if (DEPTH == GS_DEPTH_MID) dep = dm;
     else if (DEPTH == GS_DEPTH_CENTER) dep = rec[(vbase + best) * kRecFloats + 12];
     else dep = dblend;
@@ -228,7 +274,8 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(const float* __restrict__
 template <bool MASKED>
 __global__ __launch_bounds__(kBlock) void k_render_bwd(const float* __restrict__ rec, const int32_t* __restrict__ bin,
                                                        const uint32_t* __restrict__ vals,
-                                                       const uint32_t* __restrict__ ranges, int64_t n,
+                                                       const uint32_t* __restrict__ ranges,
+                                                       const uint32_t* __restrict__ order, int64_t n,
                                                        const float* __restrict__ t_final,
                                                        const uint32_t* __restrict__ last,
                                                        const float* __restrict__ dldc,
@@ -238,7 +285,7 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(const float* __restrict__
   __shared__ int2 s_box[kBatch];
   __shared__ uint32_t s_idx[kBatch];  // record index | active << 31
   __shared__ uint32_t s_jmax[kBlock / kWave];
-  const int32_t tile = xcd_remap((int32_t)blockIdx.x, (int32_t)gridDim.x);
+  const int32_t tile = order ? (int32_t)uload(order + blockIdx.x) : (int32_t)blockIdx.x;
   const int32_t v = view_of_tile(vs, tile);
   const KView& cam = vs.v[v];
   const int32_t lt = tile - cam.tile_base;
@@ -250,6 +297,8 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(const float* __restrict__
   const float pxc = (float)px + 0.5f, pyc = (float)py + 0.5f;
   const uint32_t start = uload(ranges + 2 * tile), end = uload(ranges + 2 * tile + 1);
   const int64_t vbase = (int64_t)v * n;
+  const int64_t nrec = (int64_t)vs.count * n;
+  set_wave_priority(end - start);
   const int64_t P = vs.pixels_total;
   const int64_t gp = cam.pixel_base + (int64_t)py * cam.width + px;
   float T = 1.f, g0 = 0.f, g1 = 0.f, g2 = 0.f;
@@ -274,10 +323,12 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(const float* __restrict__
     const uint32_t count = top - base;
     __syncthreads();  // the previous round's entries are consumed
     if ((uint32_t)threadIdx.x < count) {
-      const uint32_t r = vals[base + threadIdx.x];
-      const uint32_t act = (!MASKED || active[(int64_t)r - vbase] != 0) ? 1u : 0u;
+      uint32_t r = vals[base + threadIdx.x];
+      const bool valid = (int64_t)r < nrec && (int64_t)r >= vbase;  // a corrupt entry is dropped
+      r = valid ? r : (uint32_t)vbase;
+      const uint32_t act = (valid && (!MASKED || active[(int64_t)r - vbase] != 0)) ? 1u : 0u;
       s_idx[threadIdx.x] = r | (act << 31);
-      s_box[threadIdx.x] = *reinterpret_cast<const int2*>(bin + 4 * (int64_t)r);
+      s_box[threadIdx.x] = valid ? *reinterpret_cast<const int2*>(bin + 4 * (int64_t)r) : make_int2(0xffff, 0xffff);
       const float4* R4 = reinterpret_cast<const float4*>(rec + (int64_t)r * kRecFloats);
       s_r0[threadIdx.x] = R4[0];
       s_r1[threadIdx.x] = R4[1];
@@ -364,20 +415,20 @@ __global__ void k_zero_f32(float* __restrict__ p, int64_t count) {
 
 template <bool ACC, bool OUT>
 static void launch_fwd(int depth_mode, dim3 grid, hipStream_t s, const gs_projected_t* proj, const uint32_t* vals,
-                       const uint32_t* ranges, int64_t n, const gs_scene_t* scene, const FwdOut& o, const KOpts& op,
+                       const uint32_t* ranges, const uint32_t* order, int64_t n, const gs_scene_t* scene, const FwdOut& o, const KOpts& op,
                        int32_t per_view, const ViewSet& vs) {
   const float* m = scene ? scene->means : nullptr;
   const float* sc = scene ? scene->scales : nullptr;
   const float* q = scene ? scene->quats : nullptr;
   if (depth_mode == GS_DEPTH_CENTER)
     hipLaunchKernelGGL((k_render_fwd<ACC, OUT, GS_DEPTH_CENTER>), grid, dim3(kBlock), 0, s, proj->rec, proj->bin, vals,
-                       ranges, n, m, sc, q, o, op, per_view, vs);
+                       ranges, order, n, m, sc, q, o, op, per_view, vs);
   else if (depth_mode == GS_DEPTH_BLEND)
     hipLaunchKernelGGL((k_render_fwd<ACC, OUT, GS_DEPTH_BLEND>), grid, dim3(kBlock), 0, s, proj->rec, proj->bin, vals,
-                       ranges, n, m, sc, q, o, op, per_view, vs);
+                       ranges, order, n, m, sc, q, o, op, per_view, vs);
   else
     hipLaunchKernelGGL((k_render_fwd<ACC, OUT, GS_DEPTH_MID>), grid, dim3(kBlock), 0, s, proj->rec, proj->bin, vals,
-                       ranges, n, m, sc, q, o, op, per_view, vs);
+                       ranges, order, n, m, sc, q, o, op, per_view, vs);
 }
 
 }  // namespace msplat
@@ -387,8 +438,8 @@ using namespace msplat;
 extern "C" {
 
 int32_t gs_render_forward(const gs_scene_t* scene, const gs_projected_t* proj, const uint32_t* vals,
-                          const uint32_t* ranges, const gs_camera_t* cams, int32_t V, const gs_opts_t* opts,
-                          const gs_fwd_out_t* out, const gs_accum_t* acc, void* stream) {
+                          const uint32_t* ranges, const uint32_t* tile_order, const gs_camera_t* cams, int32_t V,
+                          const gs_opts_t* opts, const gs_fwd_out_t* out, const gs_accum_t* acc, void* stream) {
   int32_t st = check_scene(scene);
   if (st != GS_OK) return st;
   if (!proj || !opts || !out || !ranges) { set_error("proj/opts/out/ranges NULL"); return GS_ERR_NULL; }
@@ -407,16 +458,18 @@ int32_t gs_render_forward(const gs_scene_t* scene, const gs_projected_t* proj, c
   dim3 grid(vs.tiles_total);
   hipStream_t s = (hipStream_t)stream;
   if (accum)
-    launch_fwd<true, true>(opts->depth_mode, grid, s, proj, vals, ranges, scene->n, scene, o, op, per_view, vs);
+    launch_fwd<true, true>(opts->depth_mode, grid, s, proj, vals, ranges, tile_order, scene->n, scene, o, op, per_view,
+                           vs);
   else
-    launch_fwd<false, true>(opts->depth_mode, grid, s, proj, vals, ranges, scene->n, scene, o, op, per_view, vs);
+    launch_fwd<false, true>(opts->depth_mode, grid, s, proj, vals, ranges, tile_order, scene->n, scene, o, op,
+                            per_view, vs);
   MS_CHECK_LAUNCH("render_forward");
   return GS_OK;
 }
 
 int32_t gs_accumulate_importance(const gs_projected_t* proj, const uint32_t* vals, const uint32_t* ranges,
-                                 const gs_camera_t* cams, int32_t V, int64_t n, const gs_opts_t* opts,
-                                 const gs_accum_t* acc, void* stream) {
+                                 const uint32_t* tile_order, const gs_camera_t* cams, int32_t V, int64_t n,
+                                 const gs_opts_t* opts, const gs_accum_t* acc, void* stream) {
   if (!proj || !opts || !acc || !ranges) { set_error("proj/opts/acc/ranges NULL"); return GS_ERR_NULL; }
   if (n < 0) { set_error("n < 0"); return GS_ERR_SHAPE; }
   ViewSet vs;
@@ -431,16 +484,16 @@ int32_t gs_accumulate_importance(const gs_projected_t* proj, const uint32_t* val
   const KOpts op = make_kopts(opts);
   const int32_t per_view = (opts->flags & GS_ACCUM_PER_VIEW) ? 1 : 0;
   hipLaunchKernelGGL((k_render_fwd<true, false, GS_DEPTH_CENTER>), dim3(vs.tiles_total), dim3(kBlock), 0,
-                     (hipStream_t)stream, proj->rec, proj->bin, vals, ranges, n, nullptr, nullptr, nullptr, o, op,
-                     per_view, vs);
+                     (hipStream_t)stream, proj->rec, proj->bin, vals, ranges, tile_order, n, nullptr, nullptr, nullptr,
+                     o, op, per_view, vs);
   MS_CHECK_LAUNCH("accumulate_importance");
   return GS_OK;
 }
 
 int32_t gs_render_backward_pixels(const gs_projected_t* proj, const uint32_t* vals, const uint32_t* ranges,
-                                  const gs_camera_t* cams, int32_t V, int64_t n, const gs_opts_t* opts,
-                                  const float* t_final, const uint32_t* last, const float* dl_dcolor,
-                                  const uint8_t* active, float* grad2d, void* stream) {
+                                  const uint32_t* tile_order, const gs_camera_t* cams, int32_t V, int64_t n,
+                                  const gs_opts_t* opts, const float* t_final, const uint32_t* last,
+                                  const float* dl_dcolor, const uint8_t* active, float* grad2d, void* stream) {
   if (!proj || !opts || !ranges || !t_final || !last || !dl_dcolor) { set_error("argument NULL"); return GS_ERR_NULL; }
   if (n < 0) { set_error("n < 0"); return GS_ERR_SHAPE; }
   ViewSet vs;
@@ -453,18 +506,19 @@ int32_t gs_render_backward_pixels(const gs_projected_t* proj, const uint32_t* va
   hipStream_t s = (hipStream_t)stream;
   if (active)
     hipLaunchKernelGGL(k_render_bwd<true>, dim3(vs.tiles_total), dim3(kBlock), 0, s, proj->rec, proj->bin, vals,
-                       ranges, n, t_final, last, dl_dcolor, active, grad2d, op, vs);
+                       ranges, tile_order, n, t_final, last, dl_dcolor, active, grad2d, op, vs);
   else
     hipLaunchKernelGGL(k_render_bwd<false>, dim3(vs.tiles_total), dim3(kBlock), 0, s, proj->rec, proj->bin, vals,
-                       ranges, n, t_final, last, dl_dcolor, active, grad2d, op, vs);
+                       ranges, tile_order, n, t_final, last, dl_dcolor, active, grad2d, op, vs);
   MS_CHECK_LAUNCH("render_backward_pixels");
   return GS_OK;
 }
 
 int32_t gs_render_backward(const gs_scene_t* scene, const gs_projected_t* proj, const uint32_t* vals,
-                           const uint32_t* ranges, const gs_camera_t* cams, int32_t V, const gs_opts_t* opts,
-                           const float* t_final, const uint32_t* last, const float* dl_dcolor, const uint8_t* active,
-                           float* grad2d, const gs_grads_t* grads, void* stream) {
+                           const uint32_t* ranges, const uint32_t* tile_order, const gs_camera_t* cams, int32_t V,
+                           const gs_opts_t* opts, const float* t_final, const uint32_t* last,
+                           const float* dl_dcolor, const uint8_t* active, float* grad2d, const gs_grads_t* grads,
+                           void* stream) {
   int32_t st = check_scene(scene);
   if (st != GS_OK) return st;
   if (scene->n > 0) {
@@ -477,8 +531,8 @@ int32_t gs_render_backward(const gs_scene_t* scene, const gs_projected_t* proj, 
       MS_CHECK_LAUNCH("zero grad2d");
     }
   }
-  st = gs_render_backward_pixels(proj, vals, ranges, cams, V, scene->n, opts, t_final, last, dl_dcolor, active, grad2d,
-                                 stream);
+  st = gs_render_backward_pixels(proj, vals, ranges, tile_order, cams, V, scene->n, opts, t_final, last, dl_dcolor,
+                                 active, grad2d, stream);
   if (st != GS_OK) return st;
   return gs_project_backward(scene, proj, cams, V, opts, grad2d, active, grads, stream);
 }

@@ -1,0 +1,280 @@
+// Stable LSD radix sort of (u64 key, u32 value) pairs on the low `bits` key
+// bits: one histogram pass over the keys for all digits, then one kernel per
+// 8-bit digit ("onesweep").  Each workgroup ranks a 4096-key tile in
+// registers/LDS, publishes its per-digit counts, and obtains the count of
+// equal digits in all earlier tiles by a decoupled look-back over the
+// per-tile status words; tiles are handed out by an atomic counter, so every
+// tile a workgroup looks back at belongs to a workgroup that has already
+// started and will publish without waiting on anyone.  Keys are then staged in
+// LDS in local sorted order and written out in runs, so each digit's run is a
+// contiguous, coalesced store.  Per pass this reads 12 B and writes 12 B per
+// pair; the histograms of all passes cost one extra 8 B read per pair in total.
+//
+// Every wait is bounded: a look-back that has not resolved after kSpinLimit
+// polls raises an error flag instead of spinning on, and every global store is
+// bounds-checked, so a broken invariant yields a detectable error, not a hang
+// or a stray write.
+#include "common.hpp"
+
+namespace msplat {
+
+constexpr int kOsItems = 16;
+constexpr int kOsTile = kBlock * kOsItems;  // 4096 keys per tile
+constexpr int kOsRadix = 256;
+constexpr int kOsWaves = kBlock / kWave;
+constexpr int kMaxPasses = 8;
+constexpr uint32_t kFlagAgg = 1u << 30, kFlagInc = 2u << 30, kValMask = (1u << 30) - 1u;
+constexpr uint32_t kSpinLimit = 1u << 22;
+constexpr int kLook = 8;
+
+__device__ __forceinline__ uint64_t os_match(uint32_t d) {
+  uint64_t m = ~0ull;
+#pragma unroll
+  for (int b = 0; b < 8; ++b) {
+    const uint64_t bb = __ballot((d >> b) & 1u);
+    m &= ((d >> b) & 1u) ? bb : ~bb;
+  }
+  return m;
+}
+
+// Counts of every digit of every pass; 4 tiles per workgroup.
+__global__ __launch_bounds__(kBlock) void k_os_hist(const uint64_t* __restrict__ keys, int64_t n, int32_t passes,
+                                                    uint32_t* __restrict__ ghist) {
+  __shared__ uint32_t h[kMaxPasses][kOsRadix];
+  for (int p = 0; p < passes; ++p) h[p][threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * (4 * kOsTile);
+  for (int k = 0; k < 4 * kOsItems; ++k) {
+    const int64_t e = base + (int64_t)k * kBlock + threadIdx.x;
+    if (e < n) {
+      const uint64_t key = keys[e];
+      for (int p = 0; p < passes; ++p) atomicAdd(&h[p][(uint32_t)(key >> (8 * p)) & 0xffu], 1u);
+    }
+  }
+  __syncthreads();
+  for (int p = 0; p < passes; ++p) {
+    const uint32_t c = h[p][threadIdx.x];
+    if (c) atomicAdd(ghist + p * kOsRadix + threadIdx.x, c);
+  }
+}
+
+// Exclusive scan of each pass's 256 counts (one workgroup).
+__global__ __launch_bounds__(kBlock) void k_os_scan(uint32_t* __restrict__ ghist, int32_t passes) {
+  __shared__ uint32_t s[kOsRadix];
+  for (int p = 0; p < passes; ++p) {
+    s[threadIdx.x] = ghist[p * kOsRadix + threadIdx.x];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint32_t run = 0;
+      for (int d = 0; d < kOsRadix; ++d) {
+        const uint32_t c = s[d];
+        s[d] = run;
+        run += c;
+      }
+    }
+    __syncthreads();
+    ghist[p * kOsRadix + threadIdx.x] = s[threadIdx.x];
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_os_pass(const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin,
+                                                    uint64_t* __restrict__ kout, uint32_t* __restrict__ vout,
+                                                    int64_t n, int32_t shift, const uint32_t* __restrict__ digit_base,
+                                                    uint32_t* status, uint32_t* counter, uint32_t* err) {
+  __shared__ uint32_t s_tile;
+  __shared__ uint32_t cnt[kOsWaves][kOsRadix];
+  __shared__ uint32_t s_glob[kOsRadix];
+  __shared__ uint32_t s_loff[kOsRadix + 1];
+  __shared__ uint32_t s_wsum[kOsWaves];
+  __shared__ uint64_t s_key[kOsTile];
+  __shared__ uint32_t s_val[kOsTile];
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+  if (threadIdx.x == 0) s_tile = atomicAdd(counter, 1u);
+#pragma unroll
+  for (int k = 0; k < kOsWaves; ++k) cnt[k][threadIdx.x] = 0;
+  __syncthreads();
+  const uint32_t t = s_tile;
+  const int64_t tile_base = (int64_t)t * kOsTile;
+  const int64_t base = tile_base + (int64_t)w * (kOsItems * kWave);
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
+  uint64_t key[kOsItems];
+  uint32_t val[kOsItems];
+  uint32_t rank[kOsItems];
+#pragma unroll
+  for (int k = 0; k < kOsItems; ++k) {
+    const int64_t e = base + (int64_t)k * kWave + lane;
+    const bool in = e < n;
+    key[k] = in ? kin[e] : 0ull;
+    val[k] = in ? vin[e] : 0u;
+    const uint32_t d = (uint32_t)(key[k] >> shift) & 0xffu;
+    uint64_t m = os_match(d);
+    const uint64_t inm = __ballot(in);
+    m &= in ? inm : ~inm;
+    const uint32_t before = __popcll(m & lt);
+    const uint32_t prev = cnt[w][d];
+    rank[k] = prev + before;
+    if (in && before == 0) cnt[w][d] = prev + (uint32_t)__popcll(m);
+  }
+  __syncthreads();
+  // per digit: prefix over waves, tile total, publication and look-back
+  const uint32_t d = threadIdx.x;
+  uint32_t h = 0;
+#pragma unroll
+  for (int k = 0; k < kOsWaves; ++k) {
+    const uint32_t c = cnt[k][d];
+    cnt[k][d] = h;
+    h += c;
+  }
+  uint32_t* st = status + (int64_t)t * kOsRadix + d;
+  uint32_t excl = 0;
+  if (t == 0) {
+    __hip_atomic_store(st, kFlagInc | h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  } else {
+    __hip_atomic_store(st, kFlagAgg | h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // look back over a window of kLook predecessors per step: the loads are
+    // independent, so their latencies overlap instead of adding up
+    int64_t k = (int64_t)t - 1;
+    uint32_t spins = 0;
+    bool resolved = false;
+    while (!resolved) {
+      uint32_t win[kLook];
+#pragma unroll
+      for (int i = 0; i < kLook; ++i)
+        win[i] = (k - i >= 0) ? __hip_atomic_load(status + (k - i) * kOsRadix + d, __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT)
+                            : kFlagInc;  // before tile 0: an inclusive zero
+      uint32_t part = 0;
+      bool ready = true;
+#pragma unroll
+      for (int i = 0; i < kLook; ++i) {
+        if (resolved || !ready) continue;
+        const uint32_t flag = win[i] & ~kValMask;
+        if (flag == 0) {
+          ready = false;
+        } else {
+          part += win[i] & kValMask;
+          resolved = flag == kFlagInc;
+        }
+      }
+      if (!ready) {
+        resolved = false;
+        if (++spins > kSpinLimit) {
+          atomicOr(err, 1u);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+        continue;
+      }
+      excl += part;
+      k -= kLook;
+    }
+    __hip_atomic_store(st, kFlagInc | ((excl + h) & kValMask), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  s_glob[d] = digit_base[d] + excl;
+  // local offsets: exclusive scan of the tile's digit totals (thread = digit)
+  {
+    uint32_t inc = h;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+      const uint32_t y = __shfl_up(inc, o, kWave);
+      if (lane >= o) inc += y;
+    }
+    if (lane == kWave - 1) s_wsum[w] = inc;
+    __syncthreads();
+    uint32_t wpre = 0;
+#pragma unroll
+    for (int q = 0; q < kOsWaves; ++q) wpre += q < w ? s_wsum[q] : 0u;
+    s_loff[d] = wpre + inc - h;
+    if (d == kOsRadix - 1) s_loff[kOsRadix] = wpre + inc;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kOsItems; ++k) {
+    const int64_t e = base + (int64_t)k * kWave + lane;
+    if (e < n) {
+      const uint32_t dd = (uint32_t)(key[k] >> shift) & 0xffu;
+      const uint32_t lp = s_loff[dd] + cnt[w][dd] + rank[k];
+      if (lp < (uint32_t)kOsTile) {
+        s_key[lp] = key[k];
+        s_val[lp] = val[k];
+      }
+    }
+  }
+  __syncthreads();
+  const uint32_t total = s_loff[kOsRadix];
+  for (uint32_t i = threadIdx.x; i < total; i += kBlock) {
+    const uint64_t kk = s_key[i];
+    const uint32_t dd = (uint32_t)(kk >> shift) & 0xffu;
+    const uint64_t dst = (uint64_t)s_glob[dd] + (i - s_loff[dd]);
+    if (dst < (uint64_t)n) {
+      kout[dst] = kk;
+      vout[dst] = s_val[i];
+    }
+  }
+}
+
+size_t onesweep_ws_size(int64_t n, int32_t passes) {
+  const int64_t nn = n > 0 ? n : 1;
+  const int64_t nb = (nn + kOsTile - 1) / kOsTile;
+  auto a = [](size_t x) { return (x + 255) & ~size_t(255); };
+  return a(nn * 8) + a(nn * 4) + a(kMaxPasses * kOsRadix * 4) + a((size_t)kMaxPasses * nb * kOsRadix * 4) +
+         a(kMaxPasses * 4) + a(4);
+}
+
+int32_t launch_fill(void* dst, uint32_t value, int64_t count, hipStream_t st);
+
+// Sorts (k0, v0); the last pass writes values to vfinal and keys to the
+// buffer returned in *keys_sorted (k0 or the workspace copy).
+int32_t onesweep_sort(uint64_t* k0, uint32_t* v0, int64_t n, int32_t bits, void* ws, uint32_t* vfinal,
+                      uint64_t** keys_sorted, hipStream_t st) {
+  const int passes = (bits + 7) / 8;
+  *keys_sorted = k0;
+  if (passes > kMaxPasses) { set_error("too many key bits"); return GS_ERR_SHAPE; }
+  const int64_t nn = n > 0 ? n : 1;
+  const int64_t nb = (nn + kOsTile - 1) / kOsTile;
+  auto a = [](size_t x) { return (x + 255) & ~size_t(255); };
+  char* p = (char*)ws;
+  uint64_t* kalt = (uint64_t*)p; p += a(nn * 8);
+  uint32_t* valt = (uint32_t*)p; p += a(nn * 4);
+  uint32_t* ghist = (uint32_t*)p; p += a(kMaxPasses * kOsRadix * 4);
+  uint32_t* status = (uint32_t*)p; p += a((size_t)kMaxPasses * nb * kOsRadix * 4);
+  uint32_t* counters = (uint32_t*)p; p += a(kMaxPasses * 4);
+  uint32_t* err = (uint32_t*)p;
+  if (n <= 1 || passes == 0) {
+    if (vfinal != v0 && n > 0) {
+      int32_t r = check_hip(hipMemcpyAsync(vfinal, v0, n * 4, hipMemcpyDeviceToDevice, st), "sort copy");
+      if (r != GS_OK) return r;
+    }
+    return GS_OK;
+  }
+  // zero histograms, status words, counters and the error flag in one fill
+  const int64_t zero_words = (int64_t)((char*)err + 4 - (char*)ghist) / 4;
+  int32_t r = launch_fill(ghist, 0u, zero_words, st);
+  if (r != GS_OK) return r;
+  const int64_t hb = (nn + 4 * kOsTile - 1) / (4 * kOsTile);
+  hipLaunchKernelGGL(k_os_hist, dim3((unsigned)hb), dim3(kBlock), 0, st, k0, n, passes, ghist);
+  hipLaunchKernelGGL(k_os_scan, dim3(1), dim3(kBlock), 0, st, ghist, passes);
+  MS_CHECK_LAUNCH("sort histogram");
+  uint64_t* kin = k0;
+  uint32_t* vin = v0;
+  for (int ps = 0; ps < passes; ++ps) {
+    uint64_t* kout = (kin == k0) ? kalt : k0;
+    uint32_t* vout = (vin == v0) ? valt : v0;
+    if (ps == passes - 1) vout = vfinal;
+    if (vout == vin) vout = (vin == v0) ? valt : v0;
+    hipLaunchKernelGGL(k_os_pass, dim3((unsigned)nb), dim3(kBlock), 0, st, kin, vin, kout, vout, n, 8 * ps,
+                       ghist + ps * kOsRadix, status + (size_t)ps * nb * kOsRadix, counters + ps, err);
+    MS_CHECK_LAUNCH("sort pass");
+    kin = kout;
+    vin = vout;
+  }
+  if (vin != vfinal) {
+    r = check_hip(hipMemcpyAsync(vfinal, vin, n * 4, hipMemcpyDeviceToDevice, st), "sort copy");
+    if (r != GS_OK) return r;
+  }
+  *keys_sorted = kin;
+  return GS_OK;
+}
+
+}  // namespace msplat

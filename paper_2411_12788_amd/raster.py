@@ -144,6 +144,7 @@ class Binned:
     keys: Optional[torch.Tensor]
     stats: L.BinStats
     offsets: torch.Tensor
+    order: Optional[torch.Tensor] = None  # [tiles_total] tile processing order (longest lists first)
 
 
 def bin_count(proj: Projected, cams, n: int, stream=None):
@@ -165,11 +166,13 @@ def bin_sort(proj: Projected, cams, n: int, offsets: torch.Tensor, st: L.BinStat
     vals = torch.empty(max(ni, 1), device=dev, dtype=torch.int32)
     keys = torch.empty(max(ni, 1), device=dev, dtype=torch.int64) if want_keys else None
     ranges = torch.empty((max(st.tiles_total, 1), 2), device=dev, dtype=torch.int32)
+    order = torch.empty(max(st.tiles_total, 1), device=dev, dtype=torch.int32)
     ws = torch.empty(max(L.lib().gs_bin_sort_workspace_size(ni), 1), device=dev, dtype=torch.uint8)
     L.check(L.lib().gs_bin_sort(ctypes.byref(proj.c()), cameras(cams), V, n, _ptr(offsets), ctypes.byref(st),
-                                _ptr(keys), _ptr(vals), _ptr(ranges), _ptr(ws), ws.numel(), _stream(stream)),
-            "gs_bin_sort")
-    return Binned(vals[:ni], ranges[: st.tiles_total], None if keys is None else keys[:ni], st, offsets)
+                                _ptr(keys), _ptr(vals), _ptr(ranges), _ptr(order), _ptr(ws), ws.numel(),
+                                _stream(stream)), "gs_bin_sort")
+    return Binned(vals[:ni], ranges[: st.tiles_total], None if keys is None else keys[:ni], st, offsets,
+                  order[: st.tiles_total])
 
 
 def bin(proj: Projected, cams, n: int, want_keys: bool = False, stream=None) -> Binned:
@@ -225,7 +228,8 @@ def render_forward(scene: DeviceScene, proj: Projected, binned: Binned, cams, op
     flags = opts.flags | (L.GS_ACCUM_IMPORTANCE if accum is not None else 0)
     a = _accum_c(accum)
     L.check(L.lib().gs_render_forward(ctypes.byref(scene.c()), ctypes.byref(proj.c()), _ptr(binned.vals),
-                                      _ptr(binned.ranges), cameras(cams), len(cams), ctypes.byref(opts.c(flags)),
+                                      _ptr(binned.ranges), _ptr(binned.order), cameras(cams), len(cams),
+                                      ctypes.byref(opts.c(flags)),
                                       ctypes.byref(fo), ctypes.byref(a) if accum is not None else None,
                                       _stream(stream)), "gs_render_forward")
     return out
@@ -235,7 +239,8 @@ def accumulate_importance(proj: Projected, binned: Binned, cams, n: int, opts: R
                           accum: Dict[str, torch.Tensor], stream=None) -> None:
     a = _accum_c(accum)
     L.check(L.lib().gs_accumulate_importance(ctypes.byref(proj.c()), _ptr(binned.vals), _ptr(binned.ranges),
-                                             cameras(cams), len(cams), n, ctypes.byref(opts.c()), ctypes.byref(a),
+                                             _ptr(binned.order), cameras(cams), len(cams), n, ctypes.byref(opts.c()),
+                                             ctypes.byref(a),
                                              _stream(stream)), "gs_accumulate_importance")
 
 
@@ -263,7 +268,8 @@ def render_backward(scene: DeviceScene, proj: Projected, binned: Binned, cams, o
     if grad2d is None:
         grad2d = torch.empty((max(V * n, 1), L.GS_GRAD2D_FLOATS), device=dev)
     L.check(L.lib().gs_render_backward(ctypes.byref(scene.c()), ctypes.byref(proj.c()), _ptr(binned.vals),
-                                       _ptr(binned.ranges), cameras(cams), V, ctypes.byref(opts.c()),
+                                       _ptr(binned.ranges), _ptr(binned.order), cameras(cams), V,
+                                       ctypes.byref(opts.c()),
                                        _ptr(frame.t_final), _ptr(frame.last), _ptr(dl_dcolor.contiguous()),
                                        _ptr(active), _ptr(grad2d), ctypes.byref(_grads_c(grads)), _stream(stream)),
             "gs_render_backward")
@@ -276,7 +282,8 @@ def render_backward_pixels(proj: Projected, binned: Binned, cams, n: int, opts: 
     if grad2d is None:
         grad2d = torch.zeros((max(V * n, 1), L.GS_GRAD2D_FLOATS), device=proj.rec.device)
     L.check(L.lib().gs_render_backward_pixels(ctypes.byref(proj.c()), _ptr(binned.vals), _ptr(binned.ranges),
-                                              cameras(cams), V, n, ctypes.byref(opts.c()), _ptr(frame.t_final),
+                                              _ptr(binned.order), cameras(cams), V, n, ctypes.byref(opts.c()),
+                                              _ptr(frame.t_final),
                                               _ptr(frame.last), _ptr(dl_dcolor.contiguous()), _ptr(active),
                                               _ptr(grad2d), _stream(stream)), "gs_render_backward_pixels")
     return grad2d

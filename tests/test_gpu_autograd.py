@@ -99,7 +99,8 @@ def test_gradients_vs_oracle_and_finite_differences_256(gpu_lib):
 
     margins = [oracle.forward_view(p, c, opts, accumulate=False)["margin"] for c in cams]
     mmin = min(min(m[:, 0].min(), m[:, 1].min()) for m in margins)
-    assert mmin > 1e-5, mmin  # no decision within reach of the perturbation
+    # a 1e-7 relative perturbation moves alpha by <= ~1e-6 relative: decisions need a larger margin
+    assert mmin > 2e-6, mmin
     rng = gs_inputs.rng(6)
     fd_vals, gpu_vals, an_vals = [], [], []
     for _ in range(120):

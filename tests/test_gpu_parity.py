@@ -229,3 +229,31 @@ def test_argument_errors(gpu_lib):
     cams[0].fx = float("nan")
     assert lib.gs_project(ctypes.byref(ds.c()), cams, 1, None, ctypes.byref(o), ctypes.byref(outp), None) == \
         L.GS_ERR_CAMERA
+
+
+def test_l1_loss_grad_matches_definition(gpu_lib):
+    R = H.raster()
+    for count in (1, 7, 4099, 3 * 128 * 96 + 2):
+        g = gs_inputs.rng(count)
+        c = torch.from_numpy(g.uniform(size=count).astype(np.float32)).cuda()
+        t = torch.from_numpy(g.uniform(size=count).astype(np.float32)).cuda()
+        t[: count // 5] = c[: count // 5]  # exact ties give a zero gradient
+        dl = torch.empty_like(c)
+        loss = torch.zeros(1, device="cuda")
+        R.l1_loss_grad(c, t, dl, loss)
+        torch.cuda.synchronize()
+        d = (c - t).double().cpu().numpy()
+        assert np.array_equal(_np(dl), (np.sign(d) / count).astype(np.float32))
+        assert loss.item() == pytest.approx(np.abs(d).mean(), rel=1e-5)
+
+
+def test_tile_order_is_longest_first_permutation(gpu_lib):
+    wl = _small(seed=6)
+    out = H.run_gpu_forward(wl.scene, wl.cameras, accumulate=False)
+    b = out["binned"]
+    order = _np(b.order).astype(np.int64)
+    rng = _np(b.ranges).view(np.uint32).astype(np.int64)
+    assert np.array_equal(np.sort(order), np.arange(len(rng)))
+    lengths = rng[order, 1] - rng[order, 0]
+    bits = np.where(lengths > 0, np.floor(np.log2(np.maximum(lengths, 1))) + 1, 0)
+    assert np.all(np.diff(bits) <= 0)

@@ -1,0 +1,29 @@
+"""Build-level checks on the gfx950 kernels (CPU only: hipcc cross-compiles).
+
+No kernel may use per-thread scratch: a spill or a dynamically indexed copy of
+the kernel-argument view table costs kilobytes of scratch traffic per thread.
+"""
+import os
+import re
+import shutil
+import subprocess
+
+import pytest
+
+from paper_2411_12788_amd import build as B
+
+
+@pytest.mark.skipif(shutil.which(B.HIPCC) is None and not os.path.exists(B.HIPCC), reason="hipcc not available")
+@pytest.mark.parametrize("src", [os.path.basename(s) for s in B.sources()])
+def test_no_scratch_and_bounded_registers(tmp_path, src):
+    out = tmp_path / (src + ".s")
+    cmd = [B.HIPCC, *B.CFLAGS, "--cuda-device-only", "-S", os.path.join(B.CSRC, src), "-o", str(out)]
+    subprocess.check_call(cmd, stdout=subprocess.DEVNULL, stderr=subprocess.DEVNULL)
+    asm = out.read_text()
+    kernels = re.findall(r"\.name:\s+(\S+)\n(?:.*\n){0,40}?\s+\.private_segment_fixed_size:\s+(\d+)", asm)
+    sizes = [int(x) for x in re.findall(r"\.amdhsa_private_segment_fixed_size\s+(\d+)", asm)]
+    assert sizes, "no kernels found"
+    assert max(sizes) == 0, f"{src}: scratch in use {sizes}"
+    vgprs = [int(x) for x in re.findall(r"\.vgpr_count:\s+(\d+)", asm)]
+    # >= 2 waves per SIMD for the FP64 projection backward; the rest stay far below
+    assert max(vgprs) <= 272, f"{src}: {vgprs}"
