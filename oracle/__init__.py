@@ -20,6 +20,9 @@ other than itself live in ``tests/test_oracle_*.py``:
   render_backward   derivative of Eq. (1)                  pinned: central FD
   project_backward  derivative of Sec. 3.1 projection      pinned: central FD
   bin               tile | depth keys, stable sort, ranges pinned: numpy lexsort
+  quantile, visibility, critical, blur_split, clone
+                    Sec. 5.1, Sec. 5.2, Eq. (3)             pinned: numpy quantile,
+                    two-clone opacity identity, small-opacity limit, paper constants
 """
 from __future__ import annotations
 
@@ -50,6 +53,12 @@ def lib():
         _lib = ctypes.CDLL(_build.LIB)
         _lib.orc_order.restype = ctypes.c_int64
         _lib.orc_bin.restype = ctypes.c_int64
+        _lib.orc_quantile.restype = ctypes.c_double
+        _lib.orc_visibility.restype = ctypes.c_double
+        _lib.orc_threshold.restype = ctypes.c_double
+        _lib.orc_mass_threshold.restype = ctypes.c_double
+        _lib.orc_critical.restype = ctypes.c_double
+        _lib.orc_clone.restype = ctypes.c_int64
     return _lib
 
 
@@ -320,3 +329,70 @@ def backward_views(params: Params, cams: Sequence, opts: Opts, dldc: List[np.nda
         for k, g in grads.items():
             g[..., ~m] = 0.0
     return grads, g2ds
+
+
+# ---------------------------------------------------------------------------------
+# criteria consuming the accumulations (Sec. 5.1, Sec. 5.2, Eq. (3))
+# ---------------------------------------------------------------------------------
+KEEP_QUANTILE = 0.99   # Sec. 5.1 and Sec. 5.2
+THETA_BLUR = 2e-4      # Eq. (3)
+
+
+def quantile(values, q: float, mask=None) -> float:
+    v = _d(values)
+    m = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8)
+    return lib().orc_quantile(ctypes.c_int64(v.shape[0]), _p(v), None if m is None else _p(m), ctypes.c_double(q))
+
+
+THRESHOLD_VALUE, THRESHOLD_MASS = 0, 1
+
+
+def threshold(values, keep: float = KEEP_QUANTILE, mode: int = THRESHOLD_MASS, mask=None):
+    """(tau, margin): the keep-quantile threshold of the selected values."""
+    v = _d(values)
+    m = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8)
+    margin = ctypes.c_double(0.0)
+    tau = lib().orc_threshold(ctypes.c_int64(v.shape[0]), _p(v), None if m is None else _p(m), ctypes.c_double(keep),
+                              ctypes.c_int(mode), ctypes.byref(margin))
+    return tau, margin.value
+
+
+def visibility(importance, keep: float = KEEP_QUANTILE, mode: int = THRESHOLD_MASS):
+    """(visible[n] uint8, tau, margin) for one view's importances."""
+    v = _d(importance)
+    out = np.zeros(max(v.shape[0], 1), dtype=np.uint8)
+    margin = ctypes.c_double(0.0)
+    tau = lib().orc_visibility(ctypes.c_int64(v.shape[0]), _p(v), ctypes.c_double(keep), ctypes.c_int(mode), _p(out),
+                               ctypes.byref(margin))
+    return out[: v.shape[0]], tau, margin.value
+
+
+def critical(area, wmax, keep: float = KEEP_QUANTILE, mode: int = THRESHOLD_MASS):
+    """(critical[n] uint8, tau, margin)."""
+    a = np.ascontiguousarray(area, dtype=np.int64)
+    w = _d(wmax)
+    out = np.zeros(max(a.shape[0], 1), dtype=np.uint8)
+    margin = ctypes.c_double(0.0)
+    tau = lib().orc_critical(ctypes.c_int64(a.shape[0]), _p(a), _p(w), ctypes.c_double(keep), ctypes.c_int(mode),
+                             _p(out), ctypes.byref(margin))
+    return out[: a.shape[0]], tau, margin.value
+
+
+def blur_split(area, height: int, width: int, theta: float = THETA_BLUR):
+    a = np.ascontiguousarray(area, dtype=np.int64)
+    out = np.zeros(max(a.shape[0], 1), dtype=np.uint8)
+    lib().orc_blur_split(ctypes.c_int64(a.shape[0]), _p(a), ctypes.c_double(theta), ctypes.c_int64(height),
+                         ctypes.c_int64(width), _p(out))
+    return out[: a.shape[0]]
+
+
+def clone(params: Params, select) -> Params:
+    sel = np.ascontiguousarray(select, dtype=np.uint8)
+    n = params.n
+    m = n + int(sel.sum())
+    out = Params(np.zeros((3, m)), np.zeros((3, m)), np.zeros((4, m)), np.zeros(m), np.zeros((16, 3, m)),
+                 params.sh_degree)
+    lib().orc_clone(ctypes.c_int64(n), _p(params.means), _p(params.scales), _p(params.quats), _p(params.opacity),
+                    _p(params.sh), _p(sel), _p(out.means), _p(out.scales), _p(out.quats), _p(out.opacity),
+                    _p(out.sh))
+    return out

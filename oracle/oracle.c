@@ -741,3 +741,143 @@ int64_t orc_bin(int64_t n_views, int64_t n_per_view, const int32_t* rect, const 
 }
 
 int orc_stride(void) { return OP_STRIDE; }
+
+/* ------------------------------------------------------------------------ */
+/* densification / pruning criteria that consume the accumulations          */
+/* ------------------------------------------------------------------------ */
+static int cmp_double(const void* a, const void* b) {
+  double x = *(const double*)a, y = *(const double*)b;
+  return x < y ? -1 : (x > y ? 1 : 0);
+}
+
+/* q-quantile of the values with mask[i] != 0 (all when mask == NULL), linear
+ * interpolation between order statistics: h = (m - 1) q, x[floor h] +
+ * (h - floor h)(x[floor h + 1] - x[floor h]).  Returns NAN when no value is
+ * selected.  The "quantile function" of Sec. 5.1 / Sec. 5.2. */
+double orc_quantile(int64_t n, const double* values, const uint8_t* mask, double q) {
+  double* x = (double*)malloc(sizeof(double) * (n > 0 ? n : 1));
+  int64_t m = 0;
+  for (int64_t i = 0; i < n; i++)
+    if (!mask || mask[i]) x[m++] = values[i];
+  if (m == 0) { free(x); return NAN; }
+  qsort(x, (size_t)m, sizeof(double), cmp_double);
+  double h = (double)(m - 1) * q;
+  int64_t lo = (int64_t)floor(h);
+  if (lo >= m - 1) { double r = x[m - 1]; free(x); return r; }
+  double r = x[lo] + (h - (double)lo) * (x[lo + 1] - x[lo]);
+  free(x);
+  return r;
+}
+
+static int cmp_double_desc(const void* a, const void* b) { return -cmp_double(a, b); }
+
+/* Cumulative-mass reading of the keep quantile (Sec. 5.1, Sec. 5.2): with the
+ * selected values in descending order x_1 >= ... >= x_m, total S and prefix
+ * sums C_k, the threshold is x_k for the k that brings C_k closest to keep * S
+ * (the smaller k on a tie); the values strictly above it account for about
+ * keep of the total.  *margin (optional) receives the smallest distance from
+ * any quantity this decision compares to the one it is compared with, for
+ * judging rounding-order ambiguity.  NAN when nothing is selected. */
+double orc_mass_threshold(int64_t n, const double* values, const uint8_t* mask, double keep, double* margin) {
+  double* x = (double*)malloc(sizeof(double) * (n > 0 ? n : 1));
+  int64_t m = 0;
+  for (int64_t i = 0; i < n; i++)
+    if (!mask || mask[i]) x[m++] = values[i];
+  if (margin) *margin = INFINITY;
+  if (m == 0) { free(x); return NAN; }
+  qsort(x, (size_t)m, sizeof(double), cmp_double_desc);
+  double S = 0;
+  for (int64_t k = 0; k < m; k++) S += x[k];
+  double target = keep * S;
+  /* first k (1-based) with C_k >= keep * S; C_m = S covers keep <= 1 */
+  double C = 0, Cprev = 0;
+  int64_t k0 = m;
+  for (int64_t k = 1; k <= m; k++) {
+    Cprev = C;
+    C += x[k - 1];
+    if (C >= target) { k0 = k; break; }
+  }
+  int64_t ks = k0;
+  double d_hi = C - target, d_lo = target - Cprev;
+  if (k0 > 1 && d_lo <= d_hi) ks = k0 - 1;
+  if (margin) {
+    double g = fabs(d_hi);
+    if (k0 > 1) {
+      g = fmin(g, fabs(d_lo));
+      g = fmin(g, fabs(d_hi - d_lo));
+    }
+    *margin = g;
+  }
+  double r = x[ks - 1];
+  free(x);
+  return r;
+}
+
+/* threshold by mode: 0 = plain (1 - keep) quantile of the values, 1 = cumulative mass */
+double orc_threshold(int64_t n, const double* values, const uint8_t* mask, double keep, int mode, double* margin) {
+  if (mode == 1) return orc_mass_threshold(n, values, mask, keep, margin);
+  if (margin) *margin = INFINITY;
+  return orc_quantile(n, values, mask, 1.0 - keep);
+}
+
+/* Visibility of one view (Sec. 5.2): V_i = [I_i > tau], tau the keep-quantile
+ * threshold over the importances of the Gaussians that contribute (I_i > 0). */
+double orc_visibility(int64_t n, const double* importance, double keep, int mode, uint8_t* visible, double* margin) {
+  uint8_t* contrib = (uint8_t*)malloc((size_t)(n > 0 ? n : 1));
+  for (int64_t i = 0; i < n; i++) contrib[i] = importance[i] > 0;
+  double tau = orc_threshold(n, importance, contrib, keep, mode, margin);
+  for (int64_t i = 0; i < n; i++) visible[i] = isnan(tau) ? 0 : (importance[i] > tau);
+  free(contrib);
+  return tau;
+}
+
+/* Critical Gaussians (Sec. 5.1): members of G_imax (area S_i > 0) whose
+ * maximum blend weight lies above the keep-quantile threshold of w_max over G_imax. */
+double orc_critical(int64_t n, const int64_t* area, const double* wmax, double keep, int mode, uint8_t* critical,
+                    double* margin) {
+  uint8_t* member = (uint8_t*)malloc((size_t)(n > 0 ? n : 1));
+  for (int64_t i = 0; i < n; i++) member[i] = area[i] > 0;
+  double tau = orc_threshold(n, wmax, member, keep, mode, margin);
+  for (int64_t i = 0; i < n; i++) critical[i] = member[i] && !isnan(tau) && wmax[i] > tau;
+  free(member);
+  return tau;
+}
+
+/* Blur split criterion (Eq. (3)): S_i > theta_blur * H * W. */
+void orc_blur_split(int64_t n, const int64_t* area, double theta, int64_t H, int64_t W, uint8_t* split) {
+  double thr = theta * (double)H * (double)W;
+  for (int64_t i = 0; i < n; i++) split[i] = (double)area[i] > thr;
+}
+
+/* Aggressive clone with two copies (Sec. 5.1): each selected Gaussian keeps its
+ * centre, rotation and colour, takes opacity a' = 1 - sqrt(1 - a) and
+ * covariance a^2 (2 a' - a'^2 / sqrt 2)^-2 Sigma, i.e. every scale times
+ * a / (2 a' - a'^2 / sqrt 2); the copy is appended after the n originals in
+ * index order.  Output arrays hold n + count columns; returns count. */
+int64_t orc_clone(int64_t n, const double* means, const double* scales, const double* quats, const double* opac,
+                  const double* sh, const uint8_t* select, double* o_means, double* o_scales, double* o_quats,
+                  double* o_opac, double* o_sh) {
+  int64_t count = 0;
+  for (int64_t i = 0; i < n; i++) count += select[i] != 0;
+  int64_t m = n + count;
+  int64_t pos = n;
+  for (int64_t i = 0; i < n; i++) {
+    double a = opac[i], an = a, f = 1.0;
+    if (select[i]) {
+      an = 1.0 - sqrt(1.0 - a);
+      /* a -> 0 gives a' -> a / 2 and a factor -> 1, its limit */
+      f = a > 0 ? a / (2.0 * an - an * an / sqrt(2.0)) : 1.0;
+    }
+    int64_t dst[2] = {i, select[i] ? pos++ : -1};
+    for (int c = 0; c < 2; c++) {
+      int64_t d = dst[c];
+      if (d < 0) continue;
+      for (int k = 0; k < 3; k++) o_means[k * m + d] = means[k * n + i];
+      for (int k = 0; k < 3; k++) o_scales[k * m + d] = scales[k * n + i] * f;
+      for (int k = 0; k < 4; k++) o_quats[k * m + d] = quats[k * n + i];
+      o_opac[d] = an;
+      for (int k = 0; k < 48; k++) o_sh[k * m + d] = sh[k * n + i];
+    }
+  }
+  return count;
+}
