@@ -99,10 +99,28 @@ __device__ __forceinline__ float wave_reduce_dpp(float x) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
 }
 
-__device__ __forceinline__ bool box_meets(int2 b, int32_t sx0, int32_t sy0) {
-  // pixel box (lo | hi << 16) against the 8x8 quarter starting at (sx0, sy0)
-  return (int32_t)((uint32_t)b.x >> 16) >= sx0 && (b.x & 0xffff) <= sx0 + 7 && (int32_t)((uint32_t)b.y >> 16) >= sy0 &&
-         (b.y & 0xffff) <= sy0 + 7;
+__device__ __forceinline__ bool box_meets(int2 b, int32_t x0, int32_t x1, int32_t y0, int32_t y1) {
+  // pixel box (lo | hi << 16) against the pixel rectangle [x0, x1] x [y0, y1]
+  return (int32_t)((uint32_t)b.x >> 16) >= x0 && (b.x & 0xffff) <= x1 && (int32_t)((uint32_t)b.y >> 16) >= y0 &&
+         (b.y & 0xffff) <= y1;
+}
+
+// Bounding rectangle of the lanes set in `am` (lane = 8 * row + column of the
+// wave's 8x8 quarter at (sx0, sy0)), from the ballot mask with scalar bit ops.
+struct Rect {
+  int32_t x0, x1, y0, y1;
+};
+__device__ __forceinline__ Rect active_rect(uint64_t am, int32_t sx0, int32_t sy0) {
+  uint64_t f = am | (am >> 32);
+  f |= f >> 16;
+  f |= f >> 8;
+  const uint32_t cols = (uint32_t)f & 0xffu;
+  Rect r;
+  r.y0 = sy0 + ((int32_t)__builtin_ctzll(am) >> 3);
+  r.y1 = sy0 + ((63 - (int32_t)__builtin_clzll(am)) >> 3);
+  r.x0 = sx0 + (int32_t)__builtin_ctz(cols);
+  r.x1 = sx0 + (31 - (int32_t)__builtin_clz(cols));
+  return r;
 }
 
 constexpr int kBatch = kBlock;  // list entries staged per workgroup round
@@ -180,7 +198,9 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(const float* __restrict__
     bool wave_done = __all(done);
     for (int c = 0; c < kBatch / kWave && !wave_done; ++c) {
       const int k = c * kWave + lane;
-      const bool rel = (uint32_t)k < count && box_meets(s_box[k < kBatch ? k : 0], sx0, sy0);
+      // cull against the pixels that are still compositing, not the whole quarter
+      const Rect ar = active_rect(__ballot(!done), sx0, sy0);
+      const bool rel = (uint32_t)k < count && box_meets(s_box[k], ar.x0, ar.x1, ar.y0, ar.y1);
       uint64_t mask = __ballot(rel);
       while (mask != 0) {
         const int kk = c * kWave + (int)__builtin_ctzll(mask);
@@ -338,8 +358,12 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(const float* __restrict__
     __syncthreads();
     for (int c = kBatch / kWave - 1; c >= 0; --c) {
       const int k = c * kWave + lane;
+      // lanes that still have work in this chunk: their last entry lies above its first
+      const uint64_t am = __ballot(lst > base + (uint32_t)(c * kWave) - start);
+      if (am == 0) continue;
+      const Rect ar = active_rect(am, sx0, sy0);
       const bool rel = (uint32_t)k < count && base + (uint32_t)k < start + wjmax &&
-                       box_meets(s_box[k], sx0, sy0);
+                       box_meets(s_box[k], ar.x0, ar.x1, ar.y0, ar.y1);
       uint64_t mask = __ballot(rel);
       while (mask != 0) {
         const int hb = 63 - (int)__builtin_clzll(mask);
