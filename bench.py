@@ -53,6 +53,7 @@ def parse():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=240)
     ap.add_argument("--no-multiview", action="store_true")
+    ap.add_argument("--no-criteria", action="store_true")
     ap.add_argument("--profile", action="store_true",
                     help="short run for rocprofv3: a few steps plus a 1 GiB copy kernel for counter calibration")
     ap.add_argument("--summarize", metavar="DIR",
@@ -144,6 +145,47 @@ class Step:
         torch.cuda.synchronize()
         for k in self.names:
             self.times[k].append(self.ev[k][0].elapsed_time(self.ev[k][1]))
+
+
+def criteria_bench(step, reps: int = 10):
+    """Time the culling/densification criteria on the accumulations of the last
+    timed step: per-view visibility and critical set (both threshold readings),
+    blur split, two-way clone of the critical set, gradient statistics.
+    'gbs' uses the algorithmic minimum traffic (read the inputs once, write the
+    outputs once), so it is a lower bound on what the kernels move."""
+    from paper_2411_12788_amd import densify as Dz
+    n = step.n
+    imp = step.acc["importance"].view(1, n)
+    area, wmax = step.acc["area"], step.acc["wmax"]
+    from paper_2411_12788_amd import _lib as L
+    ws = torch.empty(L.lib().gs_select_workspace_size(1), dtype=torch.uint8, device="cuda")
+    res = {}
+
+    def timed(name, fn, nbytes):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            out = fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        res[name] = {"ms": round(ms, 4), "gbs": round(nbytes / (ms * 1e-3) / 1e9, 1)}
+        return out
+
+    for mode, tag in ((Dz.THRESHOLD_MASS, "mass"), (Dz.THRESHOLD_VALUE, "value")):
+        timed(f"visibility_{tag}", lambda: Dz.visibility(imp, mode=mode, ws=ws), 5 * n)
+        crit = timed(f"critical_{tag}", lambda: Dz.critical(area, wmax, mode=mode, ws=ws), 9 * n)
+    sel = crit[0]
+    cnt = int(sel.sum().item())
+    res["critical_count"] = cnt
+    timed("blur_split", lambda: Dz.blur_split(area, step.cams[0].height, step.cams[0].width), 5 * n)
+    timed("clone", lambda: Dz.clone(step.scene, sel, capacity=n + cnt), 236 * n + 1 * n + 236 * (n + cnt))
+    ns = torch.zeros(n, device="cuda")
+    cn = torch.zeros(n, dtype=torch.int32, device="cuda")
+    timed("grad_stats", lambda: Dz.grad_stats(step.proj, step.grad2d, step.cams, n, ns, cn), 28 * n)
+    return res
 
 
 def cpu_baseline(wl, sample_pixels: int):
@@ -436,6 +478,8 @@ def main():
                      "frac": round(achieved / peak, 5), "traffic": traffic_from_profiles(dom)},
         "stages": stages,
     }
+    if not args.no_criteria:
+        out["criteria"] = criteria_bench(step)
     if not args.no_multiview:
         out["multiview"] = multiview_bench(5, 2)
     if not args.no_serving:

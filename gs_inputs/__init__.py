@@ -174,6 +174,26 @@ def bernoulli_mask(n: int, p: float, seed: int) -> np.ndarray:
     return (rng(seed).uniform(size=n) < p).astype(np.uint8)
 
 
+def importance_like(views: int, n: int, seed: int, zero_fraction: float = 0.4, sigma: float = 2.0) -> np.ndarray:
+    """[views, n] float32: heavy-tailed non-negative sums of blend weights, with
+    a fraction of exact zeros (Gaussians that reach no pixel of the view)."""
+    g = rng(seed)
+    v = g.lognormal(mean=0.0, sigma=sigma, size=(views, n))
+    v[g.uniform(size=(views, n)) < zero_fraction] = 0.0
+    return v.astype(np.float32)
+
+
+def wmax_like(n: int, seed: int, clamp_fraction: float = 0.2, alpha_max: float = 0.99):
+    """(area[n] uint32, wmax[n] float32): maximum blend weights in (0, alpha_max],
+    a fraction exactly alpha_max (the first Gaussian of a pixel at the opacity
+    clamp), and argmax areas that are zero for about half of the Gaussians."""
+    g = rng(seed)
+    w = g.beta(2.0, 5.0, size=n) * alpha_max
+    w[g.uniform(size=n) < clamp_fraction] = alpha_max
+    area = np.where(g.uniform(size=n) < 0.5, 0, g.geometric(0.05, size=n)).astype(np.uint32)
+    return area, w.astype(np.float32)
+
+
 def uniform_image(channels: int, pixels: int, seed: int) -> np.ndarray:
     return rng(seed).uniform(0.0, 1.0, size=(channels, pixels)).astype(np.float32)
 

@@ -289,6 +289,83 @@ int32_t gs_l1_loss_grad(const float* color, const float* target, int64_t count, 
 /* Fill `count` 32-bit words with `value` (graph-capture-safe clear). */
 int32_t gs_fill_u32(void* dst, uint32_t value, int64_t count, void* stream);
 
+/* ------------------------------------------------------------------------ */
+/* Criteria that consume the accumulations: culling and densification.      */
+/* ------------------------------------------------------------------------ */
+
+/* Keep-quantile threshold readings (Sec. 5.1 and Sec. 5.2 both filter with a
+ * keep quantile of 0.99).  Over the m selected values:
+ *  GS_THRESHOLD_MASS  (default reading): sort descending, prefix sums C_k,
+ *      total S; tau = x_k for the k with C_k closest to keep * S (smaller k on
+ *      a tie), so the values strictly above tau carry about keep of the total.
+ *      Values are expected to be >= 0.
+ *  GS_THRESHOLD_VALUE: tau = the (1 - keep) quantile of the values, linear
+ *      interpolation between order statistics floor(h), floor(h) + 1 with
+ *      h = (m - 1)(1 - keep).
+ * tau is NaN when nothing is selected; NaN values give unspecified results. */
+enum { GS_THRESHOLD_VALUE = 0, GS_THRESHOLD_MASS = 1 };
+
+/* Device workspace of gs_visibility / gs_critical for `problems` thresholds
+ * (V views, or 1); reused across calls, no clearing needed. */
+size_t gs_select_workspace_size(int32_t problems);
+
+/* Visibility of each view (Sec. 5.2): visible[k][i] = I_i^k > tau_k, where
+ * tau_k is the keep-quantile threshold of view k's importances over the
+ * Gaussians with I_i^k > 0.  importance [dev, V][n] (GS_ACCUM_PER_VIEW
+ * layout); visible [dev, V][n] bytes 0/1 (all written); tau [dev, V] doubles.
+ * keep in [0, 1] (GS_ERR_SHAPE otherwise).  The mask feeds gs_project's
+ * cull_mask or the backward's `active` (view-dependent culling, Sec. 5.2). */
+int32_t gs_visibility(const float* importance, int32_t V, int64_t n, double keep, int32_t mode, uint8_t* visible,
+                      double* tau, void* ws, size_t ws_bytes, void* stream);
+
+/* Critical Gaussians (Sec. 5.1): the set G_imax of Gaussians that provide the
+ * largest blend weight of at least one pixel (area[i] > 0), filtered by the
+ * keep-quantile threshold of their w_max: critical[i] = area[i] > 0 and
+ * wmax[i] > tau.  area, wmax [dev, n] as accumulated by the forward pass;
+ * critical [dev, n] bytes 0/1; tau [dev, 1] double. */
+int32_t gs_critical(const uint32_t* area, const float* wmax, int64_t n, double keep, int32_t mode, uint8_t* critical,
+                    double* tau, void* ws, size_t ws_bytes, void* stream);
+
+/* Blur split criterion (Eq. (3)): split[i] = area[i] > theta * H * W, in
+ * double precision; the paper's theta is 2e-4.  area [dev, n]; split [dev, n]. */
+int32_t gs_blur_split(const uint32_t* area, int64_t n, double theta, int32_t height, int32_t width, uint8_t* split,
+                      void* stream);
+
+/* Positional-gradient statistics for the adaptive density control (Sec. 3.2):
+ * for each Gaussian and each view where its record touches a tile, adds the
+ * norm of d loss / d (u, v) scaled to image coordinates in [-1, 1]
+ * (u by W / 2, v by H / 2) to norm_sum[i] and 1 to count[i].  grad2d
+ * [dev, V*n][9] from the backward pass; norm_sum [dev, n] float, count
+ * [dev, n] uint32, both accumulated (caller zeroes them). */
+int32_t gs_grad_stats(const gs_projected_t* proj, const float* grad2d, const gs_camera_t* cams, int32_t V, int64_t n,
+                      float* norm_sum, uint32_t* count, void* stream);
+
+/* Writable scene planes [dev] in the gs_scene_t layout with plane stride
+ * `capacity` (the output of gs_clone). */
+typedef struct {
+  float* means;
+  float* scales;
+  float* quats;
+  float* opacity;
+  float* sh;
+  int64_t capacity;
+} gs_scene_out_t;
+
+/* Device workspace of gs_clone for n input Gaussians. */
+size_t gs_clone_workspace_size(int64_t n);
+
+/* Aggressive clone into two Gaussians (Sec. 5.1): every row i with
+ * select[i] != 0 keeps its centre, rotation and SH and takes opacity
+ * a' = 1 - sqrt(1 - a) and scales times a / (2 a' - a'^2 / sqrt 2) (covariance
+ * times its square), computed in double; its copy goes to row n + r, r the
+ * number of selected rows before i.  Unselected rows are copied unchanged.
+ * out->capacity is the plane stride of the output (>= in->n, GS_ERR_CAPACITY
+ * otherwise); copies beyond it are dropped, so size it in->n + the number of
+ * selected rows.  All 48 SH planes are copied.  *count [dev int64] receives
+ * the number of selected rows.  in and out must not overlap. */
+int32_t gs_clone(const gs_scene_t* in, const uint8_t* select, const gs_scene_out_t* out, int64_t* count, void* ws,
+                 size_t ws_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -396,3 +396,16 @@ def clone(params: Params, select) -> Params:
                     _p(params.sh), _p(sel), _p(out.means), _p(out.scales), _p(out.quats), _p(out.opacity),
                     _p(out.sh))
     return out
+
+
+def grad_stats(tiles, grad2d, widths, heights):
+    """(norm_sum[n], count[n]) from tiles[V, n], grad2d[V * n, 9] (Sec. 3.2)."""
+    t = np.ascontiguousarray(tiles, dtype=np.int32)
+    V, n = t.shape
+    g = _d(grad2d).reshape(V * n, 9)
+    w = np.ascontiguousarray(widths, dtype=np.int32)
+    h = np.ascontiguousarray(heights, dtype=np.int32)
+    ns = np.zeros(max(n, 1))
+    cnt = np.zeros(max(n, 1), dtype=np.int64)
+    lib().orc_grad_stats(ctypes.c_int32(V), ctypes.c_int64(n), _p(t), _p(g), _p(w), _p(h), _p(ns), _p(cnt))
+    return ns[:n], cnt[:n]

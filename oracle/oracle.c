@@ -881,3 +881,25 @@ int64_t orc_clone(int64_t n, const double* means, const double* scales, const do
   }
   return count;
 }
+
+/* Positional-gradient statistics of the adaptive density control (Sec. 3.2,
+ * inherited from 3DGS): for every view in which Gaussian i's record touches a
+ * tile, the norm of its screen-mean gradient expressed in [-1, 1] image
+ * coordinates (du * W / 2, dv * H / 2) is added to norm_sum[i] and 1 to
+ * count[i]. */
+void orc_grad_stats(int32_t V, int64_t n, const int32_t* tiles, const double* grad2d, const int32_t* widths,
+                    const int32_t* heights, double* norm_sum, int64_t* count) {
+  for (int64_t i = 0; i < n; i++) {
+    norm_sum[i] = 0;
+    count[i] = 0;
+  }
+  for (int32_t k = 0; k < V; k++)
+    for (int64_t i = 0; i < n; i++) {
+      int64_t r = (int64_t)k * n + i;
+      if (tiles[r] <= 0) continue;
+      double gx = grad2d[r * 9 + 0] * 0.5 * widths[k];
+      double gy = grad2d[r * 9 + 1] * 0.5 * heights[k];
+      norm_sum[i] += sqrt(gx * gx + gy * gy);
+      count[i] += 1;
+    }
+}

@@ -18,6 +18,7 @@ GS_GRAD2D_FLOATS = 9
 GS_OK, GS_ERR_NULL, GS_ERR_SHAPE, GS_ERR_CAMERA, GS_ERR_CAPACITY, GS_ERR_DEVICE, GS_ERR_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 GS_DEPTH_MID, GS_DEPTH_CENTER, GS_DEPTH_BLEND = 0, 1, 2
 GS_ACCUM_IMPORTANCE, GS_ACCUM_PER_VIEW = 1, 2
+GS_THRESHOLD_VALUE, GS_THRESHOLD_MASS = 0, 1
 
 c_p = ctypes.c_void_p
 c_i32 = ctypes.c_int32
@@ -64,6 +65,10 @@ class Grads(ctypes.Structure):
     _fields_ = [("means", c_p), ("scales", c_p), ("quats", c_p), ("opacity", c_p), ("sh", c_p)]
 
 
+class SceneOut(ctypes.Structure):
+    _fields_ = [("means", c_p), ("scales", c_p), ("quats", c_p), ("opacity", c_p), ("sh", c_p), ("capacity", c_i64)]
+
+
 P = ctypes.POINTER
 _SIGS = {
     "gs_last_error": (ctypes.c_char_p, []),
@@ -93,6 +98,13 @@ _SIGS = {
     "gs_project_backward": (c_i32, [P(Scene), P(Projected), P(Camera), c_i32, P(Opts), c_p, c_p, P(Grads), c_p]),
     "gs_l1_loss_grad": (c_i32, [c_p, c_p, c_i64, c_p, c_p, c_p]),
     "gs_fill_u32": (c_i32, [c_p, c_u32, c_i64, c_p]),
+    "gs_select_workspace_size": (c_sz, [c_i32]),
+    "gs_visibility": (c_i32, [c_p, c_i32, c_i64, ctypes.c_double, c_i32, c_p, c_p, c_p, c_sz, c_p]),
+    "gs_critical": (c_i32, [c_p, c_p, c_i64, ctypes.c_double, c_i32, c_p, c_p, c_p, c_sz, c_p]),
+    "gs_blur_split": (c_i32, [c_p, c_i64, ctypes.c_double, c_i32, c_i32, c_p, c_p]),
+    "gs_grad_stats": (c_i32, [P(Projected), c_p, P(Camera), c_i32, c_i64, c_p, c_p, c_p]),
+    "gs_clone_workspace_size": (c_sz, [c_i64]),
+    "gs_clone": (c_i32, [P(Scene), c_p, P(SceneOut), c_p, c_p, c_sz, c_p]),
 }
 
 _lib = None

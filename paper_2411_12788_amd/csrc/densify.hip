@@ -1,0 +1,662 @@
+// Densification and culling criteria that consume the per-Gaussian
+// accumulations of the forward pass:
+//   - keep-quantile thresholds by device radix select (Sec. 5.1, Sec. 5.2),
+//   - per-view visibility V_i^k = [I_i^k > tau_k] (Sec. 5.2),
+//   - critical Gaussians: S_i > 0 and w_max above the threshold (Sec. 5.1),
+//   - the blur-split criterion S_i > theta * H * W (Eq. (3)),
+//   - the two-way aggressive clone (Sec. 5.1),
+//   - positional-gradient statistics for the adaptive density control.
+//
+// The threshold never sorts: four 8-bit radix-select passes narrow a 32-bit
+// order-preserving key down to the element(s) the threshold needs.  Each pass
+// reads the values once (coalesced, grid-stride), histograms the current digit
+// in LDS and flushes non-empty bins with one global atomic each; a one-block
+// step kernel per problem then chooses the bin.  Nothing is sorted or
+// compacted, so the cost is ~4-5 streaming reads of the input.
+#include <cmath>
+
+#include "common.hpp"
+
+namespace msplat {
+
+namespace {
+
+constexpr int kSelBins = 256;
+constexpr int kSelPasses = 4;
+
+// Order-preserving map of float bits to unsigned keys (negative values flip
+// all bits, non-negative ones the sign bit).
+__device__ __forceinline__ uint32_t order_key(float v) {
+  uint32_t b = __float_as_uint(v);
+  return b ^ ((b & 0x80000000u) ? 0xFFFFFFFFu : 0x80000000u);
+}
+__device__ __forceinline__ float key_value(uint32_t k) {
+  return __uint_as_float(k ^ ((k & 0x80000000u) ? 0x80000000u : 0xFFFFFFFFu));
+}
+
+// Selection state of one problem (one view, or the single critical set).
+struct SelState {
+  uint32_t prefix[2];   // resolved high key bits of each target
+  int64_t rank[2];      // value mode: rank of each target inside its prefix group (ascending)
+  int64_t m;            // selected count
+  int64_t before_cnt;   // mass mode: selected values above the current group
+  double mass_before;   // mass mode: their sum
+  double target;        // mass mode: keep * S
+  double frac;          // value mode: interpolation weight
+  uint32_t min_above;   // mass mode: smallest key above the final group
+  int32_t need_above;   // mass mode: the threshold is that key's value
+  int32_t pad[2];
+};
+
+struct SelHist {
+  uint32_t cnt[2][kSelBins];
+  double sum[kSelBins];
+};
+
+constexpr size_t kSelStride = 8192;  // bytes per problem (state + histograms)
+static_assert(sizeof(SelState) + sizeof(SelHist) <= kSelStride, "selection workspace stride");
+
+__device__ __forceinline__ SelState* sel_state(uint8_t* ws, int p) { return (SelState*)(ws + (size_t)p * kSelStride); }
+__device__ __forceinline__ SelHist* sel_hist(uint8_t* ws, int p) {
+  return (SelHist*)(ws + (size_t)p * kSelStride + 256);
+}
+
+// Inputs of a threshold problem: values [P][n] with a per-element predicate.
+// Visibility selects I > 0; the critical set selects area > 0.
+struct Source {
+  const float* values;
+  const uint32_t* area;  // NULL: select values > 0
+  int64_t n;
+  __device__ __forceinline__ bool take(int p, int64_t i, float& v) const {
+    const int64_t j = (int64_t)p * n + i;
+    v = values[j];
+    return area ? (area[j] > 0u) : (v > 0.0f);
+  }
+};
+
+__global__ __launch_bounds__(kBlock) void k_sel_init(uint8_t* ws) {
+  uint32_t* w = (uint32_t*)(ws + (size_t)blockIdx.x * kSelStride);
+  for (int i = threadIdx.x; i < (int)(kSelStride / 4); i += kBlock) w[i] = 0u;
+}
+
+// One radix pass: histogram digit `pass` of the keys that match each target's
+// prefix.  Value mode histograms two targets (after pass 0); mass mode one,
+// with the per-bin sum of the values.
+template <bool MASS>
+__global__ __launch_bounds__(kBlock) void k_sel_hist(Source src, uint8_t* ws, int pass) {
+  __shared__ uint32_t s_cnt[2][kSelBins];
+  __shared__ double s_sum[MASS ? kSelBins : 1];
+  const int p = blockIdx.y;
+  const SelState* st = sel_state(ws, p);
+  for (int b = threadIdx.x; b < kSelBins; b += kBlock) {
+    s_cnt[0][b] = 0u;
+    s_cnt[1][b] = 0u;
+    if (MASS) s_sum[b] = 0.0;
+  }
+  const int shift = 24 - 8 * pass;
+  const uint32_t hi_mask = pass == 0 ? 0u : (0xFFFFFFFFu << (32 - 8 * pass));
+  const uint32_t pre0 = st->prefix[0], pre1 = st->prefix[1];
+  const bool two = !MASS && pass > 0;
+  __syncthreads();
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < src.n; i += stride) {
+    float v;
+    if (!src.take(p, i, v)) continue;
+    const uint32_t k = order_key(v);
+    const uint32_t d = (k >> shift) & 0xFFu;
+    if (((k ^ pre0) & hi_mask) == 0u) {
+      atomicAdd(&s_cnt[0][d], 1u);
+      if (MASS) atomicAdd(&s_sum[d], (double)v);
+    }
+    if (two && ((k ^ pre1) & hi_mask) == 0u) atomicAdd(&s_cnt[1][d], 1u);
+  }
+  __syncthreads();
+  SelHist* h = sel_hist(ws, p);
+  for (int b = threadIdx.x; b < kSelBins; b += kBlock) {
+    if (s_cnt[0][b]) {
+      atomicAdd(&h->cnt[0][b], s_cnt[0][b]);
+      if (MASS) atomicAdd(&h->sum[b], s_sum[b]);
+    }
+    if (two && s_cnt[1][b]) atomicAdd(&h->cnt[1][b], s_cnt[1][b]);
+  }
+}
+
+__device__ __forceinline__ uint64_t wave_incl_scan(uint64_t x) {
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const uint64_t y = __shfl_up(x, o, kWave);
+    if ((int)lane_id() >= o) x += y;
+  }
+  return x;
+}
+__device__ __forceinline__ double wave_incl_scan(double x) {
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const double y = __shfl_up(x, o, kWave);
+    if ((int)lane_id() >= o) x += y;
+  }
+  return x;
+}
+__device__ __forceinline__ int wave_min_i(int x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x = min(x, __shfl_xor(x, o, kWave));
+  return x;
+}
+__device__ __forceinline__ int wave_max_i(int x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x = max(x, __shfl_xor(x, o, kWave));
+  return x;
+}
+
+// Ascending walk of one wave over 256 counters: the bin holding rank r and the
+// count of the bins below it.  Lane l owns bins 4l .. 4l + 3.
+__device__ __forceinline__ void rank_walk(const uint32_t* c, int64_t r, int& bin, int64_t& below) {
+  const int l = (int)lane_id();
+  uint64_t cj[4], lt = 0;
+  for (int j = 0; j < 4; ++j) {
+    cj[j] = c[4 * l + j];
+    lt += cj[j];
+  }
+  uint64_t off = wave_incl_scan(lt) - lt;
+  int cand = kSelBins;
+  uint64_t cand_below = 0;
+  for (int j = 0; j < 4; ++j) {
+    if (cand == kSelBins && (int64_t)(off + cj[j]) > r) {
+      cand = 4 * l + j;
+      cand_below = off;
+    }
+    off += cj[j];
+  }
+  bin = wave_min_i(cand);
+  // counts of a group equal the count of the bin it came from, so the rank is
+  // always found; the clamp only keeps the index in range
+  if (bin == kSelBins) bin = kSelBins - 1;
+  below = (int64_t)__shfl(cand_below, bin >> 2, kWave);
+}
+
+// Choose the bin of each target and clear the histograms for the next pass.
+// One block per problem; the histogram is staged in LDS and one wave walks it.
+template <bool MASS>
+__global__ __launch_bounds__(kBlock) void k_sel_step(uint8_t* ws, int pass, double q_or_keep) {
+  __shared__ uint32_t s_cnt[2][kSelBins];
+  __shared__ double s_sum[MASS ? kSelBins : 1];
+  const int p = blockIdx.x;
+  SelState* st = sel_state(ws, p);
+  SelHist* h = sel_hist(ws, p);
+  for (int b = threadIdx.x; b < kSelBins; b += kBlock) {
+    s_cnt[0][b] = h->cnt[0][b];
+    s_cnt[1][b] = h->cnt[1][b];
+    if (MASS) s_sum[b] = h->sum[b];
+  }
+  __syncthreads();
+  uint32_t* w = (uint32_t*)h;
+  for (int i = threadIdx.x; i < (int)(sizeof(SelHist) / 4); i += kBlock) w[i] = 0u;
+  if (threadIdx.x >= kWave) return;
+  const int l = (int)lane_id();
+  const int shift = 24 - 8 * pass;
+  int64_t m = st->m;
+  if (pass == 0) {
+    uint64_t c = 0;
+    for (int j = 0; j < 4; ++j) c += s_cnt[0][4 * l + j];
+    m = (int64_t)__shfl(wave_incl_scan(c), kWave - 1, kWave);
+  }
+  if (MASS) {
+    // descending walk: lane l owns positions 4l .. 4l + 3, i.e. bins 255 - pos
+    uint64_t cj[4], lc = 0;
+    double sj[4], ls = 0.0;
+    for (int j = 0; j < 4; ++j) {
+      const int b = kSelBins - 1 - (4 * l + j);
+      cj[j] = s_cnt[0][b];
+      sj[j] = s_sum[b];
+      lc += cj[j];
+      ls += sj[j];
+    }
+    const double sincl = wave_incl_scan(ls);
+    double soff = sincl - ls;
+    uint64_t coff = wave_incl_scan(lc) - lc;
+    double target = st->target;
+    if (pass == 0) target = q_or_keep * __shfl(sincl, kWave - 1, kWave);
+    const double before = st->mass_before;
+    int first = kSelBins, last = -1;
+    double f_sum = 0.0, l_sum = 0.0;
+    uint64_t f_cnt = 0, l_cnt = 0;
+    for (int j = 0; j < 4; ++j) {
+      if (cj[j] != 0) {
+        if (first == kSelBins && before + (soff + sj[j]) >= target) {
+          first = 4 * l + j;
+          f_sum = soff;
+          f_cnt = coff;
+        }
+        last = 4 * l + j;
+        l_sum = soff;
+        l_cnt = coff;
+      }
+      soff += sj[j];
+      coff += cj[j];
+    }
+    int pos = wave_min_i(first);
+    double above_sum;
+    uint64_t above_cnt;
+    if (pos < kSelBins) {
+      above_sum = __shfl(f_sum, pos >> 2, kWave);
+      above_cnt = __shfl(f_cnt, pos >> 2, kWave);
+    } else {
+      // rounding of the bin sums left the target above every prefix: the smallest bin
+      pos = wave_max_i(last);
+      above_sum = __shfl(l_sum, pos >> 2, kWave);
+      above_cnt = __shfl(l_cnt, pos >> 2, kWave);
+    }
+    if (l == 0) {
+      if (pass == 0) {
+        st->m = m;
+        st->target = target;
+      }
+      if (m > 0) {
+        st->mass_before = before + above_sum;
+        st->before_cnt += (int64_t)above_cnt;
+        st->prefix[0] |= (uint32_t)(kSelBins - 1 - pos) << shift;
+      }
+    }
+  } else {
+    int64_t rank[2] = {st->rank[0], st->rank[1]};
+    double frac = 0.0;
+    if (pass == 0 && m > 0) {
+      // linear interpolation between order statistics lo and lo + 1
+      const double hpos = (double)(m - 1) * q_or_keep;
+      const double lo = floor(hpos);
+      int64_t ilo = (int64_t)lo;
+      if (ilo > m - 1) ilo = m - 1;
+      frac = hpos - lo;
+      rank[0] = ilo;
+      rank[1] = ilo + 1 < m ? ilo + 1 : ilo;
+    }
+    int bins[2] = {0, 0};
+    for (int t = 0; t < 2; ++t) {
+      int64_t below = 0;
+      if (m > 0) rank_walk(s_cnt[pass == 0 ? 0 : t], rank[t], bins[t], below);
+      rank[t] -= below;
+    }
+    if (l == 0) {
+      if (pass == 0) {
+        st->m = m;
+        st->frac = frac;
+      }
+      if (m > 0) {
+        for (int t = 0; t < 2; ++t) {
+          st->rank[t] = rank[t];
+          st->prefix[t] |= (uint32_t)bins[t] << shift;
+        }
+      }
+    }
+  }
+}
+
+// Mass mode, after the last pass: the final group holds equal values x.  The
+// first prefix sum reaching the target lies in the group; if it is the group's
+// first element and the previous prefix sum is at least as close, the
+// threshold is the smallest selected value above x.
+__global__ __launch_bounds__(kBlock) void k_sel_group(uint8_t* ws) {
+  SelState* st = sel_state(ws, blockIdx.x);
+  if (threadIdx.x != 0 || st->m == 0) return;
+  const double x = (double)key_value(st->prefix[0]);
+  const double need = st->target - st->mass_before;
+  // the first j >= 1 with mass_before + j x >= target
+  const bool first = !(x > 0.0) || need <= x;
+  st->need_above = 0;
+  if (first && st->before_cnt > 0) {
+    const double d_hi = st->mass_before + x - st->target;
+    const double d_lo = st->target - st->mass_before;
+    if (d_lo <= d_hi) st->need_above = 1;
+  }
+  st->min_above = 0xFFFFFFFFu;
+}
+
+__global__ __launch_bounds__(kBlock) void k_sel_min_above(Source src, uint8_t* ws) {
+  __shared__ uint32_t s_min;
+  const int p = blockIdx.y;
+  SelState* st = sel_state(ws, p);
+  if (!st->need_above) return;  // uniform per block
+  if (threadIdx.x == 0) s_min = 0xFFFFFFFFu;
+  __syncthreads();
+  const uint32_t key0 = st->prefix[0];
+  uint32_t best = 0xFFFFFFFFu;
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < src.n; i += stride) {
+    float v;
+    if (!src.take(p, i, v)) continue;
+    const uint32_t k = order_key(v);
+    if (k > key0 && k < best) best = k;
+  }
+  atomicMin(&s_min, best);
+  __syncthreads();
+  if (threadIdx.x == 0 && s_min != 0xFFFFFFFFu) atomicMin(&st->min_above, s_min);
+}
+
+template <bool MASS>
+__global__ __launch_bounds__(kWave) void k_sel_finish(uint8_t* ws, double* tau) {
+  const int p = blockIdx.x;
+  const SelState* st = sel_state(ws, p);
+  if (threadIdx.x != 0) return;
+  double t;
+  if (st->m == 0) {
+    t = __builtin_nan("");
+  } else if (MASS) {
+    t = (double)key_value(st->need_above ? st->min_above : st->prefix[0]);
+  } else {
+    const double a = (double)key_value(st->prefix[0]);
+    const double b = (double)key_value(st->prefix[1]);
+    // a + frac (b - a) with separate roundings (no fused multiply-add)
+    t = __dadd_rn(a, __dmul_rn(st->frac, __dsub_rn(b, a)));
+  }
+  tau[p] = t;
+}
+
+__global__ __launch_bounds__(kBlock) void k_sel_apply(Source src, const double* __restrict__ tau,
+                                                      uint8_t* __restrict__ out) {
+  const int p = blockIdx.y;
+  const double t = tau[p];
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < src.n; i += stride) {
+    float v;
+    const bool s = src.take(p, i, v);
+    out[(int64_t)p * src.n + i] = (s && (double)v > t) ? 1 : 0;
+  }
+}
+
+int32_t sel_blocks(int64_t n, int P) {
+  int64_t b = (n + (int64_t)kBlock * 16 - 1) / ((int64_t)kBlock * 16);
+  const int64_t cap = P > 1 ? 256 : 1024;
+  if (b > cap) b = cap;
+  return (int32_t)(b < 1 ? 1 : b);
+}
+
+int32_t launch_threshold(const Source& src, int P, double keep, int32_t mode, uint8_t* out, double* tau, void* ws,
+                         size_t ws_bytes, hipStream_t st) {
+  if (!(keep >= 0.0 && keep <= 1.0)) { set_error("keep must lie in [0, 1]"); return GS_ERR_SHAPE; }
+  if (mode != GS_THRESHOLD_VALUE && mode != GS_THRESHOLD_MASS) {
+    set_error("unknown threshold mode");
+    return GS_ERR_UNSUPPORTED;
+  }
+  if (!ws || !tau || !out) { set_error("NULL workspace, tau or output"); return GS_ERR_NULL; }
+  if (ws_bytes < gs_select_workspace_size(P)) { set_error("selection workspace too small"); return GS_ERR_CAPACITY; }
+  uint8_t* w = (uint8_t*)ws;
+  const bool mass = mode == GS_THRESHOLD_MASS;
+  const double param = mass ? keep : 1.0 - keep;
+  const dim3 grid((unsigned)sel_blocks(src.n, P), (unsigned)P);
+  hipLaunchKernelGGL(k_sel_init, dim3(P), dim3(kBlock), 0, st, w);
+  MS_CHECK_LAUNCH("sel_init");
+  for (int pass = 0; pass < kSelPasses; ++pass) {
+    if (mass) {
+      hipLaunchKernelGGL(k_sel_hist<true>, grid, dim3(kBlock), 0, st, src, w, pass);
+      hipLaunchKernelGGL(k_sel_step<true>, dim3(P), dim3(kBlock), 0, st, w, pass, param);
+    } else {
+      hipLaunchKernelGGL(k_sel_hist<false>, grid, dim3(kBlock), 0, st, src, w, pass);
+      hipLaunchKernelGGL(k_sel_step<false>, dim3(P), dim3(kBlock), 0, st, w, pass, param);
+    }
+    MS_CHECK_LAUNCH("sel_pass");
+  }
+  if (mass) {
+    hipLaunchKernelGGL(k_sel_group, dim3(P), dim3(kBlock), 0, st, w);
+    hipLaunchKernelGGL(k_sel_min_above, grid, dim3(kBlock), 0, st, src, w);
+    hipLaunchKernelGGL(k_sel_finish<true>, dim3(P), dim3(kWave), 0, st, w, tau);
+  } else {
+    hipLaunchKernelGGL(k_sel_finish<false>, dim3(P), dim3(kWave), 0, st, w, tau);
+  }
+  MS_CHECK_LAUNCH("sel_finish");
+  hipLaunchKernelGGL(k_sel_apply, grid, dim3(kBlock), 0, st, src, tau, out);
+  MS_CHECK_LAUNCH("sel_apply");
+  return GS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// blur split, positional-gradient statistics
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_blur_split(const uint32_t* __restrict__ area, int64_t n, double thr,
+                                                       uint8_t* __restrict__ split) {
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride)
+    split[i] = (double)area[i] > thr ? 1 : 0;
+}
+
+// For each Gaussian: sum over views where it touched a tile of the norm of
+// d loss / d (screen mean), scaled to the [-1, 1] image coordinates, and the
+// number of such views.
+__global__ __launch_bounds__(kBlock) void k_grad_stats(const int32_t* __restrict__ bin,
+                                                       const float* __restrict__ grad2d, int32_t V, int64_t n,
+                                                       ViewSet vs, float* __restrict__ norm_sum,
+                                                       uint32_t* __restrict__ count) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  float acc = 0.0f;
+  uint32_t c = 0u;
+  for (int32_t k = 0; k < V; ++k) {
+    const int64_t r = (int64_t)k * n + i;
+    if (bin[r * 4 + 3] <= 0) continue;
+    const float gx = grad2d[r * kG2d + 0] * (0.5f * (float)vs.v[k].width);
+    const float gy = grad2d[r * kG2d + 1] * (0.5f * (float)vs.v[k].height);
+    acc += sqrtf(gx * gx + gy * gy);
+    c += 1u;
+  }
+  norm_sum[i] += acc;
+  count[i] += c;
+}
+
+// ---------------------------------------------------------------------------
+// two-way clone: exclusive scan of the selection, then one pass that writes
+// every original row and the copies at n + rank
+// ---------------------------------------------------------------------------
+constexpr int kCloneItems = 4096;  // selection flags per scan block (16 per thread)
+
+__global__ __launch_bounds__(kBlock) void k_clone_count(const uint8_t* __restrict__ select, int64_t n,
+                                                        uint32_t* __restrict__ block_cnt) {
+  __shared__ uint32_t s_part[kBlock / kWave];
+  const int64_t base = (int64_t)blockIdx.x * kCloneItems;
+  uint32_t c = 0;
+  for (int j = threadIdx.x; j < kCloneItems; j += kBlock) {
+    const int64_t i = base + j;
+    c += (i < n && select[i]) ? 1u : 0u;
+  }
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, kWave);
+  if (lane_id() == 0) s_part[threadIdx.x / kWave] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) block_cnt[blockIdx.x] = s_part[0] + s_part[1] + s_part[2] + s_part[3];
+}
+
+// Single block: exclusive scan of the block counts (in place), total to *count.
+__global__ __launch_bounds__(1024) void k_clone_scan(uint32_t* __restrict__ block_cnt, int32_t nb,
+                                                     int64_t* __restrict__ count) {
+  __shared__ uint32_t s_wave[1024 / kWave];
+  __shared__ uint32_t s_carry;
+  if (threadIdx.x == 0) s_carry = 0u;
+  __syncthreads();
+  for (int32_t base = 0; base < nb; base += 1024) {
+    const int32_t i = base + (int32_t)threadIdx.x;
+    const uint32_t x = i < nb ? block_cnt[i] : 0u;
+    uint32_t incl = x;
+    for (int o = 1; o < kWave; o <<= 1) {
+      const uint32_t y = __shfl_up(incl, o, kWave);
+      if ((int)lane_id() >= o) incl += y;
+    }
+    if (lane_id() == kWave - 1) s_wave[threadIdx.x / kWave] = incl;
+    __syncthreads();
+    uint32_t wave_off = 0, total = 0;
+    for (int w = 0; w < 1024 / kWave; ++w) {
+      const uint32_t s = s_wave[w];
+      wave_off += (w < (int)(threadIdx.x / kWave)) ? s : 0u;
+      total += s;
+    }
+    const uint32_t carry = s_carry;
+    if (i < nb) block_cnt[i] = carry + wave_off + incl - x;
+    __syncthreads();
+    if (threadIdx.x == 0) s_carry = carry + total;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *count = (int64_t)s_carry;
+}
+
+struct ClonePlanes {
+  const float* means;
+  const float* scales;
+  const float* quats;
+  const float* opac;
+  const float* sh;
+  int64_t n;
+};
+struct CloneOut {
+  float* means;
+  float* scales;
+  float* quats;
+  float* opac;
+  float* sh;
+  int64_t cap;
+};
+
+__global__ __launch_bounds__(kBlock) void k_clone_write(ClonePlanes in, const uint8_t* __restrict__ select,
+                                                        const uint32_t* __restrict__ block_off, CloneOut out) {
+  __shared__ uint32_t s_wave[kBlock / kWave];
+  __shared__ uint32_t s_carry;
+  const int64_t base = (int64_t)blockIdx.x * kCloneItems;
+  if (threadIdx.x == 0) s_carry = block_off[blockIdx.x];
+  __syncthreads();
+  for (int j0 = 0; j0 < kCloneItems; j0 += kBlock) {
+    const int64_t i = base + j0 + threadIdx.x;
+    const bool sel = i < in.n && select[i];
+    // rank of this row among the selected rows of the chunk
+    const uint64_t bal = __ballot(sel);
+    const uint32_t below = __popcll(bal & ((1ull << lane_id()) - 1ull));
+    if (lane_id() == 0) s_wave[threadIdx.x / kWave] = (uint32_t)__popcll(bal);
+    __syncthreads();
+    uint32_t off = s_carry;
+    for (int w = 0; w < (int)(threadIdx.x / kWave); ++w) off += s_wave[w];
+    const uint32_t chunk = s_wave[0] + s_wave[1] + s_wave[2] + s_wave[3];
+    if (i < in.n) {
+      float a = in.opac[i];
+      double fd = 1.0;
+      if (sel) {
+        // Sec. 5.1: a' = 1 - sqrt(1 - a); Sigma' = a^2 (2 a' - a'^2 / sqrt 2)^-2 Sigma,
+        // so every scale is multiplied by a / (2 a' - a'^2 / sqrt 2); a -> 0 has limit 1.
+        const double ad = (double)a;
+        const double an = 1.0 - sqrt(1.0 - ad);
+        fd = ad > 0.0 ? ad / (2.0 * an - an * an / sqrt(2.0)) : 1.0;
+        a = (float)an;
+      }
+      const int64_t dst[2] = {i, sel ? in.n + (int64_t)(off + below) : -1};
+      for (int c = 0; c < 2; ++c) {
+        const int64_t d = dst[c];
+        if (d < 0 || d >= out.cap) continue;
+        for (int k = 0; k < 3; ++k) out.means[k * out.cap + d] = in.means[k * in.n + i];
+        for (int k = 0; k < 3; ++k) {
+          const float s = in.scales[k * in.n + i];
+          out.scales[k * out.cap + d] = sel ? (float)((double)s * fd) : s;
+        }
+        for (int k = 0; k < 4; ++k) out.quats[k * out.cap + d] = in.quats[k * in.n + i];
+        out.opac[d] = a;
+        for (int k = 0; k < 48; ++k) out.sh[k * out.cap + d] = in.sh[k * in.n + i];
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) s_carry += chunk;
+    __syncthreads();
+  }
+}
+
+}  // namespace
+
+}  // namespace msplat
+
+using namespace msplat;
+
+extern "C" {
+
+size_t gs_select_workspace_size(int32_t problems) {
+  if (problems < 1) problems = 1;
+  return (size_t)problems * kSelStride;
+}
+
+int32_t gs_visibility(const float* importance, int32_t V, int64_t n, double keep, int32_t mode, uint8_t* visible,
+                      double* tau, void* ws, size_t ws_bytes, void* stream) {
+  if (V < 1 || V > GS_MAX_VIEWS) { set_error("V out of range 1..GS_MAX_VIEWS"); return GS_ERR_SHAPE; }
+  if (n < 0 || n >= (int64_t(1) << 31)) { set_error("n out of range"); return GS_ERR_SHAPE; }
+  if (n > 0 && !importance) { set_error("importance is NULL"); return GS_ERR_NULL; }
+  Source src{importance, nullptr, n};
+  return launch_threshold(src, V, keep, mode, visible, tau, ws, ws_bytes, (hipStream_t)stream);
+}
+
+int32_t gs_critical(const uint32_t* area, const float* wmax, int64_t n, double keep, int32_t mode, uint8_t* critical,
+                    double* tau, void* ws, size_t ws_bytes, void* stream) {
+  if (n < 0 || n >= (int64_t(1) << 31)) { set_error("n out of range"); return GS_ERR_SHAPE; }
+  if (n > 0 && (!area || !wmax)) { set_error("area or wmax is NULL"); return GS_ERR_NULL; }
+  Source src{wmax, area, n};
+  return launch_threshold(src, 1, keep, mode, critical, tau, ws, ws_bytes, (hipStream_t)stream);
+}
+
+int32_t gs_blur_split(const uint32_t* area, int64_t n, double theta, int32_t height, int32_t width, uint8_t* split,
+                      void* stream) {
+  if (n < 0) { set_error("n < 0"); return GS_ERR_SHAPE; }
+  if (height <= 0 || width <= 0) { set_error("height and width must be positive"); return GS_ERR_SHAPE; }
+  if (!(theta >= 0.0)) { set_error("theta must be >= 0"); return GS_ERR_SHAPE; }
+  if (n == 0) return GS_OK;
+  if (!area || !split) { set_error("NULL buffer"); return GS_ERR_NULL; }
+  int64_t blocks = (n + kBlock - 1) / kBlock;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_blur_split, dim3((unsigned)blocks), dim3(kBlock), 0, (hipStream_t)stream, area, n,
+                     theta * (double)height * (double)width, split);
+  MS_CHECK_LAUNCH("blur_split");
+  return GS_OK;
+}
+
+int32_t gs_grad_stats(const gs_projected_t* proj, const float* grad2d, const gs_camera_t* cams, int32_t V, int64_t n,
+                      float* norm_sum, uint32_t* count, void* stream) {
+  ViewSet vs;
+  int32_t s = build_views(cams, V, &vs);
+  if (s != GS_OK) return s;
+  if ((s = check_records(V, n)) != GS_OK) return s;
+  if (n == 0) return GS_OK;
+  if (!proj || !proj->bin || !grad2d || !norm_sum || !count) { set_error("NULL buffer"); return GS_ERR_NULL; }
+  hipLaunchKernelGGL(k_grad_stats, dim3((unsigned)grid_1d(n)), dim3(kBlock), 0, (hipStream_t)stream, proj->bin,
+                     grad2d, V, n, vs, norm_sum, count);
+  MS_CHECK_LAUNCH("grad_stats");
+  return GS_OK;
+}
+
+size_t gs_clone_workspace_size(int64_t n) {
+  const int64_t nb = n > 0 ? (n + kCloneItems - 1) / kCloneItems : 1;
+  return (size_t)((nb * 4 + 255) / 256 * 256);
+}
+
+int32_t gs_clone(const gs_scene_t* in, const uint8_t* select, const gs_scene_out_t* out, int64_t* count, void* ws,
+                 size_t ws_bytes, void* stream) {
+  int32_t s = check_scene(in);
+  if (s != GS_OK) return s;
+  if (!out) { set_error("out is NULL"); return GS_ERR_NULL; }
+  if (out->capacity < in->n || out->capacity >= (int64_t(1) << 31)) {
+    set_error("output capacity below the input count or beyond 2^31");
+    return GS_ERR_CAPACITY;
+  }
+  if (in->n > 0 && (!out->means || !out->scales || !out->quats || !out->opacity || !out->sh)) {
+    set_error("output plane is NULL");
+    return GS_ERR_NULL;
+  }
+  if (!count) { set_error("count is NULL"); return GS_ERR_NULL; }
+  if (in->n > 0 && !select) { set_error("select is NULL"); return GS_ERR_NULL; }
+  if (ws_bytes < gs_clone_workspace_size(in->n) || !ws) { set_error("clone workspace too small"); return GS_ERR_CAPACITY; }
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t nb64 = in->n > 0 ? (in->n + kCloneItems - 1) / kCloneItems : 0;
+  const int32_t nb = (int32_t)nb64;
+  uint32_t* block_off = (uint32_t*)ws;
+  if (nb > 0) {
+    hipLaunchKernelGGL(k_clone_count, dim3(nb), dim3(kBlock), 0, st, select, in->n, block_off);
+    MS_CHECK_LAUNCH("clone_count");
+  }
+  hipLaunchKernelGGL(k_clone_scan, dim3(1), dim3(1024), 0, st, block_off, nb, count);
+  MS_CHECK_LAUNCH("clone_scan");
+  if (nb > 0) {
+    ClonePlanes ip{in->means, in->scales, in->quats, in->opacity, in->sh, in->n};
+    CloneOut op{out->means, out->scales, out->quats, out->opacity, out->sh, out->capacity};
+    hipLaunchKernelGGL(k_clone_write, dim3(nb), dim3(kBlock), 0, st, ip, select, block_off, op);
+    MS_CHECK_LAUNCH("clone_write");
+  }
+  return GS_OK;
+}
+
+}  // extern "C"

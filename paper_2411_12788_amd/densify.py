@@ -1,0 +1,80 @@
+"""Python binding of the culling and densification criteria (Sec. 5.1, Sec. 5.2,
+Eq. (3)): argument marshalling only, every step runs in libmsplat.so."""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Tuple
+
+import torch
+
+from . import _lib as L
+from .raster import DeviceScene, Projected, _ptr, _stream, cameras
+
+KEEP_QUANTILE = 0.99   # Sec. 5.1 and Sec. 5.2
+THETA_BLUR = 2e-4      # Eq. (3)
+THRESHOLD_VALUE, THRESHOLD_MASS = L.GS_THRESHOLD_VALUE, L.GS_THRESHOLD_MASS
+
+
+def _select_ws(problems: int, device) -> torch.Tensor:
+    nbytes = L.lib().gs_select_workspace_size(problems)
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+def visibility(importance: torch.Tensor, keep: float = KEEP_QUANTILE, mode: int = THRESHOLD_MASS,
+               ws: Optional[torch.Tensor] = None, stream=None) -> Tuple[torch.Tensor, torch.Tensor]:
+    """importance [V, n] float32 -> (visible [V, n] uint8, tau [V] float64)."""
+    imp = importance if importance.dim() == 2 else importance.view(1, -1)
+    assert imp.is_contiguous() and imp.dtype == torch.float32
+    V, n = imp.shape
+    visible = torch.empty((V, n), dtype=torch.uint8, device=imp.device)
+    tau = torch.empty(V, dtype=torch.float64, device=imp.device)
+    ws = _select_ws(V, imp.device) if ws is None else ws
+    L.check(L.lib().gs_visibility(_ptr(imp), V, n, keep, mode, _ptr(visible), _ptr(tau), _ptr(ws), ws.numel(),
+                                  _stream(stream)), "gs_visibility")
+    return visible, tau
+
+
+def critical(area: torch.Tensor, wmax: torch.Tensor, keep: float = KEEP_QUANTILE, mode: int = THRESHOLD_MASS,
+             ws: Optional[torch.Tensor] = None, stream=None) -> Tuple[torch.Tensor, torch.Tensor]:
+    """area [n] int32/uint32, wmax [n] float32 -> (critical [n] uint8, tau [1] float64)."""
+    assert area.is_contiguous() and area.element_size() == 4 and wmax.dtype == torch.float32
+    n = wmax.numel()
+    out = torch.empty(n, dtype=torch.uint8, device=wmax.device)
+    tau = torch.empty(1, dtype=torch.float64, device=wmax.device)
+    ws = _select_ws(1, wmax.device) if ws is None else ws
+    L.check(L.lib().gs_critical(_ptr(area), _ptr(wmax), n, keep, mode, _ptr(out), _ptr(tau), _ptr(ws), ws.numel(),
+                                _stream(stream)), "gs_critical")
+    return out, tau
+
+
+def blur_split(area: torch.Tensor, height: int, width: int, theta: float = THETA_BLUR, stream=None) -> torch.Tensor:
+    n = area.numel()
+    out = torch.empty(n, dtype=torch.uint8, device=area.device)
+    L.check(L.lib().gs_blur_split(_ptr(area), n, theta, height, width, _ptr(out), _stream(stream)), "gs_blur_split")
+    return out
+
+
+def grad_stats(proj: Projected, grad2d: torch.Tensor, cams, n: int, norm_sum: torch.Tensor, count: torch.Tensor,
+               stream=None) -> None:
+    cc = cameras(cams)
+    L.check(L.lib().gs_grad_stats(ctypes.byref(proj.c()), _ptr(grad2d), cc, len(cc), n, _ptr(norm_sum), _ptr(count),
+                                  _stream(stream)), "gs_grad_stats")
+
+
+def clone(scene: DeviceScene, select: torch.Tensor, capacity: Optional[int] = None,
+          stream=None) -> Tuple[DeviceScene, torch.Tensor]:
+    """Two-way clone of the selected rows (Sec. 5.1).  With capacity None the
+    selected count is read back first (one synchronisation) to size the output."""
+    n = scene.n
+    dev = scene.opacity.device
+    if capacity is None:
+        capacity = n + int(select.sum().item())
+    out = DeviceScene(torch.empty((3, capacity), device=dev), torch.empty((3, capacity), device=dev),
+                      torch.empty((4, capacity), device=dev), torch.empty(capacity, device=dev),
+                      torch.empty((16, 3, capacity), device=dev), scene.sh_degree)
+    so = L.SceneOut(_ptr(out.means), _ptr(out.scales), _ptr(out.quats), _ptr(out.opacity), _ptr(out.sh), capacity)
+    count = torch.empty(1, dtype=torch.int64, device=dev)
+    ws = torch.empty(L.lib().gs_clone_workspace_size(n), dtype=torch.uint8, device=dev)
+    L.check(L.lib().gs_clone(ctypes.byref(scene.c()), _ptr(select), ctypes.byref(so), _ptr(count), _ptr(ws),
+                             ws.numel(), _stream(stream)), "gs_clone")
+    return out, count

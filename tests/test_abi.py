@@ -78,3 +78,31 @@ def test_argument_errors_on_host(L):
     assert lib.gs_sort_pairs(None, None, 0, 8, None, 0, None) == L.GS_OK
     assert lib.gs_fill_u32(None, 0, 0, None) == L.GS_OK
     assert lib.gs_bin_count_workspace_size(10 ** 6) > 0 and lib.gs_bin_sort_workspace_size(10 ** 6) > 12 * 10 ** 6
+
+
+def test_criteria_argument_errors_on_host(L):
+    """Checks that happen before any launch (fake non-NULL pointers are never touched)."""
+    lib = L.lib()
+    fake = ctypes.c_void_p(0x1000)
+    ws = lib.gs_select_workspace_size(2)
+    assert ws >= 2 * 4096
+    assert lib.gs_visibility(fake, 2, 10, 1.5, 0, fake, fake, fake, ws, None) == L.GS_ERR_SHAPE
+    assert lib.gs_visibility(fake, 2, 10, -0.1, 0, fake, fake, fake, ws, None) == L.GS_ERR_SHAPE
+    assert lib.gs_visibility(fake, 2, 10, 0.99, 7, fake, fake, fake, ws, None) == L.GS_ERR_UNSUPPORTED
+    assert lib.gs_visibility(fake, 2, 10, 0.99, 1, fake, fake, fake, ws - 1, None) == L.GS_ERR_CAPACITY
+    assert lib.gs_visibility(fake, 0, 10, 0.99, 1, fake, fake, fake, ws, None) == L.GS_ERR_SHAPE
+    assert lib.gs_visibility(fake, 33, 10, 0.99, 1, fake, fake, fake, ws, None) == L.GS_ERR_SHAPE
+    assert lib.gs_visibility(None, 2, 10, 0.99, 1, fake, fake, fake, ws, None) == L.GS_ERR_NULL
+    assert lib.gs_critical(fake, None, 10, 0.99, 1, fake, fake, fake, ws, None) == L.GS_ERR_NULL
+    assert lib.gs_critical(fake, fake, -1, 0.99, 1, fake, fake, fake, ws, None) == L.GS_ERR_SHAPE
+    assert lib.gs_blur_split(fake, 10, 2e-4, 0, 10, fake, None) == L.GS_ERR_SHAPE
+    assert lib.gs_blur_split(fake, 10, -1.0, 10, 10, fake, None) == L.GS_ERR_SHAPE
+    assert lib.gs_blur_split(fake, 0, 2e-4, 10, 10, None, None) == L.GS_OK          # nothing to do
+    sc = L.Scene(fake, fake, fake, fake, fake, 100, 3)
+    out = L.SceneOut(fake, fake, fake, fake, fake, 99)
+    cw = lib.gs_clone_workspace_size(100)
+    assert lib.gs_clone(ctypes.byref(sc), fake, ctypes.byref(out), fake, fake, cw, None) == L.GS_ERR_CAPACITY
+    out.capacity = 200
+    assert lib.gs_clone(ctypes.byref(sc), fake, ctypes.byref(out), None, fake, cw, None) == L.GS_ERR_NULL
+    assert lib.gs_clone(ctypes.byref(sc), fake, ctypes.byref(out), fake, fake, 0, None) == L.GS_ERR_CAPACITY
+    assert lib.gs_clone(ctypes.byref(sc), fake, None, fake, fake, cw, None) == L.GS_ERR_NULL

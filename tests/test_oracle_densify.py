@@ -215,3 +215,19 @@ def test_clone_layout_and_copies():
     assert (out.opacity[:50][keep] == p.opacity[keep]).all()
     empty = oracle.clone(p, np.zeros(50, np.uint8))
     assert empty.n == 50 and (empty.scales == p.scales).all()
+
+
+def test_grad_stats_closed_form():
+    """A 3-4-5 gradient in image coordinates; views where the record touches no tile are skipped."""
+    V, n = 3, 2
+    tiles = np.array([[1, 0], [2, 5], [0, 1]])
+    g = np.zeros((V * n, 9))
+    W, H = np.array([100, 200, 50]), np.array([80, 60, 40])
+    for k in range(V):
+        for i in range(n):
+            g[k * n + i, 0] = 3.0 / (0.5 * W[k]) * (i + 1)
+            g[k * n + i, 1] = -4.0 / (0.5 * H[k]) * (i + 1)
+            g[k * n + i, 2:] = 7.0                      # other fields ignored
+    ns, cnt = oracle.grad_stats(tiles, g, W, H)
+    assert cnt.tolist() == [2, 2]
+    assert ns == pytest.approx([2 * 5.0, 2 * 10.0], rel=1e-14)
