@@ -23,6 +23,10 @@ other than itself live in ``tests/test_oracle_*.py``:
   quantile, visibility, critical, blur_split, clone
                     Sec. 5.1, Sec. 5.2, Eq. (3)             pinned: numpy quantile,
                     two-clone opacity identity, small-opacity limit, paper constants
+  depth_points      Sec. 4.1 (reprojection of the depth map)  pinned: projection round trip
+  sample            Sec. 4.2 (intersection preserving, primitive sampling)
+                                                            pinned: exact inclusion probabilities
+                                                            of sequential weighted draws
 """
 from __future__ import annotations
 
@@ -59,6 +63,8 @@ def lib():
         _lib.orc_mass_threshold.restype = ctypes.c_double
         _lib.orc_critical.restype = ctypes.c_double
         _lib.orc_clone.restype = ctypes.c_int64
+        _lib.orc_depth_points.restype = ctypes.c_int64
+        _lib.orc_sample.restype = ctypes.c_int64
     return _lib
 
 
@@ -409,3 +415,31 @@ def grad_stats(tiles, grad2d, widths, heights):
     cnt = np.zeros(max(n, 1), dtype=np.int64)
     lib().orc_grad_stats(ctypes.c_int32(V), ctypes.c_int64(n), _p(t), _p(g), _p(w), _p(h), _p(ns), _p(cnt))
     return ns[:n], cnt[:n]
+
+
+def depth_points(cam, depth, imax, hit, target, u, rate: float, require_hit: bool = True):
+    """(points[m, 3], colors[m, 3]) lifted from one view's depth map (Sec. 4.1)."""
+    P = int(cam.width) * int(cam.height)
+    d = _d(depth).reshape(P)
+    im = np.ascontiguousarray(imax, dtype=np.int32).reshape(P)
+    h = np.ascontiguousarray(hit, dtype=np.int32).reshape(P)
+    tg = _d(target).reshape(3, P)
+    uu = _d(u).reshape(P)
+    pts = np.zeros((max(P, 1), 3))
+    col = np.zeros((max(P, 1), 3))
+    c = ocam(cam)
+    m = lib().orc_depth_points(ctypes.byref(c), _p(d), _p(im), _p(h), _p(tg), _p(uu), ctypes.c_double(rate),
+                               ctypes.c_int(1 if require_hit else 0), _p(pts), _p(col))
+    return pts[:m], col[:m]
+
+
+def sample(importance, expo, k: int, area=None):
+    """selected[n] uint8: k Gaussians drawn without replacement with probability
+    proportional to importance, within area > 0 when area is given (Sec. 4.2)."""
+    imp = np.ascontiguousarray(importance, dtype=np.float32)
+    e = np.ascontiguousarray(expo, dtype=np.float32)
+    a = None if area is None else np.ascontiguousarray(area, dtype=np.uint32)
+    n = imp.shape[0]
+    out = np.zeros(max(n, 1), dtype=np.uint8)
+    lib().orc_sample(ctypes.c_int64(n), _p(imp), None if a is None else _p(a), _p(e), ctypes.c_int64(k), _p(out))
+    return out[:n]

@@ -903,3 +903,70 @@ void orc_grad_stats(int32_t V, int64_t n, const int32_t* tiles, const double* gr
       count[i] += 1;
     }
 }
+
+/* Depth reinitialisation points (Sec. 4.1): every pixel whose rendered index
+ * is valid (imax >= 0; with require_hit also hit != 0) and whose uniform draw
+ * u < rate is lifted to the world point R^T (d * ((x - cx) / fx, (y - cy) / fy, 1) - t)
+ * at the pixel centre (x, y) = (px + 0.5, py + 0.5), d the rendered camera
+ * depth, and takes the target image's colour there.  Points are written in
+ * pixel order (row-major); returns their count. */
+int64_t orc_depth_points(const ocam_t* cam, const double* depth, const int32_t* imax, const int32_t* hit,
+                         const double* target, const double* u, double rate, int require_hit, double* points,
+                         double* colors) {
+  int64_t P = (int64_t)cam->width * cam->height, c = 0;
+  for (int64_t p = 0; p < P; p++) {
+    if (imax[p] < 0 || (require_hit && !hit[p]) || !(u[p] < rate)) continue;
+    double x = (double)(p % cam->width) + 0.5, y = (double)(p / cam->width) + 0.5;
+    double d = depth[p];
+    double xc[3] = {d * (x - cam->cx) / cam->fx, d * (y - cam->cy) / cam->fy, d};
+    for (int a = 0; a < 3; a++) {
+      /* (R^T (xc - t))_a = sum_r R[r][a] (xc_r - t_r) */
+      double s = 0;
+      for (int r = 0; r < 3; r++) s += cam->R[r * 3 + a] * (xc[r] - cam->t[r]);
+      points[c * 3 + a] = s;
+    }
+    for (int ch = 0; ch < 3; ch++) colors[c * 3 + ch] = target[ch * P + p];
+    c++;
+  }
+  return c;
+}
+
+/* Primitive sampling (Sec. 4.2) restricted to the intersected set (Sec. 4.2,
+ * intersection preserving: area S_i > 0 in some view, all when area == NULL):
+ * k Gaussians drawn without replacement with probability proportional to I_i.
+ * Drawn as the k smallest keys E_i / I_i (E_i ~ Exp(1) given; the
+ * exponential-key form of weighted sampling without replacement, Efraimidis
+ * and Spirakis 2006), key computed in float32, ties broken by lower index;
+ * Gaussians with I_i <= 0 are never drawn.  Returns the number drawn. */
+typedef struct {
+  float key;
+  int64_t idx;
+} keyidx_t;
+
+static int cmp_keyidx(const void* a, const void* b) {
+  const keyidx_t* x = (const keyidx_t*)a;
+  const keyidx_t* y = (const keyidx_t*)b;
+  if (x->key != y->key) return x->key < y->key ? -1 : 1;
+  return x->idx < y->idx ? -1 : (x->idx > y->idx ? 1 : 0);
+}
+
+int64_t orc_sample(int64_t n, const float* importance, const uint32_t* area, const float* expo, int64_t k,
+                   uint8_t* selected) {
+  int64_t m = 0;
+  keyidx_t* c = (keyidx_t*)malloc(sizeof(keyidx_t) * (n > 0 ? n : 1));
+  for (int64_t i = 0; i < n; i++) {
+    selected[i] = 0;
+    if (importance[i] > 0.0f && (!area || area[i] > 0)) {
+      volatile float q = expo[i] / importance[i];
+      c[m].key = q;
+      c[m].idx = i;
+      m++;
+    }
+  }
+  qsort(c, (size_t)m, sizeof(keyidx_t), cmp_keyidx);
+  int64_t take = k < m ? k : m;
+  if (take < 0) take = 0;
+  for (int64_t t = 0; t < take; t++) selected[c[t].idx] = 1;
+  free(c);
+  return take;
+}

@@ -11,6 +11,7 @@ import numpy as np
 import pytest
 
 import oracle
+import gs_inputs
 from gs_inputs import uniform_cube_scene
 
 pytestmark = pytest.mark.filterwarnings("ignore::RuntimeWarning")
@@ -231,3 +232,83 @@ def test_grad_stats_closed_form():
     ns, cnt = oracle.grad_stats(tiles, g, W, H)
     assert cnt.tolist() == [2, 2]
     assert ns == pytest.approx([2 * 5.0, 2 * 10.0], rel=1e-14)
+
+
+# --- depth reinitialisation points (Sec. 4.1) and sampling (Sec. 4.2) ---------------
+
+def test_depth_points_round_trip():
+    """Lifted points project back onto their pixel centres at their depth."""
+    cam = gs_inputs.look_at((1.0, -2.0, 5.0), (0.2, 0.1, 0.0), 40, 30)
+    g = np.random.default_rng(3)
+    P = cam.width * cam.height
+    depth = g.uniform(0.5, 9.0, P)
+    imax = np.where(g.uniform(size=P) < 0.8, 7, -1)
+    hit = (g.uniform(size=P) < 0.7).astype(np.int32)
+    target = g.uniform(size=(3, P))
+    u = g.uniform(size=P)
+    pts, col = oracle.depth_points(cam, depth, imax, hit, target, u, rate=0.5, require_hit=True)
+    keep = np.nonzero((imax >= 0) & (hit > 0) & (u < 0.5))[0]
+    assert pts.shape == (keep.size, 3)
+    R = cam.R.astype(np.float64)
+    t = cam.t.astype(np.float64)
+    xc = pts @ R.T + t
+    # the float32 rotation is orthonormal to ~1e-7, which bounds the round trip
+    np.testing.assert_allclose(xc[:, 2], depth[keep], rtol=1e-6)
+    px = xc[:, 0] / xc[:, 2] * cam.fx + cam.cx
+    py = xc[:, 1] / xc[:, 2] * cam.fy + cam.cy
+    np.testing.assert_allclose(px, keep % cam.width + 0.5, atol=1e-4)
+    np.testing.assert_allclose(py, keep // cam.width + 0.5, atol=1e-4)
+    np.testing.assert_array_equal(col, target[:, keep].T)
+    pts2, _ = oracle.depth_points(cam, depth, imax, hit, target, u, rate=0.5, require_hit=False)
+    assert pts2.shape[0] == int(((imax >= 0) & (u < 0.5)).sum())
+    assert oracle.depth_points(cam, depth, imax, hit, target, u, rate=0.0)[0].shape == (0, 3)
+
+
+def _inclusion_exact(w, k):
+    """Inclusion probabilities of k sequential draws without replacement, each
+    with probability proportional to the remaining weights (enumeration)."""
+    import itertools
+    n = len(w)
+    p = np.zeros(n)
+    for seq in itertools.permutations(range(n), k):
+        pr, left = 1.0, float(sum(w))
+        for i in seq:
+            pr *= w[i] / left
+            left -= w[i]
+        for i in seq:
+            p[i] += pr
+    return p
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_sample_inclusion_probabilities(k):
+    w = np.array([1.0, 2.0, 3.0, 0.5, 4.0], np.float32)
+    exact = _inclusion_exact([float(x) for x in w], k)
+    g = np.random.default_rng(11 + k)
+    trials = 20000
+    freq = np.zeros(5)
+    for _ in range(trials):
+        sel = oracle.sample(w, g.exponential(size=5).astype(np.float32), k)
+        assert sel.sum() == k
+        freq += sel
+    freq /= trials
+    sd = np.sqrt(exact * (1 - exact) / trials)
+    assert (np.abs(freq - exact) <= 4.5 * sd + 1e-12).all(), (freq, exact)
+
+
+def test_sample_restrictions_and_edges():
+    g = np.random.default_rng(5)
+    imp = np.array([0.0, 1.0, 2.0, 0.0, 5.0, 1.0], np.float32)
+    area = np.array([3, 0, 1, 1, 2, 1], np.uint32)
+    e = g.exponential(size=6).astype(np.float32)
+    # zero importance is never drawn; area == 0 is outside the intersected set
+    assert oracle.sample(imp, e, 10).tolist() == [0, 1, 1, 0, 1, 1]
+    assert oracle.sample(imp, e, 10, area).tolist() == [0, 0, 1, 0, 1, 1]
+    assert oracle.sample(imp, e, 0).sum() == 0
+    # equal weights: the k smallest exponential draws
+    eq = np.ones(50, np.float32)
+    e = g.exponential(size=50).astype(np.float32)
+    sel = oracle.sample(eq, e, 7)
+    assert set(np.nonzero(sel)[0]) == set(np.argsort(e, kind="stable")[:7])
+    # ties of the key go to the lower index
+    assert oracle.sample(np.ones(4, np.float32), np.full(4, 0.5, np.float32), 2).tolist() == [1, 1, 0, 0]
