@@ -194,6 +194,30 @@ def wmax_like(n: int, seed: int, clamp_fraction: float = 0.2, alpha_max: float =
     return area, w.astype(np.float32)
 
 
+def exponential_draws(n: int, seed: int) -> np.ndarray:
+    """Exp(1) variates, float32 (the random draws of weighted sampling)."""
+    return rng(seed).exponential(size=n).astype(np.float32)
+
+
+def uniform_draws(n: int, seed: int) -> np.ndarray:
+    """U[0, 1) variates, float32."""
+    return rng(seed).uniform(size=n).astype(np.float32)
+
+
+def depth_map_like(pixels: int, seed: int, near: float = 0.5, far: float = 12.0, empty_fraction: float = 0.2):
+    """(depth[P] float32, imax[P] int32, hit[P] uint8): a rendered depth map
+    with a fraction of empty pixels (imax = -1, depth 0) and rays that miss
+    their max-weight ellipsoid (hit = 0)."""
+    g = rng(seed)
+    depth = g.uniform(near, far, size=pixels).astype(np.float32)
+    imax = g.integers(0, 1 << 20, size=pixels).astype(np.int32)
+    empty = g.uniform(size=pixels) < empty_fraction
+    imax[empty] = -1
+    depth[empty] = 0.0
+    hit = ((g.uniform(size=pixels) < 0.85) & ~empty).astype(np.uint8)
+    return depth, imax, hit
+
+
 def uniform_image(channels: int, pixels: int, seed: int) -> np.ndarray:
     return rng(seed).uniform(0.0, 1.0, size=(channels, pixels)).astype(np.float32)
 

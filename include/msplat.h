@@ -366,6 +366,38 @@ size_t gs_clone_workspace_size(int64_t n);
 int32_t gs_clone(const gs_scene_t* in, const uint8_t* select, const gs_scene_out_t* out, int64_t* count, void* ws,
                  size_t ws_bytes, void* stream);
 
+/* Device workspace of gs_sample for n Gaussians. */
+size_t gs_sample_workspace_size(int64_t n);
+
+/* Redundant-Gaussian simplification (Sec. 4.2): intersection preserving keeps
+ * the candidates with area[i] > 0 (the rendered indices of some view; all
+ * Gaussians when area == NULL), and primitive sampling draws k of them without
+ * replacement with probability proportional to importance[i].  The draw uses
+ * exponential keys (Efraimidis and Spirakis, 2006): with expo[i] ~ Exp(1)
+ * supplied by the caller, the k smallest keys expo[i] / importance[i]
+ * (float32, IEEE division; ties to the lower index) are taken; Gaussians with
+ * importance <= 0 are never drawn.  selected [dev, n] bytes 0/1 (all
+ * written); *count [dev int64] = min(k, number of candidates). */
+int32_t gs_sample(const float* importance, const uint32_t* area, const float* expo, int64_t n, int64_t k,
+                  uint8_t* selected, int64_t* count, void* ws, size_t ws_bytes, void* stream);
+
+/* Device workspace of gs_depth_points for `pixels` pixels over all views. */
+size_t gs_depth_points_workspace_size(int64_t pixels);
+
+/* Depth reinitialisation points (Sec. 4.1): every pixel with imax >= 0 (and
+ * hit != 0 when require_hit) whose uniform draw u < rate is lifted to world
+ * space, R^T (d ((x - cx) / fx, (y - cy) / fy, 1) - t) at the pixel centre
+ * (x, y) = (px + 0.5, py + 0.5) with d its rendered depth (GS_DEPTH_MID is
+ * the paper's), in double, and takes the target colour there.  Inputs are
+ * [dev] per pixel over the V views in the gs_view_layout order (depth, imax,
+ * hit and u [P], target [3][P]).  points and colors [dev, 3][capacity]
+ * receive the points in pixel order; those beyond capacity are dropped;
+ * *count [dev int64] = the number of qualifying pixels. */
+int32_t gs_depth_points(const float* depth, const int32_t* imax, const uint8_t* hit, const float* target,
+                        const float* u, const gs_camera_t* cams, int32_t V, double rate, int32_t require_hit,
+                        float* points, float* colors, int64_t capacity, int64_t* count, void* ws, size_t ws_bytes,
+                        void* stream);
+
 #ifdef __cplusplus
 }
 #endif

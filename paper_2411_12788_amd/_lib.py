@@ -105,6 +105,11 @@ _SIGS = {
     "gs_grad_stats": (c_i32, [P(Projected), c_p, P(Camera), c_i32, c_i64, c_p, c_p, c_p]),
     "gs_clone_workspace_size": (c_sz, [c_i64]),
     "gs_clone": (c_i32, [P(Scene), c_p, P(SceneOut), c_p, c_p, c_sz, c_p]),
+    "gs_sample_workspace_size": (c_sz, [c_i64]),
+    "gs_sample": (c_i32, [c_p, c_p, c_p, c_i64, c_i64, c_p, c_p, c_p, c_sz, c_p]),
+    "gs_depth_points_workspace_size": (c_sz, [c_i64]),
+    "gs_depth_points": (c_i32, [c_p, c_p, c_p, c_p, c_p, P(Camera), c_i32, ctypes.c_double, c_i32, c_p, c_p, c_i64,
+                                c_p, c_p, c_sz, c_p]),
 }
 
 _lib = None

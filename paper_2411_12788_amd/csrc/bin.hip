@@ -305,7 +305,6 @@ static int32_t bits_for(uint64_t maxval) {
   return b;
 }
 
-int32_t launch_fill(void* dst, uint32_t value, int64_t count, hipStream_t st);
 
 static int32_t launch_tile_order(const uint32_t* ranges, int32_t tiles, uint32_t* order, uint32_t* hist,
                                  hipStream_t st) {

@@ -54,6 +54,7 @@ int32_t build_views(const gs_camera_t* cams, int32_t V, ViewSet* out);
 KOpts make_kopts(const gs_opts_t* o);
 int32_t check_scene(const gs_scene_t* s);
 int32_t check_records(int32_t V, int64_t n);  // V * n must fit 31 bits (record ids)
+int32_t launch_fill(void* dst, uint32_t value, int64_t count, hipStream_t st);  // 32-bit words
 inline int32_t grid_1d(int64_t n, int block = kBlock) { return (int32_t)((n + block - 1) / block); }
 
 // Blocks are handed to the 8 XCDs round-robin; give each XCD a contiguous

@@ -61,18 +61,29 @@ __device__ __forceinline__ SelHist* sel_hist(uint8_t* ws, int p) {
   return (SelHist*)(ws + (size_t)p * kSelStride + 256);
 }
 
-// Inputs of a threshold problem: values [P][n] with a per-element predicate.
-// Visibility selects I > 0; the critical set selects area > 0.
+// Inputs of a selection problem: values [P][n] with a per-element predicate.
+// Visibility selects I > 0; the critical set selects area > 0.  With `expo`
+// the key is expo / value over value > 0 (and area > 0 when given): the
+// exponential keys of weighted sampling without replacement.
 struct Source {
   const float* values;
   const uint32_t* area;  // NULL: select values > 0
+  const float* expo;     // NULL: the key is the value itself
   int64_t n;
   __device__ __forceinline__ bool take(int p, int64_t i, float& v) const {
     const int64_t j = (int64_t)p * n + i;
     v = values[j];
-    return area ? (area[j] > 0u) : (v > 0.0f);
+    bool s = area ? (area[j] > 0u) : (v > 0.0f);
+    if (expo) {
+      s = s && v > 0.0f;
+      v = expo[j] / v;  // IEEE-rounded float division
+    }
+    return s;
   }
 };
+
+// Selection modes: the two threshold readings, and the k-th smallest key.
+enum { kModeValue = 0, kModeMass = 1, kModeRank = 2 };
 
 __global__ __launch_bounds__(kBlock) void k_sel_init(uint8_t* ws) {
   uint32_t* w = (uint32_t*)(ws + (size_t)blockIdx.x * kSelStride);
@@ -82,8 +93,9 @@ __global__ __launch_bounds__(kBlock) void k_sel_init(uint8_t* ws) {
 // One radix pass: histogram digit `pass` of the keys that match each target's
 // prefix.  Value mode histograms two targets (after pass 0); mass mode one,
 // with the per-bin sum of the values.
-template <bool MASS>
+template <int MODE>
 __global__ __launch_bounds__(kBlock) void k_sel_hist(Source src, uint8_t* ws, int pass) {
+  constexpr bool MASS = MODE == kModeMass;
   __shared__ uint32_t s_cnt[2][kSelBins];
   __shared__ double s_sum[MASS ? kSelBins : 1];
   const int p = blockIdx.y;
@@ -96,7 +108,7 @@ __global__ __launch_bounds__(kBlock) void k_sel_hist(Source src, uint8_t* ws, in
   const int shift = 24 - 8 * pass;
   const uint32_t hi_mask = pass == 0 ? 0u : (0xFFFFFFFFu << (32 - 8 * pass));
   const uint32_t pre0 = st->prefix[0], pre1 = st->prefix[1];
-  const bool two = !MASS && pass > 0;
+  const bool two = MODE == kModeValue && pass > 0;
   __syncthreads();
   const int64_t stride = (int64_t)gridDim.x * kBlock;
   for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < src.n; i += stride) {
@@ -176,8 +188,9 @@ __device__ __forceinline__ void rank_walk(const uint32_t* c, int64_t r, int& bin
 
 // Choose the bin of each target and clear the histograms for the next pass.
 // One block per problem; the histogram is staged in LDS and one wave walks it.
-template <bool MASS>
+template <int MODE>
 __global__ __launch_bounds__(kBlock) void k_sel_step(uint8_t* ws, int pass, double q_or_keep) {
+  constexpr bool MASS = MODE == kModeMass;
   __shared__ uint32_t s_cnt[2][kSelBins];
   __shared__ double s_sum[MASS ? kSelBins : 1];
   const int p = blockIdx.x;
@@ -260,7 +273,11 @@ __global__ __launch_bounds__(kBlock) void k_sel_step(uint8_t* ws, int pass, doub
   } else {
     int64_t rank[2] = {st->rank[0], st->rank[1]};
     double frac = 0.0;
-    if (pass == 0 && m > 0) {
+    if (pass == 0 && m > 0 && MODE == kModeRank) {
+      // the k-th smallest key (k = q_or_keep, at most m)
+      const int64_t k = (int64_t)q_or_keep;
+      rank[0] = rank[1] = (k < m ? k : m) - 1;
+    } else if (pass == 0 && m > 0) {
       // linear interpolation between order statistics lo and lo + 1
       const double hpos = (double)(m - 1) * q_or_keep;
       const double lo = floor(hpos);
@@ -271,7 +288,8 @@ __global__ __launch_bounds__(kBlock) void k_sel_step(uint8_t* ws, int pass, doub
       rank[1] = ilo + 1 < m ? ilo + 1 : ilo;
     }
     int bins[2] = {0, 0};
-    for (int t = 0; t < 2; ++t) {
+    constexpr int targets = MODE == kModeValue ? 2 : 1;
+    for (int t = 0; t < targets; ++t) {
       int64_t below = 0;
       if (m > 0) rank_walk(s_cnt[pass == 0 ? 0 : t], rank[t], bins[t], below);
       rank[t] -= below;
@@ -282,7 +300,7 @@ __global__ __launch_bounds__(kBlock) void k_sel_step(uint8_t* ws, int pass, doub
         st->frac = frac;
       }
       if (m > 0) {
-        for (int t = 0; t < 2; ++t) {
+        for (int t = 0; t < targets; ++t) {
           st->rank[t] = rank[t];
           st->prefix[t] |= (uint32_t)bins[t] << shift;
         }
@@ -332,21 +350,27 @@ __global__ __launch_bounds__(kBlock) void k_sel_min_above(Source src, uint8_t* w
   if (threadIdx.x == 0 && s_min != 0xFFFFFFFFu) atomicMin(&st->min_above, s_min);
 }
 
-template <bool MASS>
+template <int MODE>
 __global__ __launch_bounds__(kWave) void k_sel_finish(uint8_t* ws, double* tau) {
+  constexpr bool MASS = MODE == kModeMass;
   const int p = blockIdx.x;
   const SelState* st = sel_state(ws, p);
   if (threadIdx.x != 0) return;
   double t;
-  if (st->m == 0) {
+  if (st->m == 0 || (MODE == kModeRank && st->rank[0] < 0)) {
     t = __builtin_nan("");
+  } else if (MODE == kModeRank) {
+    t = (double)key_value(st->prefix[0]);
   } else if (MASS) {
     t = (double)key_value(st->need_above ? st->min_above : st->prefix[0]);
   } else {
+    // a + frac (b - a), rounded after the product and after the sum: the
+    // threshold decides integers, so it must not depend on FMA contraction
+#pragma clang fp contract(off)
     const double a = (double)key_value(st->prefix[0]);
     const double b = (double)key_value(st->prefix[1]);
-    // a + frac (b - a) with separate roundings (no fused multiply-add)
-    t = __dadd_rn(a, __dmul_rn(st->frac, __dsub_rn(b, a)));
+    const double prod = st->frac * (b - a);
+    t = a + prod;
   }
   tau[p] = t;
 }
@@ -387,20 +411,20 @@ int32_t launch_threshold(const Source& src, int P, double keep, int32_t mode, ui
   MS_CHECK_LAUNCH("sel_init");
   for (int pass = 0; pass < kSelPasses; ++pass) {
     if (mass) {
-      hipLaunchKernelGGL(k_sel_hist<true>, grid, dim3(kBlock), 0, st, src, w, pass);
-      hipLaunchKernelGGL(k_sel_step<true>, dim3(P), dim3(kBlock), 0, st, w, pass, param);
+      hipLaunchKernelGGL(k_sel_hist<kModeMass>, grid, dim3(kBlock), 0, st, src, w, pass);
+      hipLaunchKernelGGL(k_sel_step<kModeMass>, dim3(P), dim3(kBlock), 0, st, w, pass, param);
     } else {
-      hipLaunchKernelGGL(k_sel_hist<false>, grid, dim3(kBlock), 0, st, src, w, pass);
-      hipLaunchKernelGGL(k_sel_step<false>, dim3(P), dim3(kBlock), 0, st, w, pass, param);
+      hipLaunchKernelGGL(k_sel_hist<kModeValue>, grid, dim3(kBlock), 0, st, src, w, pass);
+      hipLaunchKernelGGL(k_sel_step<kModeValue>, dim3(P), dim3(kBlock), 0, st, w, pass, param);
     }
     MS_CHECK_LAUNCH("sel_pass");
   }
   if (mass) {
     hipLaunchKernelGGL(k_sel_group, dim3(P), dim3(kBlock), 0, st, w);
     hipLaunchKernelGGL(k_sel_min_above, grid, dim3(kBlock), 0, st, src, w);
-    hipLaunchKernelGGL(k_sel_finish<true>, dim3(P), dim3(kWave), 0, st, w, tau);
+    hipLaunchKernelGGL(k_sel_finish<kModeMass>, dim3(P), dim3(kWave), 0, st, w, tau);
   } else {
-    hipLaunchKernelGGL(k_sel_finish<false>, dim3(P), dim3(kWave), 0, st, w, tau);
+    hipLaunchKernelGGL(k_sel_finish<kModeValue>, dim3(P), dim3(kWave), 0, st, w, tau);
   }
   MS_CHECK_LAUNCH("sel_finish");
   hipLaunchKernelGGL(k_sel_apply, grid, dim3(kBlock), 0, st, src, tau, out);
@@ -560,6 +584,131 @@ __global__ __launch_bounds__(kBlock) void k_clone_write(ClonePlanes in, const ui
   }
 }
 
+// ---------------------------------------------------------------------------
+// primitive sampling: the k smallest exponential keys, ties by lower index
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_tie_count(Source src, const double* __restrict__ tau,
+                                                      uint32_t* __restrict__ block_cnt) {
+  __shared__ uint32_t s_part[kBlock / kWave];
+  const double t = *tau;
+  const int64_t base = (int64_t)blockIdx.x * kCloneItems;
+  uint32_t c = 0;
+  for (int j = threadIdx.x; j < kCloneItems; j += kBlock) {
+    const int64_t i = base + j;
+    float v;
+    if (i < src.n && src.take(0, i, v) && (double)v == t) ++c;
+  }
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, kWave);
+  if (lane_id() == 0) s_part[threadIdx.x / kWave] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) block_cnt[blockIdx.x] = s_part[0] + s_part[1] + s_part[2] + s_part[3];
+}
+
+__global__ __launch_bounds__(kBlock) void k_sample_write(Source src, const uint8_t* __restrict__ ws,
+                                                         const double* __restrict__ tau,
+                                                         const uint32_t* __restrict__ block_off, int64_t k,
+                                                         uint8_t* __restrict__ out, int64_t* __restrict__ count) {
+  __shared__ uint32_t s_wave[kBlock / kWave];
+  __shared__ uint32_t s_carry;
+  const SelState* st = (const SelState*)ws;
+  const double t = *tau;
+  const int64_t take_ties = st->rank[0] + 1;  // ties at tau taken, in index order
+  const int64_t base = (int64_t)blockIdx.x * kCloneItems;
+  if (threadIdx.x == 0) s_carry = block_off[blockIdx.x];
+  if (blockIdx.x == 0 && threadIdx.x == 0) *count = (st->m == 0 || k <= 0) ? 0 : (k < st->m ? k : st->m);
+  __syncthreads();
+  for (int j0 = 0; j0 < kCloneItems; j0 += kBlock) {
+    const int64_t i = base + j0 + threadIdx.x;
+    float v = 0.0f;
+    const bool s = i < src.n && src.take(0, i, v);
+    const bool tie = s && (double)v == t;
+    const uint64_t bal = __ballot(tie);
+    const uint32_t below = __popcll(bal & ((1ull << lane_id()) - 1ull));
+    if (lane_id() == 0) s_wave[threadIdx.x / kWave] = (uint32_t)__popcll(bal);
+    __syncthreads();
+    uint32_t off = s_carry;
+    for (int w = 0; w < (int)(threadIdx.x / kWave); ++w) off += s_wave[w];
+    const uint32_t chunk = s_wave[0] + s_wave[1] + s_wave[2] + s_wave[3];
+    if (i < src.n) {
+      const bool sel = s && ((double)v < t || (tie && (int64_t)(off + below) < take_ties));
+      out[i] = sel ? 1 : 0;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) s_carry += chunk;
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// depth reinitialisation points: pixels with a rendered index (and a ray that
+// meets its ellipsoid) whose draw u < rate, lifted to world space, compacted
+// in pixel order
+// ---------------------------------------------------------------------------
+struct DepthSrc {
+  const float* depth;
+  const int32_t* imax;
+  const uint8_t* hit;
+  const float* u;
+  double rate;
+  int32_t require_hit;
+  int64_t P;
+  __device__ __forceinline__ bool take(int64_t g) const {
+    return g < P && imax[g] >= 0 && (!require_hit || hit[g] != 0) && (double)u[g] < rate;
+  }
+};
+
+__global__ __launch_bounds__(kBlock) void k_dp_count(DepthSrc src, uint32_t* __restrict__ block_cnt) {
+  __shared__ uint32_t s_part[kBlock / kWave];
+  const int64_t base = (int64_t)blockIdx.x * kCloneItems;
+  uint32_t c = 0;
+  for (int j = threadIdx.x; j < kCloneItems; j += kBlock) c += src.take(base + j) ? 1u : 0u;
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, kWave);
+  if (lane_id() == 0) s_part[threadIdx.x / kWave] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) block_cnt[blockIdx.x] = s_part[0] + s_part[1] + s_part[2] + s_part[3];
+}
+
+__global__ __launch_bounds__(kBlock) void k_dp_write(DepthSrc src, ViewSet vs, const float* __restrict__ target,
+                                                     const uint32_t* __restrict__ block_off, float* __restrict__ points,
+                                                     float* __restrict__ colors, int64_t cap) {
+  __shared__ uint32_t s_wave[kBlock / kWave];
+  __shared__ uint32_t s_carry;
+  const int64_t base = (int64_t)blockIdx.x * kCloneItems;
+  if (threadIdx.x == 0) s_carry = block_off[blockIdx.x];
+  __syncthreads();
+  for (int j0 = 0; j0 < kCloneItems; j0 += kBlock) {
+    const int64_t g = base + j0 + threadIdx.x;
+    const bool s = src.take(g);
+    const uint64_t bal = __ballot(s);
+    const uint32_t below = __popcll(bal & ((1ull << lane_id()) - 1ull));
+    if (lane_id() == 0) s_wave[threadIdx.x / kWave] = (uint32_t)__popcll(bal);
+    __syncthreads();
+    uint32_t off = s_carry;
+    for (int w = 0; w < (int)(threadIdx.x / kWave); ++w) off += s_wave[w];
+    const uint32_t chunk = s_wave[0] + s_wave[1] + s_wave[2] + s_wave[3];
+    const int64_t d = (int64_t)off + below;
+    if (s && d < cap) {
+      int k = 0;
+      for (int j = 1; j < vs.count; ++j) k = (g >= vs.v[j].pixel_base) ? j : k;
+      const KView& cam = vs.v[k];
+      const int64_t local = g - cam.pixel_base;
+      const double x = (double)(local % cam.width) + 0.5, y = (double)(local / cam.width) + 0.5;
+      const double dep = (double)src.depth[g];
+      const double xc[3] = {dep * (x - (double)cam.cx) / (double)cam.fx, dep * (y - (double)cam.cy) / (double)cam.fy,
+                            dep};
+      for (int a = 0; a < 3; ++a) {
+        double w = 0.0;
+        for (int r = 0; r < 3; ++r) w += (double)cam.R[r * 3 + a] * (xc[r] - (double)cam.t[r]);
+        points[a * cap + d] = (float)w;
+      }
+      for (int ch = 0; ch < 3; ++ch) colors[ch * cap + d] = target[ch * vs.pixels_total + g];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) s_carry += chunk;
+    __syncthreads();
+  }
+}
+
 }  // namespace
 
 }  // namespace msplat
@@ -578,7 +727,7 @@ int32_t gs_visibility(const float* importance, int32_t V, int64_t n, double keep
   if (V < 1 || V > GS_MAX_VIEWS) { set_error("V out of range 1..GS_MAX_VIEWS"); return GS_ERR_SHAPE; }
   if (n < 0 || n >= (int64_t(1) << 31)) { set_error("n out of range"); return GS_ERR_SHAPE; }
   if (n > 0 && !importance) { set_error("importance is NULL"); return GS_ERR_NULL; }
-  Source src{importance, nullptr, n};
+  Source src{importance, nullptr, nullptr, n};
   return launch_threshold(src, V, keep, mode, visible, tau, ws, ws_bytes, (hipStream_t)stream);
 }
 
@@ -586,7 +735,7 @@ int32_t gs_critical(const uint32_t* area, const float* wmax, int64_t n, double k
                     double* tau, void* ws, size_t ws_bytes, void* stream) {
   if (n < 0 || n >= (int64_t(1) << 31)) { set_error("n out of range"); return GS_ERR_SHAPE; }
   if (n > 0 && (!area || !wmax)) { set_error("area or wmax is NULL"); return GS_ERR_NULL; }
-  Source src{wmax, area, n};
+  Source src{wmax, area, nullptr, n};
   return launch_threshold(src, 1, keep, mode, critical, tau, ws, ws_bytes, (hipStream_t)stream);
 }
 
@@ -656,6 +805,87 @@ int32_t gs_clone(const gs_scene_t* in, const uint8_t* select, const gs_scene_out
     hipLaunchKernelGGL(k_clone_write, dim3(nb), dim3(kBlock), 0, st, ip, select, block_off, op);
     MS_CHECK_LAUNCH("clone_write");
   }
+  return GS_OK;
+}
+
+size_t gs_sample_workspace_size(int64_t n) {
+  const int64_t nb = n > 0 ? (n + kCloneItems - 1) / kCloneItems : 1;
+  return kSelStride + 256 + (size_t)((nb * 4 + 16 + 255) / 256 * 256);
+}
+
+int32_t gs_sample(const float* importance, const uint32_t* area, const float* expo, int64_t n, int64_t k,
+                  uint8_t* selected, int64_t* count, void* ws, size_t ws_bytes, void* stream) {
+  if (n < 0 || n >= (int64_t(1) << 31)) { set_error("n out of range"); return GS_ERR_SHAPE; }
+  if (k < 0) { set_error("k < 0"); return GS_ERR_SHAPE; }
+  if (!count || !ws) { set_error("count or workspace is NULL"); return GS_ERR_NULL; }
+  if (n > 0 && (!importance || !expo || !selected)) { set_error("importance, expo or selected is NULL"); return GS_ERR_NULL; }
+  if (ws_bytes < gs_sample_workspace_size(n)) { set_error("sample workspace too small"); return GS_ERR_CAPACITY; }
+  int32_t s;
+  hipStream_t st = (hipStream_t)stream;
+  uint8_t* w = (uint8_t*)ws;
+  double* tau = (double*)(w + kSelStride);
+  uint32_t* block_off = (uint32_t*)(w + kSelStride + 256);
+  const int32_t nb = n > 0 ? (int32_t)((n + kCloneItems - 1) / kCloneItems) : 0;
+  int64_t* ties = (int64_t*)(block_off + ((nb + 1) & ~1));
+  Source src{importance, area, expo, n};
+  const dim3 grid((unsigned)sel_blocks(n, 1), 1u);
+  hipLaunchKernelGGL(k_sel_init, dim3(1), dim3(kBlock), 0, st, w);
+  MS_CHECK_LAUNCH("sample_init");
+  for (int pass = 0; pass < kSelPasses; ++pass) {
+    hipLaunchKernelGGL(k_sel_hist<kModeRank>, grid, dim3(kBlock), 0, st, src, w, pass);
+    hipLaunchKernelGGL(k_sel_step<kModeRank>, dim3(1), dim3(kBlock), 0, st, w, pass, (double)k);
+    MS_CHECK_LAUNCH("sample_pass");
+  }
+  hipLaunchKernelGGL(k_sel_finish<kModeRank>, dim3(1), dim3(kWave), 0, st, w, tau);
+  MS_CHECK_LAUNCH("sample_finish");
+  if (nb > 0) {
+    hipLaunchKernelGGL(k_tie_count, dim3(nb), dim3(kBlock), 0, st, src, tau, block_off);
+    MS_CHECK_LAUNCH("sample_ties");
+  }
+  hipLaunchKernelGGL(k_clone_scan, dim3(1), dim3(1024), 0, st, block_off, nb, ties);
+  MS_CHECK_LAUNCH("sample_scan");
+  if (nb > 0) {
+    hipLaunchKernelGGL(k_sample_write, dim3(nb), dim3(kBlock), 0, st, src, w, tau, block_off, k, selected, count);
+    MS_CHECK_LAUNCH("sample_write");
+  } else {
+    if ((s = launch_fill(count, 0u, 2, st)) != GS_OK) return s;
+  }
+  return GS_OK;
+}
+
+size_t gs_depth_points_workspace_size(int64_t pixels) {
+  const int64_t nb = pixels > 0 ? (pixels + kCloneItems - 1) / kCloneItems : 1;
+  return (size_t)((nb * 4 + 255) / 256 * 256);
+}
+
+int32_t gs_depth_points(const float* depth, const int32_t* imax, const uint8_t* hit, const float* target,
+                        const float* u, const gs_camera_t* cams, int32_t V, double rate, int32_t require_hit,
+                        float* points, float* colors, int64_t capacity, int64_t* count, void* ws, size_t ws_bytes,
+                        void* stream) {
+  ViewSet vs;
+  int32_t s = build_views(cams, V, &vs);
+  if (s != GS_OK) return s;
+  const int64_t P = vs.pixels_total;
+  if (capacity < 0 || capacity >= (int64_t(1) << 31)) { set_error("capacity out of range"); return GS_ERR_SHAPE; }
+  if (!depth || !imax || !target || !u || !count || (require_hit && !hit)) {
+    set_error("NULL input or count");
+    return GS_ERR_NULL;
+  }
+  if (capacity > 0 && (!points || !colors)) { set_error("points or colors is NULL"); return GS_ERR_NULL; }
+  if (!ws || ws_bytes < gs_depth_points_workspace_size(P)) {
+    set_error("depth-points workspace too small");
+    return GS_ERR_CAPACITY;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  const int32_t nb = (int32_t)((P + kCloneItems - 1) / kCloneItems);
+  uint32_t* block_off = (uint32_t*)ws;
+  DepthSrc src{depth, imax, hit, u, rate, require_hit, P};
+  hipLaunchKernelGGL(k_dp_count, dim3(nb), dim3(kBlock), 0, st, src, block_off);
+  MS_CHECK_LAUNCH("depth_points_count");
+  hipLaunchKernelGGL(k_clone_scan, dim3(1), dim3(1024), 0, st, block_off, nb, count);
+  MS_CHECK_LAUNCH("depth_points_scan");
+  hipLaunchKernelGGL(k_dp_write, dim3(nb), dim3(kBlock), 0, st, src, vs, target, block_off, points, colors, capacity);
+  MS_CHECK_LAUNCH("depth_points_write");
   return GS_OK;
 }
 

@@ -78,3 +78,35 @@ def clone(scene: DeviceScene, select: torch.Tensor, capacity: Optional[int] = No
     L.check(L.lib().gs_clone(ctypes.byref(scene.c()), _ptr(select), ctypes.byref(so), _ptr(count), _ptr(ws),
                              ws.numel(), _stream(stream)), "gs_clone")
     return out, count
+
+
+def sample(importance: torch.Tensor, expo: torch.Tensor, k: int, area: Optional[torch.Tensor] = None,
+           stream=None) -> Tuple[torch.Tensor, torch.Tensor]:
+    """Intersection preserving + primitive sampling (Sec. 4.2): (selected [n] uint8, count [1] int64).
+    expo holds Exp(1) draws, one per Gaussian."""
+    n = importance.numel()
+    dev = importance.device
+    out = torch.empty(n, dtype=torch.uint8, device=dev)
+    count = torch.empty(1, dtype=torch.int64, device=dev)
+    ws = torch.empty(L.lib().gs_sample_workspace_size(n), dtype=torch.uint8, device=dev)
+    L.check(L.lib().gs_sample(_ptr(importance), _ptr(area), _ptr(expo), n, int(k), _ptr(out), _ptr(count), _ptr(ws),
+                              ws.numel(), _stream(stream)), "gs_sample")
+    return out, count
+
+
+def depth_points(depth: torch.Tensor, imax: torch.Tensor, hit: Optional[torch.Tensor], target: torch.Tensor,
+                 u: torch.Tensor, cams, rate: float, require_hit: bool = True, capacity: Optional[int] = None,
+                 stream=None) -> Tuple[torch.Tensor, torch.Tensor, torch.Tensor]:
+    """Depth reinitialisation points (Sec. 4.1): (points [3, cap], colors [3, cap], count [1] int64)."""
+    cc = cameras(cams)
+    P = depth.numel()
+    dev = depth.device
+    cap = P if capacity is None else int(capacity)
+    pts = torch.empty((3, cap), device=dev)
+    col = torch.empty((3, cap), device=dev)
+    count = torch.empty(1, dtype=torch.int64, device=dev)
+    ws = torch.empty(L.lib().gs_depth_points_workspace_size(P), dtype=torch.uint8, device=dev)
+    L.check(L.lib().gs_depth_points(_ptr(depth), _ptr(imax), _ptr(hit), _ptr(target), _ptr(u), cc, len(cc), rate,
+                                    1 if require_hit else 0, _ptr(pts), _ptr(col), cap, _ptr(count), _ptr(ws),
+                                    ws.numel(), _stream(stream)), "gs_depth_points")
+    return pts, col, count

@@ -187,3 +187,70 @@ def test_pipeline_visibility_from_render(gpu_lib):
     assert bool(((vis > 0) <= (imp > 0)).all())
     frac = (vis.sum(1).double() / (imp > 0).sum(1).clamp(min=1).double()).cpu().numpy()
     assert (frac > 0.2).all() and (frac <= 1.0).all()
+
+
+@pytest.mark.parametrize("seed,n,k,use_area", [(0, 1, 1, False), (1, 5000, 1200, False), (2, 5000, 1200, True),
+                                               (3, 100_003, 30_000, True), (4, 4096, 0, False),
+                                               (5, 4096, 10_000, True), (6, 3_000_000, 1_500_000, True)])
+def test_sample_matches_oracle(gpu_lib, seed, n, k, use_area):
+    imp = gs_inputs.importance_like(1, n, seed)[0]
+    expo = gs_inputs.exponential_draws(n, seed + 50)
+    area = gs_inputs.wmax_like(n, seed + 60)[0] if use_area else None
+    sel_g, cnt = D().sample(torch.from_numpy(imp).cuda(), torch.from_numpy(expo).cuda(), k,
+                            None if area is None else torch.from_numpy(area.view(np.int32)).cuda())
+    sel_o = oracle.sample(imp, expo, k, area)
+    assert int(cnt.cpu()[0]) == int(sel_o.sum())
+    assert (sel_g.cpu().numpy() == sel_o).all()
+
+
+def test_sample_ties_by_index(gpu_lib):
+    n = 10_000
+    imp = np.ones(n, np.float32)
+    expo = np.full(n, 0.75, np.float32)
+    expo[::7] = 0.5
+    for k in (1, 1000, 1429, 1430, 5000, n):
+        sel_g, cnt = D().sample(torch.from_numpy(imp).cuda(), torch.from_numpy(expo).cuda(), k)
+        sel_o = oracle.sample(imp, expo, k)
+        assert (sel_g.cpu().numpy() == sel_o).all(), k
+        assert int(cnt.cpu()[0]) == min(k, n)
+
+
+@pytest.mark.parametrize("require_hit", [True, False])
+@pytest.mark.parametrize("rate", [0.0, 0.05, 1.0])
+def test_depth_points_matches_oracle(gpu_lib, require_hit, rate):
+    cams = [gs_inputs.look_at((1.0, -2.0, 5.0), (0.2, 0.1, 0.0), 333, 201),
+            gs_inputs.look_at((-4.0, 1.0, 2.0), (0.0, 0.0, 0.0), 64, 48)]
+    sizes = [c.width * c.height for c in cams]
+    P = sum(sizes)
+    depth, imax, hit = gs_inputs.depth_map_like(P, 7)
+    target = gs_inputs.uniform_image(3, P, 8)
+    u = gs_inputs.uniform_draws(P, 9)
+    t = lambda a: torch.from_numpy(a).cuda()
+    pts, col, cnt = D().depth_points(t(depth), t(imax), t(hit), t(target), t(u), cams, rate, require_hit)
+    m = int(cnt.cpu()[0])
+    ref_p, ref_c, base = [], [], 0
+    for c, sz in zip(cams, sizes):
+        sl = slice(base, base + sz)
+        p_, c_ = oracle.depth_points(c, depth[sl], imax[sl], hit[sl], target[:, sl], u[sl], rate, require_hit)
+        ref_p.append(p_)
+        ref_c.append(c_)
+        base += sz
+    ref_p = np.concatenate(ref_p)
+    ref_c = np.concatenate(ref_c)
+    assert m == ref_p.shape[0]
+    got_p = pts[:, :m].cpu().numpy().T.astype(np.float64)
+    np.testing.assert_allclose(got_p, ref_p, rtol=2e-6, atol=2e-6)
+    assert (col[:, :m].cpu().numpy().T == ref_c.astype(np.float32)).all()
+
+
+def test_depth_points_capacity(gpu_lib):
+    cams = [gs_inputs.look_at((0.0, 0.0, 4.0), (0.0, 0.0, 0.0), 128, 96)]
+    P = 128 * 96
+    depth, imax, hit = gs_inputs.depth_map_like(P, 17)
+    target = gs_inputs.uniform_image(3, P, 18)
+    u = gs_inputs.uniform_draws(P, 19)
+    t = lambda a: torch.from_numpy(a).cuda()
+    pts, col, cnt = D().depth_points(t(depth), t(imax), t(hit), t(target), t(u), cams, 1.0, True, capacity=100)
+    ref_p, _ = oracle.depth_points(cams[0], depth, imax, hit, target, u, 1.0, True)
+    assert int(cnt.cpu()[0]) == ref_p.shape[0] > 100
+    np.testing.assert_allclose(pts.cpu().numpy().T.astype(np.float64), ref_p[:100], rtol=2e-6, atol=2e-6)
