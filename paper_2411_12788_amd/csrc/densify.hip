@@ -17,6 +17,11 @@
 
 #include "common.hpp"
 
+// These kernels turn floating-point values into integer decisions (ranks,
+// thresholds, masks): every product and sum is rounded on its own, never
+// fused, so the arithmetic is the one the definitions state.
+#pragma clang fp contract(off)
+
 namespace msplat {
 
 namespace {
@@ -364,9 +369,7 @@ __global__ __launch_bounds__(kWave) void k_sel_finish(uint8_t* ws, double* tau) 
   } else if (MASS) {
     t = (double)key_value(st->need_above ? st->min_above : st->prefix[0]);
   } else {
-    // a + frac (b - a), rounded after the product and after the sum: the
-    // threshold decides integers, so it must not depend on FMA contraction
-#pragma clang fp contract(off)
+    // a + frac (b - a)
     const double a = (double)key_value(st->prefix[0]);
     const double b = (double)key_value(st->prefix[1]);
     const double prod = st->frac * (b - a);

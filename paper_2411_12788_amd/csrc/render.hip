@@ -99,6 +99,58 @@ __device__ __forceinline__ float wave_reduce_dpp(float x) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
 }
 
+// Wave sum of nine per-lane partials by a butterfly reduce-scatter: three
+// exchange steps (lane xor 1, xor 2 by quad permutes, xor 8 by a row rotate)
+// halve the values each lane carries, so each lane then holds one value summed
+// over 8 lanes; a row rotate by 4 and the two gfx950 permlane swaps (rows xor
+// 16, halves xor 32) finish the sum.  The ninth value takes the plain chain.
+// The row rotate hands lane L the value of lane L - 4 (mod 16), which is
+// L ^ 4 where bit 2 of L is set.  Afterwards lane L with bit 2 set and bits
+// 4, 5 clear holds the total of value 4 (L & 1) + 2 ((L >> 1) & 1) +
+// ((L >> 3) & 1), and lane 20 the ninth.
+template <int CTRL>
+__device__ __forceinline__ float dpp_take(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, true));
+}
+__device__ __forceinline__ float swap_sum16(float x) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ float swap_sum32(float x) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+struct Sum9 {
+  float v;   // one of the first eight totals (see above)
+  float v8;  // total of the ninth value
+};
+__device__ __forceinline__ Sum9 wave_sum9(const float (&p)[9], int lane) {
+  constexpr int kXor1 = 0xB1, kXor2 = 0x4E, kRor8 = 0x128, kRor4 = 0x124;
+  const bool o1 = (lane & 1) != 0, o2 = (lane & 2) != 0, o8 = (lane & 8) != 0;
+  float a[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const float keep = o1 ? p[4 + j] : p[j], send = o1 ? p[j] : p[4 + j];
+    a[j] = keep + dpp_take<kXor1>(send);
+  }
+  float c[2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const float keep = o2 ? a[2 + j] : a[j], send = o2 ? a[j] : a[2 + j];
+    c[j] = keep + dpp_take<kXor2>(send);
+  }
+  float d = (o8 ? c[1] : c[0]) + dpp_take<kRor8>(o8 ? c[0] : c[1]);
+  d += dpp_take<kRor4>(d);  // lanes with bit 2 set: partner is lane ^ 4
+  float e = p[8] + dpp_take<kXor1>(p[8]);
+  e += dpp_take<kXor2>(e);
+  e += dpp_take<kRor8>(e);
+  e += dpp_take<kRor4>(e);
+  Sum9 r;
+  r.v = swap_sum32(swap_sum16(d));
+  r.v8 = swap_sum32(swap_sum16(e));
+  return r;
+}
+
 __device__ __forceinline__ bool box_meets(int2 b, int32_t x0, int32_t x1, int32_t y0, int32_t y1) {
   // pixel box (lo | hi << 16) against the pixel rectangle [x0, x1] x [y0, y1]
   return (int32_t)((uint32_t)b.x >> 16) >= x0 && (b.x & 0xffff) <= x1 && (int32_t)((uint32_t)b.y >> 16) >= y0 &&
@@ -332,6 +384,9 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(const float* __restrict__
   }
   lst = lst < end - start ? lst : end - start;  // `last` never exceeds the tile's list
   float s0 = T * op.bg[0], s1 = T * op.bg[1], s2 = T * op.bg[2];
+  // 2D-gradient component this lane adds after wave_sum9, or -1
+  const int slot = (lane & 0x34) == 0x04 ? 4 * (lane & 1) + 2 * ((lane >> 1) & 1) + ((lane >> 3) & 1)
+                                         : (lane == 20 ? 8 : -1);
   const uint32_t wjmax = uniform_u32(wave_max_u32(lst));
   if (lane == 0) s_jmax[wv] = wjmax;
   __syncthreads();
@@ -408,22 +463,9 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(const float* __restrict__
           }
         }
         if (act && __any(contrib)) {
-          p0 = wave_reduce_dpp<false>(p0);
-          p1 = wave_reduce_dpp<false>(p1);
-          p2 = wave_reduce_dpp<false>(p2);
-          p3 = wave_reduce_dpp<false>(p3);
-          p4 = wave_reduce_dpp<false>(p4);
-          p5 = wave_reduce_dpp<false>(p5);
-          p6 = wave_reduce_dpp<false>(p6);
-          p7 = wave_reduce_dpp<false>(p7);
-          p8 = wave_reduce_dpp<false>(p8);
-          if (lane < kG2d) {
-            float x = p0;
-            x = lane == 1 ? p1 : x; x = lane == 2 ? p2 : x; x = lane == 3 ? p3 : x;
-            x = lane == 4 ? p4 : x; x = lane == 5 ? p5 : x; x = lane == 6 ? p6 : x;
-            x = lane == 7 ? p7 : x; x = lane == 8 ? p8 : x;
-            atomicAdd(g2d + (int64_t)(tag & 0x7fffffffu) * kG2d + lane, x);
-          }
+          const float pv[9] = {p0, p1, p2, p3, p4, p5, p6, p7, p8};
+          const Sum9 r = wave_sum9(pv, lane);
+          if (slot >= 0) atomicAdd(g2d + (int64_t)(tag & 0x7fffffffu) * kG2d + slot, slot == 8 ? r.v8 : r.v);
         }
       }
     }
