@@ -120,6 +120,31 @@ __device__ __forceinline__ float swap_sum32(float x) {
   const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(x), false, false);
   return __uint_as_float(r[0]) + __uint_as_float(r[1]);
 }
+// Full-wave sum and max of one value, in every lane: quad permutes, row
+// rotates by 4 and 8, then the row and half swaps.
+__device__ __forceinline__ float wave_sum_all(float x) {
+  x += dpp_take<0xB1>(x);
+  x += dpp_take<0x4E>(x);
+  x += dpp_take<0x124>(x);
+  x += dpp_take<0x128>(x);
+  return swap_sum32(swap_sum16(x));
+}
+__device__ __forceinline__ float swap_max16(float x) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+  return fmaxf(__uint_as_float(r[0]), __uint_as_float(r[1]));
+}
+__device__ __forceinline__ float swap_max32(float x) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+  return fmaxf(__uint_as_float(r[0]), __uint_as_float(r[1]));
+}
+__device__ __forceinline__ float wave_max_all(float x) {
+  x = fmaxf(x, dpp_take<0xB1>(x));
+  x = fmaxf(x, dpp_take<0x4E>(x));
+  x = fmaxf(x, dpp_take<0x124>(x));
+  x = fmaxf(x, dpp_take<0x128>(x));
+  return swap_max32(swap_max16(x));
+}
+
 struct Sum9 {
   float v;   // one of the first eight totals (see above)
   float v8;  // total of the ninth value
@@ -283,9 +308,14 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(const float* __restrict__
             }
           }
         }
-        if (ACC && inc) {
-          atomicAdd(&s_acc_w[kk], wgt);
-          atomicMax(&s_acc_m[kk], __float_as_uint(wgt));  // weights are >= 0: bit order is value order
+        if (ACC && __any(inc)) {
+          // one LDS update per wave and entry (the four quarter waves share the entry)
+          const float wv = inc ? wgt : 0.f;
+          const float wsum = wave_sum_all(wv), wmx = wave_max_all(wv);
+          if (lane == 0) {
+            atomicAdd(&s_acc_w[kk], wsum);
+            atomicMax(&s_acc_m[kk], __float_as_uint(wmx));  // weights are >= 0: bit order is value order
+          }
         }
         if (__all(done)) {
           wave_done = true;
