@@ -296,31 +296,64 @@ __device__ __forceinline__ void geometry_backward(const KView& cam, const KOpts&
   gq[3] += (dz - z * proj) * iq;
 }
 
+// A record carries gradient when it touched a tile and its 2D gradient row is
+// not all zero.
+__device__ __forceinline__ bool record_live(const ProjBwdArgs& pa, int64_t r) {
+  if (pa.bin[4 * r + 3] == 0) return false;
+  const float* gr = pa.g2d + r * kG2d;
+  bool nz = false;
+#pragma unroll
+  for (int k = 0; k < kG2d; ++k) nz = nz || gr[k] != 0.f;
+  return nz;
+}
+
+// Each workgroup first sorts its 256 Gaussians: rows with no gradient (inactive,
+// or live in no view) are written as zeros at once, the others are packed into
+// an LDS list, and only the first waves run the double-precision chain rule on
+// that dense list.  Without the packing a wave would run the heavy path at the
+// lane utilisation of the active fraction.
 template <int DEG>
 __global__ __launch_bounds__(kBlock) void k_project_bwd(ProjBwdArgs pa, ViewSet vs) {
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  __shared__ int32_t s_list[kBlock];
+  __shared__ uint32_t s_wave[kBlock / kWave];
   const int64_t n = pa.sc.n;
-  if (i >= n) return;
+  const int64_t i0 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  bool work = i0 < n && (pa.active == nullptr || pa.active[i0] != 0);
+  if (work) {
+    bool any = false;
+    for (int v = 0; v < vs.count && !any; ++v) any = record_live(pa, (int64_t)v * n + i0);
+    work = any;
+  }
+  if (i0 < n && !work) {
+    pa.gmeans[i0] = 0.f; pa.gmeans[n + i0] = 0.f; pa.gmeans[2 * n + i0] = 0.f;
+    pa.gscales[i0] = 0.f; pa.gscales[n + i0] = 0.f; pa.gscales[2 * n + i0] = 0.f;
+    for (int k = 0; k < 4; ++k) pa.gquats[(int64_t)k * n + i0] = 0.f;
+    pa.gopac[i0] = 0.f;
+    for (int k = 0; k < 48; ++k) pa.gsh[(int64_t)k * n + i0] = 0.f;
+  }
+  const uint64_t bal = __ballot(work);
+  const int wv = threadIdx.x >> 6;
+  if (lane_id() == 0) s_wave[wv] = (uint32_t)__popcll(bal);
+  __syncthreads();
+  uint32_t off = 0, total = 0;
+#pragma unroll
+  for (int w = 0; w < kBlock / kWave; ++w) {
+    off += w < wv ? s_wave[w] : 0u;
+    total += s_wave[w];
+  }
+  if (work) s_list[off + (uint32_t)__popcll(bal & ((1ull << lane_id()) - 1ull))] = (int32_t)(i0 - (int64_t)blockIdx.x * kBlock);
+  __syncthreads();
+  if ((uint32_t)threadIdx.x >= total) return;
+  const int64_t i = (int64_t)blockIdx.x * kBlock + s_list[threadIdx.x];
   constexpr int K = (DEG + 1) * (DEG + 1);
   double gm[3] = {0, 0, 0}, gs[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, go = 0.0;
-  const bool act = pa.active == nullptr || pa.active[i] != 0;
-  auto live = [&](int v) {
-    const int64_t r = (int64_t)v * n + i;
-    if (pa.bin[4 * r + 3] == 0) return false;
-    const float* gr = pa.g2d + r * kG2d;
-    bool nz = false;
-#pragma unroll
-    for (int k = 0; k < kG2d; ++k) nz = nz || gr[k] != 0.f;
-    return nz;
-  };
   // pass 1: geometry (mean through u, v and J; covariance; opacity)
-  if (act) {
-    for (int v = 0; v < vs.count; ++v) {
-      if (!live(v)) continue;
-      const float* gr = pa.g2d + ((int64_t)v * n + i) * kG2d;
-      go += gr[5];
-      geometry_backward(vs.v[v], pa.op, pa.sc, i, gr, gm, gs, gq);
-    }
+  for (int v = 0; v < vs.count; ++v) {
+    const int64_t r = (int64_t)v * n + i;
+    if (!record_live(pa, r)) continue;
+    const float* gr = pa.g2d + r * kG2d;
+    go += gr[5];
+    geometry_backward(vs.v[v], pa.op, pa.sc, i, gr, gm, gs, gq);
   }
   pa.gscales[i] = (float)gs[0]; pa.gscales[n + i] = (float)gs[1]; pa.gscales[2 * n + i] = (float)gs[2];
   for (int k = 0; k < 4; ++k) pa.gquats[(int64_t)k * n + i] = (float)gq[k];
@@ -329,42 +362,41 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd(ProjBwdArgs pa, ViewSet 
   float gsh[K][3];
 #pragma unroll
   for (int k = 0; k < K; ++k) gsh[k][0] = gsh[k][1] = gsh[k][2] = 0.f;
-  if (act) {
-    const float* shp = pa.sc.sh;
-    for (int v = 0; v < vs.count; ++v) {
-      if (!live(v)) continue;
-      const float* gr = pa.g2d + ((int64_t)v * n + i) * kG2d;
-      const KView& cam = vs.v[v];
-      double cc[3];
-      camera_centre(cam, cc);
-      const double e0 = pa.sc.means[i] - cc[0], e1 = pa.sc.means[n + i] - cc[1], e2 = pa.sc.means[2 * n + i] - cc[2];
-      const double il = 1.0 / sqrt(e0 * e0 + e1 * e1 + e2 * e2);
-      const double d0 = e0 * il, d1 = e1 * il, d2 = e2 * il;
-      // raw colour per channel decides the clamp at 0
-      double raw[3] = {0.5, 0.5, 0.5};
-      sh_terms<DEG>(d0, d1, d2, [&](int k, double Yk, double, double, double) {
+  const float* shp = pa.sc.sh;
+  for (int v = 0; v < vs.count; ++v) {
+    const int64_t r = (int64_t)v * n + i;
+    if (!record_live(pa, r)) continue;
+    const float* gr = pa.g2d + r * kG2d;
+    const KView& cam = vs.v[v];
+    double cc[3];
+    camera_centre(cam, cc);
+    const double e0 = pa.sc.means[i] - cc[0], e1 = pa.sc.means[n + i] - cc[1], e2 = pa.sc.means[2 * n + i] - cc[2];
+    const double il = 1.0 / sqrt(e0 * e0 + e1 * e1 + e2 * e2);
+    const double d0 = e0 * il, d1 = e1 * il, d2 = e2 * il;
+    // raw colour per channel decides the clamp at 0
+    double raw[3] = {0.5, 0.5, 0.5};
+    sh_terms<DEG>(d0, d1, d2, [&](int k, double Yk, double, double, double) {
 #pragma unroll
-        for (int ch = 0; ch < 3; ++ch) raw[ch] += (double)shp[(int64_t)(k * 3 + ch) * n + i] * Yk;
-      });
-      const double gc0 = raw[0] < 0.0 ? 0.0 : gr[6], gc1 = raw[1] < 0.0 ? 0.0 : gr[7];
-      const double gc2 = raw[2] < 0.0 ? 0.0 : gr[8];
-      double gd0 = 0.0, gd1 = 0.0, gd2 = 0.0;
-      sh_terms<DEG>(d0, d1, d2, [&](int k, double Yk, double Gx, double Gy, double Gz) {
-        gsh[k][0] += (float)(gc0 * Yk);
-        gsh[k][1] += (float)(gc1 * Yk);
-        gsh[k][2] += (float)(gc2 * Yk);
-        const double vk = gc0 * shp[(int64_t)(k * 3 + 0) * n + i] + gc1 * shp[(int64_t)(k * 3 + 1) * n + i] +
-                          gc2 * shp[(int64_t)(k * 3 + 2) * n + i];
-        gd0 += vk * Gx;
-        gd1 += vk * Gy;
-        gd2 += vk * Gz;
-      });
-      // dir = e / |e|: project out the radial part
-      const double dd = gd0 * d0 + gd1 * d1 + gd2 * d2;
-      gm[0] += (gd0 - d0 * dd) * il;
-      gm[1] += (gd1 - d1 * dd) * il;
-      gm[2] += (gd2 - d2 * dd) * il;
-    }
+      for (int ch = 0; ch < 3; ++ch) raw[ch] += (double)shp[(int64_t)(k * 3 + ch) * n + i] * Yk;
+    });
+    const double gc0 = raw[0] < 0.0 ? 0.0 : gr[6], gc1 = raw[1] < 0.0 ? 0.0 : gr[7];
+    const double gc2 = raw[2] < 0.0 ? 0.0 : gr[8];
+    double gd0 = 0.0, gd1 = 0.0, gd2 = 0.0;
+    sh_terms<DEG>(d0, d1, d2, [&](int k, double Yk, double Gx, double Gy, double Gz) {
+      gsh[k][0] += (float)(gc0 * Yk);
+      gsh[k][1] += (float)(gc1 * Yk);
+      gsh[k][2] += (float)(gc2 * Yk);
+      const double vk = gc0 * shp[(int64_t)(k * 3 + 0) * n + i] + gc1 * shp[(int64_t)(k * 3 + 1) * n + i] +
+                        gc2 * shp[(int64_t)(k * 3 + 2) * n + i];
+      gd0 += vk * Gx;
+      gd1 += vk * Gy;
+      gd2 += vk * Gz;
+    });
+    // dir = e / |e|: project out the radial part
+    const double dd = gd0 * d0 + gd1 * d1 + gd2 * d2;
+    gm[0] += (gd0 - d0 * dd) * il;
+    gm[1] += (gd1 - d1 * dd) * il;
+    gm[2] += (gd2 - d2 * dd) * il;
   }
   pa.gmeans[i] = (float)gm[0]; pa.gmeans[n + i] = (float)gm[1]; pa.gmeans[2 * n + i] = (float)gm[2];
 #pragma unroll

@@ -27,3 +27,8 @@ def test_no_scratch_and_bounded_registers(tmp_path, src):
     vgprs = [int(x) for x in re.findall(r"\.vgpr_count:\s+(\d+)", asm)]
     # >= 2 waves per SIMD for the FP64 projection backward; the rest stay far below
     assert max(vgprs) <= 272, f"{src}: {vgprs}"
+    # a same-address atomic rewritten into a loop over the active lanes reads
+    # each lane with v_readlane at an SGPR lane index; the kernels reduce such
+    # values in registers themselves, so the pattern must not appear
+    loops = re.findall(r"v_readlane_b32 s\d+, v\d+, s\d+", asm)
+    assert not loops, f"{src}: {len(loops)} per-lane atomic loops"
