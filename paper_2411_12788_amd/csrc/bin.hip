@@ -252,11 +252,22 @@ __global__ void k_order_scan(uint32_t* __restrict__ hist) {
   }
 }
 
+// Positions are taken per workgroup: LDS counters rank the tiles of each
+// bucket, then one global atomic per (workgroup, bucket) reserves the run.
+// (Per-tile global atomics on ~16 cursors serialise in the L2.)
 __global__ __launch_bounds__(kBlock) void k_order_scatter(const uint32_t* __restrict__ ranges, int32_t tiles,
                                                           uint32_t* __restrict__ cursor, uint32_t* __restrict__ order) {
+  __shared__ uint32_t cnt[kOrderBuckets], base[kOrderBuckets];
+  if (threadIdx.x < kOrderBuckets) cnt[threadIdx.x] = 0;
+  __syncthreads();
   const int32_t t = blockIdx.x * kBlock + threadIdx.x;
+  const int b = t < tiles ? order_bucket(ranges, t) : 0;
+  const uint32_t local = t < tiles ? atomicAdd(&cnt[b], 1u) : 0u;
+  __syncthreads();
+  if (threadIdx.x < kOrderBuckets && cnt[threadIdx.x]) base[threadIdx.x] = atomicAdd(cursor + threadIdx.x, cnt[threadIdx.x]);
+  __syncthreads();
   if (t >= tiles) return;
-  const uint32_t pos = atomicAdd(cursor + order_bucket(ranges, t), 1u);
+  const uint32_t pos = base[b] + local;
   if (pos < (uint32_t)tiles) order[pos] = (uint32_t)t;
 }
 

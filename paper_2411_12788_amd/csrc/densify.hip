@@ -404,7 +404,7 @@ int32_t launch_threshold(const Source& src, int P, double keep, int32_t mode, ui
     set_error("unknown threshold mode");
     return GS_ERR_UNSUPPORTED;
   }
-  if (!ws || !tau || !out) { set_error("NULL workspace, tau or output"); return GS_ERR_NULL; }
+  if (!ws || !tau || (!out && src.n > 0)) { set_error("NULL workspace, tau or output"); return GS_ERR_NULL; }
   if (ws_bytes < gs_select_workspace_size(P)) { set_error("selection workspace too small"); return GS_ERR_CAPACITY; }
   uint8_t* w = (uint8_t*)ws;
   const bool mass = mode == GS_THRESHOLD_MASS;

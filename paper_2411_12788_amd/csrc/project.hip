@@ -307,29 +307,28 @@ __device__ __forceinline__ bool record_live(const ProjBwdArgs& pa, int64_t r) {
   return nz;
 }
 
-// Each workgroup first sorts its 256 Gaussians: rows with no gradient (inactive,
-// or live in no view) are written as zeros at once, the others are packed into
-// an LDS list, and only the first waves run the double-precision chain rule on
-// that dense list.  Without the packing a wave would run the heavy path at the
-// lane utilisation of the active fraction.
+// Each workgroup first sorts its 256 Gaussians: those with gradient (active,
+// and live in some view) are packed into an LDS list, and only the first waves
+// run the double-precision chain rule on that dense list (without the packing
+// a wave would run the heavy path at the lane utilisation of the active
+// fraction).  Results go to an LDS tile in row order, and the whole workgroup
+// then writes all 59 gradient planes of its rows with coalesced stores, zeros
+// for the rows without gradient.
+constexpr int kGradPlanes = 3 + 3 + 4 + 1 + 48;  // means, scales, quats, opacity, sh
+
 template <int DEG>
 __global__ __launch_bounds__(kBlock) void k_project_bwd(ProjBwdArgs pa, ViewSet vs) {
   __shared__ int32_t s_list[kBlock];
   __shared__ uint32_t s_wave[kBlock / kWave];
+  __shared__ float s_out[kGradPlanes][kBlock];
   const int64_t n = pa.sc.n;
-  const int64_t i0 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t row0 = (int64_t)blockIdx.x * kBlock;
+  const int64_t i0 = row0 + threadIdx.x;
   bool work = i0 < n && (pa.active == nullptr || pa.active[i0] != 0);
   if (work) {
     bool any = false;
     for (int v = 0; v < vs.count && !any; ++v) any = record_live(pa, (int64_t)v * n + i0);
     work = any;
-  }
-  if (i0 < n && !work) {
-    pa.gmeans[i0] = 0.f; pa.gmeans[n + i0] = 0.f; pa.gmeans[2 * n + i0] = 0.f;
-    pa.gscales[i0] = 0.f; pa.gscales[n + i0] = 0.f; pa.gscales[2 * n + i0] = 0.f;
-    for (int k = 0; k < 4; ++k) pa.gquats[(int64_t)k * n + i0] = 0.f;
-    pa.gopac[i0] = 0.f;
-    for (int k = 0; k < 48; ++k) pa.gsh[(int64_t)k * n + i0] = 0.f;
   }
   const uint64_t bal = __ballot(work);
   const int wv = threadIdx.x >> 6;
@@ -341,69 +340,78 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd(ProjBwdArgs pa, ViewSet 
     off += w < wv ? s_wave[w] : 0u;
     total += s_wave[w];
   }
-  if (work) s_list[off + (uint32_t)__popcll(bal & ((1ull << lane_id()) - 1ull))] = (int32_t)(i0 - (int64_t)blockIdx.x * kBlock);
+  if (work) s_list[off + (uint32_t)__popcll(bal & ((1ull << lane_id()) - 1ull))] = (int32_t)threadIdx.x;
   __syncthreads();
-  if ((uint32_t)threadIdx.x >= total) return;
-  const int64_t i = (int64_t)blockIdx.x * kBlock + s_list[threadIdx.x];
-  constexpr int K = (DEG + 1) * (DEG + 1);
-  double gm[3] = {0, 0, 0}, gs[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, go = 0.0;
-  // pass 1: geometry (mean through u, v and J; covariance; opacity)
-  for (int v = 0; v < vs.count; ++v) {
-    const int64_t r = (int64_t)v * n + i;
-    if (!record_live(pa, r)) continue;
-    const float* gr = pa.g2d + r * kG2d;
-    go += gr[5];
-    geometry_backward(vs.v[v], pa.op, pa.sc, i, gr, gm, gs, gq);
+  if ((uint32_t)threadIdx.x < total) {
+    const int slot = s_list[threadIdx.x];
+    const int64_t i = row0 + slot;
+    constexpr int K = (DEG + 1) * (DEG + 1);
+    double gm[3] = {0, 0, 0}, gs[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, go = 0.0;
+    // pass 1: geometry (mean through u, v and J; covariance; opacity)
+    for (int v = 0; v < vs.count; ++v) {
+      const int64_t r = (int64_t)v * n + i;
+      if (!record_live(pa, r)) continue;
+      const float* gr = pa.g2d + r * kG2d;
+      go += gr[5];
+      geometry_backward(vs.v[v], pa.op, pa.sc, i, gr, gm, gs, gq);
+    }
+    for (int k = 0; k < 3; ++k) s_out[3 + k][slot] = (float)gs[k];
+    for (int k = 0; k < 4; ++k) s_out[6 + k][slot] = (float)gq[k];
+    s_out[10][slot] = (float)go;
+    // pass 2: colour (SH coefficients, and the mean through the viewing direction)
+    float gsh[K][3];
+#pragma unroll
+    for (int k = 0; k < K; ++k) gsh[k][0] = gsh[k][1] = gsh[k][2] = 0.f;
+    const float* shp = pa.sc.sh;
+    for (int v = 0; v < vs.count; ++v) {
+      const int64_t r = (int64_t)v * n + i;
+      if (!record_live(pa, r)) continue;
+      const float* gr = pa.g2d + r * kG2d;
+      const KView& cam = vs.v[v];
+      double cc[3];
+      camera_centre(cam, cc);
+      const double e0 = pa.sc.means[i] - cc[0], e1 = pa.sc.means[n + i] - cc[1], e2 = pa.sc.means[2 * n + i] - cc[2];
+      const double il = 1.0 / sqrt(e0 * e0 + e1 * e1 + e2 * e2);
+      const double d0 = e0 * il, d1 = e1 * il, d2 = e2 * il;
+      // raw colour per channel decides the clamp at 0
+      double raw[3] = {0.5, 0.5, 0.5};
+      sh_terms<DEG>(d0, d1, d2, [&](int k, double Yk, double, double, double) {
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) raw[ch] += (double)shp[(int64_t)(k * 3 + ch) * n + i] * Yk;
+      });
+      const double gc0 = raw[0] < 0.0 ? 0.0 : gr[6], gc1 = raw[1] < 0.0 ? 0.0 : gr[7];
+      const double gc2 = raw[2] < 0.0 ? 0.0 : gr[8];
+      double gd0 = 0.0, gd1 = 0.0, gd2 = 0.0;
+      sh_terms<DEG>(d0, d1, d2, [&](int k, double Yk, double Gx, double Gy, double Gz) {
+        gsh[k][0] += (float)(gc0 * Yk);
+        gsh[k][1] += (float)(gc1 * Yk);
+        gsh[k][2] += (float)(gc2 * Yk);
+        const double vk = gc0 * shp[(int64_t)(k * 3 + 0) * n + i] + gc1 * shp[(int64_t)(k * 3 + 1) * n + i] +
+                          gc2 * shp[(int64_t)(k * 3 + 2) * n + i];
+        gd0 += vk * Gx;
+        gd1 += vk * Gy;
+        gd2 += vk * Gz;
+      });
+      // dir = e / |e|: project out the radial part
+      const double dd = gd0 * d0 + gd1 * d1 + gd2 * d2;
+      gm[0] += (gd0 - d0 * dd) * il;
+      gm[1] += (gd1 - d1 * dd) * il;
+      gm[2] += (gd2 - d2 * dd) * il;
+    }
+    for (int k = 0; k < 3; ++k) s_out[k][slot] = (float)gm[k];
+#pragma unroll
+    for (int k = 0; k < 16; ++k)
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) s_out[11 + k * 3 + ch][slot] = k < K ? gsh[k < K ? k : 0][ch] : 0.f;
   }
-  pa.gscales[i] = (float)gs[0]; pa.gscales[n + i] = (float)gs[1]; pa.gscales[2 * n + i] = (float)gs[2];
-  for (int k = 0; k < 4; ++k) pa.gquats[(int64_t)k * n + i] = (float)gq[k];
-  pa.gopac[i] = (float)go;
-  // pass 2: colour (SH coefficients, and the mean through the viewing direction)
-  float gsh[K][3];
+  __syncthreads();
+  if (i0 >= n) return;
+  float* const planes[5] = {pa.gmeans, pa.gscales, pa.gquats, pa.gopac, pa.gsh};
+  const int first[6] = {0, 3, 6, 10, 11, kGradPlanes};
 #pragma unroll
-  for (int k = 0; k < K; ++k) gsh[k][0] = gsh[k][1] = gsh[k][2] = 0.f;
-  const float* shp = pa.sc.sh;
-  for (int v = 0; v < vs.count; ++v) {
-    const int64_t r = (int64_t)v * n + i;
-    if (!record_live(pa, r)) continue;
-    const float* gr = pa.g2d + r * kG2d;
-    const KView& cam = vs.v[v];
-    double cc[3];
-    camera_centre(cam, cc);
-    const double e0 = pa.sc.means[i] - cc[0], e1 = pa.sc.means[n + i] - cc[1], e2 = pa.sc.means[2 * n + i] - cc[2];
-    const double il = 1.0 / sqrt(e0 * e0 + e1 * e1 + e2 * e2);
-    const double d0 = e0 * il, d1 = e1 * il, d2 = e2 * il;
-    // raw colour per channel decides the clamp at 0
-    double raw[3] = {0.5, 0.5, 0.5};
-    sh_terms<DEG>(d0, d1, d2, [&](int k, double Yk, double, double, double) {
-#pragma unroll
-      for (int ch = 0; ch < 3; ++ch) raw[ch] += (double)shp[(int64_t)(k * 3 + ch) * n + i] * Yk;
-    });
-    const double gc0 = raw[0] < 0.0 ? 0.0 : gr[6], gc1 = raw[1] < 0.0 ? 0.0 : gr[7];
-    const double gc2 = raw[2] < 0.0 ? 0.0 : gr[8];
-    double gd0 = 0.0, gd1 = 0.0, gd2 = 0.0;
-    sh_terms<DEG>(d0, d1, d2, [&](int k, double Yk, double Gx, double Gy, double Gz) {
-      gsh[k][0] += (float)(gc0 * Yk);
-      gsh[k][1] += (float)(gc1 * Yk);
-      gsh[k][2] += (float)(gc2 * Yk);
-      const double vk = gc0 * shp[(int64_t)(k * 3 + 0) * n + i] + gc1 * shp[(int64_t)(k * 3 + 1) * n + i] +
-                        gc2 * shp[(int64_t)(k * 3 + 2) * n + i];
-      gd0 += vk * Gx;
-      gd1 += vk * Gy;
-      gd2 += vk * Gz;
-    });
-    // dir = e / |e|: project out the radial part
-    const double dd = gd0 * d0 + gd1 * d1 + gd2 * d2;
-    gm[0] += (gd0 - d0 * dd) * il;
-    gm[1] += (gd1 - d1 * dd) * il;
-    gm[2] += (gd2 - d2 * dd) * il;
-  }
-  pa.gmeans[i] = (float)gm[0]; pa.gmeans[n + i] = (float)gm[1]; pa.gmeans[2 * n + i] = (float)gm[2];
-#pragma unroll
-  for (int k = 0; k < 16; ++k)
-#pragma unroll
-    for (int ch = 0; ch < 3; ++ch)
-      pa.gsh[(int64_t)(k * 3 + ch) * n + i] = k < K ? gsh[k < K ? k : 0][ch] : 0.f;
+  for (int g = 0; g < 5; ++g)
+    for (int p = first[g]; p < first[g + 1]; ++p)
+      planes[g][(int64_t)(p - first[g]) * n + i0] = work ? s_out[p][threadIdx.x] : 0.f;
 }
 
 }  // namespace msplat

@@ -120,29 +120,28 @@ __device__ __forceinline__ float swap_sum32(float x) {
   const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(x), false, false);
   return __uint_as_float(r[0]) + __uint_as_float(r[1]);
 }
-// Full-wave sum and max of one value, in every lane: quad permutes, row
-// rotates by 4 and 8, then the row and half swaps.
-__device__ __forceinline__ float wave_sum_all(float x) {
-  x += dpp_take<0xB1>(x);
-  x += dpp_take<0x4E>(x);
-  x += dpp_take<0x124>(x);
-  x += dpp_take<0x128>(x);
-  return swap_sum32(swap_sum16(x));
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_take_u32(uint32_t x) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, 0xF, 0xF, true);
 }
-__device__ __forceinline__ float swap_max16(float x) {
-  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(x), false, false);
-  return fmaxf(__uint_as_float(r[0]), __uint_as_float(r[1]));
-}
-__device__ __forceinline__ float swap_max32(float x) {
-  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(x), false, false);
-  return fmaxf(__uint_as_float(r[0]), __uint_as_float(r[1]));
-}
-__device__ __forceinline__ float wave_max_all(float x) {
-  x = fmaxf(x, dpp_take<0xB1>(x));
-  x = fmaxf(x, dpp_take<0x4E>(x));
-  x = fmaxf(x, dpp_take<0x124>(x));
-  x = fmaxf(x, dpp_take<0x128>(x));
-  return swap_max32(swap_max16(x));
+// Sum and max over each 16-lane row, in every lane of the row: quad permutes
+// (xor 1, xor 2) give quad totals, row rotates by 4 and 8 add the other quads.
+struct RowSumMax {
+  float sum;
+  uint32_t max;  // bit pattern of the largest (non-negative) value
+};
+__device__ __forceinline__ RowSumMax row_sum_max(float x) {
+  float s = x;
+  uint32_t m = __float_as_uint(x);
+  s += dpp_take<0xB1>(s);
+  m = max(m, dpp_take_u32<0xB1>(m));
+  s += dpp_take<0x4E>(s);
+  m = max(m, dpp_take_u32<0x4E>(m));
+  s += dpp_take<0x124>(s);
+  m = max(m, dpp_take_u32<0x124>(m));
+  s += dpp_take<0x128>(s);
+  m = max(m, dpp_take_u32<0x128>(m));
+  return RowSumMax{s, m};
 }
 
 struct Sum9 {
@@ -283,38 +282,38 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(const float* __restrict__
         const int kk = c * kWave + (int)__builtin_ctzll(mask);
         mask &= mask - 1;
         const float4 r0 = s_r0[kk], r1 = s_r1[kk], r2 = s_r2[kk];
-        float wgt = 0.f;
-        bool inc = false;
-        if (!done) {
-          const float dx = (pxc - r0.x) - r0.z;
-          const float dy = (pyc - r0.y) - r0.w;
-          const float e = r1.w - (r1.x * dx * dx + r1.y * dx * dy + r1.z * dy * dy);
-          if (e >= op.log2_alpha_min) {
-            const float al = fminf(op.alpha_max, __builtin_amdgcn_exp2f(e));
-            const float Tn = T * (1.f - al);
-            if (Tn < op.t_min) {
-              done = true;
-            } else {
-              wgt = al * T;
-              c0 += wgt * r2.x;
-              c1 += wgt * r2.y;
-              c2 += wgt * r2.z;
-              if (DEPTH == GS_DEPTH_BLEND) dblend += wgt * s_z[kk];
-              if (wgt > wbest) { wbest = wgt; best = (int32_t)((int64_t)s_idx[kk] - vbase); }
-              T = Tn;
-              lastpos = base + (uint32_t)kk - start + 1;
-              ++cnt;
-              inc = true;
-            }
-          }
-        }
+        // Branch-free per lane: every lane evaluates, selects keep the state of
+        // lanes that skip the entry or have stopped (staged records are finite,
+        // so adding a zero weight leaves the colour unchanged).
+        const float dx = (pxc - r0.x) - r0.z;
+        const float dy = (pyc - r0.y) - r0.w;
+        const float e = r1.w - (r1.x * dx * dx + r1.y * dx * dy + r1.z * dy * dy);
+        const bool pass = !done && e >= op.log2_alpha_min;
+        const float al = fminf(op.alpha_max, __builtin_amdgcn_exp2f(e));
+        const float Tn = T * (1.f - al);
+        const bool stop = pass && Tn < op.t_min;
+        const bool inc = pass && !stop;
+        done = done || stop;
+        const float wgt = inc ? al * T : 0.f;
+        c0 += wgt * r2.x;
+        c1 += wgt * r2.y;
+        c2 += wgt * r2.z;
+        if (DEPTH == GS_DEPTH_BLEND) dblend += wgt * s_z[kk];
+        const int32_t bi = (int32_t)((int64_t)s_idx[kk] - vbase);
+        const bool better = wgt > wbest;  // strict: the nearest wins ties
+        wbest = better ? wgt : wbest;
+        best = better ? bi : best;
+        T = inc ? Tn : T;
+        lastpos = inc ? base + (uint32_t)kk - start + 1 : lastpos;
+        cnt += inc ? 1u : 0u;
         if (ACC && __any(inc)) {
-          // one LDS update per wave and entry (the four quarter waves share the entry)
-          const float wv = inc ? wgt : 0.f;
-          const float wsum = wave_sum_all(wv), wmx = wave_max_all(wv);
-          if (lane == 0) {
-            atomicAdd(&s_acc_w[kk], wsum);
-            atomicMax(&s_acc_m[kk], __float_as_uint(wmx));  // weights are >= 0: bit order is value order
+          // Row (16-lane) sum and max in registers, the two chains interleaved,
+          // then one LDS add and one LDS max per row.  Weights are >= 0, so
+          // the max runs on their bit patterns.
+          const RowSumMax r = row_sum_max(wgt);
+          if ((lane & 15) == 0 && r.max != 0u) {
+            atomicAdd(&s_acc_w[kk], r.sum);
+            atomicMax(&s_acc_m[kk], r.max);
           }
         }
         if (__all(done)) {

@@ -178,7 +178,7 @@ def test_thresholds_full_size(gpu_lib, mode):
 def test_pipeline_visibility_from_render(gpu_lib):
     """Per-view accumulations of a real render feed the visibility mask:
     every visible Gaussian contributes, and the mask culls in projection."""
-    from gpu_helpers import run_gpu_forward
+    from tests.gpu_helpers import run_gpu_forward
     wl = gs_inputs.small_cube(seed=3)
     cams = wl.cameras
     res = run_gpu_forward(wl.scene, cams, per_view=True)
