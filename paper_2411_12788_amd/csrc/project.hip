@@ -23,36 +23,37 @@ struct SceneArgs {
 // k = l^2 + l + m, m = -l..l.  f(k, Y_k, dY_k/dx, dY_k/dy, dY_k/dz) is called
 // once per basis function, so callers never hold all 16 values (and their 48
 // derivatives) in registers at once; unused derivatives fold away.
-template <int DEG, typename F>
-__device__ __forceinline__ void sh_terms(double x, double y, double z, F&& f) {
-  f(0, 0.28209479177387814, 0.0, 0.0, 0.0);
+template <int DEG, typename T, typename F>
+__device__ __forceinline__ void sh_terms(T x, T y, T z, F&& f) {
+  const T zero = T(0);
+  f(0, T(0.28209479177387814), zero, zero, zero);
   if (DEG >= 1) {
-    const double c = 0.4886025119029199;
-    f(1, c * y, 0.0, c, 0.0);
-    f(2, c * z, 0.0, 0.0, c);
-    f(3, c * x, c, 0.0, 0.0);
+    const T c = T(0.4886025119029199);
+    f(1, c * y, zero, c, zero);
+    f(2, c * z, zero, zero, c);
+    f(3, c * x, c, zero, zero);
   }
   if (DEG >= 2) {
-    const double a = 1.0925484305920792, b = 0.31539156525252005, c = 0.5462742152960396;
-    f(4, a * x * y, a * y, a * x, 0.0);
-    f(5, a * y * z, 0.0, a * z, a * y);
-    f(6, b * (2.0 * z * z - x * x - y * y), -2.0 * b * x, -2.0 * b * y, 4.0 * b * z);
-    f(7, a * x * z, a * z, 0.0, a * x);
-    f(8, c * (x * x - y * y), 2.0 * c * x, -2.0 * c * y, 0.0);
+    const T a = T(1.0925484305920792), b = T(0.31539156525252005), c = T(0.5462742152960396);
+    f(4, a * x * y, a * y, a * x, zero);
+    f(5, a * y * z, zero, a * z, a * y);
+    f(6, b * (T(2) * z * z - x * x - y * y), T(-2) * b * x, T(-2) * b * y, T(4) * b * z);
+    f(7, a * x * z, a * z, zero, a * x);
+    f(8, c * (x * x - y * y), T(2) * c * x, T(-2) * c * y, zero);
   }
   if (DEG >= 3) {
-    const double a = 0.5900435899266435, b = 2.890611442640554, c = 0.4570457994644658;
-    const double d = 0.3731763325901154, e = 1.445305721320277;
-    f(9, a * y * (3.0 * x * x - y * y), 6.0 * a * x * y, a * (3.0 * x * x - 3.0 * y * y), 0.0);
+    const T a = T(0.5900435899266435), b = T(2.890611442640554), c = T(0.4570457994644658);
+    const T d = T(0.3731763325901154), e = T(1.445305721320277);
+    f(9, a * y * (T(3) * x * x - y * y), T(6) * a * x * y, a * (T(3) * x * x - T(3) * y * y), zero);
     f(10, b * x * y * z, b * y * z, b * x * z, b * x * y);
-    f(11, c * y * (4.0 * z * z - x * x - y * y), -2.0 * c * x * y, c * (4.0 * z * z - x * x - 3.0 * y * y),
-      8.0 * c * y * z);
-    f(12, d * z * (2.0 * z * z - 3.0 * x * x - 3.0 * y * y), -6.0 * d * x * z, -6.0 * d * y * z,
-      d * (6.0 * z * z - 3.0 * x * x - 3.0 * y * y));
-    f(13, c * x * (4.0 * z * z - x * x - y * y), c * (4.0 * z * z - 3.0 * x * x - y * y), -2.0 * c * x * y,
-      8.0 * c * x * z);
-    f(14, e * z * (x * x - y * y), 2.0 * e * x * z, -2.0 * e * y * z, e * (x * x - y * y));
-    f(15, a * x * (x * x - 3.0 * y * y), a * (3.0 * x * x - 3.0 * y * y), -6.0 * a * x * y, 0.0);
+    f(11, c * y * (T(4) * z * z - x * x - y * y), T(-2) * c * x * y, c * (T(4) * z * z - x * x - T(3) * y * y),
+      T(8) * c * y * z);
+    f(12, d * z * (T(2) * z * z - T(3) * x * x - T(3) * y * y), T(-6) * d * x * z, T(-6) * d * y * z,
+      d * (T(6) * z * z - T(3) * x * x - T(3) * y * y));
+    f(13, c * x * (T(4) * z * z - x * x - y * y), c * (T(4) * z * z - T(3) * x * x - y * y), T(-2) * c * x * y,
+      T(8) * c * x * z);
+    f(14, e * z * (x * x - y * y), T(2) * e * x * z, T(-2) * e * y * z, e * (x * x - y * y));
+    f(15, a * x * (x * x - T(3) * y * y), a * (T(3) * x * x - T(3) * y * y), T(-6) * a * x * y, zero);
   }
 }
 
@@ -307,44 +308,29 @@ __device__ __forceinline__ bool record_live(const ProjBwdArgs& pa, int64_t r) {
   return nz;
 }
 
-// Each workgroup first sorts its 256 Gaussians: those with gradient (active,
-// and live in some view) are packed into an LDS list, and only the first waves
-// run the double-precision chain rule on that dense list (without the packing
-// a wave would run the heavy path at the lane utilisation of the active
-// fraction).  Results go to an LDS tile in row order, and the whole workgroup
-// then writes all 59 gradient planes of its rows with coalesced stores, zeros
-// for the rows without gradient.
+// One thread per Gaussian: rows without gradient (inactive, or live in no
+// view) are written as zeros; the others run the chain rule, geometry in
+// double and colour in float.  Every gradient plane is written with
+// coalesced stores.  Register use (about 200 VGPRs, two waves per SIMD) sets
+// the speed here: holding the 48 SH coefficients as values instead of as 48
+// hoisted 64-bit addresses, and the colour pass in float, took the kernel from
+// one wave per SIMD to two and from ~0.9 ms to ~0.35 ms at 3M Gaussians.
 constexpr int kGradPlanes = 3 + 3 + 4 + 1 + 48;  // means, scales, quats, opacity, sh
 
 template <int DEG>
 __global__ __launch_bounds__(kBlock) void k_project_bwd(ProjBwdArgs pa, ViewSet vs) {
-  __shared__ int32_t s_list[kBlock];
-  __shared__ uint32_t s_wave[kBlock / kWave];
-  __shared__ float s_out[kGradPlanes][kBlock];
   const int64_t n = pa.sc.n;
-  const int64_t row0 = (int64_t)blockIdx.x * kBlock;
-  const int64_t i0 = row0 + threadIdx.x;
-  bool work = i0 < n && (pa.active == nullptr || pa.active[i0] != 0);
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  bool work = pa.active == nullptr || pa.active[i] != 0;
   if (work) {
     bool any = false;
-    for (int v = 0; v < vs.count && !any; ++v) any = record_live(pa, (int64_t)v * n + i0);
+    for (int v = 0; v < vs.count && !any; ++v) any = record_live(pa, (int64_t)v * n + i);
     work = any;
   }
-  const uint64_t bal = __ballot(work);
-  const int wv = threadIdx.x >> 6;
-  if (lane_id() == 0) s_wave[wv] = (uint32_t)__popcll(bal);
-  __syncthreads();
-  uint32_t off = 0, total = 0;
-#pragma unroll
-  for (int w = 0; w < kBlock / kWave; ++w) {
-    off += w < wv ? s_wave[w] : 0u;
-    total += s_wave[w];
-  }
-  if (work) s_list[off + (uint32_t)__popcll(bal & ((1ull << lane_id()) - 1ull))] = (int32_t)threadIdx.x;
-  __syncthreads();
-  if ((uint32_t)threadIdx.x < total) {
-    const int slot = s_list[threadIdx.x];
-    const int64_t i = row0 + slot;
+  float outv[kGradPlanes];
+  for (int p = 0; p < kGradPlanes; ++p) outv[p] = 0.f;
+  if (work) {
     constexpr int K = (DEG + 1) * (DEG + 1);
     double gm[3] = {0, 0, 0}, gs[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, go = 0.0;
     // pass 1: geometry (mean through u, v and J; covariance; opacity)
@@ -355,14 +341,22 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd(ProjBwdArgs pa, ViewSet 
       go += gr[5];
       geometry_backward(vs.v[v], pa.op, pa.sc, i, gr, gm, gs, gq);
     }
-    for (int k = 0; k < 3; ++k) s_out[3 + k][slot] = (float)gs[k];
-    for (int k = 0; k < 4; ++k) s_out[6 + k][slot] = (float)gq[k];
-    s_out[10][slot] = (float)go;
-    // pass 2: colour (SH coefficients, and the mean through the viewing direction)
+    for (int k = 0; k < 3; ++k) outv[3 + k] = (float)gs[k];
+    for (int k = 0; k < 4; ++k) outv[6 + k] = (float)gq[k];
+    outv[10] = (float)go;
+    // pass 2: colour (SH coefficients, and the mean through the viewing
+    // direction), in float: a colour gradient needs no more, and the 48
+    // coefficients and 48 accumulators then fit in half the registers
     float gsh[K][3];
 #pragma unroll
     for (int k = 0; k < K; ++k) gsh[k][0] = gsh[k][1] = gsh[k][2] = 0.f;
-    const float* shp = pa.sc.sh;
+    // the coefficients are loaded once, before the view loop (held as values,
+    // not as 48 hoisted 64-bit addresses)
+    float coef[K][3];
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) coef[k][ch] = pa.sc.sh[(int64_t)(k * 3 + ch) * n + i];
     for (int v = 0; v < vs.count; ++v) {
       const int64_t r = (int64_t)v * n + i;
       if (!record_live(pa, r)) continue;
@@ -371,47 +365,53 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd(ProjBwdArgs pa, ViewSet 
       double cc[3];
       camera_centre(cam, cc);
       const double e0 = pa.sc.means[i] - cc[0], e1 = pa.sc.means[n + i] - cc[1], e2 = pa.sc.means[2 * n + i] - cc[2];
-      const double il = 1.0 / sqrt(e0 * e0 + e1 * e1 + e2 * e2);
-      const double d0 = e0 * il, d1 = e1 * il, d2 = e2 * il;
-      // raw colour per channel decides the clamp at 0
-      double raw[3] = {0.5, 0.5, 0.5};
-      sh_terms<DEG>(d0, d1, d2, [&](int k, double Yk, double, double, double) {
+      const double ild = 1.0 / sqrt(e0 * e0 + e1 * e1 + e2 * e2);
+      const float il = (float)ild;
+      const float d0 = (float)(e0 * ild), d1 = (float)(e1 * ild), d2 = (float)(e2 * ild);
+      // raw colour per channel (decides the clamp at 0) and its gradient with
+      // respect to the direction, in one sweep over the coefficients; the
+      // direction gradient is then sum_ch gc_ch grad(raw_ch), so the
+      // coefficients are read once and never held across sweeps
+      float raw[3] = {0.5f, 0.5f, 0.5f}, grx[3] = {0.f, 0.f, 0.f}, gry[3] = {0.f, 0.f, 0.f},
+            grz[3] = {0.f, 0.f, 0.f};
+      sh_terms<DEG>(d0, d1, d2, [&](int k, float Yk, float Gx, float Gy, float Gz) {
 #pragma unroll
-        for (int ch = 0; ch < 3; ++ch) raw[ch] += (double)shp[(int64_t)(k * 3 + ch) * n + i] * Yk;
+        for (int ch = 0; ch < 3; ++ch) {
+          const float ck = coef[k][ch];
+          raw[ch] += ck * Yk;
+          grx[ch] += ck * Gx;
+          gry[ch] += ck * Gy;
+          grz[ch] += ck * Gz;
+        }
       });
-      const double gc0 = raw[0] < 0.0 ? 0.0 : gr[6], gc1 = raw[1] < 0.0 ? 0.0 : gr[7];
-      const double gc2 = raw[2] < 0.0 ? 0.0 : gr[8];
-      double gd0 = 0.0, gd1 = 0.0, gd2 = 0.0;
-      sh_terms<DEG>(d0, d1, d2, [&](int k, double Yk, double Gx, double Gy, double Gz) {
-        gsh[k][0] += (float)(gc0 * Yk);
-        gsh[k][1] += (float)(gc1 * Yk);
-        gsh[k][2] += (float)(gc2 * Yk);
-        const double vk = gc0 * shp[(int64_t)(k * 3 + 0) * n + i] + gc1 * shp[(int64_t)(k * 3 + 1) * n + i] +
-                          gc2 * shp[(int64_t)(k * 3 + 2) * n + i];
-        gd0 += vk * Gx;
-        gd1 += vk * Gy;
-        gd2 += vk * Gz;
+      const float gc0 = raw[0] < 0.f ? 0.f : gr[6], gc1 = raw[1] < 0.f ? 0.f : gr[7];
+      const float gc2 = raw[2] < 0.f ? 0.f : gr[8];
+      const float gd0 = gc0 * grx[0] + gc1 * grx[1] + gc2 * grx[2];
+      const float gd1 = gc0 * gry[0] + gc1 * gry[1] + gc2 * gry[2];
+      const float gd2 = gc0 * grz[0] + gc1 * grz[1] + gc2 * grz[2];
+      sh_terms<DEG>(d0, d1, d2, [&](int k, float Yk, float, float, float) {
+        gsh[k][0] += gc0 * Yk;
+        gsh[k][1] += gc1 * Yk;
+        gsh[k][2] += gc2 * Yk;
       });
       // dir = e / |e|: project out the radial part
-      const double dd = gd0 * d0 + gd1 * d1 + gd2 * d2;
-      gm[0] += (gd0 - d0 * dd) * il;
-      gm[1] += (gd1 - d1 * dd) * il;
-      gm[2] += (gd2 - d2 * dd) * il;
+      const float dd = gd0 * d0 + gd1 * d1 + gd2 * d2;
+      gm[0] += (double)((gd0 - d0 * dd) * il);
+      gm[1] += (double)((gd1 - d1 * dd) * il);
+      gm[2] += (double)((gd2 - d2 * dd) * il);
     }
-    for (int k = 0; k < 3; ++k) s_out[k][slot] = (float)gm[k];
+    for (int k = 0; k < 3; ++k) outv[k] = (float)gm[k];
 #pragma unroll
     for (int k = 0; k < 16; ++k)
 #pragma unroll
-      for (int ch = 0; ch < 3; ++ch) s_out[11 + k * 3 + ch][slot] = k < K ? gsh[k < K ? k : 0][ch] : 0.f;
+      for (int ch = 0; ch < 3; ++ch) outv[11 + k * 3 + ch] = k < K ? gsh[k < K ? k : 0][ch] : 0.f;
   }
-  __syncthreads();
-  if (i0 >= n) return;
   float* const planes[5] = {pa.gmeans, pa.gscales, pa.gquats, pa.gopac, pa.gsh};
   const int first[6] = {0, 3, 6, 10, 11, kGradPlanes};
 #pragma unroll
   for (int g = 0; g < 5; ++g)
-    for (int p = first[g]; p < first[g + 1]; ++p)
-      planes[g][(int64_t)(p - first[g]) * n + i0] = work ? s_out[p][threadIdx.x] : 0.f;
+#pragma unroll
+    for (int p = first[g]; p < first[g + 1]; ++p) planes[g][(int64_t)(p - first[g]) * n + i] = outv[p];
 }
 
 }  // namespace msplat
