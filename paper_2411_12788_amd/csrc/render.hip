@@ -181,6 +181,29 @@ __device__ __forceinline__ bool box_meets(int2 b, int32_t x0, int32_t x1, int32_
          (b.y & 0xffff) <= y1;
 }
 
+// Whether the region where the exponent lo - Q(dx, dy) reaches log2(alpha_min)
+// can meet a pixel centre of [x0, x1] x [y0, y1]: the continuous minimum of
+// the convex quadratic Q over the rectangle of centres (0 if the Gaussian's
+// centre is inside, else the least of the four edge minima, each a clamped
+// 1D vertex) against lo - log2(alpha_min), with a margin far above float
+// rounding.  Conservative, so culling with it never changes a result; it
+// drops the entries whose bounding box meets the rectangle but whose
+// (elongated, tilted) ellipse does not.
+__device__ __forceinline__ bool ellipse_meets(float4 r0, float4 r1, int32_t x0, int32_t x1, int32_t y0, int32_t y1,
+                                              float log2_alpha_min) {
+  const float lx = ((float)x0 + 0.5f - r0.x) - r0.z, hx = ((float)x1 + 0.5f - r0.x) - r0.z;
+  const float ly = ((float)y0 + 0.5f - r0.y) - r0.w, hy = ((float)y1 + 0.5f - r0.y) - r0.w;
+  if (lx <= 0.f && hx >= 0.f && ly <= 0.f && hy >= 0.f) return true;
+  const float A = r1.x, B = r1.y, C = r1.z;
+  const float iA = 0.5f / A, iC = 0.5f / C;
+  auto q = [&](float dx, float dy) { return A * dx * dx + B * dx * dy + C * dy * dy; };
+  const float ya = fminf(fmaxf(-B * lx * iC, ly), hy), yb = fminf(fmaxf(-B * hx * iC, ly), hy);
+  const float xa = fminf(fmaxf(-B * ly * iA, lx), hx), xb = fminf(fmaxf(-B * hy * iA, lx), hx);
+  const float m = fminf(fminf(q(lx, ya), q(hx, yb)), fminf(q(xa, ly), q(xb, hy)));
+  const float budget = r1.w - log2_alpha_min;
+  return m <= budget + 1e-3f * (1.f + fabsf(budget));
+}
+
 // Bounding rectangle of the lanes set in `am` (lane = 8 * row + column of the
 // wave's 8x8 quarter at (sx0, sy0)), from the ballot mask with scalar bit ops.
 struct Rect {
@@ -276,12 +299,21 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(const float* __restrict__
       const int k = c * kWave + lane;
       // cull against the pixels that are still compositing, not the whole quarter
       const Rect ar = active_rect(__ballot(!done), sx0, sy0);
-      const bool rel = (uint32_t)k < count && box_meets(s_box[k], ar.x0, ar.x1, ar.y0, ar.y1);
+      const bool rel = (uint32_t)k < count && box_meets(s_box[k], ar.x0, ar.x1, ar.y0, ar.y1) &&
+                       ellipse_meets(s_r0[k], s_r1[k], ar.x0, ar.x1, ar.y0, ar.y1, op.log2_alpha_min);
       uint64_t mask = __ballot(rel);
+      // the next entry's records are read one iteration ahead, so the LDS
+      // latency overlaps this entry's arithmetic
+      int kn = c * kWave + (mask != 0 ? (int)__builtin_ctzll(mask) : 0);
+      float4 n0 = s_r0[kn], n1 = s_r1[kn], n2 = s_r2[kn];
       while (mask != 0) {
-        const int kk = c * kWave + (int)__builtin_ctzll(mask);
+        const int kk = kn;
         mask &= mask - 1;
-        const float4 r0 = s_r0[kk], r1 = s_r1[kk], r2 = s_r2[kk];
+        const float4 r0 = n0, r1 = n1, r2 = n2;
+        kn = c * kWave + (mask != 0 ? (int)__builtin_ctzll(mask) : 0);
+        n0 = s_r0[kn];
+        n1 = s_r1[kn];
+        n2 = s_r2[kn];
         // Branch-free per lane: every lane evaluates, selects keep the state of
         // lanes that skip the entry or have stopped (staged records are finite,
         // so adding a zero weight leaves the colour unchanged).
@@ -447,7 +479,8 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(const float* __restrict__
       if (am == 0) continue;
       const Rect ar = active_rect(am, sx0, sy0);
       const bool rel = (uint32_t)k < count && base + (uint32_t)k < start + wjmax &&
-                       box_meets(s_box[k], ar.x0, ar.x1, ar.y0, ar.y1);
+                       box_meets(s_box[k], ar.x0, ar.x1, ar.y0, ar.y1) &&
+                       ellipse_meets(s_r0[k], s_r1[k], ar.x0, ar.x1, ar.y0, ar.y1, op.log2_alpha_min);
       uint64_t mask = __ballot(rel);
       while (mask != 0) {
         const int hb = 63 - (int)__builtin_clzll(mask);
