@@ -46,8 +46,10 @@ def test_recompute_matches_saved_lists_and_direct_backward(gpu_lib):
     col_b, gb = _run(_leaves(sc), cams, g, save_lists=True)
     assert torch.equal(col_a, col_b)
     for x, y in zip(ga, gb):
-        # float atomics may add in a different order; the lists themselves are identical
-        assert torch.allclose(x, y, rtol=1e-5, atol=1e-9)
+        # float atomics may add in a different order; the lists themselves are
+        # identical.  A reordered float32 sum differs by a few ulps of its
+        # running magnitude, which the largest entry of the group bounds.
+        assert float((x - y).abs().max()) <= 1e-5 * float(x.abs().max()) + 1e-12
     ds = R.DeviceScene.from_numpy(sc)
     p1 = R.project(ds, cams, R.RasterOpts())
     b1 = R.bin(p1, cams, ds.n)
@@ -70,7 +72,8 @@ def test_batched_views_equal_sum_of_single_views(gpu_lib):
         assert torch.equal(c1, col[:, sl])
         tot = g1 if tot is None else [a + b for a, b in zip(tot, g1)]
     for x, y in zip(gb, tot):
-        assert torch.allclose(x, y, rtol=1e-4, atol=1e-8)
+        # same sums, grouped per view instead of over all views at once
+        assert float((x - y).abs().max()) <= 1e-4 * float(x.abs().max()) + 1e-12
 
 
 def test_gradients_vs_oracle_and_finite_differences_256(gpu_lib):
