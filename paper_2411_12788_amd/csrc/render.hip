@@ -204,6 +204,31 @@ __device__ __forceinline__ bool ellipse_meets(float4 r0, float4 r1, int32_t x0, 
   return m <= budget + 1e-3f * (1.f + fabsf(budget));
 }
 
+// One list entry as staged in LDS: record index, pixel box, the first 48
+// bytes of its record (screen mean, scaled conic, colour and opacity) and,
+// for blended depth, its camera depth.  A corrupt index (>= V n) is replaced by
+// an entry with an empty box, so it is never dereferenced and never drawn.
+struct Staged {
+  uint32_t idx;
+  int2 box;
+  float4 r0, r1, r2;
+  float z;
+};
+__device__ __forceinline__ Staged fetch_entry(const float* __restrict__ rec, const int32_t* __restrict__ bin,
+                                              uint32_t r, bool in_list, int64_t nrec) {
+  Staged e;
+  const bool valid = in_list && (int64_t)r < nrec;
+  r = valid ? r : 0u;
+  e.idx = r;
+  e.box = valid ? *reinterpret_cast<const int2*>(bin + 4 * (int64_t)r) : make_int2(0xffff, 0xffff);
+  const float4* R4 = reinterpret_cast<const float4*>(rec + (int64_t)r * kRecFloats);
+  e.r0 = R4[0];
+  e.r1 = R4[1];
+  e.r2 = R4[2];
+  e.z = rec[(int64_t)r * kRecFloats + 12];
+  return e;
+}
+
 // Bounding rectangle of the lanes set in `am` (lane = 8 * row + column of the
 // wave's 8x8 quarter at (sx0, sy0)), from the ballot mask with scalar bit ops.
 struct Rect {
@@ -219,6 +244,18 @@ __device__ __forceinline__ Rect active_rect(uint64_t am, int32_t sx0, int32_t sy
   r.y1 = sy0 + ((63 - (int32_t)__builtin_clzll(am)) >> 3);
   r.x0 = sx0 + (int32_t)__builtin_ctz(cols);
   r.x1 = sx0 + (31 - (int32_t)__builtin_clz(cols));
+  return r;
+}
+
+// Bounding rectangle of the set bits of a 16-lane group's mask (4x4 pixels,
+// bit = 4 * row + column, non-zero) whose block starts at (gx0, gy0).
+__device__ __forceinline__ Rect group_rect(uint32_t bits, int32_t gx0, int32_t gy0) {
+  const uint32_t cols = (bits | (bits >> 4) | (bits >> 8) | (bits >> 12)) & 0xfu;
+  Rect r;
+  r.y0 = gy0 + ((int32_t)__builtin_ctz(bits) >> 2);
+  r.y1 = gy0 + ((31 - (int32_t)__builtin_clz(bits)) >> 2);
+  r.x0 = gx0 + (int32_t)__builtin_ctz(cols);
+  r.x1 = gx0 + (31 - (int32_t)__builtin_clz(cols));
   return r;
 }
 
@@ -260,9 +297,14 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(const float* __restrict__
   const KView& cam = vs.v[v];
   const int32_t lt = tile - cam.tile_base;
   const int32_t tx = lt % cam.tiles_x, ty = lt / cam.tiles_x;
+  // Lanes: a wave owns an 8x8 quarter of the tile as four 4x4 pixel groups,
+  // one group per 16-lane row (lane = 16 g + 4 y + x).  Each group walks its
+  // own stream of entries (those meeting its still-compositing pixels), so a
+  // wave iterates max over groups instead of the union of the four streams.
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int grp = lane >> 4;
   const int32_t sx0 = tx * kTile + (wv & 1) * 8, sy0 = ty * kTile + (wv >> 1) * 8;
-  const int32_t px = sx0 + (lane & 7), py = sy0 + (lane >> 3);
+  const int32_t px = sx0 + (grp & 1) * 4 + (lane & 3), py = sy0 + (grp >> 1) * 4 + ((lane >> 2) & 3);
   const bool inside = px < cam.width && py < cam.height;
   const float pxc = (float)px + 0.5f, pyc = (float)py + 0.5f;
   const uint32_t start = uload(ranges + 2 * tile), end = uload(ranges + 2 * tile + 1);
@@ -273,54 +315,63 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(const float* __restrict__
   int32_t best = -1;
   uint32_t lastpos = 0, cnt = 0;
   bool done = !inside;
+  // Staging pipeline: while round R is processed, the records of round R + 1
+  // and the list indices of round R + 2 are already in flight.
+  Staged cur = fetch_entry(rec, bin, start + threadIdx.x < end ? vals[start + threadIdx.x] : 0u,
+                           start + threadIdx.x < end, nrec);
+  uint32_t nidx = start + kBatch + threadIdx.x < end ? vals[start + kBatch + threadIdx.x] : 0u;
   for (uint32_t base = start; base < end; base += kBatch) {
     if (__syncthreads_and(done)) break;  // also orders this round's LDS writes after the last round's reads
-    const uint32_t j = base + threadIdx.x;
-    if (j < end) {
-      uint32_t r = vals[j];
-      const bool valid = (int64_t)r < nrec;  // a corrupt list entry is dropped, never dereferenced
-      r = valid ? r : 0u;
-      s_idx[threadIdx.x] = r;
-      s_box[threadIdx.x] = valid ? *reinterpret_cast<const int2*>(bin + 4 * (int64_t)r) : make_int2(0xffff, 0xffff);
-      const float4* R4 = reinterpret_cast<const float4*>(rec + (int64_t)r * kRecFloats);
-      s_r0[threadIdx.x] = R4[0];
-      s_r1[threadIdx.x] = R4[1];
-      s_r2[threadIdx.x] = R4[2];
-      if (DEPTH == GS_DEPTH_BLEND) s_z[threadIdx.x] = rec[(int64_t)r * kRecFloats + 12];
-    }
+    s_idx[threadIdx.x] = cur.idx;
+    s_box[threadIdx.x] = cur.box;
+    s_r0[threadIdx.x] = cur.r0;
+    s_r1[threadIdx.x] = cur.r1;
+    s_r2[threadIdx.x] = cur.r2;
+    if (DEPTH == GS_DEPTH_BLEND) s_z[threadIdx.x] = cur.z;
     if (ACC) {
       s_acc_w[threadIdx.x] = 0.f;
       s_acc_m[threadIdx.x] = 0u;
     }
     __syncthreads();
+    {
+      const uint32_t jn = base + kBatch + threadIdx.x, jnn = jn + kBatch;
+      cur = fetch_entry(rec, bin, nidx, jn < end, nrec);
+      nidx = jnn < end ? vals[jnn] : 0u;
+    }
     const uint32_t count = (end - base) < (uint32_t)kBatch ? (end - base) : (uint32_t)kBatch;
     bool wave_done = __all(done);
     for (int c = 0; c < kBatch / kWave && !wave_done; ++c) {
+      // staged entry k against each group's still-compositing pixels
       const int k = c * kWave + lane;
-      // cull against the pixels that are still compositing, not the whole quarter
-      const Rect ar = active_rect(__ballot(!done), sx0, sy0);
-      const bool rel = (uint32_t)k < count && box_meets(s_box[k], ar.x0, ar.x1, ar.y0, ar.y1) &&
-                       ellipse_meets(s_r0[k], s_r1[k], ar.x0, ar.x1, ar.y0, ar.y1, op.log2_alpha_min);
-      uint64_t mask = __ballot(rel);
-      // the next entry's records are read one iteration ahead, so the LDS
-      // latency overlaps this entry's arithmetic
-      int kn = c * kWave + (mask != 0 ? (int)__builtin_ctzll(mask) : 0);
-      float4 n0 = s_r0[kn], n1 = s_r1[kn], n2 = s_r2[kn];
-      while (mask != 0) {
-        const int kk = kn;
-        mask &= mask - 1;
-        const float4 r0 = n0, r1 = n1, r2 = n2;
-        kn = c * kWave + (mask != 0 ? (int)__builtin_ctzll(mask) : 0);
-        n0 = s_r0[kn];
-        n1 = s_r1[kn];
-        n2 = s_r2[kn];
+      const bool kin = (uint32_t)k < count;
+      const int2 bx = s_box[k];
+      const float4 q0 = s_r0[k], q1 = s_r1[k];
+      const uint64_t am = __ballot(!done);
+      uint64_t gmask[4];
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const uint32_t bits = (uint32_t)(am >> (16 * g)) & 0xffffu;
+        bool rel = false;
+        if (bits != 0u) {
+          const Rect rg = group_rect(bits, sx0 + (g & 1) * 4, sy0 + (g >> 1) * 4);
+          rel = kin && box_meets(bx, rg.x0, rg.x1, rg.y0, rg.y1) &&
+                ellipse_meets(q0, q1, rg.x0, rg.x1, rg.y0, rg.y1, op.log2_alpha_min);
+        }
+        gmask[g] = __ballot(rel);
+      }
+      uint64_t mine = grp == 0 ? gmask[0] : grp == 1 ? gmask[1] : grp == 2 ? gmask[2] : gmask[3];
+      while (__any(mine != 0)) {
+        const bool has = mine != 0;
+        const int kk = c * kWave + (has ? (int)__builtin_ctzll(mine) : 0);
+        mine &= mine - 1;
+        const float4 r0 = s_r0[kk], r1 = s_r1[kk], r2 = s_r2[kk];
         // Branch-free per lane: every lane evaluates, selects keep the state of
         // lanes that skip the entry or have stopped (staged records are finite,
         // so adding a zero weight leaves the colour unchanged).
         const float dx = (pxc - r0.x) - r0.z;
         const float dy = (pyc - r0.y) - r0.w;
         const float e = r1.w - (r1.x * dx * dx + r1.y * dx * dy + r1.z * dy * dy);
-        const bool pass = !done && e >= op.log2_alpha_min;
+        const bool pass = has && !done && e >= op.log2_alpha_min;
         const float al = fminf(op.alpha_max, __builtin_amdgcn_exp2f(e));
         const float Tn = T * (1.f - al);
         const bool stop = pass && Tn < op.t_min;
@@ -339,16 +390,19 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(const float* __restrict__
         lastpos = inc ? base + (uint32_t)kk - start + 1 : lastpos;
         cnt += inc ? 1u : 0u;
         if (ACC && __any(inc)) {
-          // Row (16-lane) sum and max in registers, the two chains interleaved,
-          // then one LDS add and one LDS max per row.  Weights are >= 0, so
-          // the max runs on their bit patterns.
+          // Per group (= row) sum and max of the weights in registers, then
+          // one LDS add and one LDS max by the row's first lane for the row's
+          // entry.  Weights are >= 0, so the max runs on their bit patterns.
           const RowSumMax r = row_sum_max(wgt);
           if ((lane & 15) == 0 && r.max != 0u) {
             atomicAdd(&s_acc_w[kk], r.sum);
             atomicMax(&s_acc_m[kk], r.max);
           }
         }
-        if (__all(done)) {
+        // a group whose pixels have all stopped drops the rest of its stream
+        const uint64_t dm = __ballot(done);
+        if (((dm >> (16 * grp)) & 0xffffull) == 0xffffull) mine = 0;
+        if (dm == ~0ull) {
           wave_done = true;
           break;
         }
