@@ -458,6 +458,73 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(const float* __restrict__
 // suffix.  Entries of inactive Gaussians update the per-pixel state but emit
 // no gradient.  The nine partials of an entry are summed over the wave with
 // DPP and added by one lane to the record's 2D gradient.
+// One list entry for the backward: as Staged, plus the rest of the record
+// (z and the conic) and the active flag in bit 31 of the index.  A corrupt
+// index (outside this view's records) is replaced by an inactive entry with an
+// empty box.
+struct StagedB {
+  uint32_t tag;
+  int2 box;
+  float4 r0, r1, r2, r3;
+};
+template <bool MASKED>
+__device__ __forceinline__ StagedB fetch_entry_bwd(const float* __restrict__ rec, const int32_t* __restrict__ bin,
+                                                   const uint8_t* __restrict__ active, uint32_t r, bool in_list,
+                                                   int64_t nrec, int64_t vbase) {
+  StagedB e;
+  const bool valid = in_list && (int64_t)r < nrec && (int64_t)r >= vbase;
+  r = valid ? r : (uint32_t)vbase;
+  const uint32_t act = (valid && (!MASKED || active[(int64_t)r - vbase] != 0)) ? 1u : 0u;
+  e.tag = r | (act << 31);
+  e.box = valid ? *reinterpret_cast<const int2*>(bin + 4 * (int64_t)r) : make_int2(0xffff, 0xffff);
+  const float4* R4 = reinterpret_cast<const float4*>(rec + (int64_t)r * kRecFloats);
+  e.r0 = R4[0];
+  e.r1 = R4[1];
+  e.r2 = R4[2];
+  e.r3 = R4[3];
+  return e;
+}
+
+// Sum of nine per-lane partials over each 16-lane row by the butterfly
+// reduce-scatter of wave_sum9 without its cross-row steps: afterwards lane L
+// of a row with bit 2 set holds the row total of value 4 (L & 1) +
+// 2 ((L >> 1) & 1) + ((L >> 3) & 1), and every lane holds the row total of
+// the ninth value.
+__device__ __forceinline__ Sum9 row_sum9(const float (&p)[9], int lane) {
+  constexpr int kXor1 = 0xB1, kXor2 = 0x4E, kRor8 = 0x128, kRor4 = 0x124;
+  const bool o1 = (lane & 1) != 0, o2 = (lane & 2) != 0, o8 = (lane & 8) != 0;
+  float a[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const float keep = o1 ? p[4 + j] : p[j], send = o1 ? p[j] : p[4 + j];
+    a[j] = keep + dpp_take<kXor1>(send);
+  }
+  float c[2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const float keep = o2 ? a[2 + j] : a[j], send = o2 ? a[j] : a[2 + j];
+    c[j] = keep + dpp_take<kXor2>(send);
+  }
+  float d = (o8 ? c[1] : c[0]) + dpp_take<kRor8>(o8 ? c[0] : c[1]);
+  d += dpp_take<kRor4>(d);  // lanes with bit 2 set: partner is lane ^ 4
+  float e = p[8] + dpp_take<kXor1>(p[8]);
+  e += dpp_take<kXor2>(e);
+  e += dpp_take<kRor4>(e);
+  e += dpp_take<kRor8>(e);
+  Sum9 r;
+  r.v = d;
+  r.v8 = e;
+  return r;
+}
+
+// Same lane layout and group streams as the forward, walking rounds and
+// entries back to front from the largest `last` of the workgroup.  Per pixel:
+// restore the transmittance in front of the Gaussian (T /= 1 - alpha), form
+// dL/dalpha from the colour composited behind it, and add the Gaussian's own
+// weighted colour to that suffix.  Entries of inactive Gaussians update the
+// per-pixel state but emit no gradient.  The nine partials of a group's entry
+// are summed over its 16 lanes in registers and added by nine of its lanes
+// to the record's 2D gradient.
 template <bool MASKED>
 __global__ __launch_bounds__(kBlock) void k_render_bwd(const float* __restrict__ rec, const int32_t* __restrict__ bin,
                                                        const uint32_t* __restrict__ vals,
@@ -478,8 +545,9 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(const float* __restrict__
   const int32_t lt = tile - cam.tile_base;
   const int32_t tx = lt % cam.tiles_x, ty = lt / cam.tiles_x;
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int grp = lane >> 4;
   const int32_t sx0 = tx * kTile + (wv & 1) * 8, sy0 = ty * kTile + (wv >> 1) * 8;
-  const int32_t px = sx0 + (lane & 7), py = sy0 + (lane >> 3);
+  const int32_t px = sx0 + (grp & 1) * 4 + (lane & 3), py = sy0 + (grp >> 1) * 4 + ((lane >> 2) & 3);
   const bool inside = px < cam.width && py < cam.height;
   const float pxc = (float)px + 0.5f, pyc = (float)py + 0.5f;
   const uint32_t start = uload(ranges + 2 * tile), end = uload(ranges + 2 * tile + 1);
@@ -499,46 +567,66 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(const float* __restrict__
   }
   lst = lst < end - start ? lst : end - start;  // `last` never exceeds the tile's list
   float s0 = T * op.bg[0], s1 = T * op.bg[1], s2 = T * op.bg[2];
-  // 2D-gradient component this lane adds after wave_sum9, or -1
-  const int slot = (lane & 0x34) == 0x04 ? 4 * (lane & 1) + 2 * ((lane >> 1) & 1) + ((lane >> 3) & 1)
-                                         : (lane == 20 ? 8 : -1);
+  // 2D-gradient component this lane adds after row_sum9, or -1
+  const int l16 = lane & 15;
+  const int slot = (l16 & 4) != 0 ? 4 * (l16 & 1) + 2 * ((l16 >> 1) & 1) + ((l16 >> 3) & 1) : (l16 == 0 ? 8 : -1);
   const uint32_t wjmax = uniform_u32(wave_max_u32(lst));
   if (lane == 0) s_jmax[wv] = wjmax;
   __syncthreads();
   uint32_t bjmax = 0;
 #pragma unroll
   for (int k = 0; k < kBlock / kWave; ++k) bjmax = s_jmax[k] > bjmax ? s_jmax[k] : bjmax;
-  for (uint32_t top = start + bjmax; top > start;) {
-    const uint32_t base = top - start > (uint32_t)kBatch ? top - kBatch : start;
+  // Rounds cover [base, top) downwards from start + bjmax.  Staging pipeline:
+  // the records of the next round and the list indices of the one after are
+  // in flight while a round is processed.
+  auto round_base = [&](uint32_t top) { return top - start > (uint32_t)kBatch ? top - kBatch : start; };
+  uint32_t top = start + bjmax;
+  uint32_t base = round_base(top);
+  StagedB cur = fetch_entry_bwd<MASKED>(rec, bin, active, base + threadIdx.x < top ? vals[base + threadIdx.x] : 0u,
+                                        base + threadIdx.x < top, nrec, vbase);
+  uint32_t nbase = round_base(base), ntop = base;
+  uint32_t nidx = nbase + threadIdx.x < ntop ? vals[nbase + threadIdx.x] : 0u;
+  while (top > start) {
     const uint32_t count = top - base;
     __syncthreads();  // the previous round's entries are consumed
-    if ((uint32_t)threadIdx.x < count) {
-      uint32_t r = vals[base + threadIdx.x];
-      const bool valid = (int64_t)r < nrec && (int64_t)r >= vbase;  // a corrupt entry is dropped
-      r = valid ? r : (uint32_t)vbase;
-      const uint32_t act = (valid && (!MASKED || active[(int64_t)r - vbase] != 0)) ? 1u : 0u;
-      s_idx[threadIdx.x] = r | (act << 31);
-      s_box[threadIdx.x] = valid ? *reinterpret_cast<const int2*>(bin + 4 * (int64_t)r) : make_int2(0xffff, 0xffff);
-      const float4* R4 = reinterpret_cast<const float4*>(rec + (int64_t)r * kRecFloats);
-      s_r0[threadIdx.x] = R4[0];
-      s_r1[threadIdx.x] = R4[1];
-      s_r2[threadIdx.x] = R4[2];
-      s_r3[threadIdx.x] = R4[3];
-    }
+    s_idx[threadIdx.x] = cur.tag;
+    s_box[threadIdx.x] = cur.box;
+    s_r0[threadIdx.x] = cur.r0;
+    s_r1[threadIdx.x] = cur.r1;
+    s_r2[threadIdx.x] = cur.r2;
+    s_r3[threadIdx.x] = cur.r3;
     __syncthreads();
+    {
+      // next round [nbase, ntop) and the one after it
+      cur = fetch_entry_bwd<MASKED>(rec, bin, active, nidx, ntop > start && nbase + threadIdx.x < ntop, nrec, vbase);
+      const uint32_t nnbase = round_base(nbase);
+      nidx = (nbase > start && nnbase + threadIdx.x < nbase) ? vals[nnbase + threadIdx.x] : 0u;
+    }
     for (int c = kBatch / kWave - 1; c >= 0; --c) {
       const int k = c * kWave + lane;
       // lanes that still have work in this chunk: their last entry lies above its first
       const uint64_t am = __ballot(lst > base + (uint32_t)(c * kWave) - start);
       if (am == 0) continue;
-      const Rect ar = active_rect(am, sx0, sy0);
-      const bool rel = (uint32_t)k < count && base + (uint32_t)k < start + wjmax &&
-                       box_meets(s_box[k], ar.x0, ar.x1, ar.y0, ar.y1) &&
-                       ellipse_meets(s_r0[k], s_r1[k], ar.x0, ar.x1, ar.y0, ar.y1, op.log2_alpha_min);
-      uint64_t mask = __ballot(rel);
-      while (mask != 0) {
-        const int hb = 63 - (int)__builtin_clzll(mask);
-        mask &= ~(1ull << hb);
+      const bool kin = (uint32_t)k < count && base + (uint32_t)k < start + wjmax;
+      const int2 bx = s_box[k];
+      const float4 q0 = s_r0[k], q1 = s_r1[k];
+      uint64_t gmask[4];
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const uint32_t bits = (uint32_t)(am >> (16 * g)) & 0xffffu;
+        bool rel = false;
+        if (bits != 0u) {
+          const Rect rg = group_rect(bits, sx0 + (g & 1) * 4, sy0 + (g >> 1) * 4);
+          rel = kin && box_meets(bx, rg.x0, rg.x1, rg.y0, rg.y1) &&
+                ellipse_meets(q0, q1, rg.x0, rg.x1, rg.y0, rg.y1, op.log2_alpha_min);
+        }
+        gmask[g] = __ballot(rel);
+      }
+      uint64_t mine = grp == 0 ? gmask[0] : grp == 1 ? gmask[1] : grp == 2 ? gmask[2] : gmask[3];
+      while (__any(mine != 0)) {
+        const bool has = mine != 0;
+        const int hb = has ? 63 - (int)__builtin_clzll(mine) : 0;
+        mine &= ~(1ull << hb);
         const int kk = c * kWave + hb;
         const uint32_t j = base + (uint32_t)kk;
         const uint32_t tag = s_idx[kk];
@@ -546,7 +634,7 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(const float* __restrict__
         const float4 r0 = s_r0[kk], r1 = s_r1[kk], r2 = s_r2[kk];
         float p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f, p4 = 0.f, p5 = 0.f, p6 = 0.f, p7 = 0.f, p8 = 0.f;
         bool contrib = false;
-        if (j - start < lst) {
+        if (has && j - start < lst) {
           const float dx = (pxc - r0.x) - r0.z;
           const float dy = (pyc - r0.y) - r0.w;
           const float e = r1.w - (r1.x * dx * dx + r1.y * dx * dy + r1.z * dy * dy);
@@ -578,14 +666,20 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(const float* __restrict__
             s2 += wgt * r2.z;
           }
         }
-        if (act && __any(contrib)) {
+        const uint64_t cm = __ballot(contrib);
+        if (cm != 0) {
           const float pv[9] = {p0, p1, p2, p3, p4, p5, p6, p7, p8};
-          const Sum9 r = wave_sum9(pv, lane);
-          if (slot >= 0) atomicAdd(g2d + (int64_t)(tag & 0x7fffffffu) * kG2d + slot, slot == 8 ? r.v8 : r.v);
+          const Sum9 r = row_sum9(pv, lane);
+          // the row's entry is shared by its 16 lanes, so act and tag are row-uniform
+          if (slot >= 0 && ((cm >> (16 * grp)) & 0xffffull) != 0)
+            atomicAdd(g2d + (int64_t)(tag & 0x7fffffffu) * kG2d + slot, slot == 8 ? r.v8 : r.v);
         }
       }
     }
     top = base;
+    base = nbase;
+    nbase = round_base(nbase);
+    ntop = base;
   }
 }
 
