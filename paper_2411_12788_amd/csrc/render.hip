@@ -360,43 +360,78 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(const float* __restrict__
         gmask[g] = __ballot(rel);
       }
       uint64_t mine = grp == 0 ? gmask[0] : grp == 1 ? gmask[1] : grp == 2 ? gmask[2] : gmask[3];
+      // Two entries of the group's stream per iteration: their records are
+      // read and their alphas evaluated side by side, then the pair is
+      // composited in order (the second sees the first's transmittance and
+      // stop), so the result is that of one-by-one compositing with half the
+      // loop latency.
       while (__any(mine != 0)) {
-        const bool has = mine != 0;
-        const int kk = c * kWave + (has ? (int)__builtin_ctzll(mine) : 0);
+        const bool has_a = mine != 0;
+        const int ka = c * kWave + (has_a ? (int)__builtin_ctzll(mine) : 0);
         mine &= mine - 1;
-        const float4 r0 = s_r0[kk], r1 = s_r1[kk], r2 = s_r2[kk];
+        const bool has_b = mine != 0;
+        const int kb = c * kWave + (has_b ? (int)__builtin_ctzll(mine) : 0);
+        mine &= mine - 1;
+        const float4 a0 = s_r0[ka], a1 = s_r1[ka], a2 = s_r2[ka];
+        const float4 b0 = s_r0[kb], b1 = s_r1[kb], b2 = s_r2[kb];
+        const uint32_t ia = s_idx[ka], ib = s_idx[kb];
         // Branch-free per lane: every lane evaluates, selects keep the state of
-        // lanes that skip the entry or have stopped (staged records are finite,
+        // lanes that skip an entry or have stopped (staged records are finite,
         // so adding a zero weight leaves the colour unchanged).
-        const float dx = (pxc - r0.x) - r0.z;
-        const float dy = (pyc - r0.y) - r0.w;
-        const float e = r1.w - (r1.x * dx * dx + r1.y * dx * dy + r1.z * dy * dy);
-        const bool pass = has && !done && e >= op.log2_alpha_min;
-        const float al = fminf(op.alpha_max, __builtin_amdgcn_exp2f(e));
-        const float Tn = T * (1.f - al);
-        const bool stop = pass && Tn < op.t_min;
-        const bool inc = pass && !stop;
-        done = done || stop;
-        const float wgt = inc ? al * T : 0.f;
-        c0 += wgt * r2.x;
-        c1 += wgt * r2.y;
-        c2 += wgt * r2.z;
-        if (DEPTH == GS_DEPTH_BLEND) dblend += wgt * s_z[kk];
-        const int32_t bi = (int32_t)((int64_t)s_idx[kk] - vbase);
-        const bool better = wgt > wbest;  // strict: the nearest wins ties
-        wbest = better ? wgt : wbest;
-        best = better ? bi : best;
-        T = inc ? Tn : T;
-        lastpos = inc ? base + (uint32_t)kk - start + 1 : lastpos;
-        cnt += inc ? 1u : 0u;
-        if (ACC && __any(inc)) {
-          // Per group (= row) sum and max of the weights in registers, then
-          // one LDS add and one LDS max by the row's first lane for the row's
-          // entry.  Weights are >= 0, so the max runs on their bit patterns.
-          const RowSumMax r = row_sum_max(wgt);
-          if ((lane & 15) == 0 && r.max != 0u) {
-            atomicAdd(&s_acc_w[kk], r.sum);
-            atomicMax(&s_acc_m[kk], r.max);
+        const float dxa = (pxc - a0.x) - a0.z, dya = (pyc - a0.y) - a0.w;
+        const float dxb = (pxc - b0.x) - b0.z, dyb = (pyc - b0.y) - b0.w;
+        const float ea = a1.w - (a1.x * dxa * dxa + a1.y * dxa * dya + a1.z * dya * dya);
+        const float eb = b1.w - (b1.x * dxb * dxb + b1.y * dxb * dyb + b1.z * dyb * dyb);
+        const float ala = fminf(op.alpha_max, __builtin_amdgcn_exp2f(ea));
+        const float alb = fminf(op.alpha_max, __builtin_amdgcn_exp2f(eb));
+        // first entry
+        const bool pass_a = has_a && !done && ea >= op.log2_alpha_min;
+        const float Tna = T * (1.f - ala);
+        const bool stop_a = pass_a && Tna < op.t_min;
+        const bool inc_a = pass_a && !stop_a;
+        const bool done_a = done || stop_a;
+        const float wa = inc_a ? ala * T : 0.f;
+        const float Ta = inc_a ? Tna : T;
+        // second entry, behind the first
+        const bool pass_b = has_b && !done_a && eb >= op.log2_alpha_min;
+        const float Tnb = Ta * (1.f - alb);
+        const bool stop_b = pass_b && Tnb < op.t_min;
+        const bool inc_b = pass_b && !stop_b;
+        done = done_a || stop_b;
+        const float wb = inc_b ? alb * Ta : 0.f;
+        T = inc_b ? Tnb : Ta;
+        c0 += wa * a2.x;
+        c1 += wa * a2.y;
+        c2 += wa * a2.z;
+        c0 += wb * b2.x;
+        c1 += wb * b2.y;
+        c2 += wb * b2.z;
+        if (DEPTH == GS_DEPTH_BLEND) {
+          dblend += wa * s_z[ka];
+          dblend += wb * s_z[kb];
+        }
+        // strict comparisons: the nearer entry wins ties
+        const bool better_a = wa > wbest;
+        const float wbest_a = better_a ? wa : wbest;
+        const bool better_b = wb > wbest_a;
+        wbest = better_b ? wb : wbest_a;
+        best = better_b ? (int32_t)((int64_t)ib - vbase) : better_a ? (int32_t)((int64_t)ia - vbase) : best;
+        lastpos = inc_b ? base + (uint32_t)kb - start + 1 : inc_a ? base + (uint32_t)ka - start + 1 : lastpos;
+        cnt += (inc_a ? 1u : 0u) + (inc_b ? 1u : 0u);
+        if (ACC && __any(inc_a || inc_b)) {
+          // Per group (= row) sums and maxima of the two entries' weights in
+          // registers, then one LDS add and one LDS max per entry by the row's
+          // first lane.  Weights are >= 0, so the max runs on bit patterns.
+          const RowSumMax ra = row_sum_max(wa), rb = row_sum_max(wb);
+          if ((lane & 15) == 0) {
+            if (ra.max != 0u) {
+              atomicAdd(&s_acc_w[ka], ra.sum);
+              atomicMax(&s_acc_m[ka], ra.max);
+            }
+            if (rb.max != 0u) {
+              atomicAdd(&s_acc_w[kb], rb.sum);
+              atomicMax(&s_acc_m[kb], rb.max);
+            }
           }
         }
         // a group whose pixels have all stopped drops the rest of its stream
