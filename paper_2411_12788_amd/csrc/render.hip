@@ -418,20 +418,18 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(const float* __restrict__
         best = better_b ? (int32_t)((int64_t)ib - vbase) : better_a ? (int32_t)((int64_t)ia - vbase) : best;
         lastpos = inc_b ? base + (uint32_t)kb - start + 1 : inc_a ? base + (uint32_t)ka - start + 1 : lastpos;
         cnt += (inc_a ? 1u : 0u) + (inc_b ? 1u : 0u);
-        if (ACC && __any(inc_a || inc_b)) {
-          // Per group (= row) sums and maxima of the two entries' weights in
-          // registers, then one LDS add and one LDS max per entry by the row's
-          // first lane.  Weights are >= 0, so the max runs on bit patterns.
-          const RowSumMax ra = row_sum_max(wa), rb = row_sum_max(wb);
-          if ((lane & 15) == 0) {
-            if (ra.max != 0u) {
-              atomicAdd(&s_acc_w[ka], ra.sum);
-              atomicMax(&s_acc_m[ka], ra.max);
-            }
-            if (rb.max != 0u) {
-              atomicAdd(&s_acc_w[kb], rb.sum);
-              atomicMax(&s_acc_m[kb], rb.max);
-            }
+        if (ACC) {
+          // Each including lane adds its weight to the entry's LDS slot (no
+          // reply awaited, so nothing on this wave's dependency chain); the
+          // LDS serialises the group's 16 same-address updates.  Weights are
+          // >= 0, so the max runs on bit patterns.
+          if (inc_a) {
+            atomicAdd(&s_acc_w[ka], wa);
+            atomicMax(&s_acc_m[ka], __float_as_uint(wa));
+          }
+          if (inc_b) {
+            atomicAdd(&s_acc_w[kb], wb);
+            atomicMax(&s_acc_m[kb], __float_as_uint(wb));
           }
         }
         // a group whose pixels have all stopped drops the rest of its stream
