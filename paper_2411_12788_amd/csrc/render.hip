@@ -284,9 +284,10 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(const float* __restrict__
                                                        const float* __restrict__ scales,
                                                        const float* __restrict__ quats, FwdOut o, KOpts op,
                                                        int32_t per_view, ViewSet vs) {
+  // s_r2[k].w carries the record index (the forward never reads the opacity
+  // field), so one read returns colour and index
   __shared__ float4 s_r0[kBatch], s_r1[kBatch], s_r2[kBatch];
   __shared__ int2 s_box[kBatch];
-  __shared__ uint32_t s_idx[kBatch];
   __shared__ float s_z[DEPTH == GS_DEPTH_BLEND ? kBatch : 1];
   // per staged entry: importance and max weight gathered from the whole
   // workgroup with LDS atomics, flushed with one global atomic per entry
@@ -322,11 +323,10 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(const float* __restrict__
   uint32_t nidx = start + kBatch + threadIdx.x < end ? vals[start + kBatch + threadIdx.x] : 0u;
   for (uint32_t base = start; base < end; base += kBatch) {
     if (__syncthreads_and(done)) break;  // also orders this round's LDS writes after the last round's reads
-    s_idx[threadIdx.x] = cur.idx;
     s_box[threadIdx.x] = cur.box;
     s_r0[threadIdx.x] = cur.r0;
     s_r1[threadIdx.x] = cur.r1;
-    s_r2[threadIdx.x] = cur.r2;
+    s_r2[threadIdx.x] = make_float4(cur.r2.x, cur.r2.y, cur.r2.z, __uint_as_float(cur.idx));
     if (DEPTH == GS_DEPTH_BLEND) s_z[threadIdx.x] = cur.z;
     if (ACC) {
       s_acc_w[threadIdx.x] = 0.f;
@@ -374,7 +374,7 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(const float* __restrict__
         mine &= mine - 1;
         const float4 a0 = s_r0[ka], a1 = s_r1[ka], a2 = s_r2[ka];
         const float4 b0 = s_r0[kb], b1 = s_r1[kb], b2 = s_r2[kb];
-        const uint32_t ia = s_idx[ka], ib = s_idx[kb];
+        const uint32_t ia = __float_as_uint(a2.w), ib = __float_as_uint(b2.w);
         // Branch-free per lane: every lane evaluates, selects keep the state of
         // lanes that skip an entry or have stopped (staged records are finite,
         // so adding a zero weight leaves the colour unchanged).
@@ -444,7 +444,7 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(const float* __restrict__
     if (ACC) {
       __syncthreads();
       if ((uint32_t)threadIdx.x < count && s_acc_m[threadIdx.x] != 0u) {
-        const uint32_t r = s_idx[threadIdx.x];
+        const uint32_t r = __float_as_uint(s_r2[threadIdx.x].w);
         const int64_t ai = per_view ? (int64_t)r : (int64_t)r - vbase;
         if (o.imp) atomicAdd(o.imp + ai, s_acc_w[threadIdx.x]);
         if (o.wmax) atomicMax(reinterpret_cast<unsigned int*>(o.wmax) + ai, s_acc_m[threadIdx.x]);
