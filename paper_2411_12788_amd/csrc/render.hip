@@ -259,6 +259,62 @@ __device__ __forceinline__ Rect group_rect(uint32_t bits, int32_t gx0, int32_t g
   return r;
 }
 
+// Work item of a render workgroup.  With a tile order (longest lists first),
+// each of the first kSplitTiles tiles of the order gets four workgroups; if its
+// list is long they take one 8x8 quarter each, with one 4x4 pixel group per
+// wave (16 active lanes), so the tile's sixteen groups walk their streams
+// independently instead of four to a wave in lockstep: these tiles set the
+// kernel's length.  For a short list the first of the four takes the whole
+// tile and the other three exit.
+constexpr int32_t kSplitTiles = 256;
+constexpr uint32_t kSplitLen = 2048;
+struct WorkItem {
+  int32_t tile;
+  int32_t quarter;  // -1: whole tile
+  bool skip;
+};
+__device__ __forceinline__ WorkItem work_item(const uint32_t* order, const uint32_t* ranges, int32_t nsplit) {
+  WorkItem w{(int32_t)blockIdx.x, -1, false};
+  if (order == nullptr) return w;
+  const int32_t b = (int32_t)blockIdx.x;
+  if (b < 4 * nsplit) {
+    w.tile = (int32_t)uload(order + (b >> 2));
+    const uint32_t len = uload(ranges + 2 * w.tile + 1) - uload(ranges + 2 * w.tile);
+    if (len >= kSplitLen) w.quarter = b & 3;
+    else w.skip = (b & 3) != 0;
+  } else {
+    w.tile = (int32_t)uload(order + (b - 3 * nsplit));
+  }
+  return w;
+}
+// Pixel of this lane and the origin of its 4x4 group (see work_item).
+struct LanePixel {
+  int32_t sx0, sy0;  // origin of group 0 of this wave
+  int32_t px, py;
+  bool on;           // lane carries a pixel of the work item
+};
+__device__ __forceinline__ LanePixel lane_pixel(int32_t tx, int32_t ty, int32_t quarter, int wv, int lane) {
+  LanePixel l;
+  if (quarter < 0) {
+    const int grp = lane >> 4;
+    l.sx0 = tx * kTile + (wv & 1) * 8;
+    l.sy0 = ty * kTile + (wv >> 1) * 8;
+    l.px = l.sx0 + (grp & 1) * 4 + (lane & 3);
+    l.py = l.sy0 + (grp >> 1) * 4 + ((lane >> 2) & 3);
+    l.on = true;
+  } else {
+    l.sx0 = tx * kTile + (quarter & 1) * 8 + (wv & 1) * 4;
+    l.sy0 = ty * kTile + (quarter >> 1) * 8 + (wv >> 1) * 4;
+    l.px = l.sx0 + (lane & 3);
+    l.py = l.sy0 + ((lane >> 2) & 3);
+    l.on = lane < 16;
+  }
+  return l;
+}
+inline int32_t split_tiles(const uint32_t* order, int32_t tiles_total) {
+  return order ? (tiles_total < kSplitTiles ? tiles_total : kSplitTiles) : 0;
+}
+
 constexpr int kBatch = kBlock;  // list entries staged per workgroup round
 
 // Work per tile spans four orders of magnitude and a wave's list is walked in
@@ -279,7 +335,7 @@ template <bool ACC, bool OUT, int DEPTH>
 __global__ __launch_bounds__(kBlock) void k_render_fwd(const float* __restrict__ rec, const int32_t* __restrict__ bin,
                                                        const uint32_t* __restrict__ vals,
                                                        const uint32_t* __restrict__ ranges,
-                                                       const uint32_t* __restrict__ order, int64_t n,
+                                                       const uint32_t* __restrict__ order, int32_t nsplit, int64_t n,
                                                        const float* __restrict__ means,
                                                        const float* __restrict__ scales,
                                                        const float* __restrict__ quats, FwdOut o, KOpts op,
@@ -293,20 +349,23 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(const float* __restrict__
   // workgroup with LDS atomics, flushed with one global atomic per entry
   __shared__ float s_acc_w[ACC ? kBatch : 1];
   __shared__ uint32_t s_acc_m[ACC ? kBatch : 1];
-  const int32_t tile = order ? (int32_t)uload(order + blockIdx.x) : (int32_t)blockIdx.x;
+  const WorkItem wi = work_item(order, ranges, nsplit);
+  if (wi.skip) return;
+  const int32_t tile = wi.tile;
   const int32_t v = view_of_tile(vs, tile);
   const KView& cam = vs.v[v];
   const int32_t lt = tile - cam.tile_base;
   const int32_t tx = lt % cam.tiles_x, ty = lt / cam.tiles_x;
   // Lanes: a wave owns an 8x8 quarter of the tile as four 4x4 pixel groups,
-  // one group per 16-lane row (lane = 16 g + 4 y + x).  Each group walks its
-  // own stream of entries (those meeting its still-compositing pixels), so a
-  // wave iterates max over groups instead of the union of the four streams.
+  // one group per 16-lane row (lane = 16 g + 4 y + x), or, for a split heavy
+  // tile, one 4x4 group in lanes 0-15.  Each group walks its own stream of
+  // entries (those meeting its still-compositing pixels), so a wave iterates
+  // max over groups instead of the union of the four streams.
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int grp = lane >> 4;
-  const int32_t sx0 = tx * kTile + (wv & 1) * 8, sy0 = ty * kTile + (wv >> 1) * 8;
-  const int32_t px = sx0 + (grp & 1) * 4 + (lane & 3), py = sy0 + (grp >> 1) * 4 + ((lane >> 2) & 3);
-  const bool inside = px < cam.width && py < cam.height;
+  const LanePixel lp = lane_pixel(tx, ty, wi.quarter, wv, lane);
+  const int32_t sx0 = lp.sx0, sy0 = lp.sy0, px = lp.px, py = lp.py;
+  const bool inside = lp.on && px < cam.width && py < cam.height;
   const float pxc = (float)px + 0.5f, pyc = (float)py + 0.5f;
   const uint32_t start = uload(ranges + 2 * tile), end = uload(ranges + 2 * tile + 1);
   const int64_t vbase = (int64_t)v * n;
@@ -562,7 +621,7 @@ template <bool MASKED>
 __global__ __launch_bounds__(kBlock) void k_render_bwd(const float* __restrict__ rec, const int32_t* __restrict__ bin,
                                                        const uint32_t* __restrict__ vals,
                                                        const uint32_t* __restrict__ ranges,
-                                                       const uint32_t* __restrict__ order, int64_t n,
+                                                       const uint32_t* __restrict__ order, int32_t nsplit, int64_t n,
                                                        const float* __restrict__ t_final,
                                                        const uint32_t* __restrict__ last,
                                                        const float* __restrict__ dldc,
@@ -572,16 +631,18 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(const float* __restrict__
   __shared__ int2 s_box[kBatch];
   __shared__ uint32_t s_idx[kBatch];  // record index | active << 31
   __shared__ uint32_t s_jmax[kBlock / kWave];
-  const int32_t tile = order ? (int32_t)uload(order + blockIdx.x) : (int32_t)blockIdx.x;
+  const WorkItem wi = work_item(order, ranges, nsplit);
+  if (wi.skip) return;
+  const int32_t tile = wi.tile;
   const int32_t v = view_of_tile(vs, tile);
   const KView& cam = vs.v[v];
   const int32_t lt = tile - cam.tile_base;
   const int32_t tx = lt % cam.tiles_x, ty = lt / cam.tiles_x;
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int grp = lane >> 4;
-  const int32_t sx0 = tx * kTile + (wv & 1) * 8, sy0 = ty * kTile + (wv >> 1) * 8;
-  const int32_t px = sx0 + (grp & 1) * 4 + (lane & 3), py = sy0 + (grp >> 1) * 4 + ((lane >> 2) & 3);
-  const bool inside = px < cam.width && py < cam.height;
+  const LanePixel lp = lane_pixel(tx, ty, wi.quarter, wv, lane);
+  const int32_t sx0 = lp.sx0, sy0 = lp.sy0, px = lp.px, py = lp.py;
+  const bool inside = lp.on && px < cam.width && py < cam.height;
   const float pxc = (float)px + 0.5f, pyc = (float)py + 0.5f;
   const uint32_t start = uload(ranges + 2 * tile), end = uload(ranges + 2 * tile + 1);
   const int64_t vbase = (int64_t)v * n;
@@ -772,13 +833,13 @@ static void launch_fwd(int depth_mode, dim3 grid, hipStream_t s, const gs_projec
   const float* q = scene ? scene->quats : nullptr;
   if (depth_mode == GS_DEPTH_CENTER)
     hipLaunchKernelGGL((k_render_fwd<ACC, OUT, GS_DEPTH_CENTER>), grid, dim3(kBlock), 0, s, proj->rec, proj->bin, vals,
-                       ranges, order, n, m, sc, q, o, op, per_view, vs);
+                       ranges, order, split_tiles(order, vs.tiles_total), n, m, sc, q, o, op, per_view, vs);
   else if (depth_mode == GS_DEPTH_BLEND)
     hipLaunchKernelGGL((k_render_fwd<ACC, OUT, GS_DEPTH_BLEND>), grid, dim3(kBlock), 0, s, proj->rec, proj->bin, vals,
-                       ranges, order, n, m, sc, q, o, op, per_view, vs);
+                       ranges, order, split_tiles(order, vs.tiles_total), n, m, sc, q, o, op, per_view, vs);
   else
     hipLaunchKernelGGL((k_render_fwd<ACC, OUT, GS_DEPTH_MID>), grid, dim3(kBlock), 0, s, proj->rec, proj->bin, vals,
-                       ranges, order, n, m, sc, q, o, op, per_view, vs);
+                       ranges, order, split_tiles(order, vs.tiles_total), n, m, sc, q, o, op, per_view, vs);
 }
 
 }  // namespace msplat
@@ -805,7 +866,7 @@ int32_t gs_render_forward(const gs_scene_t* scene, const gs_projected_t* proj, c
            accum ? acc->importance : nullptr, accum ? acc->wmax : nullptr, accum ? acc->area : nullptr};
   const KOpts op = make_kopts(opts);
   const int32_t per_view = (opts->flags & GS_ACCUM_PER_VIEW) ? 1 : 0;
-  dim3 grid(vs.tiles_total);
+  dim3 grid(vs.tiles_total + 3 * split_tiles(tile_order, vs.tiles_total));
   hipStream_t s = (hipStream_t)stream;
   if (accum)
     launch_fwd<true, true>(opts->depth_mode, grid, s, proj, vals, ranges, tile_order, scene->n, scene, o, op, per_view,
@@ -833,8 +894,10 @@ int32_t gs_accumulate_importance(const gs_projected_t* proj, const uint32_t* val
   o.area = acc->area;
   const KOpts op = make_kopts(opts);
   const int32_t per_view = (opts->flags & GS_ACCUM_PER_VIEW) ? 1 : 0;
-  hipLaunchKernelGGL((k_render_fwd<true, false, GS_DEPTH_CENTER>), dim3(vs.tiles_total), dim3(kBlock), 0,
-                     (hipStream_t)stream, proj->rec, proj->bin, vals, ranges, tile_order, n, nullptr, nullptr, nullptr,
+  hipLaunchKernelGGL((k_render_fwd<true, false, GS_DEPTH_CENTER>),
+                     dim3(vs.tiles_total + 3 * split_tiles(tile_order, vs.tiles_total)), dim3(kBlock), 0,
+                     (hipStream_t)stream, proj->rec, proj->bin, vals, ranges, tile_order,
+                     split_tiles(tile_order, vs.tiles_total), n, nullptr, nullptr, nullptr,
                      o, op, per_view, vs);
   MS_CHECK_LAUNCH("accumulate_importance");
   return GS_OK;
@@ -854,12 +917,15 @@ int32_t gs_render_backward_pixels(const gs_projected_t* proj, const uint32_t* va
   if (!proj->rec || !proj->bin || !grad2d) { set_error("buffer NULL"); return GS_ERR_NULL; }
   const KOpts op = make_kopts(opts);
   hipStream_t s = (hipStream_t)stream;
+  const dim3 grid(vs.tiles_total + 3 * split_tiles(tile_order, vs.tiles_total));
   if (active)
-    hipLaunchKernelGGL(k_render_bwd<true>, dim3(vs.tiles_total), dim3(kBlock), 0, s, proj->rec, proj->bin, vals,
-                       ranges, tile_order, n, t_final, last, dl_dcolor, active, grad2d, op, vs);
+    hipLaunchKernelGGL(k_render_bwd<true>, grid, dim3(kBlock), 0, s, proj->rec, proj->bin, vals,
+                       ranges, tile_order, split_tiles(tile_order, vs.tiles_total), n, t_final, last, dl_dcolor,
+                       active, grad2d, op, vs);
   else
-    hipLaunchKernelGGL(k_render_bwd<false>, dim3(vs.tiles_total), dim3(kBlock), 0, s, proj->rec, proj->bin, vals,
-                       ranges, tile_order, n, t_final, last, dl_dcolor, active, grad2d, op, vs);
+    hipLaunchKernelGGL(k_render_bwd<false>, grid, dim3(kBlock), 0, s, proj->rec, proj->bin, vals,
+                       ranges, tile_order, split_tiles(tile_order, vs.tiles_total), n, t_final, last, dl_dcolor,
+                       active, grad2d, op, vs);
   MS_CHECK_LAUNCH("render_backward_pixels");
   return GS_OK;
 }
