@@ -316,6 +316,7 @@ inline int32_t split_tiles(const uint32_t* order, int32_t tiles_total) {
 }
 
 constexpr int kBatch = kBlock;  // list entries staged per workgroup round
+constexpr int kFwdUnroll = 4;   // entries of a group's stream per forward iteration
 
 // Work per tile spans four orders of magnitude and a wave's list is walked in
 // order, so the longest lists set the kernel's length.  Waves of long lists
@@ -419,76 +420,57 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(const float* __restrict__
         gmask[g] = __ballot(rel);
       }
       uint64_t mine = grp == 0 ? gmask[0] : grp == 1 ? gmask[1] : grp == 2 ? gmask[2] : gmask[3];
-      // Two entries of the group's stream per iteration: their records are
-      // read and their alphas evaluated side by side, then the pair is
-      // composited in order (the second sees the first's transmittance and
-      // stop), so the result is that of one-by-one compositing with half the
-      // loop latency.
+      // kFwdUnroll entries of the group's stream per iteration: their records
+      // are read and their alphas evaluated side by side, then they are
+      // composited in order (each sees the previous one's transmittance and
+      // stop), so the result is that of one-by-one compositing with a fraction
+      // of the loop latency.
       while (__any(mine != 0)) {
-        const bool has_a = mine != 0;
-        const int ka = c * kWave + (has_a ? (int)__builtin_ctzll(mine) : 0);
-        mine &= mine - 1;
-        const bool has_b = mine != 0;
-        const int kb = c * kWave + (has_b ? (int)__builtin_ctzll(mine) : 0);
-        mine &= mine - 1;
-        const float4 a0 = s_r0[ka], a1 = s_r1[ka], a2 = s_r2[ka];
-        const float4 b0 = s_r0[kb], b1 = s_r1[kb], b2 = s_r2[kb];
-        const uint32_t ia = __float_as_uint(a2.w), ib = __float_as_uint(b2.w);
-        // Branch-free per lane: every lane evaluates, selects keep the state of
-        // lanes that skip an entry or have stopped (staged records are finite,
-        // so adding a zero weight leaves the colour unchanged).
-        const float dxa = (pxc - a0.x) - a0.z, dya = (pyc - a0.y) - a0.w;
-        const float dxb = (pxc - b0.x) - b0.z, dyb = (pyc - b0.y) - b0.w;
-        const float ea = a1.w - (a1.x * dxa * dxa + a1.y * dxa * dya + a1.z * dya * dya);
-        const float eb = b1.w - (b1.x * dxb * dxb + b1.y * dxb * dyb + b1.z * dyb * dyb);
-        const float ala = fminf(op.alpha_max, __builtin_amdgcn_exp2f(ea));
-        const float alb = fminf(op.alpha_max, __builtin_amdgcn_exp2f(eb));
-        // first entry
-        const bool pass_a = has_a && !done && ea >= op.log2_alpha_min;
-        const float Tna = T * (1.f - ala);
-        const bool stop_a = pass_a && Tna < op.t_min;
-        const bool inc_a = pass_a && !stop_a;
-        const bool done_a = done || stop_a;
-        const float wa = inc_a ? ala * T : 0.f;
-        const float Ta = inc_a ? Tna : T;
-        // second entry, behind the first
-        const bool pass_b = has_b && !done_a && eb >= op.log2_alpha_min;
-        const float Tnb = Ta * (1.f - alb);
-        const bool stop_b = pass_b && Tnb < op.t_min;
-        const bool inc_b = pass_b && !stop_b;
-        done = done_a || stop_b;
-        const float wb = inc_b ? alb * Ta : 0.f;
-        T = inc_b ? Tnb : Ta;
-        c0 += wa * a2.x;
-        c1 += wa * a2.y;
-        c2 += wa * a2.z;
-        c0 += wb * b2.x;
-        c1 += wb * b2.y;
-        c2 += wb * b2.z;
-        if (DEPTH == GS_DEPTH_BLEND) {
-          dblend += wa * s_z[ka];
-          dblend += wb * s_z[kb];
+        int kk[kFwdUnroll];
+        bool has[kFwdUnroll];
+#pragma unroll
+        for (int u = 0; u < kFwdUnroll; ++u) {
+          has[u] = mine != 0;
+          kk[u] = c * kWave + (has[u] ? (int)__builtin_ctzll(mine) : 0);
+          mine &= mine - 1;
         }
-        // strict comparisons: the nearer entry wins ties
-        const bool better_a = wa > wbest;
-        const float wbest_a = better_a ? wa : wbest;
-        const bool better_b = wb > wbest_a;
-        wbest = better_b ? wb : wbest_a;
-        best = better_b ? (int32_t)((int64_t)ib - vbase) : better_a ? (int32_t)((int64_t)ia - vbase) : best;
-        lastpos = inc_b ? base + (uint32_t)kb - start + 1 : inc_a ? base + (uint32_t)ka - start + 1 : lastpos;
-        cnt += (inc_a ? 1u : 0u) + (inc_b ? 1u : 0u);
-        if (ACC) {
-          // Each including lane adds its weight to the entry's LDS slot (no
-          // reply awaited, so nothing on this wave's dependency chain); the
-          // LDS serialises the group's 16 same-address updates.  Weights are
-          // >= 0, so the max runs on bit patterns.
-          if (inc_a) {
-            atomicAdd(&s_acc_w[ka], wa);
-            atomicMax(&s_acc_m[ka], __float_as_uint(wa));
-          }
-          if (inc_b) {
-            atomicAdd(&s_acc_w[kb], wb);
-            atomicMax(&s_acc_m[kb], __float_as_uint(wb));
+        float4 q2[kFwdUnroll];
+        float al[kFwdUnroll], ee[kFwdUnroll];
+#pragma unroll
+        for (int u = 0; u < kFwdUnroll; ++u) {
+          const float4 r0 = s_r0[kk[u]], r1 = s_r1[kk[u]];
+          q2[u] = s_r2[kk[u]];
+          const float dx = (pxc - r0.x) - r0.z, dy = (pyc - r0.y) - r0.w;
+          ee[u] = r1.w - (r1.x * dx * dx + r1.y * dx * dy + r1.z * dy * dy);
+          al[u] = fminf(op.alpha_max, __builtin_amdgcn_exp2f(ee[u]));
+        }
+#pragma unroll
+        for (int u = 0; u < kFwdUnroll; ++u) {
+          // Branch-free per lane: selects keep the state of lanes that skip the
+          // entry or have stopped (staged records are finite, so adding a zero
+          // weight leaves the colour unchanged).
+          const bool pass = has[u] && !done && ee[u] >= op.log2_alpha_min;
+          const float Tn = T * (1.f - al[u]);
+          const bool stop = pass && Tn < op.t_min;
+          const bool inc = pass && !stop;
+          done = done || stop;
+          const float wgt = inc ? al[u] * T : 0.f;
+          T = inc ? Tn : T;
+          c0 += wgt * q2[u].x;
+          c1 += wgt * q2[u].y;
+          c2 += wgt * q2[u].z;
+          if (DEPTH == GS_DEPTH_BLEND) dblend += wgt * s_z[kk[u]];
+          const bool better = wgt > wbest;  // strict: the nearer entry wins ties
+          wbest = better ? wgt : wbest;
+          best = better ? (int32_t)((int64_t)__float_as_uint(q2[u].w) - vbase) : best;
+          lastpos = inc ? base + (uint32_t)kk[u] - start + 1 : lastpos;
+          cnt += inc ? 1u : 0u;
+          if (ACC && inc) {
+            // each including lane adds its weight to the entry's LDS slot (no
+            // reply awaited, so nothing on this wave's dependency chain);
+            // weights are >= 0, so the max runs on bit patterns
+            atomicAdd(&s_acc_w[kk[u]], wgt);
+            atomicMax(&s_acc_m[kk[u]], __float_as_uint(wgt));
           }
         }
         // a group whose pixels have all stopped drops the rest of its stream
