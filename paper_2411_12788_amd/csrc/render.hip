@@ -317,6 +317,7 @@ inline int32_t split_tiles(const uint32_t* order, int32_t tiles_total) {
 
 constexpr int kBatch = kBlock;  // list entries staged per workgroup round
 constexpr int kFwdUnroll = 4;   // entries of a group's stream per forward iteration
+constexpr int kBwdUnroll = 2;   // entries of a group's stream per backward iteration
 
 // Work per tile spans four orders of magnitude and a wave's list is walked in
 // order, so the longest lists set the kernel's length.  Waves of long lists
@@ -699,97 +700,79 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(const float* __restrict__
         gmask[g] = __ballot(rel);
       }
       uint64_t mine = grp == 0 ? gmask[0] : grp == 1 ? gmask[1] : grp == 2 ? gmask[2] : gmask[3];
-      // Two entries of the group's stream per iteration, the later one (b)
-      // first: records and alphas side by side, then the transmittance is
-      // restored through b and then a, exactly as one by one.
+      // kBwdUnroll entries of the group's stream per iteration, latest first:
+      // records and alphas side by side, then the transmittance is restored
+      // through them in reverse order, exactly as one by one.
       while (__any(mine != 0)) {
-        const bool has_b = mine != 0;
-        const int hbb = has_b ? 63 - (int)__builtin_clzll(mine) : 0;
-        mine &= ~(1ull << hbb);
-        const bool has_a = mine != 0;
-        const int hba = has_a ? 63 - (int)__builtin_clzll(mine) : 0;
-        mine &= ~(1ull << hba);
-        const int kb = c * kWave + hbb, ka = c * kWave + hba;
-        const uint32_t tag_b = s_idx[kb], tag_a = s_idx[ka];
-        const float4 b0 = s_r0[kb], b1 = s_r1[kb], b2 = s_r2[kb];
-        const float4 a0 = s_r0[ka], a1 = s_r1[ka], a2 = s_r2[ka];
-        const bool val_b = has_b && base + (uint32_t)kb - start < lst;
-        const bool val_a = has_a && base + (uint32_t)ka - start < lst;
-        const float dxb = (pxc - b0.x) - b0.z, dyb = (pyc - b0.y) - b0.w;
-        const float dxa = (pxc - a0.x) - a0.z, dya = (pyc - a0.y) - a0.w;
-        const float eb = b1.w - (b1.x * dxb * dxb + b1.y * dxb * dyb + b1.z * dyb * dyb);
-        const float ea = a1.w - (a1.x * dxa * dxa + a1.y * dxa * dya + a1.z * dya * dya);
-        const bool in_b = val_b && eb >= op.log2_alpha_min;
-        const bool in_a = val_a && ea >= op.log2_alpha_min;
-        const float G2b = __builtin_amdgcn_exp2f(eb), G2a = __builtin_amdgcn_exp2f(ea);
-        const float alb = fminf(op.alpha_max, G2b), ala = fminf(op.alpha_max, G2a);
-        const float iomb = __builtin_amdgcn_rcpf(1.f - alb), ioma = __builtin_amdgcn_rcpf(1.f - ala);
-        float pb[9], pa[9];
+        int kk[kBwdUnroll];
+        bool val[kBwdUnroll];
 #pragma unroll
-        for (int q = 0; q < 9; ++q) pb[q] = pa[q] = 0.f;
-        bool contrib = false;
-        // entry b: transmittance in front of it, its partials, then its colour joins the suffix
-        if (in_b) {
-          T = T * iomb;
-          const float wgt = alb * T;
-          if ((tag_b >> 31) != 0) {
-            const float ga = g0 * (T * b2.x - s0 * iomb) + g1 * (T * b2.y - s1 * iomb) + g2 * (T * b2.z - s2 * iomb);
-            pb[6] = wgt * g0;
-            pb[7] = wgt * g1;
-            pb[8] = wgt * g2;
-            if (G2b < op.alpha_max) {
-              const float4 b3 = s_r3[kb];
-              pb[5] = ga * alb * __builtin_amdgcn_rcpf(b2.w);
-              const float gq = -0.5f * ga * alb;  // d alpha / d q with q = d^T conic d
-              pb[2] = gq * dxb * dxb;
-              pb[3] = 2.f * gq * dxb * dyb;
-              pb[4] = gq * dyb * dyb;
-              pb[0] = -2.f * gq * (b3.y * dxb + b3.z * dyb);
-              pb[1] = -2.f * gq * (b3.z * dxb + b3.w * dyb);
+        for (int u = 0; u < kBwdUnroll; ++u) {
+          const bool has = mine != 0;
+          const int hb = has ? 63 - (int)__builtin_clzll(mine) : 0;
+          mine &= ~(1ull << hb);
+          kk[u] = c * kWave + hb;
+          val[u] = has && base + (uint32_t)kk[u] - start < lst;
+        }
+        uint32_t tag[kBwdUnroll];
+        float4 q2[kBwdUnroll];
+        float ee[kBwdUnroll], G2[kBwdUnroll], dxs[kBwdUnroll], dys[kBwdUnroll];
+#pragma unroll
+        for (int u = 0; u < kBwdUnroll; ++u) {
+          tag[u] = s_idx[kk[u]];
+          const float4 r0 = s_r0[kk[u]], r1 = s_r1[kk[u]];
+          q2[u] = s_r2[kk[u]];
+          dxs[u] = (pxc - r0.x) - r0.z;
+          dys[u] = (pyc - r0.y) - r0.w;
+          ee[u] = r1.w - (r1.x * dxs[u] * dxs[u] + r1.y * dxs[u] * dys[u] + r1.z * dys[u] * dys[u]);
+          G2[u] = __builtin_amdgcn_exp2f(ee[u]);
+        }
+        float pv[kBwdUnroll][9];
+        bool contrib[kBwdUnroll];
+#pragma unroll
+        for (int u = 0; u < kBwdUnroll; ++u) {
+#pragma unroll
+          for (int q = 0; q < 9; ++q) pv[u][q] = 0.f;
+          contrib[u] = false;
+          // transmittance in front of the entry, its partials, then its colour joins the suffix
+          if (val[u] && ee[u] >= op.log2_alpha_min) {
+            const float al = fminf(op.alpha_max, G2[u]);
+            const float iom = __builtin_amdgcn_rcpf(1.f - al);
+            T = T * iom;
+            const float wgt = al * T;
+            const float4 c4 = q2[u];
+            if ((tag[u] >> 31) != 0) {
+              const float ga = g0 * (T * c4.x - s0 * iom) + g1 * (T * c4.y - s1 * iom) + g2 * (T * c4.z - s2 * iom);
+              pv[u][6] = wgt * g0;
+              pv[u][7] = wgt * g1;
+              pv[u][8] = wgt * g2;
+              if (G2[u] < op.alpha_max) {
+                const float4 r3 = s_r3[kk[u]];
+                const float dx = dxs[u], dy = dys[u];
+                pv[u][5] = ga * al * __builtin_amdgcn_rcpf(c4.w);
+                const float gq = -0.5f * ga * al;  // d alpha / d q with q = d^T conic d
+                pv[u][2] = gq * dx * dx;
+                pv[u][3] = 2.f * gq * dx * dy;
+                pv[u][4] = gq * dy * dy;
+                pv[u][0] = -2.f * gq * (r3.y * dx + r3.z * dy);
+                pv[u][1] = -2.f * gq * (r3.z * dx + r3.w * dy);
+              }
+              contrib[u] = true;
             }
-            contrib = true;
+            s0 += wgt * c4.x;
+            s1 += wgt * c4.y;
+            s2 += wgt * c4.z;
           }
-          s0 += wgt * b2.x;
-          s1 += wgt * b2.y;
-          s2 += wgt * b2.z;
         }
-        // entry a, in front of b
-        bool contrib_a = false;
-        if (in_a) {
-          T = T * ioma;
-          const float wgt = ala * T;
-          if ((tag_a >> 31) != 0) {
-            const float ga = g0 * (T * a2.x - s0 * ioma) + g1 * (T * a2.y - s1 * ioma) + g2 * (T * a2.z - s2 * ioma);
-            pa[6] = wgt * g0;
-            pa[7] = wgt * g1;
-            pa[8] = wgt * g2;
-            if (G2a < op.alpha_max) {
-              const float4 a3 = s_r3[ka];
-              pa[5] = ga * ala * __builtin_amdgcn_rcpf(a2.w);
-              const float gq = -0.5f * ga * ala;
-              pa[2] = gq * dxa * dxa;
-              pa[3] = 2.f * gq * dxa * dya;
-              pa[4] = gq * dya * dya;
-              pa[0] = -2.f * gq * (a3.y * dxa + a3.z * dya);
-              pa[1] = -2.f * gq * (a3.z * dxa + a3.w * dya);
-            }
-            contrib_a = true;
+#pragma unroll
+        for (int u = 0; u < kBwdUnroll; ++u) {
+          const uint64_t cm = __ballot(contrib[u]);
+          if (cm != 0) {
+            const Sum9 r = row_sum9(pv[u], lane);
+            // the row's entries are shared by its 16 lanes, so the tags are row-uniform
+            if (slot >= 0 && ((cm >> (16 * grp)) & 0xffffull) != 0)
+              atomicAdd(g2d + (int64_t)(tag[u] & 0x7fffffffu) * kG2d + slot, slot == 8 ? r.v8 : r.v);
           }
-          s0 += wgt * a2.x;
-          s1 += wgt * a2.y;
-          s2 += wgt * a2.z;
-        }
-        const uint64_t cmb = __ballot(contrib), cma = __ballot(contrib_a);
-        // the row's entries are shared by its 16 lanes, so the tags are row-uniform
-        if (cmb != 0) {
-          const Sum9 r = row_sum9(pb, lane);
-          if (slot >= 0 && ((cmb >> (16 * grp)) & 0xffffull) != 0)
-            atomicAdd(g2d + (int64_t)(tag_b & 0x7fffffffu) * kG2d + slot, slot == 8 ? r.v8 : r.v);
-        }
-        if (cma != 0) {
-          const Sum9 r = row_sum9(pa, lane);
-          if (slot >= 0 && ((cma >> (16 * grp)) & 0xffffull) != 0)
-            atomicAdd(g2d + (int64_t)(tag_a & 0x7fffffffu) * kG2d + slot, slot == 8 ? r.v8 : r.v);
         }
       }
     }
