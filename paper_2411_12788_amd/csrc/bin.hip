@@ -175,8 +175,11 @@ __global__ __launch_bounds__(kBlock) void k_count_down(const int4* __restrict__ 
 // ---------------------------------------------------------------------------
 // emission of (tile | depth) keys
 // ---------------------------------------------------------------------------
+// With ibits > 0 the record index is packed below the key (key << ibits |
+// record) and no value array is written: the sort then moves 8 instead of 12
+// bytes per pair, and equal keys keep record order as before.
 __global__ __launch_bounds__(kBlock) void k_emit(const int4* __restrict__ bin, const uint32_t* __restrict__ offsets,
-                                                 int64_t n, int64_t nrec, int32_t shift, uint32_t zmin,
+                                                 int64_t n, int64_t nrec, int32_t shift, uint32_t zmin, int32_t ibits,
                                                  uint64_t* __restrict__ keys, uint32_t* __restrict__ vals,
                                                  ViewSet vs) {
   const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -192,8 +195,13 @@ __global__ __launch_bounds__(kBlock) void k_emit(const int4* __restrict__ bin, c
   for (int32_t ty = ty0; ty <= ty1; ++ty)
     for (int32_t tx = tx0; tx <= tx1; ++tx) {
       const uint64_t tile = (uint64_t)(tbase + ty * tw + tx);
-      keys[o] = (tile << shift) | low;
-      vals[o] = (uint32_t)r;
+      const uint64_t key = (tile << shift) | low;
+      if (ibits > 0) {
+        keys[o] = (key << ibits) | (uint64_t)r;
+      } else {
+        keys[o] = key;
+        vals[o] = (uint32_t)r;
+      }
       ++o;
     }
 }
@@ -201,16 +209,21 @@ __global__ __launch_bounds__(kBlock) void k_emit(const int4* __restrict__ bin, c
 // ---------------------------------------------------------------------------
 // tile ranges
 // ---------------------------------------------------------------------------
+// Packed keys (ibits > 0) also give the sorted record indices to vals.
 __global__ __launch_bounds__(kBlock) void k_ranges(const uint64_t* __restrict__ keys, int64_t n, int32_t shift,
-                                                   uint32_t zmin, int64_t tiles_total, uint32_t* __restrict__ ranges,
-                                                   uint64_t* __restrict__ keys_out) {
+                                                   uint32_t zmin, int32_t ibits, int64_t tiles_total,
+                                                   uint32_t* __restrict__ ranges, uint64_t* __restrict__ keys_out,
+                                                   uint32_t* __restrict__ vals) {
   const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (k >= n) return;
-  const uint64_t key = keys[k];
-  const uint64_t tile = key >> shift;
+  const uint64_t packed = keys[k];
+  const uint64_t key = packed >> ibits;
+  const int32_t ts = shift + ibits;
+  const uint64_t tile = packed >> ts;
+  if (ibits > 0) vals[k] = (uint32_t)(packed & ((1ull << ibits) - 1ull));
   if (tile < (uint64_t)tiles_total) {
-    if (k == 0 || (keys[k - 1] >> shift) != tile) ranges[2 * tile] = (uint32_t)k;
-    if (k == n - 1 || (keys[k + 1] >> shift) != tile) ranges[2 * tile + 1] = (uint32_t)(k + 1);
+    if (k == 0 || (keys[k - 1] >> ts) != tile) ranges[2 * tile] = (uint32_t)k;
+    if (k == n - 1 || (keys[k + 1] >> ts) != tile) ranges[2 * tile + 1] = (uint32_t)(k + 1);
   }
   if (keys_out) {
     const uint64_t lowmask = shift >= 64 ? ~0ull : ((1ull << shift) - 1ull);
@@ -305,7 +318,7 @@ static CountWs carve_count(void* ws, int64_t nrec) {
 }
 
 size_t onesweep_ws_size(int64_t n, int32_t passes);
-int32_t onesweep_sort(uint64_t* k0, uint32_t* v0, int64_t n, int32_t bits, void* ws, uint32_t* vfinal,
+int32_t onesweep_sort(uint64_t* k0, uint32_t* v0, int64_t n, int32_t lo_bit, int32_t bits, void* ws, uint32_t* vfinal,
                       uint64_t** keys_sorted, hipStream_t st);
 
 size_t sort_ws_size(int64_t n) { return onesweep_ws_size(n, 8); }
@@ -394,8 +407,8 @@ int32_t gs_emit_keys(const gs_projected_t* proj, const gs_camera_t* cams, int32_
   if (nrec == 0) return GS_OK;
   if (!proj->bin || !offsets || !keys || !vals) { set_error("buffer NULL"); return GS_ERR_NULL; }
   hipLaunchKernelGGL(k_emit, dim3(grid_1d(nrec)), dim3(kBlock), 0, (hipStream_t)stream,
-                     reinterpret_cast<const int4*>(proj->bin), offsets, n, nrec, depth_shift, zbits_min, keys, vals,
-                     vs);
+                     reinterpret_cast<const int4*>(proj->bin), offsets, n, nrec, depth_shift, zbits_min, 0, keys,
+                     vals, vs);
   MS_CHECK_LAUNCH("emit");
   return GS_OK;
 }
@@ -409,7 +422,7 @@ int32_t gs_sort_pairs(uint64_t* keys, uint32_t* vals, int64_t n, int32_t key_bit
   if (ws_bytes < sort_ws_size(n)) { set_error("sort workspace too small"); return GS_ERR_CAPACITY; }
   hipStream_t s = (hipStream_t)stream;
   uint64_t* ks = nullptr;
-  int32_t st = onesweep_sort(keys, vals, n, key_bits, ws, vals, &ks, s);
+  int32_t st = onesweep_sort(keys, vals, n, 0, key_bits, ws, vals, &ks, s);
   if (st != GS_OK) return st;
   if (ks != keys) {
     hipLaunchKernelGGL(k_copy_u64, dim3(grid_1d(n)), dim3(kBlock), 0, s, ks, keys, n);
@@ -429,8 +442,8 @@ int32_t gs_tile_ranges(const uint64_t* keys, int64_t n, int32_t depth_shift, uin
   }
   if (n == 0) return GS_OK;
   if (!keys) { set_error("keys NULL"); return GS_ERR_NULL; }
-  hipLaunchKernelGGL(k_ranges, dim3(grid_1d(n)), dim3(kBlock), 0, s, keys, n, depth_shift, zbits_min,
-                     (int64_t)tiles_total, ranges, keys_out);
+  hipLaunchKernelGGL(k_ranges, dim3(grid_1d(n)), dim3(kBlock), 0, s, keys, n, depth_shift, zbits_min, 0,
+                     (int64_t)tiles_total, ranges, keys_out, nullptr);
   MS_CHECK_LAUNCH("ranges");
   return GS_OK;
 }
@@ -456,14 +469,19 @@ int32_t gs_bin_sort(const gs_projected_t* proj, const gs_camera_t* cams, int32_t
   uint64_t* k0 = (uint64_t*)p; p += align256(ni * 8);
   uint32_t* v0 = (uint32_t*)p; p += align256(ni * 4);
   const int32_t shift = stats->depth_bits;
-  hipLaunchKernelGGL(k_emit, dim3(grid_1d((int64_t)V * n)), dim3(kBlock), 0, s,
-                     reinterpret_cast<const int4*>(proj->bin), offsets, n, (int64_t)V * n, shift, stats->zbits_min,
-                     k0, v0, vs);
+  // record indices fit below the key when key_bits + bit length(V n - 1) <= 64
+  const int64_t nrec = (int64_t)V * n;
+  int32_t ibits = 1;
+  while (ibits < 63 && (int64_t(1) << ibits) < nrec) ++ibits;
+  if (stats->key_bits + ibits > 64) ibits = 0;
+  hipLaunchKernelGGL(k_emit, dim3(grid_1d(nrec)), dim3(kBlock), 0, s, reinterpret_cast<const int4*>(proj->bin),
+                     offsets, n, nrec, shift, stats->zbits_min, ibits, k0, v0, vs);
   MS_CHECK_LAUNCH("emit");
   uint64_t* ks = nullptr;
-  if ((st = onesweep_sort(k0, v0, ni, stats->key_bits, p, vals, &ks, s)) != GS_OK) return st;
-  hipLaunchKernelGGL(k_ranges, dim3(grid_1d(ni)), dim3(kBlock), 0, s, ks, ni, shift, stats->zbits_min,
-                     (int64_t)vs.tiles_total, ranges, keys);
+  if ((st = onesweep_sort(k0, ibits > 0 ? nullptr : v0, ni, ibits, stats->key_bits, p, vals, &ks, s)) != GS_OK)
+    return st;
+  hipLaunchKernelGGL(k_ranges, dim3(grid_1d(ni)), dim3(kBlock), 0, s, ks, ni, shift, stats->zbits_min, ibits,
+                     (int64_t)vs.tiles_total, ranges, keys, vals);
   MS_CHECK_LAUNCH("ranges");
   if (tile_order) return launch_tile_order(ranges, vs.tiles_total, tile_order, order_hist, s);
   return GS_OK;

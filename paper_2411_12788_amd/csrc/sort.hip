@@ -39,7 +39,7 @@ __device__ __forceinline__ uint64_t os_match(uint32_t d) {
 
 // Counts of every digit of every pass; 4 tiles per workgroup.
 __global__ __launch_bounds__(kBlock) void k_os_hist(const uint64_t* __restrict__ keys, int64_t n, int32_t passes,
-                                                    uint32_t* __restrict__ ghist) {
+                                                    int32_t lo_bit, uint32_t* __restrict__ ghist) {
   __shared__ uint32_t h[kMaxPasses][kOsRadix];
   for (int p = 0; p < passes; ++p) h[p][threadIdx.x] = 0;
   __syncthreads();
@@ -48,7 +48,7 @@ __global__ __launch_bounds__(kBlock) void k_os_hist(const uint64_t* __restrict__
     const int64_t e = base + (int64_t)k * kBlock + threadIdx.x;
     if (e < n) {
       const uint64_t key = keys[e];
-      for (int p = 0; p < passes; ++p) atomicAdd(&h[p][(uint32_t)(key >> (8 * p)) & 0xffu], 1u);
+      for (int p = 0; p < passes; ++p) atomicAdd(&h[p][(uint32_t)(key >> (lo_bit + 8 * p)) & 0xffu], 1u);
     }
   }
   __syncthreads();
@@ -78,6 +78,7 @@ __global__ __launch_bounds__(kBlock) void k_os_scan(uint32_t* __restrict__ ghist
   }
 }
 
+template <bool VALS>
 __global__ __launch_bounds__(kBlock) void k_os_pass(const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin,
                                                     uint64_t* __restrict__ kout, uint32_t* __restrict__ vout,
                                                     int64_t n, int32_t shift, const uint32_t* __restrict__ digit_base,
@@ -88,7 +89,7 @@ __global__ __launch_bounds__(kBlock) void k_os_pass(const uint64_t* __restrict__
   __shared__ uint32_t s_loff[kOsRadix + 1];
   __shared__ uint32_t s_wsum[kOsWaves];
   __shared__ uint64_t s_key[kOsTile];
-  __shared__ uint32_t s_val[kOsTile];
+  __shared__ uint32_t s_val[VALS ? kOsTile : 1];
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
   if (threadIdx.x == 0) s_tile = atomicAdd(counter, 1u);
 #pragma unroll
@@ -106,7 +107,7 @@ __global__ __launch_bounds__(kBlock) void k_os_pass(const uint64_t* __restrict__
     const int64_t e = base + (int64_t)k * kWave + lane;
     const bool in = e < n;
     key[k] = in ? kin[e] : 0ull;
-    val[k] = in ? vin[e] : 0u;
+    val[k] = (VALS && in) ? vin[e] : 0u;
     const uint32_t d = (uint32_t)(key[k] >> shift) & 0xffu;
     uint64_t m = os_match(d);
     const uint64_t inm = __ballot(in);
@@ -197,7 +198,7 @@ __global__ __launch_bounds__(kBlock) void k_os_pass(const uint64_t* __restrict__
       const uint32_t lp = s_loff[dd] + cnt[w][dd] + rank[k];
       if (lp < (uint32_t)kOsTile) {
         s_key[lp] = key[k];
-        s_val[lp] = val[k];
+        if (VALS) s_val[lp] = val[k];
       }
     }
   }
@@ -209,7 +210,7 @@ __global__ __launch_bounds__(kBlock) void k_os_pass(const uint64_t* __restrict__
     const uint64_t dst = (uint64_t)s_glob[dd] + (i - s_loff[dd]);
     if (dst < (uint64_t)n) {
       kout[dst] = kk;
-      vout[dst] = s_val[i];
+      if (VALS) vout[dst] = s_val[i];
     }
   }
 }
@@ -224,13 +225,18 @@ size_t onesweep_ws_size(int64_t n, int32_t passes) {
 
 int32_t launch_fill(void* dst, uint32_t value, int64_t count, hipStream_t st);
 
-// Sorts (k0, v0); the last pass writes values to vfinal and keys to the
-// buffer returned in *keys_sorted (k0 or the workspace copy).
-int32_t onesweep_sort(uint64_t* k0, uint32_t* v0, int64_t n, int32_t bits, void* ws, uint32_t* vfinal,
-                      uint64_t** keys_sorted, hipStream_t st) {
+// Sorts (k0, v0) on key bits [lo_bit, lo_bit + bits); the last pass writes
+// values to vfinal and keys to the buffer returned in *keys_sorted (k0 or the
+// workspace copy).  With v0 == NULL only the keys are sorted (vfinal unused).
+int32_t onesweep_sort(uint64_t* k0, uint32_t* v0, int64_t n, int32_t lo_bit, int32_t bits, void* ws,
+                      uint32_t* vfinal, uint64_t** keys_sorted, hipStream_t st) {
   const int passes = (bits + 7) / 8;
   *keys_sorted = k0;
-  if (passes > kMaxPasses) { set_error("too many key bits"); return GS_ERR_SHAPE; }
+  if (passes > kMaxPasses || lo_bit < 0 || lo_bit + 8 * passes > 64 + 7) {
+    set_error("too many key bits");
+    return GS_ERR_SHAPE;
+  }
+  const bool vals = v0 != nullptr;
   const int64_t nn = n > 0 ? n : 1;
   const int64_t nb = (nn + kOsTile - 1) / kOsTile;
   auto a = [](size_t x) { return (x + 255) & ~size_t(255); };
@@ -242,7 +248,7 @@ int32_t onesweep_sort(uint64_t* k0, uint32_t* v0, int64_t n, int32_t bits, void*
   uint32_t* counters = (uint32_t*)p; p += a(kMaxPasses * 4);
   uint32_t* err = (uint32_t*)p;
   if (n <= 1 || passes == 0) {
-    if (vfinal != v0 && n > 0) {
+    if (vals && vfinal != v0 && n > 0) {
       int32_t r = check_hip(hipMemcpyAsync(vfinal, v0, n * 4, hipMemcpyDeviceToDevice, st), "sort copy");
       if (r != GS_OK) return r;
     }
@@ -253,23 +259,31 @@ int32_t onesweep_sort(uint64_t* k0, uint32_t* v0, int64_t n, int32_t bits, void*
   int32_t r = launch_fill(ghist, 0u, zero_words, st);
   if (r != GS_OK) return r;
   const int64_t hb = (nn + 4 * kOsTile - 1) / (4 * kOsTile);
-  hipLaunchKernelGGL(k_os_hist, dim3((unsigned)hb), dim3(kBlock), 0, st, k0, n, passes, ghist);
+  hipLaunchKernelGGL(k_os_hist, dim3((unsigned)hb), dim3(kBlock), 0, st, k0, n, passes, lo_bit, ghist);
   hipLaunchKernelGGL(k_os_scan, dim3(1), dim3(kBlock), 0, st, ghist, passes);
   MS_CHECK_LAUNCH("sort histogram");
   uint64_t* kin = k0;
   uint32_t* vin = v0;
   for (int ps = 0; ps < passes; ++ps) {
     uint64_t* kout = (kin == k0) ? kalt : k0;
-    uint32_t* vout = (vin == v0) ? valt : v0;
-    if (ps == passes - 1) vout = vfinal;
-    if (vout == vin) vout = (vin == v0) ? valt : v0;
-    hipLaunchKernelGGL(k_os_pass, dim3((unsigned)nb), dim3(kBlock), 0, st, kin, vin, kout, vout, n, 8 * ps,
-                       ghist + ps * kOsRadix, status + (size_t)ps * nb * kOsRadix, counters + ps, err);
+    uint32_t* vout = nullptr;
+    if (vals) {
+      vout = (vin == v0) ? valt : v0;
+      if (ps == passes - 1) vout = vfinal;
+      if (vout == vin) vout = (vin == v0) ? valt : v0;
+      hipLaunchKernelGGL(k_os_pass<true>, dim3((unsigned)nb), dim3(kBlock), 0, st, kin, vin, kout, vout, n,
+                         lo_bit + 8 * ps, ghist + ps * kOsRadix, status + (size_t)ps * nb * kOsRadix, counters + ps,
+                         err);
+    } else {
+      hipLaunchKernelGGL(k_os_pass<false>, dim3((unsigned)nb), dim3(kBlock), 0, st, kin, nullptr, kout, nullptr, n,
+                         lo_bit + 8 * ps, ghist + ps * kOsRadix, status + (size_t)ps * nb * kOsRadix, counters + ps,
+                         err);
+    }
     MS_CHECK_LAUNCH("sort pass");
     kin = kout;
     vin = vout;
   }
-  if (vin != vfinal) {
+  if (vals && vin != vfinal) {
     r = check_hip(hipMemcpyAsync(vfinal, vin, n * 4, hipMemcpyDeviceToDevice, st), "sort copy");
     if (r != GS_OK) return r;
   }
