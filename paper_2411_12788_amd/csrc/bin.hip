@@ -53,15 +53,21 @@ struct CountWs {
   uint64_t* stats;       // [4]: n_isect, n_visible, zmin, zmax
 };
 
+// Block = 4096 records; wave w owns the 1024 records from 1024 w, read 64 at
+// a time by its lanes, so every load is coalesced.
+__device__ __forceinline__ int64_t count_record(int k) {
+  const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+  return (int64_t)blockIdx.x * kScanTile + (int64_t)w * (kScanItems * kWave) + (int64_t)k * kWave + lane;
+}
+
 __global__ __launch_bounds__(kBlock) void k_count_reduce(const int4* __restrict__ bin, int64_t nrec, CountWs ws) {
   __shared__ uint64_t lds[kWaves + 1];
   __shared__ uint32_t lz[2 * kWaves + kWaves];
-  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
   uint64_t sum = 0;
   uint32_t zmin = 0xffffffffu, zmax = 0u, vis = 0;
 #pragma unroll 4
   for (int k = 0; k < kScanItems; ++k) {
-    const int64_t r = base + k;
+    const int64_t r = count_record(k);
     if (r < nrec) {
       int4 b = bin[r];
       if (b.w > 0) {
@@ -152,23 +158,37 @@ __global__ __launch_bounds__(kBlock) void k_count_top(int64_t nb, CountWs ws) {
 __global__ __launch_bounds__(kBlock) void k_count_down(const int4* __restrict__ bin, int64_t nrec, CountWs ws,
                                                        uint32_t* __restrict__ offsets) {
   __shared__ uint64_t lds[kWaves + 1];
-  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  const int lane = threadIdx.x & (kWave - 1);
   uint32_t t[kScanItems];
   uint64_t sum = 0;
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
-    const int64_t r = base + k;
-    int32_t w = r < nrec ? bin[r].w : 0;
+    const int64_t r = count_record(k);
+    const int32_t w = r < nrec ? bin[r].w : 0;
     t[k] = w > 0 ? (uint32_t)w : 0u;
     sum += t[k];
   }
+  // the wave's records precede those of later waves: exclusive scan of the
+  // lane sums over the block gives each wave's start (lanes' sums are added in
+  // wave order, and within a wave k-major below)
+  uint64_t wsum = sum;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) wsum += __shfl_xor(wsum, o, kWave);
   uint64_t tot;
-  uint64_t run = ws.block_sum[blockIdx.x] + block_exclusive_scan<uint64_t>(sum, lds, &tot);
+  uint64_t run = ws.block_sum[blockIdx.x] +
+                 block_exclusive_scan<uint64_t>(lane == 0 ? wsum : 0ull, lds, &tot);
+  run = __shfl(run, 0, kWave);
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
-    const int64_t r = base + k;
-    if (r < nrec) offsets[r] = (uint32_t)run;
-    run += t[k];
+    uint32_t inc = t[k];
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+      const uint32_t y = __shfl_up(inc, o, kWave);
+      if (lane >= o) inc += y;
+    }
+    const int64_t r = count_record(k);
+    if (r < nrec) offsets[r] = (uint32_t)(run + inc - t[k]);
+    run += __shfl(inc, kWave - 1, kWave);
   }
 }
 

@@ -58,23 +58,25 @@ __global__ __launch_bounds__(kBlock) void k_os_hist(const uint64_t* __restrict__
   }
 }
 
-// Exclusive scan of each pass's 256 counts (one workgroup).
+// Exclusive scan of each pass's 256 counts: one workgroup, one wave per pass
+// (a pass's 256 counts are 4 per lane, scanned with shuffles).
 __global__ __launch_bounds__(kBlock) void k_os_scan(uint32_t* __restrict__ ghist, int32_t passes) {
-  __shared__ uint32_t s[kOsRadix];
-  for (int p = 0; p < passes; ++p) {
-    s[threadIdx.x] = ghist[p * kOsRadix + threadIdx.x];
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      uint32_t run = 0;
-      for (int d = 0; d < kOsRadix; ++d) {
-        const uint32_t c = s[d];
-        s[d] = run;
-        run += c;
-      }
+  const int lane = threadIdx.x & (kWave - 1);
+  for (int p = threadIdx.x / kWave; p < passes; p += kOsWaves) {
+    uint32_t* h = ghist + p * kOsRadix;
+    const uint32_t c0 = h[4 * lane], c1 = h[4 * lane + 1], c2 = h[4 * lane + 2], c3 = h[4 * lane + 3];
+    const uint32_t sum = c0 + c1 + c2 + c3;
+    uint32_t inc = sum;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+      const uint32_t y = __shfl_up(inc, o, kWave);
+      if (lane >= o) inc += y;
     }
-    __syncthreads();
-    ghist[p * kOsRadix + threadIdx.x] = s[threadIdx.x];
-    __syncthreads();
+    const uint32_t ex = inc - sum;
+    h[4 * lane] = ex;
+    h[4 * lane + 1] = ex + c0;
+    h[4 * lane + 2] = ex + c0 + c1;
+    h[4 * lane + 3] = ex + c0 + c1 + c2;
   }
 }
 
