@@ -27,6 +27,10 @@ other than itself live in ``tests/test_oracle_*.py``:
   sample            Sec. 4.2 (intersection preserving, primitive sampling)
                                                             pinned: exact inclusion probabilities
                                                             of sequential weighted draws
+  densify_select, split
+                    Sec. 3.2 / Sec. 3.3 (3DGS density control; blur split
+                    children)                               pinned: closed-form rotations,
+                    covariance of the children vs scipy's rotation, boundary cases
 """
 from __future__ import annotations
 
@@ -65,6 +69,7 @@ def lib():
         _lib.orc_clone.restype = ctypes.c_int64
         _lib.orc_depth_points.restype = ctypes.c_int64
         _lib.orc_sample.restype = ctypes.c_int64
+        _lib.orc_split.restype = ctypes.c_int64
     return _lib
 
 
@@ -415,6 +420,38 @@ def grad_stats(tiles, grad2d, widths, heights):
     cnt = np.zeros(max(n, 1), dtype=np.int64)
     lib().orc_grad_stats(ctypes.c_int32(V), ctypes.c_int64(n), _p(t), _p(g), _p(w), _p(h), _p(ns), _p(cnt))
     return ns[:n], cnt[:n]
+
+
+SPLIT_FACTOR = 1.6  # 3DGS: children take the parent's scales divided by 1.6
+
+
+def densify_select(norm_sum, count, scales, grad_threshold: float, scale_threshold: float):
+    """(clone[n], split[n]) of the 3DGS density control (Sec. 3.2): mean
+    gradient norm >= grad_threshold, then largest scale <= / > scale_threshold."""
+    ns = _d(norm_sum).ravel()
+    n = ns.size
+    cnt = np.ascontiguousarray(count, dtype=np.int64).ravel()
+    sc = _d(scales).reshape(3, n)
+    cl = np.zeros(max(n, 1), dtype=np.uint8)
+    sp = np.zeros(max(n, 1), dtype=np.uint8)
+    lib().orc_densify_select(ctypes.c_int64(n), _p(ns), _p(cnt), _p(sc), ctypes.c_double(grad_threshold),
+                             ctypes.c_double(scale_threshold), _p(cl), _p(sp))
+    return cl[:n].astype(bool), sp[:n].astype(bool)
+
+
+def split(params: Params, select, normals, factor: float = SPLIT_FACTOR) -> Params:
+    """3DGS split into two children drawn from the parent (normals[2, 3, n]
+    standard-normal draws); unselected rows first, then the children."""
+    sel = np.ascontiguousarray(select, dtype=np.uint8)
+    n = params.n
+    z = _d(normals).reshape(2, 3, n)
+    m = n + int(sel.sum())
+    out = Params(np.zeros((3, m)), np.zeros((3, m)), np.zeros((4, m)), np.zeros(m), np.zeros((16, 3, m)),
+                 params.sh_degree)
+    lib().orc_split(ctypes.c_int64(n), _p(params.means), _p(params.scales), _p(params.quats), _p(params.opacity),
+                    _p(params.sh), _p(sel), _p(z), ctypes.c_double(factor), _p(out.means), _p(out.scales),
+                    _p(out.quats), _p(out.opacity), _p(out.sh))
+    return out
 
 
 def depth_points(cam, depth, imax, hit, target, u, rate: float, require_hit: bool = True):

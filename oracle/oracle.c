@@ -970,3 +970,65 @@ int64_t orc_sample(int64_t n, const float* importance, const uint32_t* area, con
   free(c);
   return take;
 }
+
+/* ------------------------------------------------------------------------ */
+/* adaptive density control inherited from 3DGS (Sec. 3.2), used by the      */
+/* blur split (Sec. 3.3 / Eq. (3)) and the SplitAndClone step                */
+/* ------------------------------------------------------------------------ */
+/* Selection: the mean screen-gradient norm g_i = norm_sum_i / count_i (rows
+ * never seen, count 0, are not selected) is compared with grad_thr; a
+ * selected Gaussian is cloned when its largest scale is at most scale_thr
+ * (small: under-reconstructed) and split otherwise (large). */
+void orc_densify_select(int64_t n, const double* norm_sum, const int64_t* count, const double* scales,
+                        double grad_thr, double scale_thr, uint8_t* clone, uint8_t* split) {
+  for (int64_t i = 0; i < n; i++) {
+    int big = 0, sel = 0;
+    if (count[i] > 0) sel = norm_sum[i] / (double)count[i] >= grad_thr;
+    double smax = scales[i];
+    if (scales[n + i] > smax) smax = scales[n + i];
+    if (scales[2 * n + i] > smax) smax = scales[2 * n + i];
+    big = smax > scale_thr;
+    clone[i] = sel && !big;
+    split[i] = sel && big;
+  }
+}
+
+/* Split into two (3DGS): each selected Gaussian is replaced by two children
+ * whose centres are drawn from the parent itself, p + R diag(s) z with z a
+ * standard normal 3-vector (given: normals[c][k][i] for child c, axis k, row
+ * i), R the rotation of the normalised quaternion (identity for a zero
+ * quaternion), and whose scales are the parent's divided by `factor`
+ * (3DGS: 1.6); rotation, opacity and SH are copied.  Unselected rows come
+ * first in index order, then the two children of each selected row in index
+ * order.  Output arrays hold n + count columns; returns count. */
+int64_t orc_split(int64_t n, const double* means, const double* scales, const double* quats, const double* opac,
+                  const double* sh, const uint8_t* select, const double* normals, double factor, double* o_means,
+                  double* o_scales, double* o_quats, double* o_opac, double* o_sh) {
+  int64_t count = 0;
+  for (int64_t i = 0; i < n; i++) count += select[i] != 0;
+  int64_t m = n + count, keep_pos = 0, child_pos = n - count;
+  for (int64_t i = 0; i < n; i++) {
+    int children = select[i] ? 2 : 1;
+    double R[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+    double q[4] = {quats[i], quats[n + i], quats[2 * n + i], quats[3 * n + i]};
+    double qn = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    if (select[i] && qn > 0) {
+      for (int k = 0; k < 4; k++) q[k] /= qn;
+      quat_to_rot(q, R);
+    }
+    for (int c = 0; c < children; c++) {
+      int64_t d = select[i] ? child_pos++ : keep_pos++;
+      for (int r = 0; r < 3; r++) {
+        double off = 0;
+        if (select[i])
+          for (int k = 0; k < 3; k++) off += R[r * 3 + k] * scales[k * n + i] * normals[(c * 3 + k) * n + i];
+        o_means[r * m + d] = means[r * n + i] + off;
+      }
+      for (int k = 0; k < 3; k++) o_scales[k * m + d] = select[i] ? scales[k * n + i] / factor : scales[k * n + i];
+      for (int k = 0; k < 4; k++) o_quats[k * m + d] = quats[k * n + i];
+      o_opac[d] = opac[i];
+      for (int k = 0; k < 48; k++) o_sh[k * m + d] = sh[k * n + i];
+    }
+  }
+  return count;
+}
