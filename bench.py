@@ -150,7 +150,8 @@ class Step:
 def criteria_bench(step, reps: int = 10):
     """Time the culling/densification criteria on the accumulations of the last
     timed step: per-view visibility and critical set (both threshold readings),
-    blur split, two-way clone of the critical set, gradient statistics.
+    blur split, two-way clone of the critical set, gradient statistics, the
+    3DGS clone/split selection and the split of the critical set.
     'gbs' uses the algorithmic minimum traffic (read the inputs once, write the
     outputs once), so it is a lower bound on what the kernels move."""
     from paper_2411_12788_amd import densify as Dz
@@ -185,6 +186,9 @@ def criteria_bench(step, reps: int = 10):
     ns = torch.zeros(n, device="cuda")
     cn = torch.zeros(n, dtype=torch.int32, device="cuda")
     timed("grad_stats", lambda: Dz.grad_stats(step.proj, step.grad2d, step.cams, n, ns, cn), 28 * n)
+    timed("densify_select", lambda: Dz.densify_select(ns, cn, step.scene.scales, 2e-4, 0.05), 22 * n)
+    z = torch.randn((2, 3, n), generator=torch.Generator(device="cuda").manual_seed(7), device="cuda")
+    timed("split", lambda: Dz.split(step.scene, sel, z, capacity=n + cnt), 236 * n + n + 24 * cnt + 236 * (n + cnt))
     return res
 
 

@@ -204,6 +204,21 @@ def uniform_draws(n: int, seed: int) -> np.ndarray:
     return rng(seed).uniform(size=n).astype(np.float32)
 
 
+def normal_draws(shape, seed: int) -> np.ndarray:
+    """N(0, 1) variates, float32 (the position draws of the split)."""
+    return rng(seed).standard_normal(size=shape).astype(np.float32)
+
+
+def gradient_stats_like(n: int, seed: int, unseen_fraction: float = 0.2):
+    """(norm_sum[n] float32, count[n] uint32): accumulated screen-gradient
+    norms over up to 16 views, log-normal per view, some rows never seen."""
+    g = rng(seed)
+    count = g.integers(1, 17, size=n).astype(np.uint32)
+    count[g.uniform(size=n) < unseen_fraction] = 0
+    norm_sum = (count * np.exp(g.normal(-8.0, 1.5, size=n))).astype(np.float32)
+    return norm_sum, count
+
+
 def depth_map_like(pixels: int, seed: int, near: float = 0.5, far: float = 12.0, empty_fraction: float = 0.2):
     """(depth[P] float32, imax[P] int32, hit[P] uint8): a rendered depth map
     with a fraction of empty pixels (imax = -1, depth 0) and rays that miss

@@ -366,6 +366,38 @@ size_t gs_clone_workspace_size(int64_t n);
 int32_t gs_clone(const gs_scene_t* in, const uint8_t* select, const gs_scene_out_t* out, int64_t* count, void* ws,
                  size_t ws_bytes, void* stream);
 
+/* Selection of the adaptive density control inherited from 3DGS (Sec. 3.2):
+ * a Gaussian is selected when its mean screen-gradient norm
+ * norm_sum[i] / count[i] (as accumulated by gs_grad_stats; computed in
+ * double, rows with count 0 are never selected) is >= grad_threshold; a
+ * selected Gaussian is cloned when its largest scale is <= scale_threshold
+ * (3DGS: percent_dense * scene extent) and split otherwise.  norm_sum, count
+ * [dev, n]; scales [dev, 3][n] (scene layout); clone, split [dev, n] bytes
+ * 0/1, either may be NULL (not both). */
+int32_t gs_densify_select(const float* norm_sum, const uint32_t* count, const float* scales, int64_t n,
+                          double grad_threshold, double scale_threshold, uint8_t* clone, uint8_t* split,
+                          void* stream);
+
+/* Device workspace of gs_split for n input Gaussians. */
+size_t gs_split_workspace_size(int64_t n);
+
+/* Split into two children (the 3DGS split that the blur split of Sec. 3.3,
+ * Eq. (3), and the density control apply): every row i with select[i] != 0
+ * is replaced by two children c = 0, 1 with centre p + R diag(s) z_c, in
+ * double, where R is the rotation of the normalised quaternion (w, x, y, z)
+ * (identity for a zero quaternion) and z_c = (normals[c][0][i],
+ * normals[c][1][i], normals[c][2][i]) are standard-normal draws supplied by
+ * the caller [dev, 2][3][n]; the children's scales are the parent's divided
+ * by `factor` (3DGS: 1.6, > 0 or GS_ERR_SHAPE); rotation, opacity and SH are
+ * copied.  Output order: the unselected rows in index order (row i goes to
+ * i - r, r the number of selected rows before i), then the children of the
+ * r-th selected row at (n - m) + 2r + c, m = the number of selected rows,
+ * written to *count [dev int64].  out->capacity is the output plane stride
+ * (>= in->n, GS_ERR_CAPACITY otherwise; size it n + m); rows beyond it are
+ * dropped.  in and out must not overlap. */
+int32_t gs_split(const gs_scene_t* in, const uint8_t* select, const float* normals, double factor,
+                 const gs_scene_out_t* out, int64_t* count, void* ws, size_t ws_bytes, void* stream);
+
 /* Device workspace of gs_sample for n Gaussians. */
 size_t gs_sample_workspace_size(int64_t n);
 

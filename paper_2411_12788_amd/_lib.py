@@ -105,6 +105,9 @@ _SIGS = {
     "gs_grad_stats": (c_i32, [P(Projected), c_p, P(Camera), c_i32, c_i64, c_p, c_p, c_p]),
     "gs_clone_workspace_size": (c_sz, [c_i64]),
     "gs_clone": (c_i32, [P(Scene), c_p, P(SceneOut), c_p, c_p, c_sz, c_p]),
+    "gs_densify_select": (c_i32, [c_p, c_p, c_p, c_i64, ctypes.c_double, ctypes.c_double, c_p, c_p, c_p]),
+    "gs_split_workspace_size": (c_sz, [c_i64]),
+    "gs_split": (c_i32, [P(Scene), c_p, c_p, ctypes.c_double, P(SceneOut), c_p, c_p, c_sz, c_p]),
     "gs_sample_workspace_size": (c_sz, [c_i64]),
     "gs_sample": (c_i32, [c_p, c_p, c_p, c_i64, c_i64, c_p, c_p, c_p, c_sz, c_p]),
     "gs_depth_points_workspace_size": (c_sz, [c_i64]),

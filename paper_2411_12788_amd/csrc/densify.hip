@@ -473,17 +473,14 @@ __global__ __launch_bounds__(kBlock) void k_grad_stats(const int32_t* __restrict
 // every original row and the copies at n + rank
 // ---------------------------------------------------------------------------
 constexpr int kCloneItems = 4096;  // selection flags per scan block (16 per thread)
+constexpr int kCopyRows = kBlock;  // rows per workgroup of the clone / split copies (one per thread)
+constexpr int kParamPlanes = 59;   // 3 + 3 + 4 + 1 + 48 float planes of a Gaussian
 
 __global__ __launch_bounds__(kBlock) void k_clone_count(const uint8_t* __restrict__ select, int64_t n,
                                                         uint32_t* __restrict__ block_cnt) {
   __shared__ uint32_t s_part[kBlock / kWave];
-  const int64_t base = (int64_t)blockIdx.x * kCloneItems;
-  uint32_t c = 0;
-  for (int j = threadIdx.x; j < kCloneItems; j += kBlock) {
-    const int64_t i = base + j;
-    c += (i < n && select[i]) ? 1u : 0u;
-  }
-  for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, kWave);
+  const int64_t i = (int64_t)blockIdx.x * kCopyRows + threadIdx.x;
+  const uint32_t c = (uint32_t)__popcll(__ballot(i < n && select[i]));
   if (lane_id() == 0) s_part[threadIdx.x / kWave] = c;
   __syncthreads();
   if (threadIdx.x == 0) block_cnt[blockIdx.x] = s_part[0] + s_part[1] + s_part[2] + s_part[3];
@@ -538,52 +535,147 @@ struct CloneOut {
   int64_t cap;
 };
 
+// Rank of row i among the selected rows: the block's offset from the scan
+// plus the selected rows of the earlier waves and lanes of the workgroup.
+__device__ __forceinline__ uint32_t copy_rank(bool sel, const uint32_t* __restrict__ block_off,
+                                              uint32_t* s_wave) {
+  const uint64_t bal = __ballot(sel);
+  if (lane_id() == 0) s_wave[threadIdx.x / kWave] = (uint32_t)__popcll(bal);
+  __syncthreads();
+  uint32_t rank = block_off[blockIdx.x] + (uint32_t)__popcll(bal & ((1ull << lane_id()) - 1ull));
+  for (int w = 0; w < (int)(threadIdx.x / kWave); ++w) rank += s_wave[w];
+  return rank;
+}
+
+// All 59 planes of one row, loaded before any store so that the loads are in
+// flight together.
+struct Row {
+  float v[kParamPlanes];
+};
+__device__ __forceinline__ Row load_row(const ClonePlanes& in, int64_t i) {
+  Row r;
+  const float* __restrict__ m = in.means;
+  const float* __restrict__ s = in.scales;
+  const float* __restrict__ q = in.quats;
+  const float* __restrict__ o = in.opac;
+  const float* __restrict__ h = in.sh;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) r.v[k] = m[k * in.n + i];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) r.v[3 + k] = s[k * in.n + i];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) r.v[6 + k] = q[k * in.n + i];
+  r.v[10] = o[i];
+#pragma unroll
+  for (int k = 0; k < 48; ++k) r.v[11 + k] = h[k * in.n + i];
+  return r;
+}
+__device__ __forceinline__ void store_row(const CloneOut& out, int64_t d, const Row& r) {
+#pragma unroll
+  for (int k = 0; k < 3; ++k) out.means[k * out.cap + d] = r.v[k];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) out.scales[k * out.cap + d] = r.v[3 + k];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) out.quats[k * out.cap + d] = r.v[6 + k];
+  out.opac[d] = r.v[10];
+#pragma unroll
+  for (int k = 0; k < 48; ++k) out.sh[k * out.cap + d] = r.v[11 + k];
+}
+
 __global__ __launch_bounds__(kBlock) void k_clone_write(ClonePlanes in, const uint8_t* __restrict__ select,
                                                         const uint32_t* __restrict__ block_off, CloneOut out) {
   __shared__ uint32_t s_wave[kBlock / kWave];
-  __shared__ uint32_t s_carry;
-  const int64_t base = (int64_t)blockIdx.x * kCloneItems;
-  if (threadIdx.x == 0) s_carry = block_off[blockIdx.x];
-  __syncthreads();
-  for (int j0 = 0; j0 < kCloneItems; j0 += kBlock) {
-    const int64_t i = base + j0 + threadIdx.x;
-    const bool sel = i < in.n && select[i];
-    // rank of this row among the selected rows of the chunk
-    const uint64_t bal = __ballot(sel);
-    const uint32_t below = __popcll(bal & ((1ull << lane_id()) - 1ull));
-    if (lane_id() == 0) s_wave[threadIdx.x / kWave] = (uint32_t)__popcll(bal);
-    __syncthreads();
-    uint32_t off = s_carry;
-    for (int w = 0; w < (int)(threadIdx.x / kWave); ++w) off += s_wave[w];
-    const uint32_t chunk = s_wave[0] + s_wave[1] + s_wave[2] + s_wave[3];
-    if (i < in.n) {
-      float a = in.opac[i];
-      double fd = 1.0;
-      if (sel) {
-        // Sec. 5.1: a' = 1 - sqrt(1 - a); Sigma' = a^2 (2 a' - a'^2 / sqrt 2)^-2 Sigma,
-        // so every scale is multiplied by a / (2 a' - a'^2 / sqrt 2); a -> 0 has limit 1.
-        const double ad = (double)a;
-        const double an = 1.0 - sqrt(1.0 - ad);
-        fd = ad > 0.0 ? ad / (2.0 * an - an * an / sqrt(2.0)) : 1.0;
-        a = (float)an;
-      }
-      const int64_t dst[2] = {i, sel ? in.n + (int64_t)(off + below) : -1};
-      for (int c = 0; c < 2; ++c) {
-        const int64_t d = dst[c];
-        if (d < 0 || d >= out.cap) continue;
-        for (int k = 0; k < 3; ++k) out.means[k * out.cap + d] = in.means[k * in.n + i];
-        for (int k = 0; k < 3; ++k) {
-          const float s = in.scales[k * in.n + i];
-          out.scales[k * out.cap + d] = sel ? (float)((double)s * fd) : s;
-        }
-        for (int k = 0; k < 4; ++k) out.quats[k * out.cap + d] = in.quats[k * in.n + i];
-        out.opac[d] = a;
-        for (int k = 0; k < 48; ++k) out.sh[k * out.cap + d] = in.sh[k * in.n + i];
-      }
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) s_carry += chunk;
-    __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * kCopyRows + threadIdx.x;
+  const bool sel = i < in.n && select[i];
+  const uint32_t rank = copy_rank(sel, block_off, s_wave);
+  if (i >= in.n) return;
+  Row r = load_row(in, i);
+  if (sel) {
+    // Sec. 5.1: a' = 1 - sqrt(1 - a); Sigma' = a^2 (2 a' - a'^2 / sqrt 2)^-2 Sigma,
+    // so every scale is multiplied by a / (2 a' - a'^2 / sqrt 2); a -> 0 has limit 1.
+    const double ad = (double)r.v[10];
+    const double an = 1.0 - sqrt(1.0 - ad);
+    const double fd = ad > 0.0 ? ad / (2.0 * an - an * an / sqrt(2.0)) : 1.0;
+    r.v[10] = (float)an;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) r.v[3 + k] = (float)((double)r.v[3 + k] * fd);
+  }
+  if (i < out.cap) store_row(out, i, r);
+  const int64_t d = in.n + (int64_t)rank;
+  if (sel && d < out.cap) store_row(out, d, r);
+}
+
+// ---------------------------------------------------------------------------
+// 3DGS density control: clone / split selection, and the split into two
+// children drawn from the parent's own distribution
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_densify_select(const float* __restrict__ norm_sum,
+                                                           const uint32_t* __restrict__ count,
+                                                           const float* __restrict__ scales, int64_t n,
+                                                           double grad_thr, double scale_thr,
+                                                           uint8_t* __restrict__ clone, uint8_t* __restrict__ split) {
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
+    const uint32_t c = count[i];
+    const bool sel = c > 0u && (double)norm_sum[i] / (double)c >= grad_thr;
+    const float smax = fmaxf(fmaxf(scales[i], scales[n + i]), scales[2 * n + i]);
+    const bool big = (double)smax > scale_thr;
+    if (clone) clone[i] = (sel && !big) ? 1 : 0;
+    if (split) split[i] = (sel && big) ? 1 : 0;
+  }
+}
+
+// Unselected rows are compacted to i - rank(i); the children of the r-th
+// selected row go to (n - m) + 2 r + c, m = *total (the scan's count).
+__global__ __launch_bounds__(kBlock) void k_split_write(ClonePlanes in, const uint8_t* __restrict__ select,
+                                                        const float* __restrict__ normals, double factor,
+                                                        const uint32_t* __restrict__ block_off,
+                                                        const int64_t* __restrict__ total, CloneOut out) {
+  __shared__ uint32_t s_wave[kBlock / kWave];
+  const int64_t i = (int64_t)blockIdx.x * kCopyRows + threadIdx.x;
+  const bool sel = i < in.n && select[i];
+  const uint32_t rank = copy_rank(sel, block_off, s_wave);
+  if (i >= in.n) return;
+  Row r = load_row(in, i);
+  if (!sel) {
+    const int64_t d = i - (int64_t)rank;
+    if (d < out.cap) store_row(out, d, r);
+    return;
+  }
+  float z[2][3];
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) z[c][k] = normals[(int64_t)(3 * c + k) * in.n + i];
+  // rotation of the normalised quaternion (w, x, y, z); a zero quaternion
+  // leaves the draws unrotated
+  double m[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+  const double qq = (double)r.v[6] * r.v[6] + (double)r.v[7] * r.v[7] + (double)r.v[8] * r.v[8] +
+                    (double)r.v[9] * r.v[9];
+  if (qq > 0.0) {
+    const double inv = 1.0 / sqrt(qq);
+    const double w = r.v[6] * inv, x = r.v[7] * inv, y = r.v[8] * inv, zz = r.v[9] * inv;
+    m[0] = 1.0 - 2.0 * (y * y + zz * zz);
+    m[1] = 2.0 * (x * y - w * zz);
+    m[2] = 2.0 * (x * zz + w * y);
+    m[3] = 2.0 * (x * y + w * zz);
+    m[4] = 1.0 - 2.0 * (x * x + zz * zz);
+    m[5] = 2.0 * (y * zz - w * x);
+    m[6] = 2.0 * (x * zz - w * y);
+    m[7] = 2.0 * (y * zz + w * x);
+    m[8] = 1.0 - 2.0 * (x * x + y * y);
+  }
+  const double p[3] = {r.v[0], r.v[1], r.v[2]};
+  const double sc[3] = {r.v[3], r.v[4], r.v[5]};
+#pragma unroll
+  for (int k = 0; k < 3; ++k) r.v[3 + k] = (float)(sc[k] / factor);
+  const int64_t first = in.n - *total + 2 * (int64_t)rank;
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const double a0 = sc[0] * (double)z[c][0], a1 = sc[1] * (double)z[c][1], a2 = sc[2] * (double)z[c][2];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) r.v[q] = (float)(p[q] + (m[3 * q] * a0 + m[3 * q + 1] * a1 + m[3 * q + 2] * a2));
+    if (first + c < out.cap) store_row(out, first + c, r);
   }
 }
 
@@ -771,8 +863,61 @@ int32_t gs_grad_stats(const gs_projected_t* proj, const float* grad2d, const gs_
   return GS_OK;
 }
 
+int32_t gs_densify_select(const float* norm_sum, const uint32_t* count, const float* scales, int64_t n,
+                          double grad_threshold, double scale_threshold, uint8_t* clone, uint8_t* split,
+                          void* stream) {
+  if (n < 0) { set_error("n < 0"); return GS_ERR_SHAPE; }
+  if (n == 0) return GS_OK;
+  if (!norm_sum || !count || !scales) { set_error("NULL input"); return GS_ERR_NULL; }
+  if (!clone && !split) { set_error("clone and split are both NULL"); return GS_ERR_NULL; }
+  int64_t blocks = (n + kBlock - 1) / kBlock;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_densify_select, dim3((unsigned)blocks), dim3(kBlock), 0, (hipStream_t)stream, norm_sum, count,
+                     scales, n, grad_threshold, scale_threshold, clone, split);
+  MS_CHECK_LAUNCH("densify_select");
+  return GS_OK;
+}
+
+size_t gs_split_workspace_size(int64_t n) { return gs_clone_workspace_size(n); }
+
+int32_t gs_split(const gs_scene_t* in, const uint8_t* select, const float* normals, double factor,
+                 const gs_scene_out_t* out, int64_t* count, void* ws, size_t ws_bytes, void* stream) {
+  int32_t s = check_scene(in);
+  if (s != GS_OK) return s;
+  if (!out) { set_error("out is NULL"); return GS_ERR_NULL; }
+  if (out->capacity < in->n || out->capacity >= (int64_t(1) << 31)) {
+    set_error("output capacity below the input count or beyond 2^31");
+    return GS_ERR_CAPACITY;
+  }
+  if (!(factor > 0.0)) { set_error("factor must be > 0"); return GS_ERR_SHAPE; }
+  if (in->n > 0 && (!out->means || !out->scales || !out->quats || !out->opacity || !out->sh)) {
+    set_error("output plane is NULL");
+    return GS_ERR_NULL;
+  }
+  if (!count) { set_error("count is NULL"); return GS_ERR_NULL; }
+  if (in->n > 0 && (!select || !normals)) { set_error("select or normals is NULL"); return GS_ERR_NULL; }
+  if (ws_bytes < gs_split_workspace_size(in->n) || !ws) { set_error("split workspace too small"); return GS_ERR_CAPACITY; }
+  hipStream_t st = (hipStream_t)stream;
+  const int32_t nb = (int32_t)(in->n > 0 ? (in->n + kCopyRows - 1) / kCopyRows : 0);
+  uint32_t* block_off = (uint32_t*)ws;
+  if (nb > 0) {
+    hipLaunchKernelGGL(k_clone_count, dim3(nb), dim3(kBlock), 0, st, select, in->n, block_off);
+    MS_CHECK_LAUNCH("split_count");
+  }
+  hipLaunchKernelGGL(k_clone_scan, dim3(1), dim3(1024), 0, st, block_off, nb, count);
+  MS_CHECK_LAUNCH("split_scan");
+  if (nb > 0) {
+    ClonePlanes ip{in->means, in->scales, in->quats, in->opacity, in->sh, in->n};
+    CloneOut op{out->means, out->scales, out->quats, out->opacity, out->sh, out->capacity};
+    hipLaunchKernelGGL(k_split_write, dim3(nb), dim3(kBlock), 0, st, ip, select, normals, factor, block_off, count,
+                       op);
+    MS_CHECK_LAUNCH("split_write");
+  }
+  return GS_OK;
+}
+
 size_t gs_clone_workspace_size(int64_t n) {
-  const int64_t nb = n > 0 ? (n + kCloneItems - 1) / kCloneItems : 1;
+  const int64_t nb = n > 0 ? (n + kCopyRows - 1) / kCopyRows : 1;
   return (size_t)((nb * 4 + 255) / 256 * 256);
 }
 
@@ -793,7 +938,7 @@ int32_t gs_clone(const gs_scene_t* in, const uint8_t* select, const gs_scene_out
   if (in->n > 0 && !select) { set_error("select is NULL"); return GS_ERR_NULL; }
   if (ws_bytes < gs_clone_workspace_size(in->n) || !ws) { set_error("clone workspace too small"); return GS_ERR_CAPACITY; }
   hipStream_t st = (hipStream_t)stream;
-  const int64_t nb64 = in->n > 0 ? (in->n + kCloneItems - 1) / kCloneItems : 0;
+  const int64_t nb64 = in->n > 0 ? (in->n + kCopyRows - 1) / kCopyRows : 0;
   const int32_t nb = (int32_t)nb64;
   uint32_t* block_off = (uint32_t*)ws;
   if (nb > 0) {

@@ -80,6 +80,41 @@ def clone(scene: DeviceScene, select: torch.Tensor, capacity: Optional[int] = No
     return out, count
 
 
+SPLIT_FACTOR = 1.6  # 3DGS: children take the parent's scales divided by 1.6
+
+
+def densify_select(norm_sum: torch.Tensor, count: torch.Tensor, scales: torch.Tensor, grad_threshold: float,
+                   scale_threshold: float, stream=None) -> Tuple[torch.Tensor, torch.Tensor]:
+    """(clone [n], split [n]) uint8 masks of the 3DGS density control (Sec. 3.2)."""
+    n = norm_sum.numel()
+    dev = norm_sum.device
+    clone_m = torch.empty(n, dtype=torch.uint8, device=dev)
+    split_m = torch.empty(n, dtype=torch.uint8, device=dev)
+    L.check(L.lib().gs_densify_select(_ptr(norm_sum), _ptr(count), _ptr(scales), n, float(grad_threshold),
+                                      float(scale_threshold), _ptr(clone_m), _ptr(split_m), _stream(stream)),
+            "gs_densify_select")
+    return clone_m, split_m
+
+
+def split(scene: DeviceScene, select: torch.Tensor, normals: torch.Tensor, factor: float = SPLIT_FACTOR,
+          capacity: Optional[int] = None, stream=None) -> Tuple[DeviceScene, torch.Tensor]:
+    """Split of the selected rows into two children drawn from the parent
+    (normals [2, 3, n] standard-normal draws); unselected rows first."""
+    n = scene.n
+    dev = scene.opacity.device
+    if capacity is None:
+        capacity = n + int(select.sum().item())
+    out = DeviceScene(torch.empty((3, capacity), device=dev), torch.empty((3, capacity), device=dev),
+                      torch.empty((4, capacity), device=dev), torch.empty(capacity, device=dev),
+                      torch.empty((16, 3, capacity), device=dev), scene.sh_degree)
+    so = L.SceneOut(_ptr(out.means), _ptr(out.scales), _ptr(out.quats), _ptr(out.opacity), _ptr(out.sh), capacity)
+    count = torch.empty(1, dtype=torch.int64, device=dev)
+    ws = torch.empty(L.lib().gs_split_workspace_size(n), dtype=torch.uint8, device=dev)
+    L.check(L.lib().gs_split(ctypes.byref(scene.c()), _ptr(select), _ptr(normals), float(factor), ctypes.byref(so),
+                             _ptr(count), _ptr(ws), ws.numel(), _stream(stream)), "gs_split")
+    return out, count
+
+
 def sample(importance: torch.Tensor, expo: torch.Tensor, k: int, area: Optional[torch.Tensor] = None,
            stream=None) -> Tuple[torch.Tensor, torch.Tensor]:
     """Intersection preserving + primitive sampling (Sec. 4.2): (selected [n] uint8, count [1] int64).

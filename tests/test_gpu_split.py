@@ -1,0 +1,127 @@
+"""GPU parity of the 3DGS density control (Sec. 3.2) and of the split into two
+children that the blur split (Sec. 3.3, Eq. (3)) applies, against the oracle on
+seeded inputs: selection masks bit for bit; copied attributes bit for bit;
+children's scales and centres (double arithmetic rounded once to float32)
+within one float32 ulp of the oracle's double result."""
+import numpy as np
+import pytest
+import torch
+
+import gs_inputs
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def D():
+    from paper_2411_12788_amd import densify
+    return densify
+
+
+def R():
+    from paper_2411_12788_amd import raster
+    return raster
+
+
+def _ulp_diff(a, b):
+    ia = a.astype(np.float32).view(np.int32).astype(np.int64)
+    ib = b.astype(np.float32).view(np.int32).astype(np.int64)
+    ia = np.where(ia < 0, np.int64(-2**31) - ia, ia)
+    ib = np.where(ib < 0, np.int64(-2**31) - ib, ib)
+    return np.abs(ia - ib)
+
+
+def _scene(n, seed):
+    s = gs_inputs.uniform_cube_scene(n, seed=seed)
+    q = s.quats.copy()
+    q[:, : min(n, 2)] = 0.0            # zero quaternions: unrotated draws
+    q[:, 2: min(n, 6)] *= 7.5          # unnormalised ones
+    s.quats = q
+    return s
+
+
+def _check_split(scene, sel, z, factor=1.6, capacity=None):
+    n = scene.opacity.shape[0]
+    ds = R().DeviceScene.from_numpy(scene)
+    out, count = D().split(ds, torch.from_numpy(sel).cuda(), torch.from_numpy(z).cuda(), factor, capacity)
+    ref = oracle.split(oracle.Params.of(scene), sel, z, factor)
+    m = int(sel.sum())
+    assert int(count.cpu()[0]) == m == ref.n - n
+    cap = ref.n if capacity is None else capacity
+    for name in ("quats", "opacity", "sh"):
+        g = getattr(out, name).cpu().numpy()[..., :cap]
+        assert (g == getattr(ref, name)[..., :cap].astype(np.float32)).all(), name
+    for name in ("scales", "means"):
+        g = getattr(out, name).cpu().numpy()[..., :cap]
+        d = _ulp_diff(g, getattr(ref, name)[..., :cap])
+        assert d.max(initial=0) <= 1, (name, int(d.max()))
+
+
+@pytest.mark.parametrize("n", [1, 257, 4096, 10_007, 100_003])
+@pytest.mark.parametrize("frac", [0.0, 0.3, 1.0])
+def test_split_matches_oracle(gpu_lib, n, frac):
+    seed = n % 97
+    scene = _scene(n, seed)
+    sel = gs_inputs.bernoulli_mask(n, frac, seed + 1)
+    z = gs_inputs.normal_draws((2, 3, n), seed + 2)
+    _check_split(scene, sel, z)
+
+
+def test_split_factor_and_capacity(gpu_lib):
+    n = 5000
+    scene = _scene(n, 4)
+    sel = gs_inputs.bernoulli_mask(n, 0.5, 5)
+    z = gs_inputs.normal_draws((2, 3, n), 6)
+    _check_split(scene, sel, z, factor=2.5)
+    _check_split(scene, sel, z, capacity=n + 17)  # children beyond the capacity are dropped
+
+
+def test_split_empty(gpu_lib):
+    scene = gs_inputs.uniform_cube_scene(0, seed=1)
+    ds = R().DeviceScene.from_numpy(scene)
+    out, count = D().split(ds, torch.zeros(0, dtype=torch.uint8, device="cuda"),
+                           torch.zeros((2, 3, 0), device="cuda"), capacity=0)
+    assert int(count.cpu()[0]) == 0
+
+
+def test_split_full_size(gpu_lib):
+    """3M Gaussians, the large-scene size, 2% selected."""
+    n = 3_000_000
+    scene = gs_inputs.uniform_cube_scene(n, seed=31)
+    sel = gs_inputs.bernoulli_mask(n, 0.02, 32)
+    z = gs_inputs.normal_draws((2, 3, n), 33)
+    _check_split(scene, sel, z)
+
+
+@pytest.mark.parametrize("n", [1, 1000, 100_003])
+def test_densify_select_matches_oracle(gpu_lib, n):
+    norm_sum, count = gs_inputs.gradient_stats_like(n, 40 + n % 7)
+    scales = gs_inputs.uniform_cube_scene(n, seed=41).scales
+    if n >= 4:
+        # exact boundary cases: mean gradient == threshold, largest scale == threshold
+        norm_sum[:2], count[:2] = 6e-4, 3
+        scales[:, 2:4] = 0.01
+        scales[1, 2:4] = (0.02, 0.0200001)
+    gthr = float(np.float32(6e-4)) / 3.0     # row 0/1: mean gradient exactly at the threshold
+    sthr = float(np.float32(0.02))            # row 2: largest scale exactly at the threshold
+    cl_g, sp_g = D().densify_select(torch.from_numpy(norm_sum).cuda(), torch.from_numpy(count).cuda(),
+                                    torch.from_numpy(np.ascontiguousarray(scales)).cuda(), gthr, sthr)
+    cl_o, sp_o = oracle.densify_select(norm_sum, count, scales, gthr, sthr)
+    assert (cl_g.cpu().numpy().astype(bool) == cl_o).all()
+    assert (sp_g.cpu().numpy().astype(bool) == sp_o).all()
+    if n >= 4:
+        assert cl_o[0] or sp_o[0]  # equality selects
+
+
+def test_blur_split_then_split(gpu_lib):
+    """The blur split criterion (Eq. (3)) hands its Gaussians to the split."""
+    n = 20_000
+    scene = _scene(n, 12)
+    area, _ = gs_inputs.wmax_like(n, 13)
+    area_t = torch.from_numpy(area.astype(np.uint32)).cuda()
+    sel = D().blur_split(area_t, 240, 320)  # theta H W = 15.4 pixels
+    sel_o = oracle.blur_split(area.astype(np.int64), 240, 320)
+    assert 0 < sel_o.sum() < n
+    assert (sel.cpu().numpy().astype(bool) == sel_o).all()
+    z = gs_inputs.normal_draws((2, 3, n), 14)
+    _check_split(scene, sel.cpu().numpy(), z)
