@@ -731,38 +731,37 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(const float* __restrict__
         bool contrib[kBwdUnroll];
 #pragma unroll
         for (int u = 0; u < kBwdUnroll; ++u) {
-#pragma unroll
-          for (int q = 0; q < 9; ++q) pv[u][q] = 0.f;
-          contrib[u] = false;
-          // transmittance in front of the entry, its partials, then its colour joins the suffix
-          if (val[u] && ee[u] >= op.log2_alpha_min) {
-            const float al = fminf(op.alpha_max, G2[u]);
-            const float iom = __builtin_amdgcn_rcpf(1.f - al);
-            T = T * iom;
-            const float wgt = al * T;
-            const float4 c4 = q2[u];
-            if ((tag[u] >> 31) != 0) {
-              const float ga = g0 * (T * c4.x - s0 * iom) + g1 * (T * c4.y - s1 * iom) + g2 * (T * c4.z - s2 * iom);
-              pv[u][6] = wgt * g0;
-              pv[u][7] = wgt * g1;
-              pv[u][8] = wgt * g2;
-              if (G2[u] < op.alpha_max) {
-                const float4 r3 = s_r3[kk[u]];
-                const float dx = dxs[u], dy = dys[u];
-                pv[u][5] = ga * al * __builtin_amdgcn_rcpf(c4.w);
-                const float gq = -0.5f * ga * al;  // d alpha / d q with q = d^T conic d
-                pv[u][2] = gq * dx * dx;
-                pv[u][3] = 2.f * gq * dx * dy;
-                pv[u][4] = gq * dy * dy;
-                pv[u][0] = -2.f * gq * (r3.y * dx + r3.z * dy);
-                pv[u][1] = -2.f * gq * (r3.z * dx + r3.w * dy);
-              }
-              contrib[u] = true;
-            }
-            s0 += wgt * c4.x;
-            s1 += wgt * c4.y;
-            s2 += wgt * c4.z;
-          }
+          // Branch-free per lane: a lane that skips the entry multiplies its
+          // partials by zero and keeps its transmittance; staged records are
+          // finite, so the zero products are zeros.  Transmittance in front of
+          // the entry, its partials, then its colour joins the suffix.
+          const bool inc = val[u] && ee[u] >= op.log2_alpha_min;
+          const bool act = inc && (tag[u] >> 31) != 0;
+          const float al = fminf(op.alpha_max, G2[u]);
+          const float iom = __builtin_amdgcn_rcpf(1.f - al);
+          T = inc ? T * iom : T;
+          const float wgt = inc ? al * T : 0.f;
+          const float4 c4 = q2[u];
+          const float4 r3 = s_r3[kk[u]];
+          const float ga = g0 * (T * c4.x - s0 * iom) + g1 * (T * c4.y - s1 * iom) + g2 * (T * c4.z - s2 * iom);
+          const float wa = act ? wgt : 0.f;
+          pv[u][6] = wa * g0;
+          pv[u][7] = wa * g1;
+          pv[u][8] = wa * g2;
+          // the clamped alpha has no gradient with respect to opacity or shape
+          const float gal = (act && G2[u] < op.alpha_max) ? ga * al : 0.f;
+          const float dx = dxs[u], dy = dys[u];
+          pv[u][5] = gal != 0.f ? gal * __builtin_amdgcn_rcpf(c4.w) : 0.f;
+          const float gq = -0.5f * gal;  // d alpha / d q with q = d^T conic d
+          pv[u][2] = gq * dx * dx;
+          pv[u][3] = 2.f * gq * dx * dy;
+          pv[u][4] = gq * dy * dy;
+          pv[u][0] = -2.f * gq * (r3.y * dx + r3.z * dy);
+          pv[u][1] = -2.f * gq * (r3.z * dx + r3.w * dy);
+          contrib[u] = act;
+          s0 += wgt * c4.x;
+          s1 += wgt * c4.y;
+          s2 += wgt * c4.z;
         }
 #pragma unroll
         for (int u = 0; u < kBwdUnroll; ++u) {
