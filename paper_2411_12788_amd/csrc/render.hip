@@ -120,6 +120,73 @@ __device__ __forceinline__ float swap_sum32(float x) {
   const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(x), false, false);
   return __uint_as_float(r[0]) + __uint_as_float(r[1]);
 }
+// Exchanges between the four 16-lane rows of one column (lanes j, 16 + j,
+// 32 + j, 48 + j) with the gfx950 permlane swaps: permlane16_swap hands each
+// row the values of the even and the odd row of its pair (rows 0-1, 2-3),
+// permlane32_swap the values of the same row parity in the lower and upper
+// pair.  Split work items use the rows as four consecutive entries of one
+// pixel group's stream; the scans below combine them in row order.
+struct RowsTwo {
+  uint32_t a, b;
+};
+__device__ __forceinline__ RowsTwo rows_pair(uint32_t x) {
+  const auto r = __builtin_amdgcn_permlane16_swap(x, x, false, false);
+  return {r[0], r[1]};
+}
+__device__ __forceinline__ RowsTwo rows_halves(uint32_t x) {
+  const auto r = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+  return {r[0], r[1]};
+}
+struct RowScan {
+  float incl, excl, total;
+};
+// Products over the rows of a column: inclusive and exclusive up to `row`,
+// and over all four rows.
+__device__ __forceinline__ RowScan rows_scan_mul(float x, int row) {
+  const RowsTwo p = rows_pair(__float_as_uint(x));
+  const float e = __uint_as_float(p.a), o = __uint_as_float(p.b);
+  const float pair = e * o;
+  const RowsTwo h = rows_halves(__float_as_uint(pair));
+  const float lo = __uint_as_float(h.a), hi = __uint_as_float(h.b);
+  const float in2 = (row & 1) ? pair : e, ex2 = (row & 1) ? e : 1.f;
+  RowScan r;
+  r.incl = row >= 2 ? lo * in2 : in2;
+  r.excl = row >= 2 ? lo * ex2 : ex2;
+  r.total = lo * hi;
+  return r;
+}
+// Sums over the rows of a column: exclusive up to `row` and over all four.
+__device__ __forceinline__ RowScan rows_scan_add(float x, int row) {
+  const RowsTwo p = rows_pair(__float_as_uint(x));
+  const float e = __uint_as_float(p.a), o = __uint_as_float(p.b);
+  const float pair = e + o;
+  const RowsTwo h = rows_halves(__float_as_uint(pair));
+  const float lo = __uint_as_float(h.a), hi = __uint_as_float(h.b);
+  const float ex2 = (row & 1) ? e : 0.f;
+  RowScan r;
+  r.incl = 0.f;
+  r.excl = row >= 2 ? lo + ex2 : ex2;
+  r.total = lo + hi;
+  return r;
+}
+__device__ __forceinline__ float rows_sum(float x) {
+  const RowsTwo p = rows_pair(__float_as_uint(x));
+  const float pair = __uint_as_float(p.a) + __uint_as_float(p.b);
+  const RowsTwo h = rows_halves(__float_as_uint(pair));
+  return __uint_as_float(h.a) + __uint_as_float(h.b);
+}
+__device__ __forceinline__ uint32_t rows_sum_u32(uint32_t x) {
+  const RowsTwo p = rows_pair(x);
+  const RowsTwo h = rows_halves(p.a + p.b);
+  return h.a + h.b;
+}
+__device__ __forceinline__ uint32_t rows_max_u32(uint32_t x) {
+  const RowsTwo p = rows_pair(x);
+  const uint32_t m = p.a > p.b ? p.a : p.b;
+  const RowsTwo h = rows_halves(m);
+  return h.a > h.b ? h.a : h.b;
+}
+
 template <int CTRL>
 __device__ __forceinline__ uint32_t dpp_take_u32(uint32_t x) {
   return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, 0xF, 0xF, true);
@@ -262,9 +329,10 @@ __device__ __forceinline__ Rect group_rect(uint32_t bits, int32_t gx0, int32_t g
 // Work item of a render workgroup.  With a tile order (longest lists first),
 // each of the first kSplitTiles tiles of the order gets four workgroups; if its
 // list is long they take one 8x8 quarter each, with one 4x4 pixel group per
-// wave (16 active lanes), so the tile's sixteen groups walk their streams
-// independently instead of four to a wave in lockstep: these tiles set the
-// kernel's length.  For a short list the first of the four takes the whole
+// wave, so the tile's sixteen groups walk their streams independently instead
+// of four to a wave in lockstep: these tiles set the kernel's length.  Such a
+// wave's four rows hold the same 16 pixels and take four consecutive entries
+// of the group's stream per step, combined across rows by scans.  For a short list the first of the four takes the whole
 // tile and the other three exit.
 constexpr int32_t kSplitTiles = 256;
 constexpr uint32_t kSplitLen = 2048;
@@ -287,7 +355,8 @@ __device__ __forceinline__ WorkItem work_item(const uint32_t* order, const uint3
   }
   return w;
 }
-// Pixel of this lane and the origin of its 4x4 group (see work_item).
+// Pixel of this lane and the origin of its 4x4 group (see work_item).  In a
+// split work item the four rows of a wave carry the same 16 pixels.
 struct LanePixel {
   int32_t sx0, sy0;  // origin of group 0 of this wave
   int32_t px, py;
@@ -307,7 +376,7 @@ __device__ __forceinline__ LanePixel lane_pixel(int32_t tx, int32_t ty, int32_t 
     l.sy0 = ty * kTile + (quarter >> 1) * 8 + (wv >> 1) * 4;
     l.px = l.sx0 + (lane & 3);
     l.py = l.sy0 + ((lane >> 2) & 3);
-    l.on = lane < 16;
+    l.on = true;  // every row carries the group's 16 pixels (rows = consecutive entries)
   }
   return l;
 }
@@ -365,6 +434,7 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(const float* __restrict__
   // max over groups instead of the union of the four streams.
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int grp = lane >> 4;
+  const bool rp = wi.quarter >= 0;  // split work item: rows are consecutive entries
   const LanePixel lp = lane_pixel(tx, ty, wi.quarter, wv, lane);
   const int32_t sx0 = lp.sx0, sy0 = lp.sy0, px = lp.px, py = lp.py;
   const bool inside = lp.on && px < cam.width && py < cam.height;
@@ -376,6 +446,7 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(const float* __restrict__
   float T = 1.f, c0 = 0.f, c1 = 0.f, c2 = 0.f, wbest = 0.f, dblend = 0.f;
   int32_t best = -1;
   uint32_t lastpos = 0, cnt = 0;
+  uint32_t bpos = 0xffffffffu;  // list position of `best` (split work items)
   bool done = !inside;
   // Staging pipeline: while round R is processed, the records of round R + 1
   // and the list indices of round R + 2 are already in flight.
@@ -411,7 +482,7 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(const float* __restrict__
       uint64_t gmask[4];
 #pragma unroll
       for (int g = 0; g < 4; ++g) {
-        const uint32_t bits = (uint32_t)(am >> (16 * g)) & 0xffffu;
+        const uint32_t bits = (rp && g > 0) ? 0u : (uint32_t)(am >> (16 * g)) & 0xffffu;
         bool rel = false;
         if (bits != 0u) {
           const Rect rg = group_rect(bits, sx0 + (g & 1) * 4, sy0 + (g >> 1) * 4);
@@ -420,7 +491,60 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(const float* __restrict__
         }
         gmask[g] = __ballot(rel);
       }
-      uint64_t mine = grp == 0 ? gmask[0] : grp == 1 ? gmask[1] : grp == 2 ? gmask[2] : gmask[3];
+      uint64_t mine = rp ? gmask[0] : grp == 0 ? gmask[0] : grp == 1 ? gmask[1] : grp == 2 ? gmask[2] : gmask[3];
+      // Split work item: row r takes the r-th of the next four entries of the
+      // group's stream.  The transmittance in front of each is T times the
+      // product of (1 - alpha) over the rows before it; an entry is composited
+      // unless its own or an earlier row's entry reaches the stop.  Each row
+      // keeps partial colour, depth, count and argmax, merged at the end.
+      while (rp && mine != 0) {
+        int kk[4];
+        bool has[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          has[u] = mine != 0;
+          kk[u] = c * kWave + (has[u] ? (int)__builtin_ctzll(mine) : 0);
+          mine &= mine - 1;
+        }
+        const int kr = grp == 0 ? kk[0] : grp == 1 ? kk[1] : grp == 2 ? kk[2] : kk[3];
+        const bool hr = grp == 0 ? has[0] : grp == 1 ? has[1] : grp == 2 ? has[2] : has[3];
+        const float4 r0 = s_r0[kr], r1 = s_r1[kr], q2 = s_r2[kr];
+        const float dx = (pxc - r0.x) - r0.z, dy = (pyc - r0.y) - r0.w;
+        const float ee = r1.w - (r1.x * dx * dx + r1.y * dx * dy + r1.z * dy * dy);
+        const float al = fminf(op.alpha_max, __builtin_amdgcn_exp2f(ee));
+        const bool pass = hr && !done && ee >= op.log2_alpha_min;
+        const float om = pass ? 1.f - al : 1.f;
+        const RowScan tf = rows_scan_mul(om, grp);
+        const bool stop = pass && T * tf.incl < op.t_min;
+        const uint64_t sb = __ballot(stop);
+        const uint64_t col = 0x0001000100010001ull << (lane & 15);
+        const bool earlier = (sb & col & ((1ull << (16 * grp)) - 1ull)) != 0;
+        const bool inc = pass && !stop && !earlier;
+        const float wgt = inc ? al * (T * tf.excl) : 0.f;
+        c0 += wgt * q2.x;
+        c1 += wgt * q2.y;
+        c2 += wgt * q2.z;
+        if (DEPTH == GS_DEPTH_BLEND) dblend += wgt * s_z[kr];
+        const uint32_t pos = base + (uint32_t)kr - start;
+        const bool better = wgt > wbest;  // a row's entries arrive in order: the nearer wins ties
+        wbest = better ? wgt : wbest;
+        best = better ? (int32_t)((int64_t)__float_as_uint(q2.w) - vbase) : best;
+        bpos = better ? pos : bpos;
+        lastpos = inc ? pos + 1 : lastpos;
+        cnt += inc ? 1u : 0u;
+        if (ACC && inc) {
+          atomicAdd(&s_acc_w[kr], wgt);
+          atomicMax(&s_acc_m[kr], __float_as_uint(wgt));
+        }
+        T = T * rows_scan_mul(inc ? om : 1.f, grp).total;
+        done = done || (sb & col) != 0;
+        const uint64_t dm = __ballot(done);
+        if ((dm & 0xffffull) == 0xffffull) mine = 0;
+        if (dm == ~0ull) {
+          wave_done = true;
+          break;
+        }
+      }
       // kFwdUnroll entries of the group's stream per iteration: their records
       // are read and their alphas evaluated side by side, then they are
       // composited in order (each sees the previous one's transmittance and
@@ -492,6 +616,28 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(const float* __restrict__
         if (o.wmax) atomicMax(reinterpret_cast<unsigned int*>(o.wmax) + ai, s_acc_m[threadIdx.x]);
       }
     }
+  }
+  if (rp) {
+    // merge the rows' partials (every row of a column holds the same pixel)
+    c0 = rows_sum(c0);
+    c1 = rows_sum(c1);
+    c2 = rows_sum(c2);
+    if (DEPTH == GS_DEPTH_BLEND) dblend = rows_sum(dblend);
+    cnt = rows_sum_u32(cnt);
+    lastpos = rows_max_u32(lastpos);
+    // argmax: the larger weight, on equal weights the earlier list position
+#pragma unroll
+    for (int step = 0; step < 2; ++step) {
+      const RowsTwo w = step == 0 ? rows_pair(__float_as_uint(wbest)) : rows_halves(__float_as_uint(wbest));
+      const RowsTwo b = step == 0 ? rows_pair((uint32_t)best) : rows_halves((uint32_t)best);
+      const RowsTwo q = step == 0 ? rows_pair(bpos) : rows_halves(bpos);
+      const float wa = __uint_as_float(w.a), wb = __uint_as_float(w.b);
+      const bool take_b = wb > wa || (wb == wa && q.b < q.a);
+      wbest = take_b ? wb : wa;
+      best = (int32_t)(take_b ? b.b : b.a);
+      bpos = take_b ? q.b : q.a;
+    }
+    if (grp != 0) return;  // row 0 writes the pixel
   }
   if (!inside) return;
   if (ACC && o.area && best >= 0) atomicAdd(o.area + (per_view ? vbase + best : (int64_t)best), 1u);
@@ -623,6 +769,7 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(const float* __restrict__
   const int32_t tx = lt % cam.tiles_x, ty = lt / cam.tiles_x;
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int grp = lane >> 4;
+  const bool rp = wi.quarter >= 0;  // split work item: rows are consecutive entries
   const LanePixel lp = lane_pixel(tx, ty, wi.quarter, wv, lane);
   const int32_t sx0 = lp.sx0, sy0 = lp.sy0, px = lp.px, py = lp.py;
   const bool inside = lp.on && px < cam.width && py < cam.height;
@@ -690,7 +837,7 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(const float* __restrict__
       uint64_t gmask[4];
 #pragma unroll
       for (int g = 0; g < 4; ++g) {
-        const uint32_t bits = (uint32_t)(am >> (16 * g)) & 0xffffu;
+        const uint32_t bits = (rp && g > 0) ? 0u : (uint32_t)(am >> (16 * g)) & 0xffffu;
         bool rel = false;
         if (bits != 0u) {
           const Rect rg = group_rect(bits, sx0 + (g & 1) * 4, sy0 + (g >> 1) * 4);
@@ -699,7 +846,65 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(const float* __restrict__
         }
         gmask[g] = __ballot(rel);
       }
-      uint64_t mine = grp == 0 ? gmask[0] : grp == 1 ? gmask[1] : grp == 2 ? gmask[2] : gmask[3];
+      uint64_t mine = rp ? gmask[0] : grp == 0 ? gmask[0] : grp == 1 ? gmask[1] : grp == 2 ? gmask[2] : gmask[3];
+      // Split work item: row r takes the r-th latest of the next four entries
+      // of the group's stream.  The transmittance in front of each is the
+      // product of 1 / (1 - alpha) over the rows up to it, its suffix colour
+      // the sum of the weighted colours of the rows before it; the nine
+      // partials of each row's entry are then summed over the row as usual.
+      while (rp && mine != 0) {
+        int kk[4];
+        bool has[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          has[u] = mine != 0;
+          const int hb = has[u] ? 63 - (int)__builtin_clzll(mine) : 0;
+          mine &= ~(1ull << hb);
+          kk[u] = c * kWave + hb;
+        }
+        const int kr = grp == 0 ? kk[0] : grp == 1 ? kk[1] : grp == 2 ? kk[2] : kk[3];
+        const bool hr = grp == 0 ? has[0] : grp == 1 ? has[1] : grp == 2 ? has[2] : has[3];
+        const bool val = hr && base + (uint32_t)kr - start < lst;
+        const uint32_t tag = s_idx[kr];
+        const float4 r0 = s_r0[kr], r1 = s_r1[kr], c4 = s_r2[kr], r3 = s_r3[kr];
+        const float dx = (pxc - r0.x) - r0.z, dy = (pyc - r0.y) - r0.w;
+        const float ee = r1.w - (r1.x * dx * dx + r1.y * dx * dy + r1.z * dy * dy);
+        const float G2 = __builtin_amdgcn_exp2f(ee);
+        const bool inc = val && ee >= op.log2_alpha_min;
+        const bool act = inc && (tag >> 31) != 0;
+        const float al = fminf(op.alpha_max, G2);
+        const float iom = __builtin_amdgcn_rcpf(1.f - al);
+        const RowScan tr = rows_scan_mul(inc ? iom : 1.f, grp);
+        const float Tr = T * tr.incl;
+        const float wgt = inc ? al * Tr : 0.f;
+        const RowScan u0 = rows_scan_add(wgt * c4.x, grp), u1 = rows_scan_add(wgt * c4.y, grp),
+                      u2 = rows_scan_add(wgt * c4.z, grp);
+        const float sr0 = s0 + u0.excl, sr1 = s1 + u1.excl, sr2 = s2 + u2.excl;
+        const float ga = g0 * (Tr * c4.x - sr0 * iom) + g1 * (Tr * c4.y - sr1 * iom) + g2 * (Tr * c4.z - sr2 * iom);
+        float pv[9];
+        const float wa = act ? wgt : 0.f;
+        pv[6] = wa * g0;
+        pv[7] = wa * g1;
+        pv[8] = wa * g2;
+        const float gal = (act && G2 < op.alpha_max) ? ga * al : 0.f;
+        pv[5] = gal != 0.f ? gal * __builtin_amdgcn_rcpf(c4.w) : 0.f;
+        const float gq = -0.5f * gal;
+        pv[2] = gq * dx * dx;
+        pv[3] = 2.f * gq * dx * dy;
+        pv[4] = gq * dy * dy;
+        pv[0] = -2.f * gq * (r3.y * dx + r3.z * dy);
+        pv[1] = -2.f * gq * (r3.z * dx + r3.w * dy);
+        T = T * tr.total;
+        s0 += u0.total;
+        s1 += u1.total;
+        s2 += u2.total;
+        const uint64_t cm = __ballot(act);
+        if (cm != 0) {
+          const Sum9 r = row_sum9(pv, lane);
+          if (slot >= 0 && ((cm >> (16 * grp)) & 0xffffull) != 0)
+            atomicAdd(g2d + (int64_t)(tag & 0x7fffffffu) * kG2d + slot, slot == 8 ? r.v8 : r.v);
+        }
+      }
       // kBwdUnroll entries of the group's stream per iteration, latest first:
       // records and alphas side by side, then the transmittance is restored
       // through them in reverse order, exactly as one by one.
