@@ -91,6 +91,9 @@ __device__ __forceinline__ int2 uload(const int2* p) {
   return make_int2(q[0], q[1]);
 }
 __device__ __forceinline__ uint32_t uniform_u32(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t x) {
+  return (uint64_t)uniform_u32((uint32_t)x) | ((uint64_t)uniform_u32((uint32_t)(x >> 32)) << 32);
+}
 
 // Wave-wide reductions over 64 lanes.
 __device__ __forceinline__ float wave_sum(float x) {

@@ -332,10 +332,12 @@ __device__ __forceinline__ Rect group_rect(uint32_t bits, int32_t gx0, int32_t g
 // wave, so the tile's sixteen groups walk their streams independently instead
 // of four to a wave in lockstep: these tiles set the kernel's length.  Such a
 // wave's four rows hold the same 16 pixels and take four consecutive entries
-// of the group's stream per step, combined across rows by scans.  For a short list the first of the four takes the whole
-// tile and the other three exit.
-constexpr int32_t kSplitTiles = 256;
-constexpr uint32_t kSplitLen = 2048;
+// of the group's stream per step, combined across rows by scans.  For a short
+// list one of the four takes the whole tile and the other three exit; which
+// one rotates with the tile, so that these runners spread over the eight XCDs
+// (workgroup b runs on XCD b mod 8).
+constexpr int32_t kSplitTiles = 2048;
+constexpr uint32_t kSplitLen = 256;
 struct WorkItem {
   int32_t tile;
   int32_t quarter;  // -1: whole tile
@@ -349,7 +351,7 @@ __device__ __forceinline__ WorkItem work_item(const uint32_t* order, const uint3
     w.tile = (int32_t)uload(order + (b >> 2));
     const uint32_t len = uload(ranges + 2 * w.tile + 1) - uload(ranges + 2 * w.tile);
     if (len >= kSplitLen) w.quarter = b & 3;
-    else w.skip = (b & 3) != 0;
+    else w.skip = (b & 3) != ((b >> 3) & 3);  // the runner rotates over the XCDs (block b runs on XCD b % 8)
   } else {
     w.tile = (int32_t)uload(order + (b - 3 * nsplit));
   }
@@ -497,17 +499,15 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(const float* __restrict__
       // product of (1 - alpha) over the rows before it; an entry is composited
       // unless its own or an earlier row's entry reaches the stop.  Each row
       // keeps partial colour, depth, count and argmax, merged at the end.
-      while (rp && mine != 0) {
-        int kk[4];
-        bool has[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          has[u] = mine != 0;
-          kk[u] = c * kWave + (has[u] ? (int)__builtin_ctzll(mine) : 0);
-          mine &= mine - 1;
-        }
-        const int kr = grp == 0 ? kk[0] : grp == 1 ? kk[1] : grp == 2 ? kk[2] : kk[3];
-        const bool hr = grp == 0 ? has[0] : grp == 1 ? has[1] : grp == 2 ? has[2] : has[3];
+      uint64_t rmine = rp ? uniform_u64(mine) : 0ull;  // the same in every lane: keep it scalar
+      if (rp) mine = 0;
+      while (rmine != 0) {
+        // row r's entry: the lowest set bit of the mask with r lower bits cleared
+        const uint64_t m1 = rmine & (rmine - 1), m2 = m1 & (m1 - 1), m3 = m2 & (m2 - 1);
+        const uint64_t mr = grp < 2 ? (grp == 0 ? rmine : m1) : (grp == 2 ? m2 : m3);
+        rmine = m3 & (m3 - 1);
+        const bool hr = mr != 0;
+        const int kr = c * kWave + (hr ? (int)__builtin_ctzll(mr) : 0);
         const float4 r0 = s_r0[kr], r1 = s_r1[kr], q2 = s_r2[kr];
         const float dx = (pxc - r0.x) - r0.z, dy = (pyc - r0.y) - r0.w;
         const float ee = r1.w - (r1.x * dx * dx + r1.y * dx * dy + r1.z * dy * dy);
@@ -539,7 +539,7 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(const float* __restrict__
         T = T * rows_scan_mul(inc ? om : 1.f, grp).total;
         done = done || (sb & col) != 0;
         const uint64_t dm = __ballot(done);
-        if ((dm & 0xffffull) == 0xffffull) mine = 0;
+        if ((dm & 0xffffull) == 0xffffull) rmine = 0;
         if (dm == ~0ull) {
           wave_done = true;
           break;
@@ -852,18 +852,16 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(const float* __restrict__
       // product of 1 / (1 - alpha) over the rows up to it, its suffix colour
       // the sum of the weighted colours of the rows before it; the nine
       // partials of each row's entry are then summed over the row as usual.
-      while (rp && mine != 0) {
-        int kk[4];
-        bool has[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          has[u] = mine != 0;
-          const int hb = has[u] ? 63 - (int)__builtin_clzll(mine) : 0;
-          mine &= ~(1ull << hb);
-          kk[u] = c * kWave + hb;
-        }
-        const int kr = grp == 0 ? kk[0] : grp == 1 ? kk[1] : grp == 2 ? kk[2] : kk[3];
-        const bool hr = grp == 0 ? has[0] : grp == 1 ? has[1] : grp == 2 ? has[2] : has[3];
+      uint64_t rmine = rp ? uniform_u64(mine) : 0ull;  // the same in every lane: keep it scalar
+      if (rp) mine = 0;
+      while (rmine != 0) {
+        // row r's entry: the highest set bit of the mask with r higher bits cleared
+        auto drop_top = [](uint64_t m) { return m != 0 ? m & ~(1ull << (63 - __builtin_clzll(m))) : 0ull; };
+        const uint64_t m1 = drop_top(rmine), m2 = drop_top(m1), m3 = drop_top(m2);
+        const uint64_t mr = grp < 2 ? (grp == 0 ? rmine : m1) : (grp == 2 ? m2 : m3);
+        rmine = drop_top(m3);
+        const bool hr = mr != 0;
+        const int kr = c * kWave + (hr ? 63 - (int)__builtin_clzll(mr) : 0);
         const bool val = hr && base + (uint32_t)kr - start < lst;
         const uint32_t tag = s_idx[kr];
         const float4 r0 = s_r0[kr], r1 = s_r1[kr], c4 = s_r2[kr], r3 = s_r3[kr];
