@@ -336,21 +336,29 @@ __device__ __forceinline__ Rect group_rect(uint32_t bits, int32_t gx0, int32_t g
 // list one of the four takes the whole tile and the other three exit; which
 // one rotates with the tile, so that these runners spread over the eight XCDs
 // (workgroup b runs on XCD b mod 8).
-constexpr int32_t kSplitTiles = 2048;
-constexpr uint32_t kSplitLen = 256;
+// (tiles of the order that may split, minimum list length to split) per kernel
+struct SplitCfg {
+  int32_t tiles;
+  uint32_t len;
+};
+constexpr SplitCfg kFwdSplit{256, 2048};
+constexpr SplitCfg kBwdSplit{2048, 256};
+// forward split waves: rows as consecutive entries (true) or one 16-lane group (false)
+constexpr bool kFwdRowParallel = false;
 struct WorkItem {
   int32_t tile;
   int32_t quarter;  // -1: whole tile
   bool skip;
 };
-__device__ __forceinline__ WorkItem work_item(const uint32_t* order, const uint32_t* ranges, int32_t nsplit) {
+__device__ __forceinline__ WorkItem work_item(const uint32_t* order, const uint32_t* ranges, int32_t nsplit,
+                                              uint32_t split_len) {
   WorkItem w{(int32_t)blockIdx.x, -1, false};
   if (order == nullptr) return w;
   const int32_t b = (int32_t)blockIdx.x;
   if (b < 4 * nsplit) {
     w.tile = (int32_t)uload(order + (b >> 2));
     const uint32_t len = uload(ranges + 2 * w.tile + 1) - uload(ranges + 2 * w.tile);
-    if (len >= kSplitLen) w.quarter = b & 3;
+    if (len >= split_len) w.quarter = b & 3;
     else w.skip = (b & 3) != ((b >> 3) & 3);  // the runner rotates over the XCDs (block b runs on XCD b % 8)
   } else {
     w.tile = (int32_t)uload(order + (b - 3 * nsplit));
@@ -364,7 +372,8 @@ struct LanePixel {
   int32_t px, py;
   bool on;           // lane carries a pixel of the work item
 };
-__device__ __forceinline__ LanePixel lane_pixel(int32_t tx, int32_t ty, int32_t quarter, int wv, int lane) {
+__device__ __forceinline__ LanePixel lane_pixel(int32_t tx, int32_t ty, int32_t quarter, int wv, int lane,
+                                                bool rows_share) {
   LanePixel l;
   if (quarter < 0) {
     const int grp = lane >> 4;
@@ -378,12 +387,12 @@ __device__ __forceinline__ LanePixel lane_pixel(int32_t tx, int32_t ty, int32_t 
     l.sy0 = ty * kTile + (quarter >> 1) * 8 + (wv >> 1) * 4;
     l.px = l.sx0 + (lane & 3);
     l.py = l.sy0 + ((lane >> 2) & 3);
-    l.on = true;  // every row carries the group's 16 pixels (rows = consecutive entries)
+    l.on = rows_share || lane < 16;  // rows = consecutive entries of the group's stream, or lanes 0-15 only
   }
   return l;
 }
-inline int32_t split_tiles(const uint32_t* order, int32_t tiles_total) {
-  return order ? (tiles_total < kSplitTiles ? tiles_total : kSplitTiles) : 0;
+inline int32_t split_tiles(const uint32_t* order, int32_t tiles_total, SplitCfg cfg) {
+  return order ? (tiles_total < cfg.tiles ? tiles_total : cfg.tiles) : 0;
 }
 
 constexpr int kBatch = kBlock;  // list entries staged per workgroup round
@@ -422,7 +431,7 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(const float* __restrict__
   // workgroup with LDS atomics, flushed with one global atomic per entry
   __shared__ float s_acc_w[ACC ? kBatch : 1];
   __shared__ uint32_t s_acc_m[ACC ? kBatch : 1];
-  const WorkItem wi = work_item(order, ranges, nsplit);
+  const WorkItem wi = work_item(order, ranges, nsplit, kFwdSplit.len);
   if (wi.skip) return;
   const int32_t tile = wi.tile;
   const int32_t v = view_of_tile(vs, tile);
@@ -436,8 +445,8 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(const float* __restrict__
   // max over groups instead of the union of the four streams.
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int grp = lane >> 4;
-  const bool rp = wi.quarter >= 0;  // split work item: rows are consecutive entries
-  const LanePixel lp = lane_pixel(tx, ty, wi.quarter, wv, lane);
+  const bool rp = kFwdRowParallel && wi.quarter >= 0;  // split work item: rows are consecutive entries
+  const LanePixel lp = lane_pixel(tx, ty, wi.quarter, wv, lane, rp);
   const int32_t sx0 = lp.sx0, sy0 = lp.sy0, px = lp.px, py = lp.py;
   const bool inside = lp.on && px < cam.width && py < cam.height;
   const float pxc = (float)px + 0.5f, pyc = (float)py + 0.5f;
@@ -517,9 +526,18 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(const float* __restrict__
         const RowScan tf = rows_scan_mul(om, grp);
         const bool stop = pass && T * tf.incl < op.t_min;
         const uint64_t sb = __ballot(stop);
-        const uint64_t col = 0x0001000100010001ull << (lane & 15);
-        const bool earlier = (sb & col & ((1ull << (16 * grp)) - 1ull)) != 0;
-        const bool inc = pass && !stop && !earlier;
+        bool inc = pass;
+        float Tn = T * tf.total;
+        if (sb != 0ull) {
+          // rare: some pixel stops at one of these entries; later rows of its
+          // column are dropped and its transmittance is the one in front of
+          // the stopping entry
+          const uint64_t col = 0x0001000100010001ull << (lane & 15);
+          const bool earlier = (sb & col & ((1ull << (16 * grp)) - 1ull)) != 0;
+          inc = pass && !stop && !earlier;
+          Tn = T * rows_scan_mul(inc ? om : 1.f, grp).total;
+          done = done || (sb & col) != 0;
+        }
         const float wgt = inc ? al * (T * tf.excl) : 0.f;
         c0 += wgt * q2.x;
         c1 += wgt * q2.y;
@@ -536,13 +554,14 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(const float* __restrict__
           atomicAdd(&s_acc_w[kr], wgt);
           atomicMax(&s_acc_m[kr], __float_as_uint(wgt));
         }
-        T = T * rows_scan_mul(inc ? om : 1.f, grp).total;
-        done = done || (sb & col) != 0;
-        const uint64_t dm = __ballot(done);
-        if ((dm & 0xffffull) == 0xffffull) rmine = 0;
-        if (dm == ~0ull) {
-          wave_done = true;
-          break;
+        T = Tn;
+        if (sb != 0ull) {
+          const uint64_t dm = __ballot(done);
+          if ((dm & 0xffffull) == 0xffffull) rmine = 0;
+          if (dm == ~0ull) {
+            wave_done = true;
+            break;
+          }
         }
       }
       // kFwdUnroll entries of the group's stream per iteration: their records
@@ -760,7 +779,7 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(const float* __restrict__
   __shared__ int2 s_box[kBatch];
   __shared__ uint32_t s_idx[kBatch];  // record index | active << 31
   __shared__ uint32_t s_jmax[kBlock / kWave];
-  const WorkItem wi = work_item(order, ranges, nsplit);
+  const WorkItem wi = work_item(order, ranges, nsplit, kBwdSplit.len);
   if (wi.skip) return;
   const int32_t tile = wi.tile;
   const int32_t v = view_of_tile(vs, tile);
@@ -770,7 +789,7 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(const float* __restrict__
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int grp = lane >> 4;
   const bool rp = wi.quarter >= 0;  // split work item: rows are consecutive entries
-  const LanePixel lp = lane_pixel(tx, ty, wi.quarter, wv, lane);
+  const LanePixel lp = lane_pixel(tx, ty, wi.quarter, wv, lane, rp);
   const int32_t sx0 = lp.sx0, sy0 = lp.sy0, px = lp.px, py = lp.py;
   const bool inside = lp.on && px < cam.width && py < cam.height;
   const float pxc = (float)px + 0.5f, pyc = (float)py + 0.5f;
@@ -1000,13 +1019,13 @@ static void launch_fwd(int depth_mode, dim3 grid, hipStream_t s, const gs_projec
   const float* q = scene ? scene->quats : nullptr;
   if (depth_mode == GS_DEPTH_CENTER)
     hipLaunchKernelGGL((k_render_fwd<ACC, OUT, GS_DEPTH_CENTER>), grid, dim3(kBlock), 0, s, proj->rec, proj->bin, vals,
-                       ranges, order, split_tiles(order, vs.tiles_total), n, m, sc, q, o, op, per_view, vs);
+                       ranges, order, split_tiles(order, vs.tiles_total, kFwdSplit), n, m, sc, q, o, op, per_view, vs);
   else if (depth_mode == GS_DEPTH_BLEND)
     hipLaunchKernelGGL((k_render_fwd<ACC, OUT, GS_DEPTH_BLEND>), grid, dim3(kBlock), 0, s, proj->rec, proj->bin, vals,
-                       ranges, order, split_tiles(order, vs.tiles_total), n, m, sc, q, o, op, per_view, vs);
+                       ranges, order, split_tiles(order, vs.tiles_total, kFwdSplit), n, m, sc, q, o, op, per_view, vs);
   else
     hipLaunchKernelGGL((k_render_fwd<ACC, OUT, GS_DEPTH_MID>), grid, dim3(kBlock), 0, s, proj->rec, proj->bin, vals,
-                       ranges, order, split_tiles(order, vs.tiles_total), n, m, sc, q, o, op, per_view, vs);
+                       ranges, order, split_tiles(order, vs.tiles_total, kFwdSplit), n, m, sc, q, o, op, per_view, vs);
 }
 
 }  // namespace msplat
@@ -1033,7 +1052,7 @@ int32_t gs_render_forward(const gs_scene_t* scene, const gs_projected_t* proj, c
            accum ? acc->importance : nullptr, accum ? acc->wmax : nullptr, accum ? acc->area : nullptr};
   const KOpts op = make_kopts(opts);
   const int32_t per_view = (opts->flags & GS_ACCUM_PER_VIEW) ? 1 : 0;
-  dim3 grid(vs.tiles_total + 3 * split_tiles(tile_order, vs.tiles_total));
+  dim3 grid(vs.tiles_total + 3 * split_tiles(tile_order, vs.tiles_total, kFwdSplit));
   hipStream_t s = (hipStream_t)stream;
   if (accum)
     launch_fwd<true, true>(opts->depth_mode, grid, s, proj, vals, ranges, tile_order, scene->n, scene, o, op, per_view,
@@ -1062,9 +1081,9 @@ int32_t gs_accumulate_importance(const gs_projected_t* proj, const uint32_t* val
   const KOpts op = make_kopts(opts);
   const int32_t per_view = (opts->flags & GS_ACCUM_PER_VIEW) ? 1 : 0;
   hipLaunchKernelGGL((k_render_fwd<true, false, GS_DEPTH_CENTER>),
-                     dim3(vs.tiles_total + 3 * split_tiles(tile_order, vs.tiles_total)), dim3(kBlock), 0,
+                     dim3(vs.tiles_total + 3 * split_tiles(tile_order, vs.tiles_total, kFwdSplit)), dim3(kBlock), 0,
                      (hipStream_t)stream, proj->rec, proj->bin, vals, ranges, tile_order,
-                     split_tiles(tile_order, vs.tiles_total), n, nullptr, nullptr, nullptr,
+                     split_tiles(tile_order, vs.tiles_total, kFwdSplit), n, nullptr, nullptr, nullptr,
                      o, op, per_view, vs);
   MS_CHECK_LAUNCH("accumulate_importance");
   return GS_OK;
@@ -1084,14 +1103,14 @@ int32_t gs_render_backward_pixels(const gs_projected_t* proj, const uint32_t* va
   if (!proj->rec || !proj->bin || !grad2d) { set_error("buffer NULL"); return GS_ERR_NULL; }
   const KOpts op = make_kopts(opts);
   hipStream_t s = (hipStream_t)stream;
-  const dim3 grid(vs.tiles_total + 3 * split_tiles(tile_order, vs.tiles_total));
+  const dim3 grid(vs.tiles_total + 3 * split_tiles(tile_order, vs.tiles_total, kBwdSplit));
   if (active)
     hipLaunchKernelGGL(k_render_bwd<true>, grid, dim3(kBlock), 0, s, proj->rec, proj->bin, vals,
-                       ranges, tile_order, split_tiles(tile_order, vs.tiles_total), n, t_final, last, dl_dcolor,
+                       ranges, tile_order, split_tiles(tile_order, vs.tiles_total, kBwdSplit), n, t_final, last, dl_dcolor,
                        active, grad2d, op, vs);
   else
     hipLaunchKernelGGL(k_render_bwd<false>, grid, dim3(kBlock), 0, s, proj->rec, proj->bin, vals,
-                       ranges, tile_order, split_tiles(tile_order, vs.tiles_total), n, t_final, last, dl_dcolor,
+                       ranges, tile_order, split_tiles(tile_order, vs.tiles_total, kBwdSplit), n, t_final, last, dl_dcolor,
                        active, grad2d, op, vs);
   MS_CHECK_LAUNCH("render_backward_pixels");
   return GS_OK;
