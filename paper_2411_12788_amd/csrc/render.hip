@@ -169,24 +169,6 @@ __device__ __forceinline__ RowScan rows_scan_add(float x, int row) {
   r.total = lo + hi;
   return r;
 }
-__device__ __forceinline__ float rows_sum(float x) {
-  const RowsTwo p = rows_pair(__float_as_uint(x));
-  const float pair = __uint_as_float(p.a) + __uint_as_float(p.b);
-  const RowsTwo h = rows_halves(__float_as_uint(pair));
-  return __uint_as_float(h.a) + __uint_as_float(h.b);
-}
-__device__ __forceinline__ uint32_t rows_sum_u32(uint32_t x) {
-  const RowsTwo p = rows_pair(x);
-  const RowsTwo h = rows_halves(p.a + p.b);
-  return h.a + h.b;
-}
-__device__ __forceinline__ uint32_t rows_max_u32(uint32_t x) {
-  const RowsTwo p = rows_pair(x);
-  const uint32_t m = p.a > p.b ? p.a : p.b;
-  const RowsTwo h = rows_halves(m);
-  return h.a > h.b ? h.a : h.b;
-}
-
 template <int CTRL>
 __device__ __forceinline__ uint32_t dpp_take_u32(uint32_t x) {
   return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, 0xF, 0xF, true);
@@ -327,24 +309,26 @@ __device__ __forceinline__ Rect group_rect(uint32_t bits, int32_t gx0, int32_t g
 }
 
 // Work item of a render workgroup.  With a tile order (longest lists first),
-// each of the first kSplitTiles tiles of the order gets four workgroups; if its
-// list is long they take one 8x8 quarter each, with one 4x4 pixel group per
-// wave, so the tile's sixteen groups walk their streams independently instead
-// of four to a wave in lockstep: these tiles set the kernel's length.  Such a
-// wave's four rows hold the same 16 pixels and take four consecutive entries
-// of the group's stream per step, combined across rows by scans.  For a short
-// list one of the four takes the whole tile and the other three exit; which
-// one rotates with the tile, so that these runners spread over the eight XCDs
-// (workgroup b runs on XCD b mod 8).
-// (tiles of the order that may split, minimum list length to split) per kernel
+// each of the first cfg.tiles tiles of the order gets four workgroups; if its
+// list has at least cfg.len entries they take one 8x8 quarter each, with one
+// 4x4 pixel group per wave, so the tile's sixteen groups walk their streams
+// independently instead of four to a wave in lockstep: these tiles set the
+// kernel's length.  In the backward such a wave's four rows hold the same 16
+// pixels and take four consecutive entries of the group's stream per step,
+// combined across rows by scans; in the forward the group sits in lanes 0-15.
+// For a short list one of the four takes the whole tile and the other three
+// exit; which one rotates with the tile, so that these runners spread over the
+// eight XCDs (workgroup b runs on XCD b mod 8).
+// (tiles of the order that may split, minimum list length to split) per
+// kernel.  The backward's split waves run row-parallel at about the cost per
+// entry of a whole-tile wave, so it splits every sizeable list; the forward's
+// split waves leave 48 lanes idle, so it splits only the very longest.
 struct SplitCfg {
   int32_t tiles;
   uint32_t len;
 };
 constexpr SplitCfg kFwdSplit{256, 2048};
 constexpr SplitCfg kBwdSplit{2048, 256};
-// forward split waves: rows as consecutive entries (true) or one 16-lane group (false)
-constexpr bool kFwdRowParallel = false;
 struct WorkItem {
   int32_t tile;
   int32_t quarter;  // -1: whole tile
@@ -445,8 +429,7 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(const float* __restrict__
   // max over groups instead of the union of the four streams.
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int grp = lane >> 4;
-  const bool rp = kFwdRowParallel && wi.quarter >= 0;  // split work item: rows are consecutive entries
-  const LanePixel lp = lane_pixel(tx, ty, wi.quarter, wv, lane, rp);
+  const LanePixel lp = lane_pixel(tx, ty, wi.quarter, wv, lane, false);
   const int32_t sx0 = lp.sx0, sy0 = lp.sy0, px = lp.px, py = lp.py;
   const bool inside = lp.on && px < cam.width && py < cam.height;
   const float pxc = (float)px + 0.5f, pyc = (float)py + 0.5f;
@@ -457,7 +440,6 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(const float* __restrict__
   float T = 1.f, c0 = 0.f, c1 = 0.f, c2 = 0.f, wbest = 0.f, dblend = 0.f;
   int32_t best = -1;
   uint32_t lastpos = 0, cnt = 0;
-  uint32_t bpos = 0xffffffffu;  // list position of `best` (split work items)
   bool done = !inside;
   // Staging pipeline: while round R is processed, the records of round R + 1
   // and the list indices of round R + 2 are already in flight.
@@ -493,7 +475,7 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(const float* __restrict__
       uint64_t gmask[4];
 #pragma unroll
       for (int g = 0; g < 4; ++g) {
-        const uint32_t bits = (rp && g > 0) ? 0u : (uint32_t)(am >> (16 * g)) & 0xffffu;
+        const uint32_t bits = (uint32_t)(am >> (16 * g)) & 0xffffu;
         bool rel = false;
         if (bits != 0u) {
           const Rect rg = group_rect(bits, sx0 + (g & 1) * 4, sy0 + (g >> 1) * 4);
@@ -502,68 +484,7 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(const float* __restrict__
         }
         gmask[g] = __ballot(rel);
       }
-      uint64_t mine = rp ? gmask[0] : grp == 0 ? gmask[0] : grp == 1 ? gmask[1] : grp == 2 ? gmask[2] : gmask[3];
-      // Split work item: row r takes the r-th of the next four entries of the
-      // group's stream.  The transmittance in front of each is T times the
-      // product of (1 - alpha) over the rows before it; an entry is composited
-      // unless its own or an earlier row's entry reaches the stop.  Each row
-      // keeps partial colour, depth, count and argmax, merged at the end.
-      uint64_t rmine = rp ? uniform_u64(mine) : 0ull;  // the same in every lane: keep it scalar
-      if (rp) mine = 0;
-      while (rmine != 0) {
-        // row r's entry: the lowest set bit of the mask with r lower bits cleared
-        const uint64_t m1 = rmine & (rmine - 1), m2 = m1 & (m1 - 1), m3 = m2 & (m2 - 1);
-        const uint64_t mr = grp < 2 ? (grp == 0 ? rmine : m1) : (grp == 2 ? m2 : m3);
-        rmine = m3 & (m3 - 1);
-        const bool hr = mr != 0;
-        const int kr = c * kWave + (hr ? (int)__builtin_ctzll(mr) : 0);
-        const float4 r0 = s_r0[kr], r1 = s_r1[kr], q2 = s_r2[kr];
-        const float dx = (pxc - r0.x) - r0.z, dy = (pyc - r0.y) - r0.w;
-        const float ee = r1.w - (r1.x * dx * dx + r1.y * dx * dy + r1.z * dy * dy);
-        const float al = fminf(op.alpha_max, __builtin_amdgcn_exp2f(ee));
-        const bool pass = hr && !done && ee >= op.log2_alpha_min;
-        const float om = pass ? 1.f - al : 1.f;
-        const RowScan tf = rows_scan_mul(om, grp);
-        const bool stop = pass && T * tf.incl < op.t_min;
-        const uint64_t sb = __ballot(stop);
-        bool inc = pass;
-        float Tn = T * tf.total;
-        if (sb != 0ull) {
-          // rare: some pixel stops at one of these entries; later rows of its
-          // column are dropped and its transmittance is the one in front of
-          // the stopping entry
-          const uint64_t col = 0x0001000100010001ull << (lane & 15);
-          const bool earlier = (sb & col & ((1ull << (16 * grp)) - 1ull)) != 0;
-          inc = pass && !stop && !earlier;
-          Tn = T * rows_scan_mul(inc ? om : 1.f, grp).total;
-          done = done || (sb & col) != 0;
-        }
-        const float wgt = inc ? al * (T * tf.excl) : 0.f;
-        c0 += wgt * q2.x;
-        c1 += wgt * q2.y;
-        c2 += wgt * q2.z;
-        if (DEPTH == GS_DEPTH_BLEND) dblend += wgt * s_z[kr];
-        const uint32_t pos = base + (uint32_t)kr - start;
-        const bool better = wgt > wbest;  // a row's entries arrive in order: the nearer wins ties
-        wbest = better ? wgt : wbest;
-        best = better ? (int32_t)((int64_t)__float_as_uint(q2.w) - vbase) : best;
-        bpos = better ? pos : bpos;
-        lastpos = inc ? pos + 1 : lastpos;
-        cnt += inc ? 1u : 0u;
-        if (ACC && inc) {
-          atomicAdd(&s_acc_w[kr], wgt);
-          atomicMax(&s_acc_m[kr], __float_as_uint(wgt));
-        }
-        T = Tn;
-        if (sb != 0ull) {
-          const uint64_t dm = __ballot(done);
-          if ((dm & 0xffffull) == 0xffffull) rmine = 0;
-          if (dm == ~0ull) {
-            wave_done = true;
-            break;
-          }
-        }
-      }
+      uint64_t mine = grp == 0 ? gmask[0] : grp == 1 ? gmask[1] : grp == 2 ? gmask[2] : gmask[3];
       // kFwdUnroll entries of the group's stream per iteration: their records
       // are read and their alphas evaluated side by side, then they are
       // composited in order (each sees the previous one's transmittance and
@@ -635,28 +556,6 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(const float* __restrict__
         if (o.wmax) atomicMax(reinterpret_cast<unsigned int*>(o.wmax) + ai, s_acc_m[threadIdx.x]);
       }
     }
-  }
-  if (rp) {
-    // merge the rows' partials (every row of a column holds the same pixel)
-    c0 = rows_sum(c0);
-    c1 = rows_sum(c1);
-    c2 = rows_sum(c2);
-    if (DEPTH == GS_DEPTH_BLEND) dblend = rows_sum(dblend);
-    cnt = rows_sum_u32(cnt);
-    lastpos = rows_max_u32(lastpos);
-    // argmax: the larger weight, on equal weights the earlier list position
-#pragma unroll
-    for (int step = 0; step < 2; ++step) {
-      const RowsTwo w = step == 0 ? rows_pair(__float_as_uint(wbest)) : rows_halves(__float_as_uint(wbest));
-      const RowsTwo b = step == 0 ? rows_pair((uint32_t)best) : rows_halves((uint32_t)best);
-      const RowsTwo q = step == 0 ? rows_pair(bpos) : rows_halves(bpos);
-      const float wa = __uint_as_float(w.a), wb = __uint_as_float(w.b);
-      const bool take_b = wb > wa || (wb == wa && q.b < q.a);
-      wbest = take_b ? wb : wa;
-      best = (int32_t)(take_b ? b.b : b.a);
-      bpos = take_b ? q.b : q.a;
-    }
-    if (grp != 0) return;  // row 0 writes the pixel
   }
   if (!inside) return;
   if (ACC && o.area && best >= 0) atomicAdd(o.area + (per_view ? vbase + best : (int64_t)best), 1u);
