@@ -34,9 +34,15 @@ import gs_inputs  # noqa: E402
 PEAK_HBM_GBS = 8000.0
 PEAK_FP32_TFLOPS = 157.3
 # algorithmic work per unit (measurement section)
-FLOPS_FWD_PER_PAIR = 26.0          # alpha, transmittance, colour, argmax per included (pixel, Gaussian)
-FLOPS_BWD_RECOMPUTE_PER_PAIR = 20.0  # alpha recompute, transmittance restore, suffix colour
-FLOPS_BWD_GRAD_PER_PAIR = 35.0       # the nine partial derivatives of an active pair
+# Render work is counted in pair-evaluations of the tile algorithm (a pixel
+# evaluates the entries of its tile's list in depth order until it stops; the
+# backward revisits them up to the pixel's last contributor): ~25 VALU
+# lane-ops + 1 exp2 each forward, ~3x that backward.  The kernels skip most of
+# these evaluations with exact ellipse culling; they still count as the work
+# the algorithm defines.
+FLOPS_FWD_PER_EVAL = 26.0
+FLOPS_BWD_PER_EVAL = 75.0
+STOP_T = 0.01  # a pixel with final transmittance >= 1e-4 / (1 - 0.99) never stopped
 PROJECT_BYTES_PER_RECORD = 59 * 4 + 64 + 16     # params read, record + bin written
 PROJECT_BWD_BYTES_PER_ACTIVE = 59 * 4 + 59 * 4 + 36 + 16  # params read, grads written, 2D grad + bin read
 PROJECT_BWD_BYTES_PER_INACTIVE = 59 * 4 + 1     # zero rows written, mask read
@@ -140,11 +146,33 @@ class Step:
         mark("project_bwd", 1)
         self.stats = st
         self.proj = proj
+        self.binned = binned
 
     def collect(self):
         torch.cuda.synchronize()
         for k in self.names:
             self.times[k].append(self.ev[k][0].elapsed_time(self.ev[k][1]))
+
+
+def pair_evaluations(step):
+    """(forward, backward) pair-evaluations of the tile algorithm for the last
+    step of a one-view workload: per pixel the length of its tile's list, or
+    for a pixel that may have stopped (T_final < STOP_T) its last contributor
+    (a lower bound of where it stopped); backward: the last contributor."""
+    assert len(step.cams) == 1
+    cam = step.cams[0]
+    W, H = cam.width, cam.height
+    tx = (W + 15) // 16
+    rng = step.binned.ranges.view(-1, 2).long()
+    L = rng[:, 1] - rng[:, 0]
+    py = torch.arange(H, device="cuda").view(H, 1) // 16
+    px = torch.arange(W, device="cuda").view(1, W) // 16
+    Lp = L[(py * tx + px).reshape(-1)]
+    P = W * H
+    last = step.frame.last[:P].long()
+    tf = step.frame.t_final[:P]
+    fwd = torch.where(tf >= STOP_T, Lp, last).sum().item()
+    return float(fwd), float(last.sum().item())
 
 
 def criteria_bench(step, reps: int = 10):
@@ -446,10 +474,10 @@ def main():
     act_frac = float(step.active.float().mean().item()) if step.active is not None else 1.0
     n_vis = int(st.n_visible)
     n_act = int(step.active.sum().item()) if step.active is not None else n
+    ev_fwd, ev_bwd = pair_evaluations(step)
     work = {
-        "render_fwd": ("alu", nc * FLOPS_FWD_PER_PAIR / 1e12, "TFLOP/s", PEAK_FP32_TFLOPS),
-        "render_bwd": ("alu", nc * (FLOPS_BWD_RECOMPUTE_PER_PAIR + act_frac * FLOPS_BWD_GRAD_PER_PAIR) / 1e12,
-                       "TFLOP/s", PEAK_FP32_TFLOPS),
+        "render_fwd": ("alu", ev_fwd * FLOPS_FWD_PER_EVAL / 1e12, "TFLOP/s", PEAK_FP32_TFLOPS),
+        "render_bwd": ("alu", ev_bwd * FLOPS_BWD_PER_EVAL / 1e12, "TFLOP/s", PEAK_FP32_TFLOPS),
         "project": ("hbm", n * PROJECT_BYTES_PER_RECORD / 1e9, "GB/s", PEAK_HBM_GBS),
         "project_bwd": ("hbm", (n_act * PROJECT_BWD_BYTES_PER_ACTIVE + (n - n_act) * PROJECT_BWD_BYTES_PER_INACTIVE)
                         / 1e9, "GB/s", PEAK_HBM_GBS),
@@ -477,7 +505,8 @@ def main():
         "config": {"workload": wl.name, "gaussians": n, "views": len(wl.cameras),
                    "resolution": f"{wl.cameras[0].width}x{wl.cameras[0].height}", "active_fraction": act_frac,
                    "n_visible": n_vis, "n_isect": int(st.n_isect), "key_bits": int(st.key_bits),
-                   "included_pairs": int(nc)},
+                   "included_pairs": int(nc), "pair_evaluations_fwd": int(ev_fwd),
+                   "pair_evaluations_bwd": int(ev_bwd)},
         "roofline": {"bound": bound, "kernel": dom, "achieved": round(achieved, 3), "peak": peak, "unit": unit,
                      "frac": round(achieved / peak, 5), "traffic": traffic_from_profiles(dom)},
         "stages": stages,
