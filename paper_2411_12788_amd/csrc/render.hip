@@ -316,9 +316,8 @@ __device__ __forceinline__ Rect group_rect(uint32_t bits, int32_t gx0, int32_t g
 // kernel's length.  In the backward such a wave's four rows hold the same 16
 // pixels and take four consecutive entries of the group's stream per step,
 // combined across rows by scans; in the forward the group sits in lanes 0-15.
-// For a short list one of the four takes the whole tile and the other three
-// exit; which one rotates with the tile, so that these runners spread over the
-// eight XCDs (workgroup b runs on XCD b mod 8).
+// For a short list the first of the four takes the whole tile and the other
+// three exit.
 // (tiles of the order that may split, minimum list length to split) per
 // kernel.  The backward's split waves run row-parallel at about the cost per
 // entry of a whole-tile wave, so it splits every sizeable list; the forward's
@@ -340,10 +339,15 @@ __device__ __forceinline__ WorkItem work_item(const uint32_t* order, const uint3
   if (order == nullptr) return w;
   const int32_t b = (int32_t)blockIdx.x;
   if (b < 4 * nsplit) {
-    w.tile = (int32_t)uload(order + (b >> 2));
+    // blocks b, b + 8, b + 16, b + 24 of each run of 32 are the four quarters of
+    // one tile: they run on the same XCD (b mod 8) and share its L2, so the
+    // tile's records are fetched from HBM once instead of four times
+    const int32_t t = ((b >> 5) << 3) + (b & 7);
+    w.tile = (int32_t)uload(order + t);
     const uint32_t len = uload(ranges + 2 * w.tile + 1) - uload(ranges + 2 * w.tile);
-    if (len >= split_len) w.quarter = b & 3;
-    else w.skip = (b & 3) != ((b >> 3) & 3);  // the runner rotates over the XCDs (block b runs on XCD b % 8)
+    const int32_t q = (b >> 3) & 3;
+    if (len >= split_len) w.quarter = q;
+    else w.skip = q != 0;
   } else {
     w.tile = (int32_t)uload(order + (b - 3 * nsplit));
   }
@@ -375,8 +379,10 @@ __device__ __forceinline__ LanePixel lane_pixel(int32_t tx, int32_t ty, int32_t 
   }
   return l;
 }
+// Tiles of the order that get four workgroups: a multiple of 8 (see work_item).
 inline int32_t split_tiles(const uint32_t* order, int32_t tiles_total, SplitCfg cfg) {
-  return order ? (tiles_total < cfg.tiles ? tiles_total : cfg.tiles) : 0;
+  const int32_t t = tiles_total < cfg.tiles ? tiles_total : cfg.tiles;
+  return order ? t & ~7 : 0;
 }
 
 constexpr int kBatch = kBlock;  // list entries staged per workgroup round
