@@ -1,6 +1,6 @@
 // Stable LSD radix sort of (u64 key, u32 value) pairs on the low `bits` key
 // bits: one histogram pass over the keys for all digits, then one kernel per
-// 8-bit digit ("onesweep").  Each workgroup ranks a 4096-key tile in
+// 8-bit digit ("onesweep").  Each workgroup ranks an 8192-key tile in
 // registers/LDS, publishes its per-digit counts, and obtains the count of
 // equal digits in all earlier tiles by a decoupled look-back over the
 // per-tile status words; tiles are handed out by an atomic counter, so every
@@ -8,7 +8,11 @@
 // started and will publish without waiting on anyone.  Keys are then staged in
 // LDS in local sorted order and written out in runs, so each digit's run is a
 // contiguous, coalesced store.  Per pass this reads 12 B and writes 12 B per
-// pair; the histograms of all passes cost one extra 8 B read per pair in total.
+// pair (8 B each when the value is packed under the key); the histograms of
+// all passes cost one extra 8 B read per pair in total.  The look-back is what
+// bounds a pass at a few million keys (the front of inclusive prefixes moves
+// one window of predecessors per round trip), so the tiles are large: 8192
+// keys instead of 4096 took a pass from 44 to 38 us at 3.3M keys.
 //
 // Every wait is bounded: a look-back that has not resolved after kSpinLimit
 // polls raises an error flag instead of spinning on, and every global store is
@@ -18,8 +22,15 @@
 
 namespace msplat {
 
-constexpr int kOsItems = 16;
-constexpr int kOsTile = kBlock * kOsItems;  // 4096 keys per tile
+// keys per thread and per tile of a pass: 32 (8192 keys) for keys-only passes;
+// 16 when values travel too, which keeps that kernel within 256 VGPRs
+template <bool VALS>
+struct OsTile {
+  static constexpr int items = VALS ? 16 : 32;
+  static constexpr int keys = kBlock * items;
+};
+constexpr int kOsMinTile = OsTile<true>::keys;  // sizes the per-tile status words
+constexpr int kHistItems = 16;                   // keys per thread of the histogram kernel
 constexpr int kOsRadix = 256;
 constexpr int kOsWaves = kBlock / kWave;
 constexpr int kMaxPasses = 8;
@@ -37,14 +48,14 @@ __device__ __forceinline__ uint64_t os_match(uint32_t d) {
   return m;
 }
 
-// Counts of every digit of every pass; 4 tiles per workgroup.
+// Counts of every digit of every pass; kBlock * kHistItems keys per workgroup.
 __global__ __launch_bounds__(kBlock) void k_os_hist(const uint64_t* __restrict__ keys, int64_t n, int32_t passes,
                                                     int32_t lo_bit, uint32_t* __restrict__ ghist) {
   __shared__ uint32_t h[kMaxPasses][kOsRadix];
   for (int p = 0; p < passes; ++p) h[p][threadIdx.x] = 0;
   __syncthreads();
-  const int64_t base = (int64_t)blockIdx.x * (4 * kOsTile);
-  for (int k = 0; k < 4 * kOsItems; ++k) {
+  const int64_t base = (int64_t)blockIdx.x * (kBlock * kHistItems);
+  for (int k = 0; k < kHistItems; ++k) {
     const int64_t e = base + (int64_t)k * kBlock + threadIdx.x;
     if (e < n) {
       const uint64_t key = keys[e];
@@ -90,22 +101,22 @@ __global__ __launch_bounds__(kBlock) void k_os_pass(const uint64_t* __restrict__
   __shared__ uint32_t s_glob[kOsRadix];
   __shared__ uint32_t s_loff[kOsRadix + 1];
   __shared__ uint32_t s_wsum[kOsWaves];
-  __shared__ uint64_t s_key[kOsTile];
-  __shared__ uint32_t s_val[VALS ? kOsTile : 1];
+  __shared__ uint64_t s_key[OsTile<VALS>::keys];
+  __shared__ uint32_t s_val[VALS ? OsTile<VALS>::keys : 1];
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
   if (threadIdx.x == 0) s_tile = atomicAdd(counter, 1u);
 #pragma unroll
   for (int k = 0; k < kOsWaves; ++k) cnt[k][threadIdx.x] = 0;
   __syncthreads();
   const uint32_t t = s_tile;
-  const int64_t tile_base = (int64_t)t * kOsTile;
-  const int64_t base = tile_base + (int64_t)w * (kOsItems * kWave);
+  const int64_t tile_base = (int64_t)t * OsTile<VALS>::keys;
+  const int64_t base = tile_base + (int64_t)w * (OsTile<VALS>::items * kWave);
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
-  uint64_t key[kOsItems];
-  uint32_t val[kOsItems];
-  uint32_t rank[kOsItems];
+  uint64_t key[OsTile<VALS>::items];
+  uint32_t val[OsTile<VALS>::items];
+  uint32_t rank[OsTile<VALS>::items];
 #pragma unroll
-  for (int k = 0; k < kOsItems; ++k) {
+  for (int k = 0; k < OsTile<VALS>::items; ++k) {
     const int64_t e = base + (int64_t)k * kWave + lane;
     const bool in = e < n;
     key[k] = in ? kin[e] : 0ull;
@@ -193,12 +204,12 @@ __global__ __launch_bounds__(kBlock) void k_os_pass(const uint64_t* __restrict__
   }
   __syncthreads();
 #pragma unroll
-  for (int k = 0; k < kOsItems; ++k) {
+  for (int k = 0; k < OsTile<VALS>::items; ++k) {
     const int64_t e = base + (int64_t)k * kWave + lane;
     if (e < n) {
       const uint32_t dd = (uint32_t)(key[k] >> shift) & 0xffu;
       const uint32_t lp = s_loff[dd] + cnt[w][dd] + rank[k];
-      if (lp < (uint32_t)kOsTile) {
+      if (lp < (uint32_t)OsTile<VALS>::keys) {
         s_key[lp] = key[k];
         if (VALS) s_val[lp] = val[k];
       }
@@ -219,7 +230,7 @@ __global__ __launch_bounds__(kBlock) void k_os_pass(const uint64_t* __restrict__
 
 size_t onesweep_ws_size(int64_t n, int32_t passes) {
   const int64_t nn = n > 0 ? n : 1;
-  const int64_t nb = (nn + kOsTile - 1) / kOsTile;
+  const int64_t nb = (nn + kOsMinTile - 1) / kOsMinTile;
   auto a = [](size_t x) { return (x + 255) & ~size_t(255); };
   return a(nn * 8) + a(nn * 4) + a(kMaxPasses * kOsRadix * 4) + a((size_t)kMaxPasses * nb * kOsRadix * 4) +
          a(kMaxPasses * 4) + a(4);
@@ -240,7 +251,8 @@ int32_t onesweep_sort(uint64_t* k0, uint32_t* v0, int64_t n, int32_t lo_bit, int
   }
   const bool vals = v0 != nullptr;
   const int64_t nn = n > 0 ? n : 1;
-  const int64_t nb = (nn + kOsTile - 1) / kOsTile;
+  const int64_t tile = vals ? OsTile<true>::keys : OsTile<false>::keys;
+  const int64_t nb = (nn + tile - 1) / tile;
   auto a = [](size_t x) { return (x + 255) & ~size_t(255); };
   char* p = (char*)ws;
   uint64_t* kalt = (uint64_t*)p; p += a(nn * 8);
@@ -260,7 +272,7 @@ int32_t onesweep_sort(uint64_t* k0, uint32_t* v0, int64_t n, int32_t lo_bit, int
   const int64_t zero_words = (int64_t)((char*)err + 4 - (char*)ghist) / 4;
   int32_t r = launch_fill(ghist, 0u, zero_words, st);
   if (r != GS_OK) return r;
-  const int64_t hb = (nn + 4 * kOsTile - 1) / (4 * kOsTile);
+  const int64_t hb = (nn + kBlock * kHistItems - 1) / (kBlock * kHistItems);
   hipLaunchKernelGGL(k_os_hist, dim3((unsigned)hb), dim3(kBlock), 0, st, k0, n, passes, lo_bit, ghist);
   hipLaunchKernelGGL(k_os_scan, dim3(1), dim3(kBlock), 0, st, ghist, passes);
   MS_CHECK_LAUNCH("sort histogram");
