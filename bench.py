@@ -103,6 +103,7 @@ class Step:
                    for k in self.names}
         self.times = {k: [] for k in self.names}
         self.frame = None
+        self.bin_buffers = R.BinBuffers()
 
     def run(self, record: bool):
         R, ev = self.R, self.ev
@@ -117,20 +118,22 @@ class Step:
         mark("bin_count", 0)
         offsets, st = R.bin_count(proj, self.cams, self.n)
         mark("bin_count", 1)
-        mark("bin_sort", 0)
-        binned = R.bin_sort(proj, self.cams, self.n, offsets, st)
-        mark("bin_sort", 1)
+        # clears that the step needs anyway, queued while the host prepares the
+        # sort launches (the pair count above is read back by the host)
         for t in self.acc.values():
             t.zero_()
+        self.loss.zero_()
+        self.grad2d.zero_()
+        mark("bin_sort", 0)
+        binned = R.bin_sort(proj, self.cams, self.n, offsets, st, buffers=self.bin_buffers)
+        mark("bin_sort", 1)
         mark("render_fwd", 0)
         self.frame = R.render_forward(self.scene, proj, binned, self.cams, self.opts, accum=self.acc,
                                       extras=True, out=self.frame)
         mark("render_fwd", 1)
-        self.loss.zero_()
         mark("loss", 0)
         R.l1_loss_grad(self.frame.color, self.target, self.dldc, self.loss)
         mark("loss", 1)
-        self.grad2d.zero_()
         mark("render_bwd", 0)
         R.render_backward_pixels(proj, binned, self.cams, self.n, self.opts, self.frame, self.dldc, self.active,
                                  self.grad2d)

@@ -158,21 +158,45 @@ def bin_count(proj: Projected, cams, n: int, stream=None):
     return offsets, st
 
 
+class BinBuffers:
+    """Reusable device buffers of bin_sort (grown when a call needs more), so
+    a training loop does not allocate between the pair count and the sort."""
+
+    def __init__(self):
+        self.vals = self.keys = self.ranges = self.order = self.ws = None
+
+    @staticmethod
+    def _fit(t, count, dtype, dev):
+        if t is None or t.numel() < count:
+            return torch.empty(count + count // 8, device=dev, dtype=dtype)
+        return t
+
+    def get(self, ni, tiles, want_keys, dev):
+        self.vals = self._fit(self.vals, max(ni, 1), torch.int32, dev)
+        if want_keys:
+            self.keys = self._fit(self.keys, max(ni, 1), torch.int64, dev)
+        self.ranges = self._fit(self.ranges, 2 * max(tiles, 1), torch.int32, dev)
+        self.order = self._fit(self.order, max(tiles, 1), torch.int32, dev)
+        self.ws = self._fit(self.ws, max(L.lib().gs_bin_sort_workspace_size(ni), 1), torch.uint8, dev)
+        return self.vals, (self.keys if want_keys else None), self.ranges, self.order, self.ws
+
+
 def bin_sort(proj: Projected, cams, n: int, offsets: torch.Tensor, st: L.BinStats, want_keys: bool = False,
-             stream=None) -> Binned:
+             stream=None, buffers: Optional[BinBuffers] = None) -> Binned:
+    """With `buffers` the pair lists live in (and are overwritten on the next
+    call with) those reusable buffers."""
     V = len(cams)
     dev = proj.rec.device
     ni = int(st.n_isect)
-    vals = torch.empty(max(ni, 1), device=dev, dtype=torch.int32)
-    keys = torch.empty(max(ni, 1), device=dev, dtype=torch.int64) if want_keys else None
-    ranges = torch.empty((max(st.tiles_total, 1), 2), device=dev, dtype=torch.int32)
-    order = torch.empty(max(st.tiles_total, 1), device=dev, dtype=torch.int32)
-    ws = torch.empty(max(L.lib().gs_bin_sort_workspace_size(ni), 1), device=dev, dtype=torch.uint8)
+    tiles = int(st.tiles_total)
+    if buffers is None:
+        buffers = BinBuffers()
+    vals, keys, ranges, order, ws = buffers.get(ni, tiles, want_keys, dev)
     L.check(L.lib().gs_bin_sort(ctypes.byref(proj.c()), cameras(cams), V, n, _ptr(offsets), ctypes.byref(st),
                                 _ptr(keys), _ptr(vals), _ptr(ranges), _ptr(order), _ptr(ws), ws.numel(),
                                 _stream(stream)), "gs_bin_sort")
-    return Binned(vals[:ni], ranges[: st.tiles_total], None if keys is None else keys[:ni], st, offsets,
-                  order[: st.tiles_total])
+    return Binned(vals[:ni], ranges[: 2 * tiles].view(tiles, 2), None if keys is None else keys[:ni], st, offsets,
+                  order[:tiles])
 
 
 def bin(proj: Projected, cams, n: int, want_keys: bool = False, stream=None) -> Binned:
