@@ -278,6 +278,19 @@ def heavy_tiles(seed: int = 0, n: int = 40_000, width: int = 64, height: int = 4
     return Workload("heavy_tiles_40k_64x48", sc, [cam])
 
 
+def elongated_cube(seed: int = 0, n: int = 3000, width: int = 160, height: int = 128,
+                   stretch: float = 12.0) -> Workload:
+    """Cube scene whose Gaussians are needles (one axis `stretch` times the
+    others, random orientation): their screen ellipses are long and tilted,
+    so many tiles of their bounding boxes lie outside the alpha >= 1/255
+    region (the case tile culling at emission addresses)."""
+    sc = uniform_cube_scene(n, seed, log_scale_mu=-3.8)
+    sc.scales = sc.scales.copy()
+    sc.scales[0] *= np.float32(stretch)
+    cam = look_at((0.0, 0.0, 4.0), (0.0, 0.0, 0.0), width, height)
+    return Workload("elongated_cube_3k", sc, [cam])
+
+
 def training_view(seed: int = 1, n: int = 500_000) -> Workload:
     """500k surface-sampled Gaussians, one 1245x825 view from a radius-6 sphere."""
     sc = surface_scene(n, seed, centre_half=2.0)

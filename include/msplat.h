@@ -119,7 +119,20 @@ typedef struct {
 typedef struct {
   float* rec;
   int32_t* bin;
+  /* Tile culling at emission (opt-in; 0 = off).  When < 0 it is
+   * log2(alpha_cull): gs_project counts, and gs_emit_keys / gs_bin_sort emit,
+   * only the tiles of a record's box where exp2(lo - A dx^2 - B dx dy - C dy^2)
+   * can reach alpha_cull at a pixel centre of the tile's part of the box (a
+   * conservative test: the continuous minimum of the quadratic over that
+   * rectangle, with a margin).  Records whose box spans more than
+   * GS_TILE_CULL_MAX_TILES tiles keep every tile.  With alpha_cull <= the
+   * alpha_min the compositing kernels use, a dropped pair could never have
+   * been composited (Sec. 3.1's tile-based rasterizer; the paper's baseline
+   * cites tile-based culling of this kind), so every output is unchanged.
+   * Set it before gs_project and keep it for the binning calls. */
+  float tile_cull_log2_alpha;
 } gs_projected_t;
+enum { GS_TILE_CULL_MAX_TILES = 64 };
 
 /* Statistics returned by gs_bin_count [host]. */
 typedef struct {

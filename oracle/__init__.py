@@ -31,6 +31,9 @@ other than itself live in ``tests/test_oracle_*.py``:
                     Sec. 3.2 / Sec. 3.3 (3DGS density control; blur split
                     children)                               pinned: closed-form rotations,
                     covariance of the children vs scipy's rotation, boundary cases
+  tile_alpha_max    Eq. (1) alpha over a tile's pixel centres (tile culling checks)
+                                                            pinned: isotropic closed form,
+                    centre inside the tile
 """
 from __future__ import annotations
 
@@ -420,6 +423,23 @@ def grad_stats(tiles, grad2d, widths, heights):
     cnt = np.zeros(max(n, 1), dtype=np.int64)
     lib().orc_grad_stats(ctypes.c_int32(V), ctypes.c_int64(n), _p(t), _p(g), _p(w), _p(h), _p(ns), _p(cnt))
     return ns[:n], cnt[:n]
+
+
+def tile_alpha_max(proj_row: np.ndarray, tx: int, ty: int, tile: int = 16) -> float:
+    """Largest alpha = opacity * exp(-d^T conic d / 2) (Eq. (1)'s per-Gaussian
+    alpha before the clamp) of one projected record over the pixel centres of
+    tile (tx, ty) that lie in the record's pixel box; 0 if there are none.
+    Brute force over the at most tile x tile pixels."""
+    P = np.asarray(proj_row, dtype=np.float64)
+    x0, x1 = max(tx * tile, int(P[F["XLO"]])), min(tx * tile + tile - 1, int(P[F["XHI"]]))
+    y0, y1 = max(ty * tile, int(P[F["YLO"]])), min(ty * tile + tile - 1, int(P[F["YHI"]]))
+    if x0 > x1 or y0 > y1:
+        return 0.0
+    xs = np.arange(x0, x1 + 1) + 0.5 - P[F["U"]]
+    ys = np.arange(y0, y1 + 1) + 0.5 - P[F["V"]]
+    dx, dy = np.meshgrid(xs, ys)
+    q = P[F["CA"]] * dx * dx + 2.0 * P[F["CB"]] * dx * dy + P[F["CC"]] * dy * dy
+    return float(P[F["OPAC"]] * np.exp(-0.5 * q.min()))
 
 
 SPLIT_FACTOR = 1.6  # 3DGS: children take the parent's scales divided by 1.6

@@ -44,7 +44,7 @@ class Opts(ctypes.Structure):
 
 
 class Projected(ctypes.Structure):
-    _fields_ = [("rec", c_p), ("bin", c_p)]
+    _fields_ = [("rec", c_p), ("bin", c_p), ("tile_cull_log2_alpha", ctypes.c_float)]
 
 
 class BinStats(ctypes.Structure):

@@ -198,7 +198,8 @@ __global__ __launch_bounds__(kBlock) void k_count_down(const int4* __restrict__ 
 // With ibits > 0 the record index is packed below the key (key << ibits |
 // record) and no value array is written: the sort then moves 8 instead of 12
 // bytes per pair, and equal keys keep record order as before.
-__global__ __launch_bounds__(kBlock) void k_emit(const int4* __restrict__ bin, const uint32_t* __restrict__ offsets,
+__global__ __launch_bounds__(kBlock) void k_emit(const int4* __restrict__ bin, const float* __restrict__ rec,
+                                                 float tile_cull, const uint32_t* __restrict__ offsets,
                                                  int64_t n, int64_t nrec, int32_t shift, uint32_t zmin, int32_t ibits,
                                                  uint64_t* __restrict__ keys, uint32_t* __restrict__ vals,
                                                  ViewSet vs) {
@@ -207,13 +208,25 @@ __global__ __launch_bounds__(kBlock) void k_emit(const int4* __restrict__ bin, c
   const int4 b = bin[r];
   if (b.w <= 0) return;
   const int32_t v = (int32_t)(r / n);
-  const int32_t tx0 = (b.x & 0xffff) >> 4, tx1 = ((uint32_t)b.x >> 16) >> 4;
-  const int32_t ty0 = (b.y & 0xffff) >> 4, ty1 = ((uint32_t)b.y >> 16) >> 4;
+  const int32_t x0 = b.x & 0xffff, x1 = (int32_t)((uint32_t)b.x >> 16);
+  const int32_t y0 = b.y & 0xffff, y1 = (int32_t)((uint32_t)b.y >> 16);
+  const int32_t tx0 = x0 >> 4, tx1 = x1 >> 4, ty0 = y0 >> 4, ty1 = y1 >> 4;
   const uint64_t low = (uint64_t)((uint32_t)b.z - zmin);
   const int32_t tbase = vs.v[v].tile_base, tw = vs.v[v].tiles_x;
+  // tile culling: the projection counted the kept tiles with the same test
+  const bool test = b.w < (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
+  float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0;
+  if (test) {
+    const float4* R4 = reinterpret_cast<const float4*>(rec + r * kRecFloats);
+    r0 = R4[0];
+    r1 = R4[1];
+  }
   uint32_t o = offsets[r];
+  const uint32_t o_end = o + (uint32_t)b.w;
   for (int32_t ty = ty0; ty <= ty1; ++ty)
     for (int32_t tx = tx0; tx <= tx1; ++tx) {
+      if (test && !tile_kept(r0, r1, tx, ty, x0, x1, y0, y1, tile_cull)) continue;
+      if (o >= o_end) return;  // never with a consistent count; keeps writes inside the record's slots
       const uint64_t tile = (uint64_t)(tbase + ty * tw + tx);
       const uint64_t key = (tile << shift) | low;
       if (ibits > 0) {
@@ -426,9 +439,10 @@ int32_t gs_emit_keys(const gs_projected_t* proj, const gs_camera_t* cams, int32_
   const int64_t nrec = (int64_t)V * n;
   if (nrec == 0) return GS_OK;
   if (!proj->bin || !offsets || !keys || !vals) { set_error("buffer NULL"); return GS_ERR_NULL; }
+  if (proj->tile_cull_log2_alpha < 0.f && !proj->rec) { set_error("tile culling needs proj->rec"); return GS_ERR_NULL; }
   hipLaunchKernelGGL(k_emit, dim3(grid_1d(nrec)), dim3(kBlock), 0, (hipStream_t)stream,
-                     reinterpret_cast<const int4*>(proj->bin), offsets, n, nrec, depth_shift, zbits_min, 0, keys,
-                     vals, vs);
+                     reinterpret_cast<const int4*>(proj->bin), proj->rec, proj->tile_cull_log2_alpha, offsets, n, nrec,
+                     depth_shift, zbits_min, 0, keys, vals, vs);
   MS_CHECK_LAUNCH("emit");
   return GS_OK;
 }
@@ -485,6 +499,7 @@ int32_t gs_bin_sort(const gs_projected_t* proj, const gs_camera_t* cams, int32_t
   uint32_t* order_hist = (uint32_t*)((char*)ws + gs_bin_sort_workspace_size(ni) - 256);
   if (ni == 0) return tile_order ? launch_tile_order(ranges, vs.tiles_total, tile_order, order_hist, s) : GS_OK;
   if (!vals || !offsets) { set_error("buffer NULL"); return GS_ERR_NULL; }
+  if (proj->tile_cull_log2_alpha < 0.f && !proj->rec) { set_error("tile culling needs proj->rec"); return GS_ERR_NULL; }
   char* p = (char*)ws;
   uint64_t* k0 = (uint64_t*)p; p += align256(ni * 8);
   uint32_t* v0 = (uint32_t*)p; p += align256(ni * 4);
@@ -495,7 +510,8 @@ int32_t gs_bin_sort(const gs_projected_t* proj, const gs_camera_t* cams, int32_t
   while (ibits < 63 && (int64_t(1) << ibits) < nrec) ++ibits;
   if (stats->key_bits + ibits > 64) ibits = 0;
   hipLaunchKernelGGL(k_emit, dim3(grid_1d(nrec)), dim3(kBlock), 0, s, reinterpret_cast<const int4*>(proj->bin),
-                     offsets, n, nrec, shift, stats->zbits_min, ibits, k0, v0, vs);
+                     proj->rec, proj->tile_cull_log2_alpha, offsets, n, nrec, shift, stats->zbits_min, ibits, k0, v0,
+                     vs);
   MS_CHECK_LAUNCH("emit");
   uint64_t* ks = nullptr;
   if ((st = onesweep_sort(k0, ibits > 0 ? nullptr : v0, ni, ibits, stats->key_bits, p, vals, &ks, s)) != GS_OK)

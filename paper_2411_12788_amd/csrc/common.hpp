@@ -115,6 +115,41 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t x) {
   return x;
 }
 
+// Whether the region where the exponent lo - Q(dx, dy) reaches log2(alpha_min)
+// can meet a pixel centre of [x0, x1] x [y0, y1]: the continuous minimum of
+// the convex quadratic Q over the rectangle of centres (0 if the Gaussian's
+// centre is inside, else the least of the four edge minima, each a clamped
+// 1D vertex) against lo - log2(alpha_min), with a margin far above float
+// rounding.  Conservative, so culling with it never changes a result; it
+// drops the entries whose bounding box meets the rectangle but whose
+// (elongated, tilted) ellipse does not.
+__device__ __forceinline__ bool ellipse_meets(float4 r0, float4 r1, int32_t x0, int32_t x1, int32_t y0, int32_t y1,
+                                              float log2_alpha_min) {
+  const float lx = ((float)x0 + 0.5f - r0.x) - r0.z, hx = ((float)x1 + 0.5f - r0.x) - r0.z;
+  const float ly = ((float)y0 + 0.5f - r0.y) - r0.w, hy = ((float)y1 + 0.5f - r0.y) - r0.w;
+  if (lx <= 0.f && hx >= 0.f && ly <= 0.f && hy >= 0.f) return true;
+  const float A = r1.x, B = r1.y, C = r1.z;
+  const float iA = 0.5f / A, iC = 0.5f / C;
+  auto q = [&](float dx, float dy) { return A * dx * dx + B * dx * dy + C * dy * dy; };
+  const float ya = fminf(fmaxf(-B * lx * iC, ly), hy), yb = fminf(fmaxf(-B * hx * iC, ly), hy);
+  const float xa = fminf(fmaxf(-B * ly * iA, lx), hx), xb = fminf(fmaxf(-B * hy * iA, lx), hx);
+  const float m = fminf(fminf(q(lx, ya), q(hx, yb)), fminf(q(xa, ly), q(xb, hy)));
+  const float budget = r1.w - log2_alpha_min;
+  return m <= budget + 1e-3f * (1.f + fabsf(budget));
+}
+
+
+// Tile culling at emission: whether the record (r0, r1 its first two float4)
+// can reach the culling alpha in the part of tile (tx, ty) inside its pixel
+// box [x0, x1] x [y0, y1].  Shared by the projection (which counts the kept
+// tiles) and the key emission (which emits them), so the two agree exactly.
+__device__ __forceinline__ bool tile_kept(float4 r0, float4 r1, int32_t tx, int32_t ty, int32_t x0, int32_t x1,
+                                          int32_t y0, int32_t y1, float log2_alpha) {
+  const int32_t px0 = tx * kTile > x0 ? tx * kTile : x0, px1 = tx * kTile + kTile - 1 < x1 ? tx * kTile + kTile - 1 : x1;
+  const int32_t py0 = ty * kTile > y0 ? ty * kTile : y0, py1 = ty * kTile + kTile - 1 < y1 ? ty * kTile + kTile - 1 : y1;
+  return ellipse_meets(r0, r1, px0, px1, py0, py1, log2_alpha);
+}
+
 }  // namespace msplat
 
 #define MS_CHECK_LAUNCH(where)                                         \

@@ -136,6 +136,7 @@ struct ProjArgs {
   float* rec;
   int32_t* bin;
   KOpts op;
+  float tile_cull;  // log2 of the tile-culling alpha, or 0 (off)
 };
 
 template <int DEG>
@@ -188,9 +189,19 @@ __global__ __launch_bounds__(kBlock) void k_project(ProjArgs pa, ViewSet vs) {
   if (ok) {
     const double log2e = 1.4426950408889634;
     const float uh = (float)g.u, vh = (float)g.v;
-    out[0] = make_float4(uh, vh, (float)(g.u - (double)uh), (float)(g.v - (double)vh));
-    out[1] = make_float4((float)(0.5 * log2e * g.a), (float)(log2e * g.b), (float)(0.5 * log2e * g.c),
-                         (float)log2(o));
+    const float4 r0 = make_float4(uh, vh, (float)(g.u - (double)uh), (float)(g.v - (double)vh));
+    const float4 r1 = make_float4((float)(0.5 * log2e * g.a), (float)(log2e * g.b), (float)(0.5 * log2e * g.c),
+                                  (float)log2(o));
+    if (pa.tile_cull < 0.f && tiles <= GS_TILE_CULL_MAX_TILES && tiles > 1) {
+      // count only the tiles the record's alpha can reach (emission repeats the test)
+      int32_t kept = 0;
+      for (int32_t ty = ylo >> 4; ty <= (yhi >> 4); ++ty)
+        for (int32_t tx = xlo >> 4; tx <= (xhi >> 4); ++tx)
+          kept += tile_kept(r0, r1, tx, ty, xlo, xhi, ylo, yhi, pa.tile_cull) ? 1 : 0;
+      tiles = kept;
+    }
+    out[0] = r0;
+    out[1] = r1;
     out[2] = make_float4((float)rgb[0], (float)rgb[1], (float)rgb[2], (float)o);
     out[3] = make_float4(zf, (float)g.a, (float)g.b, (float)g.c);
   } else {
@@ -434,6 +445,7 @@ extern "C" int32_t gs_project(const gs_scene_t* scene, const gs_camera_t* cams, 
   pa.rec = out->rec;
   pa.bin = out->bin;
   pa.op = make_kopts(opts);
+  pa.tile_cull = out->tile_cull_log2_alpha < 0.f ? out->tile_cull_log2_alpha : 0.f;
   dim3 grid(grid_1d(scene->n), V);
   hipStream_t s = (hipStream_t)stream;
   switch (scene->sh_degree) {

@@ -35,6 +35,7 @@ class RasterOpts:
     bg: Sequence[float] = (0.0, 0.0, 0.0)
     depth_mode: int = L.GS_DEPTH_MID
     flags: int = 0
+    tile_cull: bool = False  # bin only the tiles a record's alpha >= alpha_min region can reach
 
     def c(self, flags: Optional[int] = None) -> L.Opts:
         o = L.Opts()
@@ -119,10 +120,12 @@ def view_layout(cams) -> Layout:
 class Projected:
     rec: torch.Tensor  # [V*n, 16] float32
     bin: torch.Tensor  # [V*n, 4] int32
+    tile_cull_log2_alpha: float = 0.0  # < 0: binning keeps only reachable tiles
 
     def c(self) -> L.Projected:
         p = L.Projected()
         p.rec, p.bin = _ptr(self.rec), _ptr(self.bin)
+        p.tile_cull_log2_alpha = float(self.tile_cull_log2_alpha)
         return p
 
 
@@ -131,7 +134,8 @@ def project(scene: DeviceScene, cams, opts: RasterOpts, cull_mask: Optional[torc
     V, n = len(cams), scene.n
     dev = scene.opacity.device
     out = Projected(torch.empty((max(V * n, 1), L.GS_REC_FLOATS), device=dev, dtype=torch.float32),
-                    torch.empty((max(V * n, 1), 4), device=dev, dtype=torch.int32))
+                    torch.empty((max(V * n, 1), 4), device=dev, dtype=torch.int32),
+                    float(np.log2(opts.alpha_min)) if opts.tile_cull else 0.0)
     L.check(L.lib().gs_project(ctypes.byref(scene.c()), cameras(cams), V, _ptr(cull_mask), ctypes.byref(opts.c()),
                                ctypes.byref(out.c()), _stream(stream)), "gs_project")
     return out
