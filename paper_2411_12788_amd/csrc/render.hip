@@ -99,26 +99,10 @@ __device__ __forceinline__ float wave_reduce_dpp(float x) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
 }
 
-// Wave sum of nine per-lane partials by a butterfly reduce-scatter: three
-// exchange steps (lane xor 1, xor 2 by quad permutes, xor 8 by a row rotate)
-// halve the values each lane carries, so each lane then holds one value summed
-// over 8 lanes; a row rotate by 4 and the two gfx950 permlane swaps (rows xor
-// 16, halves xor 32) finish the sum.  The ninth value takes the plain chain.
-// The row rotate hands lane L the value of lane L - 4 (mod 16), which is
-// L ^ 4 where bit 2 of L is set.  Afterwards lane L with bit 2 set and bits
-// 4, 5 clear holds the total of value 4 (L & 1) + 2 ((L >> 1) & 1) +
-// ((L >> 3) & 1), and lane 20 the ninth.
+// Value of another lane of the same 16-lane row (DPP control CTRL).
 template <int CTRL>
 __device__ __forceinline__ float dpp_take(float x) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, true));
-}
-__device__ __forceinline__ float swap_sum16(float x) {
-  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(x), false, false);
-  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
-}
-__device__ __forceinline__ float swap_sum32(float x) {
-  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(x), false, false);
-  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
 }
 // Exchanges between the four 16-lane rows of one column (lanes j, 16 + j,
 // 32 + j, 48 + j) with the gfx950 permlane swaps: permlane16_swap hands each
@@ -169,61 +153,10 @@ __device__ __forceinline__ RowScan rows_scan_add(float x, int row) {
   r.total = lo + hi;
   return r;
 }
-template <int CTRL>
-__device__ __forceinline__ uint32_t dpp_take_u32(uint32_t x) {
-  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, 0xF, 0xF, true);
-}
-// Sum and max over each 16-lane row, in every lane of the row: quad permutes
-// (xor 1, xor 2) give quad totals, row rotates by 4 and 8 add the other quads.
-struct RowSumMax {
-  float sum;
-  uint32_t max;  // bit pattern of the largest (non-negative) value
-};
-__device__ __forceinline__ RowSumMax row_sum_max(float x) {
-  float s = x;
-  uint32_t m = __float_as_uint(x);
-  s += dpp_take<0xB1>(s);
-  m = max(m, dpp_take_u32<0xB1>(m));
-  s += dpp_take<0x4E>(s);
-  m = max(m, dpp_take_u32<0x4E>(m));
-  s += dpp_take<0x124>(s);
-  m = max(m, dpp_take_u32<0x124>(m));
-  s += dpp_take<0x128>(s);
-  m = max(m, dpp_take_u32<0x128>(m));
-  return RowSumMax{s, m};
-}
-
 struct Sum9 {
-  float v;   // one of the first eight totals (see above)
+  float v;   // one of the first eight totals (see row_sum9)
   float v8;  // total of the ninth value
 };
-__device__ __forceinline__ Sum9 wave_sum9(const float (&p)[9], int lane) {
-  constexpr int kXor1 = 0xB1, kXor2 = 0x4E, kRor8 = 0x128, kRor4 = 0x124;
-  const bool o1 = (lane & 1) != 0, o2 = (lane & 2) != 0, o8 = (lane & 8) != 0;
-  float a[4];
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const float keep = o1 ? p[4 + j] : p[j], send = o1 ? p[j] : p[4 + j];
-    a[j] = keep + dpp_take<kXor1>(send);
-  }
-  float c[2];
-#pragma unroll
-  for (int j = 0; j < 2; ++j) {
-    const float keep = o2 ? a[2 + j] : a[j], send = o2 ? a[j] : a[2 + j];
-    c[j] = keep + dpp_take<kXor2>(send);
-  }
-  float d = (o8 ? c[1] : c[0]) + dpp_take<kRor8>(o8 ? c[0] : c[1]);
-  d += dpp_take<kRor4>(d);  // lanes with bit 2 set: partner is lane ^ 4
-  float e = p[8] + dpp_take<kXor1>(p[8]);
-  e += dpp_take<kXor2>(e);
-  e += dpp_take<kRor8>(e);
-  e += dpp_take<kRor4>(e);
-  Sum9 r;
-  r.v = swap_sum32(swap_sum16(d));
-  r.v8 = swap_sum32(swap_sum16(e));
-  return r;
-}
-
 __device__ __forceinline__ bool box_meets(int2 b, int32_t x0, int32_t x1, int32_t y0, int32_t y1) {
   // pixel box (lo | hi << 16) against the pixel rectangle [x0, x1] x [y0, y1]
   return (int32_t)((uint32_t)b.x >> 16) >= x0 && (b.x & 0xffff) <= x1 && (int32_t)((uint32_t)b.y >> 16) >= y0 &&
@@ -255,23 +188,9 @@ __device__ __forceinline__ Staged fetch_entry(const float* __restrict__ rec, con
   return e;
 }
 
-// Bounding rectangle of the lanes set in `am` (lane = 8 * row + column of the
-// wave's 8x8 quarter at (sx0, sy0)), from the ballot mask with scalar bit ops.
 struct Rect {
   int32_t x0, x1, y0, y1;
 };
-__device__ __forceinline__ Rect active_rect(uint64_t am, int32_t sx0, int32_t sy0) {
-  uint64_t f = am | (am >> 32);
-  f |= f >> 16;
-  f |= f >> 8;
-  const uint32_t cols = (uint32_t)f & 0xffu;
-  Rect r;
-  r.y0 = sy0 + ((int32_t)__builtin_ctzll(am) >> 3);
-  r.y1 = sy0 + ((63 - (int32_t)__builtin_clzll(am)) >> 3);
-  r.x0 = sx0 + (int32_t)__builtin_ctz(cols);
-  r.x1 = sx0 + (31 - (int32_t)__builtin_clz(cols));
-  return r;
-}
 
 // Bounding rectangle of the set bits of a 16-lane group's mask (4x4 pixels,
 // bit = 4 * row + column, non-zero) whose block starts at (gx0, gy0).
@@ -607,11 +526,14 @@ __device__ __forceinline__ StagedB fetch_entry_bwd(const float* __restrict__ rec
   return e;
 }
 
-// Sum of nine per-lane partials over each 16-lane row by the butterfly
-// reduce-scatter of wave_sum9 without its cross-row steps: afterwards lane L
-// of a row with bit 2 set holds the row total of value 4 (L & 1) +
-// 2 ((L >> 1) & 1) + ((L >> 3) & 1), and every lane holds the row total of
-// the ninth value.
+// Sum of nine per-lane partials over each 16-lane row by a butterfly
+// reduce-scatter: three exchange steps (lane xor 1 and xor 2 by quad
+// permutes, xor 8 by a row rotate) halve the values each lane carries, then a
+// row rotate by 4 (lane L reads lane L - 4 mod 16, which is L xor 4 where bit
+// 2 of L is set) adds the last pair.  Afterwards lane L of a row with bit 2
+// set holds the row total of value 4 (L & 1) + 2 ((L >> 1) & 1) +
+// ((L >> 3) & 1), and every lane holds the row total of the ninth value (a
+// plain chain).
 __device__ __forceinline__ Sum9 row_sum9(const float (&p)[9], int lane) {
   constexpr int kXor1 = 0xB1, kXor2 = 0x4E, kRor8 = 0x128, kRor4 = 0x124;
   const bool o1 = (lane & 1) != 0, o2 = (lane & 2) != 0, o8 = (lane & 8) != 0;
