@@ -309,7 +309,8 @@ def serving_bench(n_requests: int):
 def multiview_bench(steps: int, warmup: int):
     """Batched differentiation: one launch per stage for 16 views of a 1M-Gaussian
     scene at mixed resolutions (640x480 .. 1600x1200), forward + backward
-    through the autograd Function with recompute-in-backward, L1 loss."""
+    through the autograd Function, L1 loss; with recompute-in-backward (the
+    default, least memory) and with the forward's lists kept (save_lists)."""
     from paper_2411_12788_amd import raster as R
     from paper_2411_12788_amd.autograd import rasterize
     wl = gs_inputs.multiview()
@@ -318,23 +319,28 @@ def multiview_bench(steps: int, warmup: int):
     lay = R.view_layout(wl.cameras)
     target = torch.from_numpy(gs_inputs.uniform_image(3, lay.pixels_total, 777)).cuda()
 
-    def one():
-        for x in leaves:
-            x.grad = None
-        color, depth, imax = rasterize(*leaves, wl.cameras)
-        (color - target).abs().mean().backward()
+    def run(save_lists):
+        def one():
+            for x in leaves:
+                x.grad = None
+            color, depth, imax = rasterize(*leaves, wl.cameras, save_lists=save_lists)
+            (color - target).abs().mean().backward()
 
-    for _ in range(warmup):
-        one()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        one()
-    torch.cuda.synchronize()
-    ms = 1e3 * (time.perf_counter() - t0) / steps
+        for _ in range(warmup):
+            one()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            one()
+        torch.cuda.synchronize()
+        return 1e3 * (time.perf_counter() - t0) / steps
+
+    ms = run(False)
+    ms_saved = run(True)
     return {"workload": wl.name, "gaussians": wl.scene.n, "views": len(wl.cameras),
             "pixels": lay.pixels_total, "ms_per_step": round(ms, 3), "views_per_s": round(1e3 * len(wl.cameras) / ms, 2),
-            "mode": "autograd, recompute in backward"}
+            "mode": "autograd, recompute in backward",
+            "saved_lists": {"ms_per_step": round(ms_saved, 3), "views_per_s": round(1e3 * len(wl.cameras) / ms_saved, 2)}}
 
 
 def source_hash() -> str:
