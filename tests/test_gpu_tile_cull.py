@@ -30,6 +30,24 @@ def _workloads():
     return [gs_inputs.elongated_cube(seed=3), gs_inputs.small_cube(seed=4, n=3000, width=128, height=96)]
 
 
+def test_multiview_culled_lists_match_single_views(gpu_lib):
+    """Two views in one launch: each view's culled pairs equal those of the
+    view binned alone (records of view v are v * n + i)."""
+    R = H.raster()
+    wl = gs_inputs.elongated_cube(seed=8)
+    cams = [wl.cameras[0], gs_inputs.look_at((1.5, 0.5, 3.5), (0.0, 0.0, 0.0), 144, 112)]
+    opts = R.RasterOpts(tile_cull=True)
+    both = H.run_gpu_forward(wl.scene, cams, opts=opts, accumulate=False, want_keys=True)
+    lay = R.view_layout(cams)
+    n = wl.scene.n
+    got = _pairs(both["binned"], n)
+    want = set()
+    for v, cam in enumerate(cams):
+        one = H.run_gpu_forward(wl.scene, [cam], opts=opts, accumulate=False, want_keys=True)
+        want |= {(t + lay.tile_base[v], r + v * n) for (t, r) in _pairs(one["binned"], n)}
+    assert got == want
+
+
 @pytest.mark.parametrize("k", [0, 1])
 def test_dropped_pairs_are_unreachable(gpu_lib, k):
     R = H.raster()
