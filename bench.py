@@ -404,7 +404,7 @@ def summarize(d: str) -> None:
     import csv
     stats = list(csv.DictReader(open(os.path.join(d, "kt", "kt_kernel_stats.csv"))))
     lines = ["# Kernel times: 3M Gaussians, one 1920x1080 view, fwd+bwd step", "",
-             "Command (from the repository root): `" + PROFILE_CMDS["kt"].format(d="gpurun_out/prof") + "`", "",
+             "Command (from the repository root): `" + PROFILE_CMDS["kt"].format(d=d.rstrip("/")) + "`", "",
              f"source_sha256: {source_hash()}", "",
              "| kernel | calls | avg us | min us | max us | share % |", "|---|---|---|---|---|---|"]
     for r in stats:
@@ -434,9 +434,9 @@ def summarize(d: str) -> None:
         traffic = 1024.0 * (fk / f_fac + wk / w_fac)
         txt = [f"# HBM traffic of {k}: 3M Gaussians, one 1920x1080 view", "",
                "Commands (from the repository root):", "",
-               "- `" + PROFILE_CMDS["fetch"].format(d="gpurun_out/prof") + "`",
-               "- `" + PROFILE_CMDS["write"].format(d="gpurun_out/prof") + "`",
-               "- `" + PROFILE_CMDS["kt"].format(d="gpurun_out/prof") + "` (durations)", "",
+               "- `" + PROFILE_CMDS["fetch"].format(d=d.rstrip("/")) + "`",
+               "- `" + PROFILE_CMDS["write"].format(d=d.rstrip("/")) + "`",
+               "- `" + PROFILE_CMDS["kt"].format(d=d.rstrip("/")) + "` (durations)", "",
                f"- FETCH_SIZE per dispatch: {fk:.1f} KiB (mean of {len(fetch[k])} dispatches)",
                f"- WRITE_SIZE per dispatch: {wk:.1f} KiB",
                f"- calibration: a 1 GiB device copy reads {f_fac:.4f} GiB by FETCH_SIZE and writes "
@@ -455,7 +455,7 @@ def main():
         summarize(args.summarize)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU only; multi-GPU scaling is not implemented "
+        print(json.dumps({"error": "bench.py measures one GPU only; multi-GPU runs are not implemented "
                                    "(the path would shard by view with a gradient all-reduce)",
                           "n_gpus": args.gpus}))
         sys.exit(2)
