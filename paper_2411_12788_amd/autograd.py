@@ -6,8 +6,10 @@ the list position of the last included Gaussian).  Backward recomputes the
 projection and the sorted lists — both are deterministic, so they come out
 bit-identical to the forward's — and then runs the masked pixel backward and
 the projection backward.  With ``save_lists=True`` the forward's records and
-lists are kept instead (more memory, no recompute); both modes return the same
-gradients bit for bit.
+lists are kept instead (more memory, no recompute); both modes run the same
+kernels on bit-identical lists, so their gradients differ only by the
+summation order of the float atomics that gather per-pixel partials
+(~1e-6 relative).
 
 Differentiable output: colour [3, P].  Depth and the argmax index are marked
 non-differentiable; per-Gaussian accumulations, when requested, are returned
