@@ -106,3 +106,15 @@ def test_criteria_argument_errors_on_host(L):
     assert lib.gs_clone(ctypes.byref(sc), fake, ctypes.byref(out), None, fake, cw, None) == L.GS_ERR_NULL
     assert lib.gs_clone(ctypes.byref(sc), fake, ctypes.byref(out), fake, fake, 0, None) == L.GS_ERR_CAPACITY
     assert lib.gs_clone(ctypes.byref(sc), fake, None, fake, fake, cw, None) == L.GS_ERR_NULL
+    # split and the density-control selection
+    out.capacity = 99
+    sw = lib.gs_split_workspace_size(100)
+    assert lib.gs_split(ctypes.byref(sc), fake, fake, 1.6, ctypes.byref(out), fake, fake, sw, None) == L.GS_ERR_CAPACITY
+    out.capacity = 200
+    assert lib.gs_split(ctypes.byref(sc), fake, fake, 0.0, ctypes.byref(out), fake, fake, sw, None) == L.GS_ERR_SHAPE
+    assert lib.gs_split(ctypes.byref(sc), fake, None, 1.6, ctypes.byref(out), fake, fake, sw, None) == L.GS_ERR_NULL
+    assert lib.gs_split(ctypes.byref(sc), fake, fake, 1.6, ctypes.byref(out), fake, fake, 0, None) == L.GS_ERR_CAPACITY
+    assert lib.gs_densify_select(fake, fake, fake, -1, 1e-4, 0.1, fake, fake, None) == L.GS_ERR_SHAPE
+    assert lib.gs_densify_select(fake, fake, fake, 10, 1e-4, 0.1, None, None, None) == L.GS_ERR_NULL
+    assert lib.gs_densify_select(None, fake, fake, 10, 1e-4, 0.1, fake, None, None) == L.GS_ERR_NULL
+    assert lib.gs_densify_select(None, None, None, 0, 1e-4, 0.1, None, None, None) == L.GS_OK  # nothing to do
