@@ -267,14 +267,14 @@ def small_cube(seed: int = 0, n: int = 4096, width: int = 128, height: int = 128
 
 
 def heavy_tiles(seed: int = 0, n: int = 40_000, width: int = 64, height: int = 48,
-                opacity=(0.01, 0.05)) -> Workload:
+                opacity=(0.01, 0.05), distance: float = 2.5) -> Workload:
     """Dense, faint cube filling a small view: every 16x16 tile holds a list of
     a few thousand entries and pixels composite hundreds of them before the
     transmittance stop (default opacity U(0.01, 0.05)), the regime of the heavy tiles
     of a full-size scene at a size the oracle renders in seconds."""
     sc = uniform_cube_scene(n, seed)
     sc.opacity = rng(seed + 1).uniform(opacity[0], opacity[1], size=n).astype(np.float32)
-    cam = look_at((0.0, 0.0, 2.5), (0.0, 0.0, 0.0), width, height)
+    cam = look_at((0.0, 0.0, distance), (0.0, 0.0, 0.0), width, height)
     return Workload("heavy_tiles_40k_64x48", sc, [cam])
 
 

@@ -153,6 +153,24 @@ __device__ __forceinline__ RowScan rows_scan_add(float x, int row) {
   r.total = lo + hi;
   return r;
 }
+__device__ __forceinline__ float rows_sum(float x) {
+  const RowsTwo p = rows_pair(__float_as_uint(x));
+  const float pair = __uint_as_float(p.a) + __uint_as_float(p.b);
+  const RowsTwo h = rows_halves(__float_as_uint(pair));
+  return __uint_as_float(h.a) + __uint_as_float(h.b);
+}
+__device__ __forceinline__ uint32_t rows_sum_u32(uint32_t x) {
+  const RowsTwo p = rows_pair(x);
+  const RowsTwo h = rows_halves(p.a + p.b);
+  return h.a + h.b;
+}
+__device__ __forceinline__ uint32_t rows_max_u32(uint32_t x) {
+  const RowsTwo p = rows_pair(x);
+  const uint32_t m = p.a > p.b ? p.a : p.b;
+  const RowsTwo h = rows_halves(m);
+  return h.a > h.b ? h.a : h.b;
+}
+
 struct Sum9 {
   float v;   // one of the first eight totals (see row_sum9)
   float v8;  // total of the ninth value
@@ -205,45 +223,64 @@ __device__ __forceinline__ Rect group_rect(uint32_t bits, int32_t gx0, int32_t g
 }
 
 // Work item of a render workgroup.  With a tile order (longest lists first),
-// each of the first cfg.tiles tiles of the order gets four workgroups; if its
-// list has at least cfg.len entries they take one 8x8 quarter each, with one
-// 4x4 pixel group per wave, so the tile's sixteen groups walk their streams
-// independently instead of four to a wave in lockstep: these tiles set the
-// kernel's length.  In the backward such a wave's four rows hold the same 16
-// pixels and take four consecutive entries of the group's stream per step,
-// combined across rows by scans; in the forward the group sits in lanes 0-15.
-// For a short list the first of the four takes the whole tile and the other
-// three exit.
-// (tiles of the order that may split, minimum list length to split) per
-// kernel.  The backward's split waves run row-parallel at about the cost per
-// entry of a whole-tile wave, so it splits every sizeable list; the forward's
-// split waves leave 48 lanes idle, so it splits only the very longest.
-struct SplitCfg {
-  int32_t tiles;
-  uint32_t len;
-};
-constexpr SplitCfg kFwdSplit{256, 2048};
-constexpr SplitCfg kBwdSplit{2048, 256};
+// each of the first kSplitTiles tiles of the order gets four workgroups.  If
+// the tile splits, they take one 8x8 quarter each, with one 4x4 pixel group
+// per wave, so the tile's sixteen groups walk their streams independently
+// instead of four to a wave in lockstep: the longest lists set the kernels'
+// length.  Otherwise one of the four takes the whole tile and the other three
+// exit.  The four blocks of a tile are b, b + 8, b + 16, b + 24 of a run of
+// 32: they run on one XCD (block b runs on XCD b mod 8) and share its L2, so
+// the tile's records are fetched from HBM once.  The whole-tile runner is the
+// tile's block with quarter index (b >> 5) & 3, rotating from run to run: an
+// XCD places its workgroups on its CUs in turn, and a fixed runner would put
+// every runner on every fourth CU while the others got only the exiting
+// blocks (measured: forward-only renders 1.7x slower).
+//
+// Backward: a tile splits when its list has at least kSplitLen entries; a
+// split wave's four rows hold the same 16 pixels and take four consecutive
+// entries of the group's stream per step, combined across rows by scans.
+// Forward: the row-parallel form costs about twice the instructions per
+// (entry, group) of a whole-tile wave, so it only pays when the work is
+// concentrated in few tiles.  When at least half of the tiles are empty (the
+// tile at the middle of the order has no entries) every tile of at least
+// kSplitLen entries splits row-parallel; otherwise only the kFwdSpreadTiles
+// longest split, when they reach kFwdSpreadLen entries, with the group in
+// lanes 0-15.
+constexpr int32_t kSplitTiles = 2048;
+constexpr uint32_t kSplitLen = 256;
+constexpr int32_t kFwdSpreadTiles = 256;
+constexpr uint32_t kFwdSpreadLen = 2048;
 struct WorkItem {
   int32_t tile;
   int32_t quarter;  // -1: whole tile
   bool skip;
+  bool rowpar;      // split with the rows as consecutive entries
 };
 __device__ __forceinline__ WorkItem work_item(const uint32_t* order, const uint32_t* ranges, int32_t nsplit,
-                                              uint32_t split_len) {
-  WorkItem w{(int32_t)blockIdx.x, -1, false};
+                                              int32_t tiles_total, bool forward) {
+  WorkItem w{(int32_t)blockIdx.x, -1, false, false};
   if (order == nullptr) return w;
   const int32_t b = (int32_t)blockIdx.x;
   if (b < 4 * nsplit) {
-    // blocks b, b + 8, b + 16, b + 24 of each run of 32 are the four quarters of
-    // one tile: they run on the same XCD (b mod 8) and share its L2, so the
-    // tile's records are fetched from HBM once instead of four times
     const int32_t t = ((b >> 5) << 3) + (b & 7);
     w.tile = (int32_t)uload(order + t);
     const uint32_t len = uload(ranges + 2 * w.tile + 1) - uload(ranges + 2 * w.tile);
     const int32_t q = (b >> 3) & 3;
-    if (len >= split_len) w.quarter = q;
-    else w.skip = q != 0;
+    bool split = len >= kSplitLen, rowpar = true;
+    if (forward) {
+      const uint32_t mid = uload(order + tiles_total / 2);
+      const bool concentrated = uload(ranges + 2 * mid + 1) == uload(ranges + 2 * mid);
+      if (!concentrated) {
+        split = t < kFwdSpreadTiles && len >= kFwdSpreadLen;
+        rowpar = false;
+      }
+    }
+    if (split) {
+      w.quarter = q;
+      w.rowpar = rowpar;
+    } else {
+      w.skip = q != ((b >> 5) & 3);
+    }
   } else {
     w.tile = (int32_t)uload(order + (b - 3 * nsplit));
   }
@@ -276,8 +313,8 @@ __device__ __forceinline__ LanePixel lane_pixel(int32_t tx, int32_t ty, int32_t 
   return l;
 }
 // Tiles of the order that get four workgroups: a multiple of 8 (see work_item).
-inline int32_t split_tiles(const uint32_t* order, int32_t tiles_total, SplitCfg cfg) {
-  const int32_t t = tiles_total < cfg.tiles ? tiles_total : cfg.tiles;
+inline int32_t split_tiles(const uint32_t* order, int32_t tiles_total) {
+  const int32_t t = tiles_total < kSplitTiles ? tiles_total : kSplitTiles;
   return order ? t & ~7 : 0;
 }
 
@@ -317,7 +354,7 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(const float* __restrict__
   // workgroup with LDS atomics, flushed with one global atomic per entry
   __shared__ float s_acc_w[ACC ? kBatch : 1];
   __shared__ uint32_t s_acc_m[ACC ? kBatch : 1];
-  const WorkItem wi = work_item(order, ranges, nsplit, kFwdSplit.len);
+  const WorkItem wi = work_item(order, ranges, nsplit, vs.tiles_total, true);
   if (wi.skip) return;
   const int32_t tile = wi.tile;
   const int32_t v = view_of_tile(vs, tile);
@@ -331,7 +368,8 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(const float* __restrict__
   // max over groups instead of the union of the four streams.
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int grp = lane >> 4;
-  const LanePixel lp = lane_pixel(tx, ty, wi.quarter, wv, lane, false);
+  const bool rp = wi.quarter >= 0 && wi.rowpar;  // split work item: rows are consecutive entries
+  const LanePixel lp = lane_pixel(tx, ty, wi.quarter, wv, lane, rp);
   const int32_t sx0 = lp.sx0, sy0 = lp.sy0, px = lp.px, py = lp.py;
   const bool inside = lp.on && px < cam.width && py < cam.height;
   const float pxc = (float)px + 0.5f, pyc = (float)py + 0.5f;
@@ -342,6 +380,7 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(const float* __restrict__
   float T = 1.f, c0 = 0.f, c1 = 0.f, c2 = 0.f, wbest = 0.f, dblend = 0.f;
   int32_t best = -1;
   uint32_t lastpos = 0, cnt = 0;
+  uint32_t bpos = 0xffffffffu;  // list position of `best` (split work items)
   bool done = !inside;
   // Staging pipeline: while round R is processed, the records of round R + 1
   // and the list indices of round R + 2 are already in flight.
@@ -377,7 +416,7 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(const float* __restrict__
       uint64_t gmask[4];
 #pragma unroll
       for (int g = 0; g < 4; ++g) {
-        const uint32_t bits = (uint32_t)(am >> (16 * g)) & 0xffffu;
+        const uint32_t bits = (rp && g > 0) ? 0u : (uint32_t)(am >> (16 * g)) & 0xffffu;
         bool rel = false;
         if (bits != 0u) {
           const Rect rg = group_rect(bits, sx0 + (g & 1) * 4, sy0 + (g >> 1) * 4);
@@ -386,7 +425,68 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(const float* __restrict__
         }
         gmask[g] = __ballot(rel);
       }
-      uint64_t mine = grp == 0 ? gmask[0] : grp == 1 ? gmask[1] : grp == 2 ? gmask[2] : gmask[3];
+      uint64_t mine = rp ? gmask[0] : grp == 0 ? gmask[0] : grp == 1 ? gmask[1] : grp == 2 ? gmask[2] : gmask[3];
+      // Split work item: row r takes the r-th of the next four entries of the
+      // group's stream.  The transmittance in front of each is T times the
+      // product of (1 - alpha) over the rows before it; an entry is composited
+      // unless its own or an earlier row's entry reaches the stop.  Each row
+      // keeps partial colour, depth, count and argmax, merged at the end.
+      uint64_t rmine = rp ? uniform_u64(mine) : 0ull;  // the same in every lane: keep it scalar
+      if (rp) mine = 0;
+      while (rmine != 0) {
+        // row r's entry: the lowest set bit of the mask with r lower bits cleared
+        const uint64_t m1 = rmine & (rmine - 1), m2 = m1 & (m1 - 1), m3 = m2 & (m2 - 1);
+        const uint64_t mr = grp < 2 ? (grp == 0 ? rmine : m1) : (grp == 2 ? m2 : m3);
+        rmine = m3 & (m3 - 1);
+        const bool hr = mr != 0;
+        const int kr = c * kWave + (hr ? (int)__builtin_ctzll(mr) : 0);
+        const float4 r0 = s_r0[kr], r1 = s_r1[kr], q2 = s_r2[kr];
+        const float dx = (pxc - r0.x) - r0.z, dy = (pyc - r0.y) - r0.w;
+        const float ee = r1.w - (r1.x * dx * dx + r1.y * dx * dy + r1.z * dy * dy);
+        const float al = fminf(op.alpha_max, __builtin_amdgcn_exp2f(ee));
+        const bool pass = hr && !done && ee >= op.log2_alpha_min;
+        const float om = pass ? 1.f - al : 1.f;
+        const RowScan tf = rows_scan_mul(om, grp);
+        const bool stop = pass && T * tf.incl < op.t_min;
+        const uint64_t sb = __ballot(stop);
+        bool inc = pass;
+        float Tn = T * tf.total;
+        if (sb != 0ull) {
+          // rare: some pixel stops at one of these entries; later rows of its
+          // column are dropped and its transmittance is the one in front of
+          // the stopping entry
+          const uint64_t col = 0x0001000100010001ull << (lane & 15);
+          const bool earlier = (sb & col & ((1ull << (16 * grp)) - 1ull)) != 0;
+          inc = pass && !stop && !earlier;
+          Tn = T * rows_scan_mul(inc ? om : 1.f, grp).total;
+          done = done || (sb & col) != 0;
+        }
+        const float wgt = inc ? al * (T * tf.excl) : 0.f;
+        c0 += wgt * q2.x;
+        c1 += wgt * q2.y;
+        c2 += wgt * q2.z;
+        if (DEPTH == GS_DEPTH_BLEND) dblend += wgt * s_z[kr];
+        const uint32_t pos = base + (uint32_t)kr - start;
+        const bool better = wgt > wbest;  // a row's entries arrive in order: the nearer wins ties
+        wbest = better ? wgt : wbest;
+        best = better ? (int32_t)((int64_t)__float_as_uint(q2.w) - vbase) : best;
+        bpos = better ? pos : bpos;
+        lastpos = inc ? pos + 1 : lastpos;
+        cnt += inc ? 1u : 0u;
+        if (ACC && inc) {
+          atomicAdd(&s_acc_w[kr], wgt);
+          atomicMax(&s_acc_m[kr], __float_as_uint(wgt));
+        }
+        T = Tn;
+        if (sb != 0ull) {
+          const uint64_t dm = __ballot(done);
+          if ((dm & 0xffffull) == 0xffffull) rmine = 0;
+          if (dm == ~0ull) {
+            wave_done = true;
+            break;
+          }
+        }
+      }
       // kFwdUnroll entries of the group's stream per iteration: their records
       // are read and their alphas evaluated side by side, then they are
       // composited in order (each sees the previous one's transmittance and
@@ -458,6 +558,28 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(const float* __restrict__
         if (o.wmax) atomicMax(reinterpret_cast<unsigned int*>(o.wmax) + ai, s_acc_m[threadIdx.x]);
       }
     }
+  }
+  if (rp) {
+    // merge the rows' partials (every row of a column holds the same pixel)
+    c0 = rows_sum(c0);
+    c1 = rows_sum(c1);
+    c2 = rows_sum(c2);
+    if (DEPTH == GS_DEPTH_BLEND) dblend = rows_sum(dblend);
+    cnt = rows_sum_u32(cnt);
+    lastpos = rows_max_u32(lastpos);
+    // argmax: the larger weight, on equal weights the earlier list position
+#pragma unroll
+    for (int step = 0; step < 2; ++step) {
+      const RowsTwo w = step == 0 ? rows_pair(__float_as_uint(wbest)) : rows_halves(__float_as_uint(wbest));
+      const RowsTwo b = step == 0 ? rows_pair((uint32_t)best) : rows_halves((uint32_t)best);
+      const RowsTwo q = step == 0 ? rows_pair(bpos) : rows_halves(bpos);
+      const float wa = __uint_as_float(w.a), wb = __uint_as_float(w.b);
+      const bool take_b = wb > wa || (wb == wa && q.b < q.a);
+      wbest = take_b ? wb : wa;
+      best = (int32_t)(take_b ? b.b : b.a);
+      bpos = take_b ? q.b : q.a;
+    }
+    if (grp != 0) return;  // row 0 writes the pixel
   }
   if (!inside) return;
   if (ACC && o.area && best >= 0) atomicAdd(o.area + (per_view ? vbase + best : (int64_t)best), 1u);
@@ -583,7 +705,7 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(const float* __restrict__
   __shared__ int2 s_box[kBatch];
   __shared__ uint32_t s_idx[kBatch];  // record index | active << 31
   __shared__ uint32_t s_jmax[kBlock / kWave];
-  const WorkItem wi = work_item(order, ranges, nsplit, kBwdSplit.len);
+  const WorkItem wi = work_item(order, ranges, nsplit, vs.tiles_total, false);
   if (wi.skip) return;
   const int32_t tile = wi.tile;
   const int32_t v = view_of_tile(vs, tile);
@@ -823,13 +945,13 @@ static void launch_fwd(int depth_mode, dim3 grid, hipStream_t s, const gs_projec
   const float* q = scene ? scene->quats : nullptr;
   if (depth_mode == GS_DEPTH_CENTER)
     hipLaunchKernelGGL((k_render_fwd<ACC, OUT, GS_DEPTH_CENTER>), grid, dim3(kBlock), 0, s, proj->rec, proj->bin, vals,
-                       ranges, order, split_tiles(order, vs.tiles_total, kFwdSplit), n, m, sc, q, o, op, per_view, vs);
+                       ranges, order, split_tiles(order, vs.tiles_total), n, m, sc, q, o, op, per_view, vs);
   else if (depth_mode == GS_DEPTH_BLEND)
     hipLaunchKernelGGL((k_render_fwd<ACC, OUT, GS_DEPTH_BLEND>), grid, dim3(kBlock), 0, s, proj->rec, proj->bin, vals,
-                       ranges, order, split_tiles(order, vs.tiles_total, kFwdSplit), n, m, sc, q, o, op, per_view, vs);
+                       ranges, order, split_tiles(order, vs.tiles_total), n, m, sc, q, o, op, per_view, vs);
   else
     hipLaunchKernelGGL((k_render_fwd<ACC, OUT, GS_DEPTH_MID>), grid, dim3(kBlock), 0, s, proj->rec, proj->bin, vals,
-                       ranges, order, split_tiles(order, vs.tiles_total, kFwdSplit), n, m, sc, q, o, op, per_view, vs);
+                       ranges, order, split_tiles(order, vs.tiles_total), n, m, sc, q, o, op, per_view, vs);
 }
 
 }  // namespace msplat
@@ -856,7 +978,7 @@ int32_t gs_render_forward(const gs_scene_t* scene, const gs_projected_t* proj, c
            accum ? acc->importance : nullptr, accum ? acc->wmax : nullptr, accum ? acc->area : nullptr};
   const KOpts op = make_kopts(opts);
   const int32_t per_view = (opts->flags & GS_ACCUM_PER_VIEW) ? 1 : 0;
-  dim3 grid(vs.tiles_total + 3 * split_tiles(tile_order, vs.tiles_total, kFwdSplit));
+  dim3 grid(vs.tiles_total + 3 * split_tiles(tile_order, vs.tiles_total));
   hipStream_t s = (hipStream_t)stream;
   if (accum)
     launch_fwd<true, true>(opts->depth_mode, grid, s, proj, vals, ranges, tile_order, scene->n, scene, o, op, per_view,
@@ -885,9 +1007,9 @@ int32_t gs_accumulate_importance(const gs_projected_t* proj, const uint32_t* val
   const KOpts op = make_kopts(opts);
   const int32_t per_view = (opts->flags & GS_ACCUM_PER_VIEW) ? 1 : 0;
   hipLaunchKernelGGL((k_render_fwd<true, false, GS_DEPTH_CENTER>),
-                     dim3(vs.tiles_total + 3 * split_tiles(tile_order, vs.tiles_total, kFwdSplit)), dim3(kBlock), 0,
+                     dim3(vs.tiles_total + 3 * split_tiles(tile_order, vs.tiles_total)), dim3(kBlock), 0,
                      (hipStream_t)stream, proj->rec, proj->bin, vals, ranges, tile_order,
-                     split_tiles(tile_order, vs.tiles_total, kFwdSplit), n, nullptr, nullptr, nullptr,
+                     split_tiles(tile_order, vs.tiles_total), n, nullptr, nullptr, nullptr,
                      o, op, per_view, vs);
   MS_CHECK_LAUNCH("accumulate_importance");
   return GS_OK;
@@ -907,14 +1029,14 @@ int32_t gs_render_backward_pixels(const gs_projected_t* proj, const uint32_t* va
   if (!proj->rec || !proj->bin || !grad2d) { set_error("buffer NULL"); return GS_ERR_NULL; }
   const KOpts op = make_kopts(opts);
   hipStream_t s = (hipStream_t)stream;
-  const dim3 grid(vs.tiles_total + 3 * split_tiles(tile_order, vs.tiles_total, kBwdSplit));
+  const dim3 grid(vs.tiles_total + 3 * split_tiles(tile_order, vs.tiles_total));
   if (active)
     hipLaunchKernelGGL(k_render_bwd<true>, grid, dim3(kBlock), 0, s, proj->rec, proj->bin, vals,
-                       ranges, tile_order, split_tiles(tile_order, vs.tiles_total, kBwdSplit), n, t_final, last, dl_dcolor,
+                       ranges, tile_order, split_tiles(tile_order, vs.tiles_total), n, t_final, last, dl_dcolor,
                        active, grad2d, op, vs);
   else
     hipLaunchKernelGGL(k_render_bwd<false>, grid, dim3(kBlock), 0, s, proj->rec, proj->bin, vals,
-                       ranges, tile_order, split_tiles(tile_order, vs.tiles_total, kBwdSplit), n, t_final, last, dl_dcolor,
+                       ranges, tile_order, split_tiles(tile_order, vs.tiles_total), n, t_final, last, dl_dcolor,
                        active, grad2d, op, vs);
   MS_CHECK_LAUNCH("render_backward_pixels");
   return GS_OK;

@@ -49,3 +49,31 @@ def test_heavy_tiles_forward_backward(gpu_lib, opacity):
     for k in ("means", "scales", "quats", "opacity", "sh"):
         gk = _np(grads[k])[..., :n].astype(np.float64)
         assert H.rel_l2(gk, og[k]) <= H.GRAD_REL_L2, k
+
+
+def test_concentrated_heavy_tiles_forward_backward(gpu_lib):
+    """Most tiles empty, a few with long lists: the forward takes its
+    row-parallel split form (the four rows of a wave are consecutive entries
+    of one pixel group's stream) as well as the backward."""
+    R = H.raster()
+    wl = gs_inputs.heavy_tiles(seed=9, n=20_000, width=128, height=96, opacity=(0.02, 0.2), distance=9.0)
+    cam = wl.cameras[0]
+    n, Pn = wl.scene.n, cam.width * cam.height
+    out = H.run_gpu_forward(wl.scene, wl.cameras, accumulate=True)
+    rng = _np(out["binned"].ranges).reshape(-1, 2)
+    lens = rng[:, 1] - rng[:, 0]
+    assert (lens == 0).mean() > 0.5 and (lens >= 256).sum() >= 4
+    p = oracle.Params.of(wl.scene)
+    orc = oracle.forward_view(p, cam, oracle.Opts())
+    amb, amb_arg = H.compare_forward(out["frame"], orc, slice(0, Pn), "concentrated heavy tiles", max_ambiguous=0.08)
+    _check_accum(out["acc"], orc, amb_arg, n)
+    dldc = gs_inputs.normal_image(3, Pn, 41, scale=1.0 / Pn)
+    active = gs_inputs.bernoulli_mask(n, 0.25, 42)
+    grads, g2d = R.render_backward(out["scene"], out["proj"], out["binned"], wl.cameras, R.RasterOpts(),
+                                   out["frame"], torch.from_numpy(dldc).cuda(), torch.from_numpy(active).cuda())
+    torch.cuda.synchronize()
+    og, og2d = oracle.backward_views(p, wl.cameras, oracle.Opts(), [dldc.T.astype(np.float64)], active=active)
+    assert H.rel_l2(_np(g2d).astype(np.float64)[:n], og2d[0] * active[:, None]) <= H.GRAD_REL_L2
+    for k in ("means", "scales", "quats", "opacity", "sh"):
+        assert H.rel_l2(_np(grads[k])[..., :n].astype(np.float64), og[k]) <= H.GRAD_REL_L2, k
+
