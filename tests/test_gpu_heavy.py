@@ -65,6 +65,7 @@ def test_concentrated_heavy_tiles_forward_backward(gpu_lib):
     assert (lens == 0).mean() > 0.5 and (lens >= 256).sum() >= 4
     p = oracle.Params.of(wl.scene)
     orc = oracle.forward_view(p, cam, oracle.Opts())
+    assert (orc["t_final"] < 1e-3).sum() > 100  # pixels that stop inside the four-entry steps
     amb, amb_arg = H.compare_forward(out["frame"], orc, slice(0, Pn), "concentrated heavy tiles", max_ambiguous=0.08)
     _check_accum(out["acc"], orc, amb_arg, n)
     dldc = gs_inputs.normal_image(3, Pn, 41, scale=1.0 / Pn)
