@@ -247,7 +247,7 @@ __device__ __forceinline__ Rect group_rect(uint32_t bits, int32_t gx0, int32_t g
 // longest split, when they reach kFwdSpreadLen entries, with the group in
 // lanes 0-15.
 constexpr int32_t kSplitTiles = 2048;
-constexpr uint32_t kSplitLen = 256;
+constexpr uint32_t kSplitLen = 128;
 constexpr int32_t kFwdSpreadTiles = 256;
 constexpr uint32_t kFwdSpreadLen = 2048;
 struct WorkItem {
