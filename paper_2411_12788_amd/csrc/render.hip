@@ -319,8 +319,8 @@ inline int32_t split_tiles(const uint32_t* order, int32_t tiles_total) {
 }
 
 constexpr int kBatch = kBlock;  // list entries staged per workgroup round
-constexpr int kFwdUnroll = 4;   // entries of a group's stream per forward iteration
-constexpr int kBwdUnroll = 2;   // entries of a group's stream per backward iteration
+constexpr int kFwdUnroll = 2;   // entries of a group's stream per forward iteration
+constexpr int kBwdUnroll = 1;   // entries of a group's stream per backward iteration
 
 // Work per tile spans four orders of magnitude and a wave's list is walked in
 // order, so the longest lists set the kernel's length.  Waves of long lists
