@@ -19,8 +19,9 @@
  *    *_workspace_size() query, 256-byte aligned.
  *  - Asynchrony: work is enqueued on `stream` (a hipStream_t; NULL = the null
  *    stream).  Only gs_bin_count synchronises (it returns the pair count).
- *  - Reentrancy: no global mutable state; concurrent calls on different
- *    streams with disjoint buffers are safe.
+ *  - Reentrancy: no global mutable state (apart from the diagnostic
+ *    gs_sort_set_spin_limit); concurrent calls on different streams with
+ *    disjoint buffers are safe.
  *  - Views: V cameras (1 <= V <= GS_MAX_VIEWS) are rendered in one launch per
  *    stage.  A record is one (view, Gaussian) pair, index r = v * n + i.
  *    Per-pixel arrays are indexed by the global pixel id
@@ -202,7 +203,7 @@ int32_t gs_project(const gs_scene_t* scene, const gs_camera_t* cams, int32_t V, 
 
 /* a2 -- binning count: exclusive scan of tiles_touched into offsets [dev, u32
  * V*n] and the statistics above.  Synchronises `stream` to return *stats.
- * GS_ERR_CAPACITY if the pair count does not fit 32 bits. */
+ * GS_ERR_CAPACITY if the pair count is 2^30 or more (the sort's limit). */
 size_t gs_bin_count_workspace_size(int64_t n_records);
 int32_t gs_bin_count(const gs_projected_t* proj, const gs_camera_t* cams, int32_t V, int64_t n,
                      uint32_t* offsets, gs_bin_stats_t* stats, void* ws, size_t ws_bytes, void* stream);
@@ -234,7 +235,8 @@ int32_t gs_tile_order(const uint32_t* ranges, int32_t tiles_total, uint32_t* til
 /* The three stages of gs_bin_sort, exported separately.
  * gs_emit_keys: key = (global tile << depth_shift) | (zbits - zbits_min) for each pair.
  * gs_sort_pairs: in-place stable ascending sort of (keys, vals) on key bits
- *   [0, key_bits) (1..64); ws sized by gs_sort_workspace_size(n).
+ *   [0, key_bits) (1..64); ws sized by gs_sort_workspace_size(n); n < 2^30
+ *   (GS_ERR_CAPACITY otherwise).
  * gs_tile_ranges: ranges from sorted keys whose tile id is key >> depth_shift;
  *   keys_out (may be NULL) receives (tile << 32) | (low bits + zbits_min). */
 int32_t gs_emit_keys(const gs_projected_t* proj, const gs_camera_t* cams, int32_t V, int64_t n,
@@ -245,6 +247,22 @@ int32_t gs_sort_pairs(uint64_t* keys, uint32_t* vals, int64_t n, int32_t key_bit
                       void* stream);
 int32_t gs_tile_ranges(const uint64_t* keys, int64_t n, int32_t depth_shift, uint32_t zbits_min,
                        int32_t tiles_total, uint32_t* ranges, uint64_t* keys_out, void* stream);
+
+/* Sort status.  The radix sort of gs_bin_sort and gs_sort_pairs waits on
+ * other workgroups in bounded loops; a wait that exhausts its bound does not
+ * hang but raises an error flag in the first word of the workspace (the
+ * workspaces of both calls start with a 512-byte header) and leaves an invalid
+ * order.  gs_sort_status synchronises `stream`, reads the flag of the last
+ * sort run on the workspace `ws` [dev] and returns GS_OK, or GS_ERR_DEVICE
+ * with gs_last_error() saying the order is invalid.  The flag is cleared at
+ * the start of every sort on that workspace. */
+int32_t gs_sort_status(const void* ws, void* stream);
+
+/* Diagnostic: the number of polls a sort look-back may make before it gives
+ * up (default 2^22; 0 makes every look-back give up at once, which exercises
+ * the error path above without any wait).  Process-wide; affects sorts
+ * enqueued after the call. */
+void gs_sort_set_spin_limit(uint32_t polls);
 
 /* a5 (+a6) -- forward compositing, Eq. (1): per pixel, front to back over its
  * tile's list: alpha = min(alpha_max, opacity * G2D); skip when alpha <
@@ -394,7 +412,7 @@ int32_t gs_densify_select(const float* norm_sum, const uint32_t* count, const fl
 /* Device workspace of gs_split for n input Gaussians. */
 size_t gs_split_workspace_size(int64_t n);
 
-/* Split into two children (the 3DGS split that the blur split of Sec. 3.3,
+/* Split into two children (the 3DGS split that the blur split of Sec. 4.1,
  * Eq. (3), and the density control apply): every row i with select[i] != 0
  * is replaced by two children c = 0, 1 with centre p + R diag(s) z_c, in
  * double, where R is the rotation of the normalised quaternion (w, x, y, z)

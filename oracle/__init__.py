@@ -28,7 +28,7 @@ other than itself live in ``tests/test_oracle_*.py``:
                                                             pinned: exact inclusion probabilities
                                                             of sequential weighted draws
   densify_select, split
-                    Sec. 3.2 / Sec. 3.3 (3DGS density control; blur split
+                    Sec. 3.2 / Sec. 4.1 (3DGS density control; blur split
                     children)                               pinned: closed-form rotations,
                     covariance of the children vs scipy's rotation, boundary cases
   tile_alpha_max    Eq. (1) alpha over a tile's pixel centres (tile culling checks)

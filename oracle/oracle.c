@@ -973,7 +973,7 @@ int64_t orc_sample(int64_t n, const float* importance, const uint32_t* area, con
 
 /* ------------------------------------------------------------------------ */
 /* adaptive density control inherited from 3DGS (Sec. 3.2), used by the      */
-/* blur split (Sec. 3.3 / Eq. (3)) and the SplitAndClone step                */
+/* blur split (Sec. 4.1, Eq. (3)) and the SplitAndClone step                */
 /* ------------------------------------------------------------------------ */
 /* Selection: the mean screen-gradient norm g_i = norm_sum_i / count_i (rows
  * never seen, count 0, are not selected) is compared with grad_thr; a

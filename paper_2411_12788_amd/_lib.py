@@ -87,6 +87,8 @@ _SIGS = {
     "gs_sort_workspace_size": (c_sz, [c_i64]),
     "gs_sort_pairs": (c_i32, [c_p, c_p, c_i64, c_i32, c_p, c_sz, c_p]),
     "gs_tile_ranges": (c_i32, [c_p, c_i64, c_i32, c_u32, c_i32, c_p, c_p, c_p]),
+    "gs_sort_status": (c_i32, [c_p, c_p]),
+    "gs_sort_set_spin_limit": (None, [c_u32]),
     "gs_render_forward": (c_i32, [P(Scene), P(Projected), c_p, c_p, c_p, P(Camera), c_i32, P(Opts), P(FwdOut),
                                   P(Accum), c_p]),
     "gs_accumulate_importance": (c_i32, [P(Projected), c_p, c_p, c_p, P(Camera), c_i32, c_i64, P(Opts), P(Accum),

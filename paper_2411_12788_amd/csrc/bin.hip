@@ -329,7 +329,6 @@ __global__ void k_copy_u32(const uint32_t* __restrict__ a, uint32_t* __restrict_
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
-static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 static int64_t count_blocks(int64_t nrec) { return (nrec + kScanTile - 1) / kScanTile; }
 
@@ -354,7 +353,7 @@ size_t onesweep_ws_size(int64_t n, int32_t passes);
 int32_t onesweep_sort(uint64_t* k0, uint32_t* v0, int64_t n, int32_t lo_bit, int32_t bits, void* ws, uint32_t* vfinal,
                       uint64_t** keys_sorted, hipStream_t st);
 
-size_t sort_ws_size(int64_t n) { return onesweep_ws_size(n, 8); }
+size_t sort_ws_size(int64_t n) { return sort_ws_bytes(n); }
 
 static int32_t bits_for(uint64_t maxval) {
   int32_t b = 0;
@@ -372,6 +371,40 @@ static int32_t launch_tile_order(const uint32_t* ranges, int32_t tiles, uint32_t
   hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(64), 0, st, hist);
   hipLaunchKernelGGL(k_order_scatter, dim3(grid_1d(tiles)), dim3(kBlock), 0, st, ranges, tiles, hist, order);
   MS_CHECK_LAUNCH("tile_order");
+  return GS_OK;
+}
+
+
+int32_t bin_sort_on_ws(const gs_projected_t* proj, const ViewSet& vs, int32_t V, int64_t n,
+                           const uint32_t* offsets, const gs_bin_stats_t* stats, uint64_t* keys, uint32_t* vals,
+                           uint32_t* ranges, uint32_t* tile_order, void* ws, hipStream_t s) {
+  const int64_t ni = stats->n_isect;
+  int32_t st;
+  if ((st = launch_fill(ranges, 0u, 2 * (int64_t)vs.tiles_total, s)) != GS_OK) return st;
+  uint32_t* order_hist = (uint32_t*)((char*)ws + 256);
+  if (ni == 0) return tile_order ? launch_tile_order(ranges, vs.tiles_total, tile_order, order_hist, s) : GS_OK;
+  if (!vals || !offsets) { set_error("buffer NULL"); return GS_ERR_NULL; }
+  if (proj->tile_cull_log2_alpha < 0.f && !proj->rec) { set_error("tile culling needs proj->rec"); return GS_ERR_NULL; }
+  char* p = (char*)ws + sort_ws_size(ni);
+  uint64_t* k0 = (uint64_t*)p; p += align256(ni * 8);
+  uint32_t* v0 = (uint32_t*)p;
+  const int32_t shift = stats->depth_bits;
+  // record indices fit below the key when key_bits + bit length(V n - 1) <= 64
+  const int64_t nrec = (int64_t)V * n;
+  int32_t ibits = 1;
+  while (ibits < 63 && (int64_t(1) << ibits) < nrec) ++ibits;
+  if (stats->key_bits + ibits > 64) ibits = 0;
+  hipLaunchKernelGGL(k_emit, dim3(grid_1d(nrec)), dim3(kBlock), 0, s, reinterpret_cast<const int4*>(proj->bin),
+                     proj->rec, proj->tile_cull_log2_alpha, offsets, n, nrec, shift, stats->zbits_min, ibits, k0, v0,
+                     vs);
+  MS_CHECK_LAUNCH("emit");
+  uint64_t* ks = nullptr;
+  if ((st = onesweep_sort(k0, ibits > 0 ? nullptr : v0, ni, ibits, stats->key_bits, ws, vals, &ks, s)) != GS_OK)
+    return st;
+  hipLaunchKernelGGL(k_ranges, dim3(grid_1d(ni)), dim3(kBlock), 0, s, ks, ni, shift, stats->zbits_min, ibits,
+                     (int64_t)vs.tiles_total, ranges, keys, vals);
+  MS_CHECK_LAUNCH("ranges");
+  if (tile_order) return launch_tile_order(ranges, vs.tiles_total, tile_order, order_hist, s);
   return GS_OK;
 }
 
@@ -417,16 +450,14 @@ int32_t gs_bin_count(const gs_projected_t* proj, const gs_camera_t* cams, int32_
   stats->zbits_max = (uint32_t)h[3];
   stats->depth_bits = bits_for((uint64_t)(stats->zbits_max - stats->zbits_min));
   stats->key_bits = stats->depth_bits + bits_for((uint64_t)(vs.tiles_total - 1));
-  if (h[0] >= (uint64_t(1) << 32)) { set_error("pair count exceeds 32 bits"); return GS_ERR_CAPACITY; }
+  if (h[0] >= (uint64_t)kSortMaxPairs) { set_error("pair count of 2^30 or more (sort limit)"); return GS_ERR_CAPACITY; }
   return GS_OK;
 }
 
 size_t gs_sort_workspace_size(int64_t n) { return sort_ws_size(n); }
 
-size_t gs_bin_sort_workspace_size(int64_t n_isect) {
-  const int64_t nn = n_isect > 0 ? n_isect : 1;
-  return align256(nn * 8) + align256(nn * 4) + sort_ws_size(n_isect) + 256;  // + tile-order histogram
-}
+// [sort workspace, header first][emitted keys][emitted values]
+size_t gs_bin_sort_workspace_size(int64_t n_isect) { return bin_sort_ws_bytes(n_isect); }
 
 int32_t gs_emit_keys(const gs_projected_t* proj, const gs_camera_t* cams, int32_t V, int64_t n,
                      const uint32_t* offsets, int32_t depth_shift, uint32_t zbits_min, uint64_t* keys, uint32_t* vals,
@@ -452,7 +483,7 @@ int32_t gs_sort_pairs(uint64_t* keys, uint32_t* vals, int64_t n, int32_t key_bit
   if (n < 0 || key_bits < 1 || key_bits > 64) { set_error("bad n / key_bits"); return GS_ERR_SHAPE; }
   if (n == 0) return GS_OK;
   if (!keys || !vals || !ws) { set_error("buffer NULL"); return GS_ERR_NULL; }
-  if (n >= (int64_t(1) << 32)) { set_error("n exceeds 32 bits"); return GS_ERR_CAPACITY; }
+  if (n >= kSortMaxPairs) { set_error("n of 2^30 or more (sort limit)"); return GS_ERR_CAPACITY; }
   if (ws_bytes < sort_ws_size(n)) { set_error("sort workspace too small"); return GS_ERR_CAPACITY; }
   hipStream_t s = (hipStream_t)stream;
   uint64_t* ks = nullptr;
@@ -494,35 +525,10 @@ int32_t gs_bin_sort(const gs_projected_t* proj, const gs_camera_t* cams, int32_t
   const int64_t ni = stats->n_isect;
   if (!ranges) { set_error("ranges NULL"); return GS_ERR_NULL; }
   if (!ws) { set_error("workspace NULL"); return GS_ERR_NULL; }
+  if (ni < 0 || ni >= kSortMaxPairs) { set_error("pair count of 2^30 or more (sort limit)"); return GS_ERR_CAPACITY; }
   if (ws_bytes < gs_bin_sort_workspace_size(ni)) { set_error("bin_sort workspace too small"); return GS_ERR_CAPACITY; }
-  if ((st = launch_fill(ranges, 0u, 2 * (int64_t)vs.tiles_total, s)) != GS_OK) return st;
-  uint32_t* order_hist = (uint32_t*)((char*)ws + gs_bin_sort_workspace_size(ni) - 256);
-  if (ni == 0) return tile_order ? launch_tile_order(ranges, vs.tiles_total, tile_order, order_hist, s) : GS_OK;
-  if (!vals || !offsets) { set_error("buffer NULL"); return GS_ERR_NULL; }
-  if (proj->tile_cull_log2_alpha < 0.f && !proj->rec) { set_error("tile culling needs proj->rec"); return GS_ERR_NULL; }
-  char* p = (char*)ws;
-  uint64_t* k0 = (uint64_t*)p; p += align256(ni * 8);
-  uint32_t* v0 = (uint32_t*)p; p += align256(ni * 4);
-  const int32_t shift = stats->depth_bits;
-  // record indices fit below the key when key_bits + bit length(V n - 1) <= 64
-  const int64_t nrec = (int64_t)V * n;
-  int32_t ibits = 1;
-  while (ibits < 63 && (int64_t(1) << ibits) < nrec) ++ibits;
-  if (stats->key_bits + ibits > 64) ibits = 0;
-  hipLaunchKernelGGL(k_emit, dim3(grid_1d(nrec)), dim3(kBlock), 0, s, reinterpret_cast<const int4*>(proj->bin),
-                     proj->rec, proj->tile_cull_log2_alpha, offsets, n, nrec, shift, stats->zbits_min, ibits, k0, v0,
-                     vs);
-  MS_CHECK_LAUNCH("emit");
-  uint64_t* ks = nullptr;
-  if ((st = onesweep_sort(k0, ibits > 0 ? nullptr : v0, ni, ibits, stats->key_bits, p, vals, &ks, s)) != GS_OK)
-    return st;
-  hipLaunchKernelGGL(k_ranges, dim3(grid_1d(ni)), dim3(kBlock), 0, s, ks, ni, shift, stats->zbits_min, ibits,
-                     (int64_t)vs.tiles_total, ranges, keys, vals);
-  MS_CHECK_LAUNCH("ranges");
-  if (tile_order) return launch_tile_order(ranges, vs.tiles_total, tile_order, order_hist, s);
-  return GS_OK;
+  return bin_sort_on_ws(proj, vs, V, n, offsets, stats, keys, vals, ranges, tile_order, ws, s);
 }
-
 size_t gs_tile_order_workspace_size(void) { return 256; }
 
 int32_t gs_tile_order(const uint32_t* ranges, int32_t tiles_total, uint32_t* tile_order, void* ws, size_t ws_bytes,

@@ -16,6 +16,26 @@ constexpr int kWave = 64;              // CDNA wavefront width
 constexpr int kBlock = 256;            // threads per workgroup: one 16x16 tile
 constexpr int kRecFloats = GS_REC_FLOATS;
 constexpr int kG2d = GS_GRAD2D_FLOATS;
+// Sort workspaces (gs_sort_pairs, gs_bin_sort) start with a header: word 0 is
+// the error flag of the last sort, bytes 256..511 the tile-order histogram.
+constexpr size_t kSortHeaderBytes = 512;
+constexpr int64_t kSortMaxPairs = int64_t(1) << 30;  // per-digit prefixes are 30-bit
+constexpr int kSortMaxPasses = 8;                    // 8-bit digits of a 64-bit key
+constexpr int64_t kSortMinTile = 4096;               // keys per tile of the value-carrying pass
+constexpr size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+// Bytes of a sort workspace for n pairs: header, 8 x 256 digit counts, per
+// (pass, tile) 256 status words, 8 tile counters, alternate keys and values.
+constexpr size_t sort_ws_bytes(int64_t n) {
+  const int64_t nn = n > 0 ? n : 1;
+  const int64_t nb = (nn + kSortMinTile - 1) / kSortMinTile;
+  return kSortHeaderBytes + align256(kSortMaxPasses * 256 * 4) + align256((size_t)kSortMaxPasses * nb * 256 * 4) +
+         align256(kSortMaxPasses * 4) + align256((size_t)nn * 8) + align256((size_t)nn * 4);
+}
+// gs_bin_sort: the sort workspace, then the emitted keys and values.
+constexpr size_t bin_sort_ws_bytes(int64_t n) {
+  const int64_t nn = n > 0 ? n : 1;
+  return sort_ws_bytes(n) + align256((size_t)nn * 8) + align256((size_t)nn * 4);
+}
 
 // Camera and layout of one view as kernels see it (passed by value inside
 // ViewSet, so it lives in the kernel-argument segment: no device allocation).
@@ -55,6 +75,11 @@ KOpts make_kopts(const gs_opts_t* o);
 int32_t check_scene(const gs_scene_t* s);
 int32_t check_records(int32_t V, int64_t n);  // V * n must fit 31 bits (record ids)
 int32_t launch_fill(void* dst, uint32_t value, int64_t count, hipStream_t st);  // 32-bit words
+// Emission, sort and ranges of gs_bin_sort on a workspace of
+// bin_sort_ws_bytes(stats->n_isect) bytes (checked by the caller).
+int32_t bin_sort_on_ws(const gs_projected_t* proj, const ViewSet& vs, int32_t V, int64_t n, const uint32_t* offsets,
+                       const gs_bin_stats_t* stats, uint64_t* keys, uint32_t* vals, uint32_t* ranges,
+                       uint32_t* tile_order, void* ws, hipStream_t s);
 inline int32_t grid_1d(int64_t n, int block = kBlock) { return (int32_t)((n + block - 1) / block); }
 
 // Blocks are handed to the 8 XCDs round-robin; give each XCD a contiguous

@@ -3,14 +3,20 @@
 // Sec. 5.1), and the reverse-order backward restricted to an active mask
 // (Sec. 5.2).
 //
-// Work mapping: one 256-thread workgroup per 16x16 tile, one wave per 8x8
-// quarter, one pixel per lane.  The tile's sorted list is walked in
-// wave-uniform order: the record index, its pixel box and its 48-byte record
-// are uniform across the wave, so they travel through the scalar cache, and a
-// wave skips (with one uniform branch) every Gaussian whose pixel box misses
-// its 8x8 quarter.  That box bounds exactly the pixels where
-// opacity * G2D >= alpha_min, so the skip never changes a result.  A wave stops
-// as soon as all its lanes have terminated.
+// Work mapping: a 256-thread workgroup per 16x16 tile (or per 8x8 quarter of
+// a heavy tile, see work_item), one wave per 8x8 quarter, and inside a wave
+// four 4x4 pixel groups, one per 16-lane row.  Per round the workgroup stages
+// up to 256 consecutive list entries (record index, pixel box and the 48 or
+// 64 bytes of the record the pass reads) in LDS with one gather per thread,
+// while the next round's records and the list indices of the round after are
+// already in flight.  Each lane then tests one staged entry against the
+// bounding rectangle of each group's still-active pixels (pixel box, then an
+// exact conservative ellipse-rectangle test), the ballots give every group its
+// own stream of entries that can reach it, and each group walks its stream in
+// list order reading records with broadcast LDS loads.  Culled entries never
+// reach alpha_min at those pixels, so culling never changes a result.  Groups
+// whose pixels have all stopped drop the rest of their stream, and a wave ends
+// when all its groups have.
 #include <cmath>
 
 #include "common.hpp"

@@ -14,10 +14,14 @@
 // one window of predecessors per round trip), so the tiles are large: 8192
 // keys instead of 4096 took a pass from 44 to 38 us at 3.3M keys.
 //
-// Every wait is bounded: a look-back that has not resolved after kSpinLimit
-// polls raises an error flag instead of spinning on, and every global store is
-// bounds-checked, so a broken invariant yields a detectable error, not a hang
-// or a stray write.
+// Every wait is bounded: a look-back that has not resolved after the spin
+// limit raises the error word in the workspace header instead of spinning on,
+// and every global store is bounds-checked, so a broken invariant leaves a
+// wrong order behind a raised flag (read by gs_sort_status), never a hang or a
+// stray write.  The per-digit prefixes in the status words hold 30 bits, so
+// the entry points reject 2^30 or more pairs.
+#include <atomic>
+
 #include "common.hpp"
 
 namespace msplat {
@@ -30,12 +34,12 @@ struct OsTile {
   static constexpr int keys = kBlock * items;
 };
 constexpr int kOsMinTile = OsTile<true>::keys;  // sizes the per-tile status words
+static_assert(kOsMinTile == kSortMinTile, "status words are sized for the smallest tile");
 constexpr int kHistItems = 16;                   // keys per thread of the histogram kernel
 constexpr int kOsRadix = 256;
 constexpr int kOsWaves = kBlock / kWave;
-constexpr int kMaxPasses = 8;
+constexpr int kMaxPasses = kSortMaxPasses;
 constexpr uint32_t kFlagAgg = 1u << 30, kFlagInc = 2u << 30, kValMask = (1u << 30) - 1u;
-constexpr uint32_t kSpinLimit = 1u << 22;
 constexpr int kLook = 8;
 
 __device__ __forceinline__ uint64_t os_match(uint32_t d) {
@@ -95,7 +99,8 @@ template <bool VALS>
 __global__ __launch_bounds__(kBlock) void k_os_pass(const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin,
                                                     uint64_t* __restrict__ kout, uint32_t* __restrict__ vout,
                                                     int64_t n, int32_t shift, const uint32_t* __restrict__ digit_base,
-                                                    uint32_t* status, uint32_t* counter, uint32_t* err) {
+                                                    uint32_t* status, uint32_t* counter, uint32_t* err,
+                                                    uint32_t spin_limit) {
   __shared__ uint32_t s_tile;
   __shared__ uint32_t cnt[kOsWaves][kOsRadix];
   __shared__ uint32_t s_glob[kOsRadix];
@@ -151,7 +156,13 @@ __global__ __launch_bounds__(kBlock) void k_os_pass(const uint64_t* __restrict__
     int64_t k = (int64_t)t - 1;
     uint32_t spins = 0;
     bool resolved = false;
+    // spin_limit == 0 makes every look-back give up at once (error-path tests)
+    bool give_up = spin_limit == 0u;
     while (!resolved) {
+      if (give_up) {
+        atomicOr(err, 1u);
+        break;
+      }
       uint32_t win[kLook];
 #pragma unroll
       for (int i = 0; i < kLook; ++i)
@@ -173,11 +184,8 @@ __global__ __launch_bounds__(kBlock) void k_os_pass(const uint64_t* __restrict__
       }
       if (!ready) {
         resolved = false;
-        if (++spins > kSpinLimit) {
-          atomicOr(err, 1u);
-          break;
-        }
-        __builtin_amdgcn_s_sleep(1);
+        give_up = ++spins > spin_limit;
+        if (!give_up) __builtin_amdgcn_s_sleep(1);
         continue;
       }
       excl += part;
@@ -228,15 +236,15 @@ __global__ __launch_bounds__(kBlock) void k_os_pass(const uint64_t* __restrict__
   }
 }
 
-size_t onesweep_ws_size(int64_t n, int32_t passes) {
-  const int64_t nn = n > 0 ? n : 1;
-  const int64_t nb = (nn + kOsMinTile - 1) / kOsMinTile;
-  auto a = [](size_t x) { return (x + 255) & ~size_t(255); };
-  return a(nn * 8) + a(nn * 4) + a(kMaxPasses * kOsRadix * 4) + a((size_t)kMaxPasses * nb * kOsRadix * 4) +
-         a(kMaxPasses * 4) + a(4);
-}
+// Workspace: a 512-byte header (word 0: error flag of the last sort; bytes
+// 256..511 free for the caller), the histograms, per-tile status words and
+// tile counters (cleared together with the flag by one fill), then the
+// alternate key and value buffers.
+size_t onesweep_ws_size(int64_t n, int32_t passes) { return sort_ws_bytes(n); }
 
 int32_t launch_fill(void* dst, uint32_t value, int64_t count, hipStream_t st);
+
+static std::atomic<uint32_t> g_spin_limit{1u << 22};
 
 // Sorts (k0, v0) on key bits [lo_bit, lo_bit + bits); the last pass writes
 // values to vfinal and keys to the buffer returned in *keys_sorted (k0 or the
@@ -249,29 +257,35 @@ int32_t onesweep_sort(uint64_t* k0, uint32_t* v0, int64_t n, int32_t lo_bit, int
     set_error("too many key bits");
     return GS_ERR_SHAPE;
   }
+  if (n >= kSortMaxPairs) {
+    set_error("radix sort: 2^30 or more pairs");
+    return GS_ERR_CAPACITY;
+  }
   const bool vals = v0 != nullptr;
   const int64_t nn = n > 0 ? n : 1;
   const int64_t tile = vals ? OsTile<true>::keys : OsTile<false>::keys;
   const int64_t nb = (nn + tile - 1) / tile;
+  const int64_t nb_min = (nn + kOsMinTile - 1) / kOsMinTile;
   auto a = [](size_t x) { return (x + 255) & ~size_t(255); };
   char* p = (char*)ws;
-  uint64_t* kalt = (uint64_t*)p; p += a(nn * 8);
-  uint32_t* valt = (uint32_t*)p; p += a(nn * 4);
+  uint32_t* err = (uint32_t*)p; p += kSortHeaderBytes;
   uint32_t* ghist = (uint32_t*)p; p += a(kMaxPasses * kOsRadix * 4);
-  uint32_t* status = (uint32_t*)p; p += a((size_t)kMaxPasses * nb * kOsRadix * 4);
+  uint32_t* status = (uint32_t*)p; p += a((size_t)kMaxPasses * nb_min * kOsRadix * 4);
   uint32_t* counters = (uint32_t*)p; p += a(kMaxPasses * 4);
-  uint32_t* err = (uint32_t*)p;
+  uint64_t* kalt = (uint64_t*)p; p += a(nn * 8);
+  uint32_t* valt = (uint32_t*)p;
+  // the flag, histograms, status words and counters in one fill
+  const int64_t zero_words = (int64_t)((char*)(counters + kMaxPasses) - (char*)err) / 4;
+  int32_t r = launch_fill(err, 0u, zero_words, st);
+  if (r != GS_OK) return r;
   if (n <= 1 || passes == 0) {
     if (vals && vfinal != v0 && n > 0) {
-      int32_t r = check_hip(hipMemcpyAsync(vfinal, v0, n * 4, hipMemcpyDeviceToDevice, st), "sort copy");
+      r = check_hip(hipMemcpyAsync(vfinal, v0, n * 4, hipMemcpyDeviceToDevice, st), "sort copy");
       if (r != GS_OK) return r;
     }
     return GS_OK;
   }
-  // zero histograms, status words, counters and the error flag in one fill
-  const int64_t zero_words = (int64_t)((char*)err + 4 - (char*)ghist) / 4;
-  int32_t r = launch_fill(ghist, 0u, zero_words, st);
-  if (r != GS_OK) return r;
+  const uint32_t spin_limit = g_spin_limit.load();
   const int64_t hb = (nn + kBlock * kHistItems - 1) / (kBlock * kHistItems);
   hipLaunchKernelGGL(k_os_hist, dim3((unsigned)hb), dim3(kBlock), 0, st, k0, n, passes, lo_bit, ghist);
   hipLaunchKernelGGL(k_os_scan, dim3(1), dim3(kBlock), 0, st, ghist, passes);
@@ -287,11 +301,11 @@ int32_t onesweep_sort(uint64_t* k0, uint32_t* v0, int64_t n, int32_t lo_bit, int
       if (vout == vin) vout = (vin == v0) ? valt : v0;
       hipLaunchKernelGGL(k_os_pass<true>, dim3((unsigned)nb), dim3(kBlock), 0, st, kin, vin, kout, vout, n,
                          lo_bit + 8 * ps, ghist + ps * kOsRadix, status + (size_t)ps * nb * kOsRadix, counters + ps,
-                         err);
+                         err, spin_limit);
     } else {
       hipLaunchKernelGGL(k_os_pass<false>, dim3((unsigned)nb), dim3(kBlock), 0, st, kin, nullptr, kout, nullptr, n,
                          lo_bit + 8 * ps, ghist + ps * kOsRadix, status + (size_t)ps * nb * kOsRadix, counters + ps,
-                         err);
+                         err, spin_limit);
     }
     MS_CHECK_LAUNCH("sort pass");
     kin = kout;
@@ -306,3 +320,26 @@ int32_t onesweep_sort(uint64_t* k0, uint32_t* v0, int64_t n, int32_t lo_bit, int
 }
 
 }  // namespace msplat
+
+using namespace msplat;
+
+extern "C" {
+
+int32_t gs_sort_status(const void* ws, void* stream) {
+  int32_t st;
+  if (!ws) { set_error("workspace NULL"); return GS_ERR_NULL; }
+  hipStream_t s = (hipStream_t)stream;
+  uint32_t flag = 0;
+  st = check_hip(hipMemcpyAsync(&flag, ws, sizeof(flag), hipMemcpyDeviceToHost, s), "sort status copy");
+  if (st != GS_OK) return st;
+  if ((st = check_hip(hipStreamSynchronize(s), "sort status sync")) != GS_OK) return st;
+  if (flag != 0u) {
+    set_error("radix sort: a look-back did not resolve within its spin limit; the sorted order is invalid");
+    return GS_ERR_DEVICE;
+  }
+  return GS_OK;
+}
+
+void gs_sort_set_spin_limit(uint32_t polls) { g_spin_limit.store(polls); }
+
+}  // extern "C"

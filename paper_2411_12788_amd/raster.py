@@ -203,16 +203,29 @@ def bin_sort(proj: Projected, cams, n: int, offsets: torch.Tensor, st: L.BinStat
                   order[:tiles])
 
 
-def bin(proj: Projected, cams, n: int, want_keys: bool = False, stream=None) -> Binned:
+def sort_status(ws: torch.Tensor, stream=None) -> None:
+    """Raises if the last sort on workspace `ws` raised its error flag (synchronises)."""
+    L.check(L.lib().gs_sort_status(_ptr(ws), _stream(stream)), "gs_sort_status")
+
+
+def bin(proj: Projected, cams, n: int, want_keys: bool = False, stream=None, check: bool = True) -> Binned:
+    """Pair count, key emission, sort and ranges; with `check` the sort's
+    status flag is read back (one synchronisation)."""
     offsets, st = bin_count(proj, cams, n, stream)
-    return bin_sort(proj, cams, n, offsets, st, want_keys, stream)
+    buffers = BinBuffers()
+    out = bin_sort(proj, cams, n, offsets, st, want_keys, stream, buffers)
+    if check:
+        sort_status(buffers.ws, stream)
+    return out
 
 
-def sort_pairs(keys: torch.Tensor, vals: torch.Tensor, key_bits: int, stream=None) -> None:
+def sort_pairs(keys: torch.Tensor, vals: torch.Tensor, key_bits: int, stream=None, check: bool = True) -> None:
     n = keys.numel()
     ws = torch.empty(max(L.lib().gs_sort_workspace_size(n), 1), device=keys.device, dtype=torch.uint8)
     L.check(L.lib().gs_sort_pairs(_ptr(keys), _ptr(vals), n, key_bits, _ptr(ws), ws.numel(), _stream(stream)),
             "gs_sort_pairs")
+    if check and n > 0:
+        sort_status(ws, stream)
 
 
 @dataclasses.dataclass

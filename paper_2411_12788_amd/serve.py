@@ -63,6 +63,7 @@ class Server:
         self.peak_reserved = 0
         self.in_flight = 0
         self.growing = 0
+        self.slot_extra: Dict[int, int] = {}  # second-phase adjustment of each running batch
         self.completed: List[Result] = []
         self.admitted_batches: List[int] = []
         self.running = True
@@ -101,8 +102,10 @@ class Server:
             t.join(timeout=30)
 
     # -- reservations --------------------------------------------------------
-    def grow(self, delta: int, timeout: float = 60.0) -> None:
-        """Second admission phase: adjust a running batch's reservation.
+    def grow(self, delta: int, slot: int, timeout: float = 60.0) -> None:
+        """Second admission phase: adjust the reservation of the batch running
+        on `slot`.  The adjustment is recorded per slot and released with the
+        batch, whether or not the batch then completes.
 
         A batch that needs more memory waits while some other in-flight batch
         is still running (it will release memory); when every in-flight batch
@@ -121,6 +124,7 @@ class Server:
                 finally:
                     self.growing -= 1
             self.reserved += delta
+            self.slot_extra[slot] = self.slot_extra.get(slot, 0) + delta
             self.peak_reserved = max(self.peak_reserved, self.reserved)
             self.cv.notify_all()
 
@@ -171,7 +175,7 @@ class Server:
 
     def _work(self, batch: List[Request], slot: int, reserved: int) -> None:
         try:
-            outs, extra = self.ex.run(batch, slot, self)
+            outs = self.ex.run(batch, slot, self)
             done = self.clock()
             results = []
             for r, (color, depth) in zip(batch, outs):
@@ -179,9 +183,9 @@ class Server:
                 results.append(res)
             err = None
         except BaseException as e:  # noqa: BLE001 - propagate to the futures
-            extra, err, results = 0, e, []
+            err, results = e, []
         with self.cv:
-            self.reserved -= reserved + extra
+            self.reserved -= reserved + self.slot_extra.pop(slot, 0)
             self.in_flight -= 1
             self.free_slots.append(slot)
             self.completed.extend(results)
@@ -251,15 +255,13 @@ class GpuExecutor:
         scene = self.scenes[sid]
         cams = [r.camera for r in batch]
         st = self.streams[slot]
-        extra = 0
         with torch.cuda.stream(st):
             proj = R.project(scene, cams, self.opts, stream=st)
             offsets, stats = R.bin_count(proj, cams, scene.n, stream=st)
             real = self._bytes(scene.n, len(cams), sum(c.width * c.height for c in cams), int(stats.n_isect))
             est = self.footprint(batch)
             if real != est:
-                server.grow(real - est)
-                extra = real - est
+                server.grow(real - est, slot)
             with self.lock:
                 ppr = stats.n_isect / max(1, len(cams) * scene.n)
                 old = self.pairs_per_record.get(sid)
@@ -276,19 +278,20 @@ class GpuExecutor:
             outs.append((frame.color[:, off:off + m].view(3, int(c.height), int(c.width)),
                          frame.depth[off:off + m].view(int(c.height), int(c.width))))
             off += m
-        return outs, extra
+        return outs
 
 
 class FakeExecutor:
     """CPU stand-in with simulated durations and footprints (scheduler tests)."""
 
     def __init__(self, sizes: Dict[Any, int], per_view_s: float = 0.002, per_batch_s: float = 0.003,
-                 bytes_per_gaussian: int = 100, realised_factor: float = 1.0):
+                 bytes_per_gaussian: int = 100, realised_factor: float = 1.0, fail_after_grow: bool = False):
         self.sizes = sizes
         self.per_view_s = per_view_s
         self.per_batch_s = per_batch_s
         self.bpg = bytes_per_gaussian
         self.realised = realised_factor
+        self.fail_after_grow = fail_after_grow
         self.max_concurrency = 0
         self.active = 0
         self.lock = threading.Lock()
@@ -302,14 +305,16 @@ class FakeExecutor:
             self.active += 1
             self.max_concurrency = max(self.max_concurrency, self.active)
             self.batches.append([r.seq for r in batch])
-        extra = 0
-        if self.realised != 1.0:
-            extra = int(self.footprint(batch) * (self.realised - 1.0))
-            server.grow(extra)
-        time.sleep(self.per_batch_s + self.per_view_s * len(batch))
-        with self.lock:
-            self.active -= 1
-        return [((r.scene_id, r.camera), None) for r in batch], extra
+        try:
+            if self.realised != 1.0:
+                server.grow(int(self.footprint(batch) * (self.realised - 1.0)), slot)
+                if self.fail_after_grow:
+                    raise RuntimeError("simulated failure after the reservation grew")
+            time.sleep(self.per_batch_s + self.per_view_s * len(batch))
+        finally:
+            with self.lock:
+                self.active -= 1
+        return [((r.scene_id, r.camera), None) for r in batch]
 
 
 def poisson_arrivals(qps: float, count: int, seed: int) -> List[float]:

@@ -77,6 +77,18 @@ def test_argument_errors_on_host(L):
     assert lib.gs_sort_pairs(None, None, 10, 0, None, 0, None) == L.GS_ERR_SHAPE
     assert lib.gs_sort_pairs(None, None, 0, 8, None, 0, None) == L.GS_OK
     assert lib.gs_fill_u32(None, 0, 0, None) == L.GS_OK
+    # the sort's 30-bit per-digit prefixes: 2^30 pairs or more are refused before any launch
+    fake = ctypes.c_void_p(0x1000)
+    big = 1 << 30
+    assert lib.gs_sort_pairs(fake, fake, big, 40, fake, lib.gs_sort_workspace_size(big), None) == L.GS_ERR_CAPACITY
+    assert b"2^30" in lib.gs_last_error()
+    cams[0].width = 64
+    st = L.BinStats()
+    st.n_isect, st.tiles_total = big, 4
+    proj = L.Projected(fake, fake, 0.0)
+    assert lib.gs_bin_sort(ctypes.byref(proj), cams, 1, 10, fake, ctypes.byref(st), fake, fake, fake, None, fake,
+                           lib.gs_bin_sort_workspace_size(big), None) == L.GS_ERR_CAPACITY
+    assert lib.gs_sort_status(None, None) == L.GS_ERR_NULL
     assert lib.gs_bin_count_workspace_size(10 ** 6) > 0 and lib.gs_bin_sort_workspace_size(10 ** 6) > 12 * 10 ** 6
 
 

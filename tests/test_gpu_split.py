@@ -1,5 +1,5 @@
 """GPU parity of the 3DGS density control (Sec. 3.2) and of the split into two
-children that the blur split (Sec. 3.3, Eq. (3)) applies, against the oracle on
+children that the blur split (Sec. 4.1, Eq. (3)) applies, against the oracle on
 seeded inputs: selection masks bit for bit; copied attributes bit for bit;
 children's scales and centres (double arithmetic rounded once to float32)
 within one float32 ulp of the oracle's double result."""

@@ -1,6 +1,6 @@
 """Pins of the oracle's 3DGS density control: the clone/split selection and the
 split into two children drawn from the parent (Sec. 3.2; the blur split of
-Sec. 3.3 hands its Gaussians to the same split).  Rotation conventions are
+Sec. 4.1 hands its Gaussians to the same split).  Rotation conventions are
 pinned against scipy's quaternion rotation and closed-form rotations, the
 children's spread against the parent covariance by Monte Carlo."""
 import math

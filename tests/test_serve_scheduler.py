@@ -89,6 +89,20 @@ def test_two_phase_growth_does_not_deadlock():
     assert srv.reserved == 0
 
 
+def test_failed_batch_releases_its_grown_reservation():
+    """A batch whose reservation grew and that then fails releases both parts:
+    admission does not drift after failures."""
+    ex = FakeExecutor(SIZES, per_view_s=0.001, per_batch_s=0.001, realised_factor=1.5, fail_after_grow=True)
+    srv = Server(ex, hbm_budget=10 ** 9, slots=2, max_batch=2)
+    futs = [srv.submit(sid, cam) for sid, cam in _reqs(12, 6)]
+    for f in futs:
+        with pytest.raises(RuntimeError):
+            f.result(timeout=10)
+    srv.drain(timeout=10)
+    srv.close()
+    assert srv.reserved == 0 and srv.slot_extra == {}
+
+
 def test_poisson_arrivals_are_seeded():
     a = poisson_arrivals(100.0, 50, 7)
     b = poisson_arrivals(100.0, 50, 7)
