@@ -183,14 +183,23 @@ def order(proj: np.ndarray) -> np.ndarray:
     return out[:m]
 
 
+def _amb(amb) -> Optional[np.ndarray]:
+    return None if amb is None else _d(amb).reshape(3)
+
+
 def render(params: Params, cam, proj: np.ndarray, ordr: np.ndarray, opts: Opts,
-           pixels: Optional[np.ndarray] = None, tiles=None, accumulate: bool = True) -> Dict[str, np.ndarray]:
+           pixels: Optional[np.ndarray] = None, tiles=None, accumulate: bool = True,
+           amb=None, flips: Optional[np.ndarray] = None) -> Dict[str, np.ndarray]:
     """Eq. (1) compositing with Eq. (2) argmax depth and the per-Gaussian sums.
 
     ``pixels``: optional int32 [m, 2] (x, y) list; default every pixel, row-major.
     ``tiles``: optional (vals, ranges) from :func:`bin` to restrict each pixel to
     its tile's list.  ``margin`` columns: alpha vs skip threshold, transmittance
-    vs stop threshold, top-two weight gap, opacity*G vs clamp (all relative).
+    vs stop threshold, top-two weight gap, opacity*G vs clamp, and the relative
+    ray/ellipsoid discriminant of the hit flag (all relative).
+    ``amb`` (alpha, stop, argmax widths) and ``flips`` (uint32 per pixel) invert
+    the decisions that lie within those widths of their thresholds (bit k of
+    ``flips`` for the k-th such decision met); ``namb`` returns how many were met.
     """
     n = params.n
     W, H = int(cam.width), int(cam.height)
@@ -198,7 +207,7 @@ def render(params: Params, cam, proj: np.ndarray, ordr: np.ndarray, opts: Opts,
     npx = W * H if pix is None else pix.shape[0]
     out = dict(color=np.zeros((npx, 3)), depth=np.zeros(npx), imax=np.zeros(npx, dtype=np.int64),
                t_final=np.zeros(npx), n_contrib=np.zeros(npx, dtype=np.int32),
-               hit=np.zeros(npx, dtype=np.uint8), margin=np.zeros((npx, 4)))
+               hit=np.zeros(npx, dtype=np.uint8), margin=np.zeros((npx, 5)), namb=np.zeros(npx, dtype=np.int32))
     if accumulate:
         out.update(importance=np.zeros(max(n, 1)), wmax=np.zeros(max(n, 1)),
                    area=np.zeros(max(n, 1), dtype=np.int64))
@@ -206,13 +215,16 @@ def render(params: Params, cam, proj: np.ndarray, ordr: np.ndarray, opts: Opts,
     if tiles is not None:
         tv = np.ascontiguousarray(tiles[0], dtype=np.uint32)
         tr = np.ascontiguousarray(tiles[1], dtype=np.uint32)
+    a = _amb(amb)
+    fl = None if flips is None else np.ascontiguousarray(flips, dtype=np.uint32).reshape(npx)
     c, o = ocam(cam), opts.c()
     ordr = np.ascontiguousarray(ordr, dtype=np.int64)
-    rc = lib().orc_render(
+    rc = lib().orc_render_ex(
         ctypes.c_int64(n), _p(np.ascontiguousarray(proj)), _p(ordr), ctypes.c_int64(len(ordr)),
         _p(params.means), _p(params.scales), _p(params.quats), ctypes.byref(c), ctypes.byref(o),
         ctypes.c_int64(npx), None if pix is None else _p(pix), None if tv is None else _p(tv),
-        None if tr is None else _p(tr), _p(out["color"]), _p(out["depth"]), _p(out["imax"]),
+        None if tr is None else _p(tr), None if a is None else _p(a), None if fl is None else _p(fl),
+        _p(out["namb"]), _p(out["color"]), _p(out["depth"]), _p(out["imax"]),
         _p(out["t_final"]), _p(out["n_contrib"]), _p(out["hit"]), _p(out["margin"]),
         _p(out["importance"]) if accumulate else None, _p(out["wmax"]) if accumulate else None,
         _p(out["area"]) if accumulate else None)
@@ -223,21 +235,78 @@ def render(params: Params, cam, proj: np.ndarray, ordr: np.ndarray, opts: Opts,
     return out
 
 
+def branches(params: Params, cam, proj: np.ndarray, ordr: np.ndarray, opts: Opts, pixels: np.ndarray,
+             amb, max_branches: int = 64, tiles=None) -> Dict[str, np.ndarray]:
+    """Every outcome of Eq. (1)-(2) at the given pixels when each decision that
+    lies within ``amb`` of its threshold may go either way (test support for a
+    float32 renderer).  Flip masks are enumerated in increasing order; a mask is
+    a distinct branch when it sets no bit beyond the ambiguous decisions its own
+    path meets, and the masks below 2^(most decisions met on any branch) cover
+    every branch.  Returns per pixel ``count`` and, for branch j < count, the
+    arrays ``flips``, ``color``, ``t_final``, ``n_contrib``, ``imax``, ``depth``,
+    ``hit`` and ``margin`` with a leading [m, max_branches] shape; ``complete``
+    is False for a pixel with more than max_branches branches.  ``tiles`` as in
+    :func:`render`."""
+    pix = np.ascontiguousarray(pixels, dtype=np.int32).reshape(-1, 2)
+    m, B = pix.shape[0], int(max_branches)
+    res = dict(count=np.zeros(m, dtype=np.int64), complete=np.ones(m, dtype=bool),
+               flips=np.zeros((m, B), dtype=np.uint32), color=np.zeros((m, B, 3)), t_final=np.zeros((m, B)),
+               n_contrib=np.zeros((m, B), dtype=np.int32), imax=np.zeros((m, B), dtype=np.int64),
+               depth=np.zeros((m, B)), hit=np.zeros((m, B), dtype=np.uint8), margin=np.zeros((m, B, 5)))
+    need = np.ones(m, dtype=np.int64)  # 2^(most ambiguous decisions met so far), per pixel
+    mask = 0
+    while True:
+        todo = np.nonzero(mask < need)[0]
+        if todo.size == 0:
+            break
+        r = render(params, cam, proj, ordr, opts, pixels=pix[todo], tiles=tiles, accumulate=False, amb=amb,
+                   flips=np.full(todo.size, mask, dtype=np.uint32))
+        d = r["namb"].astype(np.int64)
+        valid = (mask >> np.minimum(d, 62)) == 0
+        need[todo] = np.maximum(need[todo], np.left_shift(1, np.minimum(d, 62)))
+        for j in np.nonzero(valid)[0]:
+            p = todo[j]
+            c = res["count"][p]
+            if c >= B:
+                res["complete"][p] = False
+                continue
+            res["flips"][p, c] = mask
+            for k in ("color", "t_final", "n_contrib", "imax", "depth", "hit", "margin"):
+                res[k][p, c] = r[k][j]
+            res["count"][p] = c + 1
+        mask += 1
+        if mask >= (1 << 20):
+            res["complete"][todo] = False
+            break
+    return res
+
+
 def render_backward(params: Params, cam, proj: np.ndarray, ordr: np.ndarray, opts: Opts,
-                    dldc: np.ndarray, pixels: Optional[np.ndarray] = None) -> np.ndarray:
+                    dldc: np.ndarray, pixels: Optional[np.ndarray] = None, amb=None,
+                    flips: Optional[np.ndarray] = None, tiles=None) -> np.ndarray:
     """Gradient of sum(dldc * C) w.r.t. each record's (u, v, a, b, c, opacity, r, g, b).
 
-    ``dldc`` is [m, 3] for the pixel list (or [H*W, 3] row-major)."""
+    ``dldc`` is [m, 3] for the pixel list (or [H*W, 3] row-major).  ``amb`` and
+    ``flips`` select a decision branch per pixel, and ``tiles`` restricts each
+    pixel to its tile's list, as in :func:`render`."""
     n = params.n
     pix = None if pixels is None else np.ascontiguousarray(pixels, dtype=np.int32)
     npx = int(cam.width) * int(cam.height) if pix is None else pix.shape[0]
     g = _d(dldc).reshape(npx, 3)
     g2d = np.zeros((max(n, 1), 9))
+    a = _amb(amb)
+    fl = None if flips is None else np.ascontiguousarray(flips, dtype=np.uint32).reshape(npx)
+    tv = tr = None
+    if tiles is not None:
+        tv = np.ascontiguousarray(tiles[0], dtype=np.uint32)
+        tr = np.ascontiguousarray(tiles[1], dtype=np.uint32)
     c, o = ocam(cam), opts.c()
     ordr = np.ascontiguousarray(ordr, dtype=np.int64)
-    rc = lib().orc_render_backward(ctypes.c_int64(n), _p(np.ascontiguousarray(proj)), _p(ordr),
-                                   ctypes.c_int64(len(ordr)), ctypes.byref(c), ctypes.byref(o),
-                                   ctypes.c_int64(npx), None if pix is None else _p(pix), _p(g), _p(g2d))
+    rc = lib().orc_render_backward_ex(ctypes.c_int64(n), _p(np.ascontiguousarray(proj)), _p(ordr),
+                                      ctypes.c_int64(len(ordr)), ctypes.byref(c), ctypes.byref(o),
+                                      ctypes.c_int64(npx), None if pix is None else _p(pix),
+                                      None if tv is None else _p(tv), None if tr is None else _p(tr),
+                                      None if a is None else _p(a), None if fl is None else _p(fl), _p(g), _p(g2d))
     assert rc == 0
     return g2d[:n]
 

@@ -337,14 +337,39 @@ typedef struct {
   int clamped;
 } ostep_t;
 
+/* Decision flips (test support for comparing a float32 renderer).  Eq. (1)
+ * takes three discrete decisions per evaluated pair: skip (alpha below
+ * alpha_min), stop (transmittance would fall below t_min) and, for Eq. (2),
+ * whether the pair's weight beats the best one so far.  A renderer working in
+ * float32 may legitimately take the other branch of a decision whose operands
+ * lie within its rounding error of the threshold.  With `amb` = relative
+ * widths (alpha, stop, argmax), every decision closer than that to its
+ * threshold is "ambiguous"; the k-th ambiguous decision met along the pixel's
+ * path is inverted when bit k of `flips` is set.  *namb receives the number of
+ * ambiguous decisions met, so a caller can enumerate every consistent branch.
+ * With amb == NULL the plain definition is evaluated. */
+typedef struct {
+  const double* amb; /* [3] or NULL */
+  uint32_t flips;
+  int namb;
+} oflip_t;
+
+static int take_decision(oflip_t* f, int decision, double margin, int which) {
+  if (!f || !f->amb || !(margin < f->amb[which])) return decision;
+  int bit = f->namb < 32 ? (int)((f->flips >> f->namb) & 1u) : 0;
+  f->namb++;
+  return bit ? !decision : decision;
+}
+
 /* Composite one pixel over `list` (record indices, depth order).  Fills the
  * included steps into `steps` (capacity cap) and returns their count, or
- * -1 when cap is too small. */
+ * -1 when cap is too small.  *best receives the step index of the largest
+ * weight (first wins ties, Eq. (2)), -1 when nothing is included. */
 static int64_t composite_pixel(const double* proj, const int64_t* list, int64_t nl, double xc, double yc,
                                const oopts_t* opt, ostep_t* steps, int64_t cap, double* T_out,
-                               double* m_alpha, double* m_stop, double* m_clamp) {
-  double T = 1.0;
-  int64_t ns = 0;
+                               double* m_alpha, double* m_stop, double* m_clamp, oflip_t* fl, int64_t* best) {
+  double T = 1.0, wbest = 0.0;
+  int64_t ns = 0, kb = -1;
   double ma = INFINITY, mt = INFINITY, mc = INFINITY;
   for (int64_t k = 0; k < nl; k++) {
     const double* P = proj + list[k] * OP_STRIDE;
@@ -356,11 +381,11 @@ static int64_t composite_pixel(const double* proj, const int64_t* list, int64_t 
     double alpha = oG < opt->alpha_max ? oG : opt->alpha_max;
     double m1 = fabs(alpha - opt->alpha_min) / opt->alpha_min;
     if (m1 < ma) ma = m1;
-    if (alpha < opt->alpha_min) continue;
+    if (take_decision(fl, alpha < opt->alpha_min, m1, 0)) continue;
     double Tn = T * (1 - alpha);
     double m2 = fabs(Tn - opt->t_min) / opt->t_min;
     if (m2 < mt) mt = m2;
-    if (Tn < opt->t_min) break;
+    if (take_decision(fl, Tn < opt->t_min, m2, 1)) break;
     double m3 = fabs(oG - opt->alpha_max) / opt->alpha_max;
     if (m3 < mc) mc = m3;
     if (ns >= cap) return -1;
@@ -371,6 +396,9 @@ static int64_t composite_pixel(const double* proj, const int64_t* list, int64_t 
     steps[ns].dx = dx;
     steps[ns].dy = dy;
     steps[ns].clamped = oG >= opt->alpha_max;
+    double w = alpha * T;
+    double gap = kb >= 0 ? fabs(w - wbest) / (w > wbest ? w : wbest) : INFINITY;
+    if (take_decision(fl, w > wbest, gap, 2)) { wbest = w; kb = ns; }
     ns++;
     T = Tn;
   }
@@ -378,6 +406,7 @@ static int64_t composite_pixel(const double* proj, const int64_t* list, int64_t 
   *m_alpha = ma;
   *m_stop = mt;
   *m_clamp = mc;
+  *best = kb;
   return ns;
 }
 
@@ -387,7 +416,7 @@ static int64_t composite_pixel(const double* proj, const int64_t* list, int64_t 
  * and the discriminant tells whether the ray meets the ellipsoid.  d has unit
  * camera-z, so t* is a camera depth. */
 static void mid_depth(const ocam_t* cam, const double* means, const double* scales, const double* quats,
-                      int64_t n, int64_t g, double xc, double yc, double* tstar, int* hit) {
+                      int64_t n, int64_t g, double xc, double yc, double* tstar, int* hit, double* hit_margin) {
   double campos[3];
   camera_centre(cam, campos);
   double dc[3] = {(xc - cam->cx) / cam->fx, (yc - cam->cy) / cam->fy, 1.0};
@@ -410,7 +439,10 @@ static void mid_depth(const ocam_t* cam, const double* means, const double* scal
   double dd = d2[0] * d2[0] + d2[1] * d2[1] + d2[2] * d2[2];
   double oo = o2[0] * o2[0] + o2[1] * o2[1] + o2[2] * o2[2];
   *tstar = -od / dd;
-  *hit = (od * od - dd * (oo - 1.0)) >= 0;
+  double disc = od * od - dd * (oo - 1.0);
+  *hit = disc >= 0;
+  /* relative size of the discriminant: how close the ray is to tangency */
+  if (hit_margin) *hit_margin = fabs(disc) / (od * od + dd * fabs(oo - 1.0) + 1e-300);
 }
 
 /* Render pixels of one view.  `order` holds the valid records in depth order
@@ -419,16 +451,21 @@ static void mid_depth(const ocam_t* cam, const double* means, const double* scal
  * pixel composites only the list of its tile (tile-restricted mode) instead of
  * all records.  Outputs per pixel: colour [3], depth, imax (-1 when nothing is
  * drawn), final transmittance, count of included Gaussians, ray/ellipsoid hit,
- * margins [4]: relative distance of the nearest evaluated alpha to the skip
+ * margins [5]: relative distance of the nearest evaluated alpha to the skip
  * threshold, of the nearest transmittance to the stop threshold, the relative
- * gap between the two largest weights, and the nearest opacity*G to the clamp.  Accumulators (may be NULL)
- * are added to, over the given pixels: importance (sum of w), max w, and area
- * (count of pixels whose imax is the record). */
-int orc_render(int64_t n, const double* proj, const int64_t* order, int64_t n_order, const double* means,
-               const double* scales, const double* quats, const ocam_t* cam, const oopts_t* opt,
-               int64_t n_pix, const int32_t* pix, const uint32_t* tile_vals, const uint32_t* tile_ranges,
-               double* color, double* depth, int64_t* imax, double* t_final, int32_t* n_contrib, uint8_t* hit,
-               double* margin, double* imp, double* wmax, int64_t* area) {
+ * gap between the two largest weights, the nearest opacity*G to the clamp,
+ * and the relative size of imax's ray/ellipsoid discriminant.  Accumulators
+ * (may be NULL) are added to, over the given pixels: importance (sum of w),
+ * max w, and area (count of pixels whose imax is the record).
+ * orc_render_ex also takes decision flips (see oflip_t): amb [3] or NULL,
+ * flips [n_pix] or NULL, and returns the count of ambiguous decisions met per
+ * pixel in namb [n_pix] (may be NULL). */
+int orc_render_ex(int64_t n, const double* proj, const int64_t* order, int64_t n_order, const double* means,
+                  const double* scales, const double* quats, const ocam_t* cam, const oopts_t* opt,
+                  int64_t n_pix, const int32_t* pix, const uint32_t* tile_vals, const uint32_t* tile_ranges,
+                  const double* amb, const uint32_t* flips, int32_t* namb,
+                  double* color, double* depth, int64_t* imax, double* t_final, int32_t* n_contrib, uint8_t* hit,
+                  double* margin, double* imp, double* wmax, int64_t* area) {
   int64_t W = cam->width, H = cam->height;
   int64_t np = pix ? n_pix : W * H;
   int64_t cap = n_order > 0 ? n_order : 1;
@@ -449,17 +486,21 @@ int orc_render(int64_t n, const double* proj, const int64_t* order, int64_t n_or
       list = tl;
     }
     double T, ma, mt, mc;
-    int64_t ns = composite_pixel(proj, list, nl, xc, yc, opt, steps, cap, &T, &ma, &mt, &mc);
+    int64_t kb;
+    oflip_t fl = {amb, flips ? flips[p] : 0u, 0};
+    int64_t ns = composite_pixel(proj, list, nl, xc, yc, opt, steps, cap, &T, &ma, &mt, &mc, &fl, &kb);
     if (ns < 0) { free(steps); if (tl) free(tl); return -1; }
+    if (namb) namb[p] = fl.namb;
     double C[3] = {0, 0, 0};
     double wbest = 0, wsecond = 0, dblend = 0;
-    int64_t best = -1;
+    int64_t best = kb >= 0 ? steps[kb].g : -1;
     for (int64_t k = 0; k < ns; k++) {
       const double* P = proj + steps[k].g * OP_STRIDE;
       double w = steps[k].alpha * steps[k].T;
       for (int ch = 0; ch < 3; ch++) C[ch] += w * P[OP_R + ch];
       dblend += w * P[OP_Z];
-      if (w > wbest) { wsecond = wbest; wbest = w; best = steps[k].g; }
+      /* top two weights for the margin */
+      if (w > wbest) { wsecond = wbest; wbest = w; }
       else if (w > wsecond) wsecond = w;
       if (imp) imp[steps[k].g] += w;
       if (wmax && w > wmax[steps[k].g]) wmax[steps[k].g] = w;
@@ -470,25 +511,36 @@ int orc_render(int64_t n, const double* proj, const int64_t* order, int64_t n_or
     if (n_contrib) n_contrib[p] = (int32_t)ns;
     if (imax) imax[p] = best;
     if (area && best >= 0) area[best] += 1;
-    double dep = 0;
+    double dep = 0, tmid = 0, hm = INFINITY;
     int h = 0;
     if (best >= 0) {
-      if (opt->depth_mode == 0) mid_depth(cam, means, scales, quats, n, best, xc, yc, &dep, &h);
-      else if (opt->depth_mode == 1) { dep = proj[best * OP_STRIDE + OP_Z]; mid_depth(cam, means, scales, quats, n, best, xc, yc, &(double){0}, &h); }
-      else { dep = dblend; mid_depth(cam, means, scales, quats, n, best, xc, yc, &(double){0}, &h); }
+      mid_depth(cam, means, scales, quats, n, best, xc, yc, &tmid, &h, &hm);
+      if (opt->depth_mode == 0) dep = tmid;
+      else if (opt->depth_mode == 1) dep = proj[best * OP_STRIDE + OP_Z];
+      else dep = dblend;
     }
     if (depth) depth[p] = dep;
     if (hit) hit[p] = (uint8_t)h;
     if (margin) {
-      margin[4 * p + 0] = ma;
-      margin[4 * p + 1] = mt;
-      margin[4 * p + 2] = ns >= 2 ? (wbest - wsecond) / wbest : 1.0;
-      margin[4 * p + 3] = mc;
+      margin[5 * p + 0] = ma;
+      margin[5 * p + 1] = mt;
+      margin[5 * p + 2] = ns >= 2 ? (wbest - wsecond) / wbest : 1.0;
+      margin[5 * p + 3] = mc;
+      margin[5 * p + 4] = hm;
     }
   }
   free(steps);
   if (tl) free(tl);
   return 0;
+}
+
+int orc_render(int64_t n, const double* proj, const int64_t* order, int64_t n_order, const double* means,
+               const double* scales, const double* quats, const ocam_t* cam, const oopts_t* opt,
+               int64_t n_pix, const int32_t* pix, const uint32_t* tile_vals, const uint32_t* tile_ranges,
+               double* color, double* depth, int64_t* imax, double* t_final, int32_t* n_contrib, uint8_t* hit,
+               double* margin, double* imp, double* wmax, int64_t* area) {
+  return orc_render_ex(n, proj, order, n_order, means, scales, quats, cam, opt, n_pix, pix, tile_vals, tile_ranges,
+                       NULL, NULL, NULL, color, depth, imax, t_final, n_contrib, hit, margin, imp, wmax, area);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -501,21 +553,35 @@ int orc_render(int64_t n, const double* proj, const int64_t* order, int64_t n_or
  * conic.  Derivation: C = sum_k T_k a_k c_k + T_final bg with
  * T_k = prod_{j<k}(1 - a_j), so dC/da_k = T_k c_k - S_k / (1 - a_k) where S_k is
  * everything composited behind k (including the background term). */
-int orc_render_backward(int64_t n, const double* proj, const int64_t* order, int64_t n_order,
-                        const ocam_t* cam, const oopts_t* opt, int64_t n_pix, const int32_t* pix,
-                        const double* dldc, double* g2d) {
+int orc_render_backward_ex(int64_t n, const double* proj, const int64_t* order, int64_t n_order,
+                           const ocam_t* cam, const oopts_t* opt, int64_t n_pix, const int32_t* pix,
+                           const uint32_t* tile_vals, const uint32_t* tile_ranges,
+                           const double* amb, const uint32_t* flips, const double* dldc, double* g2d) {
   int64_t W = cam->width, H = cam->height;
   int64_t np = pix ? n_pix : W * H;
   int64_t cap = n_order > 0 ? n_order : 1;
   ostep_t* steps = (ostep_t*)malloc(sizeof(ostep_t) * cap);
   double* suffix = (double*)malloc(sizeof(double) * 3 * (cap + 1));
+  int64_t* tl = tile_vals ? (int64_t*)malloc(sizeof(int64_t) * (n > 0 ? n : 1)) : NULL;
+  int TW = (int)((W + opt->tile - 1) / opt->tile);
   for (int64_t p = 0; p < np; p++) {
     int64_t px = pix ? pix[2 * p] : p % W;
     int64_t py = pix ? pix[2 * p + 1] : p / W;
     double xc = px + 0.5, yc = py + 0.5;
+    const int64_t* list = order;
+    int64_t nl = n_order;
+    if (tile_vals) {
+      int64_t tile = (py / opt->tile) * TW + px / opt->tile;
+      uint32_t s0 = tile_ranges[2 * tile], s1 = tile_ranges[2 * tile + 1];
+      nl = 0;
+      for (uint32_t j = s0; j < s1; j++) tl[nl++] = tile_vals[j];
+      list = tl;
+    }
     double T, ma, mt, mc;
-    int64_t ns = composite_pixel(proj, order, n_order, xc, yc, opt, steps, cap, &T, &ma, &mt, &mc);
-    if (ns < 0) { free(steps); free(suffix); return -1; }
+    int64_t kb;
+    oflip_t fl = {amb, flips ? flips[p] : 0u, 0};
+    int64_t ns = composite_pixel(proj, list, nl, xc, yc, opt, steps, cap, &T, &ma, &mt, &mc, &fl, &kb);
+    if (ns < 0) { free(steps); free(suffix); if (tl) free(tl); return -1; }
     /* suffix[k] = sum_{j >= k} w_j c_j + T_final bg */
     for (int ch = 0; ch < 3; ch++) suffix[3 * ns + ch] = T * opt->bg[ch];
     for (int64_t k = ns - 1; k >= 0; k--) {
@@ -548,7 +614,14 @@ int orc_render_backward(int64_t n, const double* proj, const int64_t* order, int
   }
   free(steps);
   free(suffix);
+  if (tl) free(tl);
   return 0;
+}
+
+int orc_render_backward(int64_t n, const double* proj, const int64_t* order, int64_t n_order,
+                        const ocam_t* cam, const oopts_t* opt, int64_t n_pix, const int32_t* pix,
+                        const double* dldc, double* g2d) {
+  return orc_render_backward_ex(n, proj, order, n_order, cam, opt, n_pix, pix, NULL, NULL, NULL, NULL, dldc, g2d);
 }
 
 /* ------------------------------------------------------------------------ */
