@@ -200,6 +200,9 @@ def render(params: Params, cam, proj: np.ndarray, ordr: np.ndarray, opts: Opts,
     ``amb`` (alpha, stop, argmax widths) and ``flips`` (uint32 per pixel) invert
     the decisions that lie within those widths of their thresholds (bit k of
     ``flips`` for the k-th such decision met); ``namb`` returns how many were met.
+    With ``accumulate``, ``acc_tol`` [n, 3] holds per Gaussian the first-order
+    float32 error bounds of the importance terms and of the max weight, and the
+    number of included pairs (test tolerances; see oracle.c).
     """
     n = params.n
     W, H = int(cam.width), int(cam.height)
@@ -210,7 +213,7 @@ def render(params: Params, cam, proj: np.ndarray, ordr: np.ndarray, opts: Opts,
                hit=np.zeros(npx, dtype=np.uint8), margin=np.zeros((npx, 5)), namb=np.zeros(npx, dtype=np.int32))
     if accumulate:
         out.update(importance=np.zeros(max(n, 1)), wmax=np.zeros(max(n, 1)),
-                   area=np.zeros(max(n, 1), dtype=np.int64))
+                   area=np.zeros(max(n, 1), dtype=np.int64), acc_tol=np.zeros((max(n, 1), 3)))
     tv = tr = None
     if tiles is not None:
         tv = np.ascontiguousarray(tiles[0], dtype=np.uint32)
@@ -227,10 +230,10 @@ def render(params: Params, cam, proj: np.ndarray, ordr: np.ndarray, opts: Opts,
         _p(out["namb"]), _p(out["color"]), _p(out["depth"]), _p(out["imax"]),
         _p(out["t_final"]), _p(out["n_contrib"]), _p(out["hit"]), _p(out["margin"]),
         _p(out["importance"]) if accumulate else None, _p(out["wmax"]) if accumulate else None,
-        _p(out["area"]) if accumulate else None)
+        _p(out["area"]) if accumulate else None, _p(out["acc_tol"]) if accumulate else None)
     assert rc == 0
     if accumulate:
-        for k in ("importance", "wmax", "area"):
+        for k in ("importance", "wmax", "area", "acc_tol"):
             out[k] = out[k][:n]
     return out
 

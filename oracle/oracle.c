@@ -335,7 +335,15 @@ typedef struct {
   int64_t g;
   double alpha, T, G, dx, dy;
   int clamped;
+  double rel; /* first-order bound of a float32 renderer's relative error in w = alpha T (see orc_render_ex) */
 } ostep_t;
+
+/* Float32 error model used only for test tolerances: unit roundoff u, and the
+ * relative error of alpha = 2^e computed from a float32 exponent
+ * e = log2(o) - (conic quadratic) log2(e) / 2, whose absolute error is at most
+ * a few ulp of the magnitudes summed (4 u (|log2 o| + |terms|)), times ln 2,
+ * plus 2 u for the exponential itself.  A clamped alpha is the constant. */
+#define ORC_U (1.0 / 16777216.0)
 
 /* Decision flips (test support for comparing a float32 renderer).  Eq. (1)
  * takes three discrete decisions per evaluated pair: skip (alpha below
@@ -368,7 +376,7 @@ static int take_decision(oflip_t* f, int decision, double margin, int which) {
 static int64_t composite_pixel(const double* proj, const int64_t* list, int64_t nl, double xc, double yc,
                                const oopts_t* opt, ostep_t* steps, int64_t cap, double* T_out,
                                double* m_alpha, double* m_stop, double* m_clamp, oflip_t* fl, int64_t* best) {
-  double T = 1.0, wbest = 0.0;
+  double T = 1.0, wbest = 0.0, relT = 0.0;
   int64_t ns = 0, kb = -1;
   double ma = INFINITY, mt = INFINITY, mc = INFINITY;
   for (int64_t k = 0; k < nl; k++) {
@@ -376,6 +384,7 @@ static int64_t composite_pixel(const double* proj, const int64_t* list, int64_t 
     if (P[OP_VALID] == 0) continue;
     double dx = xc - P[OP_U], dy = yc - P[OP_V];
     double q = P[OP_CA] * dx * dx + 2 * P[OP_CB] * dx * dy + P[OP_CC] * dy * dy;
+    double qmag = fabs(P[OP_CA] * dx * dx) + fabs(2 * P[OP_CB] * dx * dy) + fabs(P[OP_CC] * dy * dy);
     double G = exp(-0.5 * q);
     double oG = P[OP_OPAC] * G;
     double alpha = oG < opt->alpha_max ? oG : opt->alpha_max;
@@ -396,6 +405,11 @@ static int64_t composite_pixel(const double* proj, const int64_t* list, int64_t 
     steps[ns].dx = dx;
     steps[ns].dy = dy;
     steps[ns].clamped = oG >= opt->alpha_max;
+    double ea = steps[ns].clamped ? 0.0
+                                  : log(2.0) * 4.0 * ORC_U * (fabs(log2(P[OP_OPAC])) + 0.5 * qmag / log(2.0)) +
+                                        2.0 * ORC_U;
+    steps[ns].rel = relT + ea + ORC_U;
+    relT += alpha * ea / (1.0 - alpha) + 2.0 * ORC_U;
     double w = alpha * T;
     double gap = kb >= 0 ? fabs(w - wbest) / (w > wbest ? w : wbest) : INFINITY;
     if (take_decision(fl, w > wbest, gap, 2)) { wbest = w; kb = ns; }
@@ -459,13 +473,20 @@ static void mid_depth(const ocam_t* cam, const double* means, const double* scal
  * max w, and area (count of pixels whose imax is the record).
  * orc_render_ex also takes decision flips (see oflip_t): amb [3] or NULL,
  * flips [n_pix] or NULL, and returns the count of ambiguous decisions met per
- * pixel in namb [n_pix] (may be NULL). */
+ * pixel in namb [n_pix] (may be NULL).  acc_tol [n][3] (may be NULL) is added
+ * to, per Gaussian: sum of w times its first-order float32 error bound (the
+ * bound of the importance sum's terms), the largest such product (bound of
+ * the max weight), and the number of included pairs (for the bound of a
+ * float32 summation).  The bound of w_k = alpha_k T_k is
+ * sum_{j<k} (alpha_j e_j / (1 - alpha_j) + 2 u) + e_k + u with e the alpha
+ * error above: each factor 1 - alpha_j carries alpha_j's error magnified by
+ * alpha_j / (1 - alpha_j), and each product one rounding. */
 int orc_render_ex(int64_t n, const double* proj, const int64_t* order, int64_t n_order, const double* means,
                   const double* scales, const double* quats, const ocam_t* cam, const oopts_t* opt,
                   int64_t n_pix, const int32_t* pix, const uint32_t* tile_vals, const uint32_t* tile_ranges,
                   const double* amb, const uint32_t* flips, int32_t* namb,
                   double* color, double* depth, int64_t* imax, double* t_final, int32_t* n_contrib, uint8_t* hit,
-                  double* margin, double* imp, double* wmax, int64_t* area) {
+                  double* margin, double* imp, double* wmax, int64_t* area, double* acc_tol) {
   int64_t W = cam->width, H = cam->height;
   int64_t np = pix ? n_pix : W * H;
   int64_t cap = n_order > 0 ? n_order : 1;
@@ -504,6 +525,12 @@ int orc_render_ex(int64_t n, const double* proj, const int64_t* order, int64_t n
       else if (w > wsecond) wsecond = w;
       if (imp) imp[steps[k].g] += w;
       if (wmax && w > wmax[steps[k].g]) wmax[steps[k].g] = w;
+      if (acc_tol) {
+        double* tg = acc_tol + 3 * steps[k].g;
+        tg[0] += w * steps[k].rel;
+        if (w * steps[k].rel > tg[1]) tg[1] = w * steps[k].rel;
+        tg[2] += 1.0;
+      }
     }
     for (int ch = 0; ch < 3; ch++) C[ch] += T * opt->bg[ch];
     if (color) for (int ch = 0; ch < 3; ch++) color[3 * p + ch] = C[ch];
@@ -540,7 +567,7 @@ int orc_render(int64_t n, const double* proj, const int64_t* order, int64_t n_or
                double* color, double* depth, int64_t* imax, double* t_final, int32_t* n_contrib, uint8_t* hit,
                double* margin, double* imp, double* wmax, int64_t* area) {
   return orc_render_ex(n, proj, order, n_order, means, scales, quats, cam, opt, n_pix, pix, tile_vals, tile_ranges,
-                       NULL, NULL, NULL, color, depth, imax, t_final, n_contrib, hit, margin, imp, wmax, area);
+                       NULL, NULL, NULL, color, depth, imax, t_final, n_contrib, hit, margin, imp, wmax, area, NULL);
 }
 
 /* ------------------------------------------------------------------------ */

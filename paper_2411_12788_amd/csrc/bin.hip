@@ -382,7 +382,11 @@ int32_t bin_sort_on_ws(const gs_projected_t* proj, const ViewSet& vs, int32_t V,
   int32_t st;
   if ((st = launch_fill(ranges, 0u, 2 * (int64_t)vs.tiles_total, s)) != GS_OK) return st;
   uint32_t* order_hist = (uint32_t*)((char*)ws + 256);
-  if (ni == 0) return tile_order ? launch_tile_order(ranges, vs.tiles_total, tile_order, order_hist, s) : GS_OK;
+  if (ni == 0) {
+    // no sort runs: clear the status flag it would have cleared
+    if ((st = launch_fill(ws, 0u, 1, s)) != GS_OK) return st;
+    return tile_order ? launch_tile_order(ranges, vs.tiles_total, tile_order, order_hist, s) : GS_OK;
+  }
   if (!vals || !offsets) { set_error("buffer NULL"); return GS_ERR_NULL; }
   if (proj->tile_cull_log2_alpha < 0.f && !proj->rec) { set_error("tile culling needs proj->rec"); return GS_ERR_NULL; }
   char* p = (char*)ws + sort_ws_size(ni);
@@ -481,7 +485,7 @@ int32_t gs_emit_keys(const gs_projected_t* proj, const gs_camera_t* cams, int32_
 int32_t gs_sort_pairs(uint64_t* keys, uint32_t* vals, int64_t n, int32_t key_bits, void* ws, size_t ws_bytes,
                       void* stream) {
   if (n < 0 || key_bits < 1 || key_bits > 64) { set_error("bad n / key_bits"); return GS_ERR_SHAPE; }
-  if (n == 0) return GS_OK;
+  if (n == 0) return ws ? launch_fill(ws, 0u, 1, (hipStream_t)stream) : GS_OK;  // status flag: a valid (empty) order
   if (!keys || !vals || !ws) { set_error("buffer NULL"); return GS_ERR_NULL; }
   if (n >= kSortMaxPairs) { set_error("n of 2^30 or more (sort limit)"); return GS_ERR_CAPACITY; }
   if (ws_bytes < sort_ws_size(n)) { set_error("sort workspace too small"); return GS_ERR_CAPACITY; }

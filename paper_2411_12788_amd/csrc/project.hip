@@ -165,13 +165,16 @@ __global__ __launch_bounds__(kBlock) void k_project(ProjArgs pa, ViewSet vs) {
 #pragma unroll
     for (int ch = 0; ch < 3; ++ch) rgb[ch] += (double)shp[(int64_t)(k * 3 + ch) * n + i] * Yk;
   });
+  // a colour that is not finite before the clamp (NaN or infinite SH terms)
+  // makes the record invalid; the clamp must not turn NaN into black
+  const bool rgb_finite = isfinite(rgb[0]) && isfinite(rgb[1]) && isfinite(rgb[2]);
 #pragma unroll
   for (int ch = 0; ch < 3; ++ch) rgb[ch] = rgb[ch] > 0.0 ? rgb[ch] : 0.0;
   // extent of the ellipse where opacity * G2D >= alpha_min
   const double kk = 2.0 * log(o / (double)op.alpha_min);
   const double ex = sqrt(kk * g.S00), ey = sqrt(kk * g.S11);
   ok = ok && isfinite(g.u) && isfinite(g.v) && isfinite(ex) && isfinite(ey) && isfinite(g.a) && isfinite(g.b) &&
-       isfinite(g.c) && isfinite(rgb[0]) && isfinite(rgb[1]) && isfinite(rgb[2]) && isfinite(g.t[2]);
+       isfinite(g.c) && rgb_finite && isfinite(g.t[2]);
   int32_t xlo = 1, xhi = 0, ylo = 1, yhi = 0, tiles = 0;
   if (ok) {
     const double W1 = cam.width - 1, H1 = cam.height - 1;

@@ -11,7 +11,6 @@ import torch
 import gs_inputs
 import oracle
 from tests import gpu_helpers as H
-from tests.test_gpu_parity import _check_accum
 
 pytestmark = pytest.mark.gpu
 
@@ -31,11 +30,11 @@ def test_heavy_tiles_forward_backward(gpu_lib, opacity):
     assert ((rng[:, 1] - rng[:, 0]) >= 2048).all()  # every tile is a heavy one
     p = oracle.Params.of(wl.scene)
     orc = oracle.forward_view(p, cam, oracle.Opts())
-    # most bright pixels stop inside their stream, and a stop decided within the
-    # float32 error of the threshold is ambiguous for ~6% of them
-    amb, amb_arg = H.compare_forward(out["frame"], orc, slice(0, Pn), f"heavy tiles {opacity}",
-                                     max_ambiguous=0.08 if opacity[1] > 0.1 else H.MAX_AMBIGUOUS_FRACTION)
-    _check_accum(out["acc"], orc, amb_arg, n)
+    # most bright pixels stop inside their stream, and many stops are decided
+    # within the float32 error of the threshold: those pixels are checked
+    # against both branches
+    flips, namb = H.compare_forward(out["frame"], orc, slice(0, Pn), f"heavy tiles {opacity}", p, cam)
+    H.check_accum(out["acc"], p, cam, orc["proj"], orc["order"], oracle.Opts(), flips, n, f"heavy tiles {opacity}")
     if opacity[1] > 0.1:
         assert (orc["t_final"] < 1e-3).mean() > 0.2  # the stop is reached inside the streams
     dldc = gs_inputs.normal_image(3, Pn, 31, scale=1.0 / Pn)
@@ -43,7 +42,8 @@ def test_heavy_tiles_forward_backward(gpu_lib, opacity):
     grads, g2d = R.render_backward(out["scene"], out["proj"], out["binned"], wl.cameras, R.RasterOpts(),
                                    out["frame"], torch.from_numpy(dldc).cuda(), torch.from_numpy(active).cuda())
     torch.cuda.synchronize()
-    og, og2d = oracle.backward_views(p, wl.cameras, oracle.Opts(), [dldc.T.astype(np.float64)], active=active)
+    og, og2d = H.backward_views(p, wl.cameras, oracle.Opts(), [dldc.T.astype(np.float64)], active=active,
+                                flips=[flips])
     g2 = _np(g2d).astype(np.float64)[:n]
     assert H.rel_l2(g2, og2d[0] * active[:, None]) <= H.GRAD_REL_L2
     for k in ("means", "scales", "quats", "opacity", "sh"):
@@ -66,14 +66,15 @@ def test_concentrated_heavy_tiles_forward_backward(gpu_lib):
     p = oracle.Params.of(wl.scene)
     orc = oracle.forward_view(p, cam, oracle.Opts())
     assert (orc["t_final"] < 1e-3).sum() > 100  # pixels that stop inside the four-entry steps
-    amb, amb_arg = H.compare_forward(out["frame"], orc, slice(0, Pn), "concentrated heavy tiles", max_ambiguous=0.08)
-    _check_accum(out["acc"], orc, amb_arg, n)
+    flips, _ = H.compare_forward(out["frame"], orc, slice(0, Pn), "concentrated heavy tiles", p, cam)
+    H.check_accum(out["acc"], p, cam, orc["proj"], orc["order"], oracle.Opts(), flips, n, "concentrated heavy tiles")
     dldc = gs_inputs.normal_image(3, Pn, 41, scale=1.0 / Pn)
     active = gs_inputs.bernoulli_mask(n, 0.25, 42)
     grads, g2d = R.render_backward(out["scene"], out["proj"], out["binned"], wl.cameras, R.RasterOpts(),
                                    out["frame"], torch.from_numpy(dldc).cuda(), torch.from_numpy(active).cuda())
     torch.cuda.synchronize()
-    og, og2d = oracle.backward_views(p, wl.cameras, oracle.Opts(), [dldc.T.astype(np.float64)], active=active)
+    og, og2d = H.backward_views(p, wl.cameras, oracle.Opts(), [dldc.T.astype(np.float64)], active=active,
+                                flips=[flips])
     assert H.rel_l2(_np(g2d).astype(np.float64)[:n], og2d[0] * active[:, None]) <= H.GRAD_REL_L2
     for k in ("means", "scales", "quats", "opacity", "sh"):
         assert H.rel_l2(_np(grads[k])[..., :n].astype(np.float64), og[k]) <= H.GRAD_REL_L2, k

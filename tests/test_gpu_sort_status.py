@@ -78,3 +78,27 @@ def test_binning_checks_the_flag(gpu_lib):
     wl = gs_inputs.small_cube(seed=1)
     out = H.run_gpu_forward(wl.scene, wl.cameras, accumulate=False)
     assert out["binned"].stats.n_isect > 0
+
+
+def test_empty_sorts_leave_a_clear_flag(gpu_lib):
+    """No pairs: nothing is sorted, and the flag of a workspace that holds
+    stale bytes reads clear (an empty order is valid)."""
+    from paper_2411_12788_amd import _lib as L
+    R = H.raster()
+    ws = torch.full((L.lib().gs_sort_workspace_size(1),), 0xFF, dtype=torch.uint8, device="cuda")
+    kt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    vt = torch.zeros(1, dtype=torch.int32, device="cuda")
+    assert L.lib().gs_sort_pairs(ctypes.c_void_p(kt.data_ptr()), ctypes.c_void_p(vt.data_ptr()), 0, 40,
+                                 ctypes.c_void_p(ws.data_ptr()), ws.numel(), None) == L.GS_OK
+    assert L.lib().gs_sort_status(ctypes.c_void_p(ws.data_ptr()), None) == L.GS_OK
+    # a view where every Gaussian is culled: zero pairs through gs_bin_sort
+    cam = gs_inputs.look_at((0, 0, 4), (0, 0, 0), 37, 23)
+    sc = gs_inputs.uniform_cube_scene(500, 3)
+    ds = R.DeviceScene.from_numpy(sc)
+    proj = R.project(ds, [cam], R.RasterOpts(), torch.zeros(500, dtype=torch.uint8, device="cuda"))
+    offsets, st = R.bin_count(proj, [cam], sc.n)
+    assert st.n_isect == 0
+    bufs = R.BinBuffers()
+    bufs.ws = torch.full((L.lib().gs_bin_sort_workspace_size(1),), 0xFF, dtype=torch.uint8, device="cuda")
+    R.bin_sort(proj, [cam], sc.n, offsets, st, buffers=bufs)
+    R.sort_status(bufs.ws)

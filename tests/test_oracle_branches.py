@@ -207,3 +207,49 @@ def test_tiled_backward_equals_untiled():
     tiled = oracle.render_backward(p, cam, proj, ordr, OPTS, g, tiles=(vals, ranges))
     assert np.abs(full).max() > 0
     assert np.allclose(tiled, full, rtol=1e-12, atol=1e-15)
+
+
+def test_float32_weight_error_within_bound():
+    """The oracle's first-order bound of a float32 renderer's error in each
+    weight w = alpha T holds for an emulated float32 compositing of the same
+    pairs (alpha = exp2 of a float32 exponent, float32 transmittance product),
+    and is not vacuous.  Pixels are taken whole: one pixel at a time, so the
+    per-Gaussian bound is the per-pair bound."""
+    sc = random_small_scene(21, n=80, spread=0.5, scale_lo=0.05, scale_hi=0.25)
+    sc.opacity[:] = np.linspace(0.3, 0.995, sc.n).astype(np.float32)
+    p, proj, ordr = _setup(sc)
+    f32 = np.float32
+    l2e = 1.4426950408889634
+    checked, ratios = 0, []
+    for (x, y) in [(x, y) for y in range(6, 26, 3) for x in range(6, 26, 3)]:
+        pix = np.array([[x, y]], dtype=np.int32)
+        o = oracle.render(p, CAM, proj, ordr, OPTS, pixels=pix, accumulate=True)
+        T32 = f32(1.0)
+        for g in ordr:
+            P = proj[g]
+            dx, dy = f32(x + 0.5 - P[F["U"]]), f32(y + 0.5 - P[F["V"]])
+            A, B, C = f32(0.5 * l2e * P[F["CA"]]), f32(l2e * P[F["CB"]]), f32(0.5 * l2e * P[F["CC"]])
+            ee = f32(np.log2(P[F["OPAC"]])) - (A * dx * dx + B * dx * dy + C * dy * dy)
+            a32 = min(f32(OPTS.alpha_max), np.exp2(ee, dtype=np.float32))
+            Tn = T32 * (f32(1.0) - a32)
+            inc32 = a32 >= f32(OPTS.alpha_min) and Tn >= f32(OPTS.t_min)
+            if inc32 != (o["acc_tol"][g, 2] == 1):
+                break  # the float32 walk left the oracle's decisions: not this pin's case
+            if a32 >= f32(OPTS.alpha_min) and Tn < f32(OPTS.t_min):
+                break
+            if not inc32:
+                continue
+            w32 = float(a32 * T32)
+            T32 = Tn
+            w64, tol = o["importance"][g], o["acc_tol"][g, 0]
+            assert abs(w32 - w64) <= tol, (x, y, g, w32, w64, tol)
+            ratios.append(abs(w32 - w64) / tol)
+            checked += 1
+    assert checked > 100
+    assert max(ratios) > 1e-3  # the bound is tight enough to matter
+    # a clamped alpha carries no error of its own: only the product's rounding
+    sc1 = scene_from([_on_pixel_ray(0.0)], [[0.05] * 3], [[1, 0, 0, 0]], [0.995], dc_rgb=[[0.5] * 3])
+    p1, proj1, ordr1 = _setup(sc1)
+    o1 = oracle.render(p1, CAM, proj1, ordr1, OPTS, pixels=np.array([[PX, PY]], dtype=np.int32), accumulate=True)
+    assert o1["acc_tol"][0, 0] == pytest.approx(OPTS.alpha_max * 2.0 ** -24, rel=1e-12)
+    assert o1["acc_tol"][0, 2] == 1
