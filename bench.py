@@ -32,20 +32,23 @@ import torch  # noqa: E402
 import gs_inputs  # noqa: E402
 
 PEAK_HBM_GBS = 8000.0
-PEAK_FP32_TFLOPS = 157.3
-# algorithmic work per unit (measurement section)
-# Render work is counted in pair-evaluations of the tile algorithm (a pixel
-# evaluates the entries of its tile's list in depth order until it stops; the
-# backward revisits them up to the pixel's last contributor): ~25 VALU
-# lane-ops + 1 exp2 each forward, ~3x that backward.  The kernels skip most of
-# these evaluations with exact ellipse culling; they still count as the work
-# the algorithm defines.
-FLOPS_FWD_PER_EVAL = 26.0
-FLOPS_BWD_PER_EVAL = 75.0
+# FP32 VALU issue rate without packed FP32 (disabled in this build): 256 CUs x
+# 4 SIMDs x 16 lanes per clock x 2.4 GHz = 39.3 T lane-ops/s
+PEAK_VALU_TOPS = 256 * 64 * 2.4e9 / 1e12
 STOP_T = 0.01  # a pixel with final transmittance >= 1e-4 / (1 - 0.99) never stopped
+# algorithmic bytes per unit (kernels table)
 PROJECT_BYTES_PER_RECORD = 59 * 4 + 64 + 16     # params read, record + bin written
 PROJECT_BWD_BYTES_PER_ACTIVE = 59 * 4 + 59 * 4 + 36 + 16  # params read, grads written, 2D grad + bin read
 PROJECT_BWD_BYTES_PER_INACTIVE = 59 * 4 + 1     # zero rows written, mask read
+RENDER_FWD_BYTES_PER_PAIR = 4 + 8 + 48          # list index, pixel box, the 48 record bytes compositing reads
+RENDER_FWD_BYTES_PER_PIXEL = 12 + 4 + 4 + 4 + 4 + 4 + 1  # colour, depth, imax, T, last, count, hit
+RENDER_BWD_BYTES_PER_PAIR = 4 + 8 + 64 + 1      # list index, box, full record, active flag
+RENDER_BWD_BYTES_PER_PIXEL = 12 + 4 + 4         # dL/dC, T, last
+STAGE_KERNELS = {"project": ["k_project"], "bin_count": ["k_count_reduce", "k_count_top", "k_count_down"],
+                 "bin_sort": ["k_emit", "k_os_hist", "k_os_scan", "k_os_pass", "k_ranges", "k_order_hist",
+                              "k_order_scan", "k_order_scatter"],
+                 "render_fwd": ["k_render_fwd"], "loss": ["k_l1_loss_grad"], "render_bwd": ["k_render_bwd"],
+                 "project_bwd": ["k_project_bwd"]}
 
 
 def parse():
@@ -55,9 +58,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="large", choices=["large", "training", "small"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-pixels", type=int, default=48)
+    ap.add_argument("--cpu-cores", type=int, default=0, help="oracle baseline processes (default: host cores, <= 16)")
     ap.add_argument("--no-serving", action="store_true")
-    ap.add_argument("--serving-requests", type=int, default=240)
+    ap.add_argument("--serving-requests", type=int, default=2000)
+    ap.add_argument("--serving-warmup", type=int, default=200)
     ap.add_argument("--no-multiview", action="store_true")
     ap.add_argument("--no-criteria", action="store_true")
     ap.add_argument("--profile", action="store_true",
@@ -105,7 +109,10 @@ class Step:
         self.frame = None
         self.bin_buffers = R.BinBuffers()
 
-    def run(self, record: bool):
+    def run(self, record: bool, recompute: bool = False):
+        """One step.  With `recompute` the backward re-derives the projection
+        and the sorted lists instead of keeping the forward's (the memory-lean
+        mode of the autograd wrapper)."""
         R, ev = self.R, self.ev
 
         def mark(k, i):
@@ -134,6 +141,10 @@ class Step:
         mark("loss", 0)
         R.l1_loss_grad(self.frame.color, self.target, self.dldc, self.loss)
         mark("loss", 1)
+        if recompute:
+            proj = R.project(self.scene, self.cams, self.opts)
+            offsets, st = R.bin_count(proj, self.cams, self.n)
+            binned = R.bin_sort(proj, self.cams, self.n, offsets, st, buffers=self.bin_buffers)
         mark("render_bwd", 0)
         R.render_backward_pixels(proj, binned, self.cams, self.n, self.opts, self.frame, self.dldc, self.active,
                                  self.grad2d)
@@ -223,48 +234,174 @@ def criteria_bench(step, reps: int = 10):
     return res
 
 
-def cpu_baseline(wl, sample_pixels: int):
-    """The FP64 oracle on a bounded sample of the same step, scaled to ms/step."""
+# --------------------------------------------------------------------------
+# CPU baseline: the FP64 oracle over the host's cores
+# --------------------------------------------------------------------------
+_CPU = {}  # read by the forked workers (copy-on-write)
+
+
+def _cpu_project(sl):
     import oracle
+    c = _CPU
+    p = c["params"]
+    sub = oracle.Params(p.means[:, sl], p.scales[:, sl], p.quats[:, sl], p.opacity[sl], p.sh[:, :, sl], p.sh_degree)
+    t = time.process_time()
+    out = oracle.project(sub, c["cam"], c["opts"])
+    return sl, out, time.process_time() - t
+
+
+def _band_pixels(ty):
+    cam = _CPU["cam"]
+    y0, y1 = 16 * ty, min(16 * ty + 16, cam.height)
+    ys, xs = np.mgrid[y0:y1, 0:cam.width]
+    return np.stack([xs.ravel(), ys.ravel()], 1).astype(np.int32)
+
+
+def _cpu_render(ty):
+    import oracle
+    c = _CPU
+    pix = _band_pixels(ty)
+    t = time.process_time()
+    r = oracle.render(c["params"], c["cam"], c["proj"], c["order"], c["opts"], pixels=pix, tiles=c["tiles"],
+                      accumulate=True)
+    cpu = time.process_time() - t
+    nz = np.nonzero(r["importance"])[0]
+    acc = (nz, r["importance"][nz], r["wmax"][nz], r["area"][nz])
+    return ty, r["color"], r["t_final"], r["imax"], acc, cpu
+
+
+def _cpu_backward(ty):
+    import oracle
+    c = _CPU
+    pix = _band_pixels(ty)
+    idx = pix[:, 1] * c["cam"].width + pix[:, 0]
+    t = time.process_time()
+    g2d = oracle.render_backward(c["params"], c["cam"], c["proj"], c["order"], c["opts"], c["dldc"][idx],
+                                 pixels=pix, tiles=c["tiles"])
+    cpu = time.process_time() - t
+    nz = np.nonzero(np.any(g2d != 0, axis=1))[0]
+    return nz, g2d[nz], cpu
+
+
+def _cpu_project_backward(sl):
+    import oracle
+    c = _CPU
+    p = c["params"]
+    sub = oracle.Params(p.means[:, sl], p.scales[:, sl], p.quats[:, sl], p.opacity[sl], p.sh[:, :, sl], p.sh_degree)
+    t = time.process_time()
+    g = oracle.project_backward(sub, c["cam"], c["opts"], c["proj"][sl], c["g2d"][sl])
+    return sl, g, time.process_time() - t
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(wl, cores: int = 0):
+    """The FP64 oracle as it stands, timed on the host's cores over the whole
+    step of the same workload: projection, depth order and binning, the
+    tile-restricted forward with the three accumulations over every pixel, the
+    L1 loss gradient, the backward over every pixel, and the projection
+    backward with the active mask.  Per-Gaussian stages are split over chunks
+    of Gaussians and per-pixel stages over 16-pixel rows of tiles, across a
+    pool of forked processes (one per core, at most 16).  Stage times are wall
+    clock; the summed process CPU time gives the one-core figure."""
+    import multiprocessing as mp
+    import oracle
+    avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    cores = cores or min(16, avail)
     cam = wl.cameras[0]
-    p = oracle.Params.of(wl.scene)
-    opts = oracle.Opts()
+    n, W, H = wl.scene.n, cam.width, cam.height
+    P = W * H
+    _CPU.clear()
+    _CPU.update(params=oracle.Params.of(wl.scene), cam=cam, opts=oracle.Opts())
+    target = gs_inputs.uniform_image(3, P, 4242).T.astype(np.float64)
+    chunks = [slice(a, min(a + 65536, n)) for a in range(0, n, 65536)]
+    bands = list(range((H + 15) // 16))
+    times, cpu = {}, 0.0
+    ctx = mp.get_context("fork")
     t0 = time.perf_counter()
-    proj = oracle.project(p, cam, opts)
-    t1 = time.perf_counter()
+    proj = np.zeros((n, oracle.STRIDE))
+    with ctx.Pool(cores) as pool:
+        for sl, out, c in pool.imap_unordered(_cpu_project, chunks):
+            proj[sl] = out
+            cpu += c
+    times["project"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    c0 = time.process_time()
     ordr = oracle.order(proj)
-    t2 = time.perf_counter()
-    g = gs_inputs.rng(99)
-    pix = np.stack([g.integers(0, cam.width, sample_pixels), g.integers(0, cam.height, sample_pixels)], 1)
-    oracle.render(p, cam, proj, ordr, opts, pixels=pix)
-    dldc = g.normal(size=(sample_pixels, 3)) / (cam.width * cam.height)
-    g2d = oracle.render_backward(p, cam, proj, ordr, opts, dldc, pixels=pix)
-    t3 = time.perf_counter()
-    oracle.project_backward(p, cam, opts, proj, g2d)
-    t4 = time.perf_counter()
-    per_pixel = (t3 - t2) / sample_pixels
-    P = cam.width * cam.height
-    ms = 1e3 * ((t1 - t0) + (t2 - t1) + (t4 - t3) + per_pixel * P)
-    return {"value": ms, "unit": "ms/step", "cores": 1, "kind": "oracle",
-            "sample": (f"full FP64 projection, depth order and projection backward of all {wl.scene.n} Gaussians "
-                       f"+ forward and backward of {sample_pixels} seeded pixels over every Gaussian; per-pixel "
-                       f"time scaled to the {P} pixels of the view; measured {t4 - t0:.1f} s")}
+    tx, ty, base, total = oracle.view_layout([cam])
+    _, vals, ranges = oracle.bin(oracle.tile_rects(proj), oracle.zbits(proj), 1, n, base, tx, total)
+    cpu += time.process_time() - c0
+    times["order_and_bin"] = time.perf_counter() - t0
+    _CPU.update(proj=proj, order=ordr, tiles=(vals, ranges))
+    t0 = time.perf_counter()
+    color = np.zeros((P, 3))
+    imp, wmax, area = np.zeros(n), np.zeros(n), np.zeros(n, dtype=np.int64)
+    with ctx.Pool(cores) as pool:
+        for tyk, col, tf, im, (nz, a_i, a_w, a_s), c in pool.imap_unordered(_cpu_render, bands):
+            y0 = 16 * tyk
+            color[y0 * W:y0 * W + col.shape[0]] = col
+            imp[nz] += a_i
+            np.maximum.at(wmax, nz, a_w)
+            area[nz] += a_s
+            cpu += c
+    times["render_forward"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    c0 = time.process_time()
+    dldc = np.sign(color - target) / (3.0 * P)
+    cpu += time.process_time() - c0
+    times["loss"] = time.perf_counter() - t0
+    _CPU.update(dldc=dldc)
+    t0 = time.perf_counter()
+    g2d = np.zeros((n, 9))
+    with ctx.Pool(cores) as pool:
+        for nz, rows, c in pool.imap_unordered(_cpu_backward, bands):
+            g2d[nz] += rows
+            cpu += c
+    times["render_backward"] = time.perf_counter() - t0
+    _CPU.update(g2d=g2d)
+    t0 = time.perf_counter()
+    grads = {}
+    with ctx.Pool(cores) as pool:
+        for sl, g, c in pool.imap_unordered(_cpu_project_backward, chunks):
+            for k, v in g.items():
+                grads.setdefault(k, np.zeros(v.shape[:-1] + (n,)))[..., sl] = v
+            cpu += c
+    if wl.active is not None:
+        for v in grads.values():
+            v[..., wl.active == 0] = 0.0
+    times["project_backward"] = time.perf_counter() - t0
+    _CPU.clear()
+    ms = 1e3 * sum(times.values())
+    return {"value": round(ms, 1), "unit": "ms/step", "cores": cores, "kind": "oracle",
+            "cpu_model": _cpu_model(), "host_cpus_available": avail,
+            "stages_ms": {k: round(1e3 * v, 1) for k, v in times.items()},
+            "one_core_ms_est": round(1e3 * cpu, 1),
+            "sample": (f"the whole step, not a sample: FP64 oracle over all {n} Gaussians and all {P} pixels of "
+                       f"the {W}x{H} view ({len(vals)} tile pairs), forward and backward in the oracle's tile-restricted mode, {cores} forked "
+                       f"processes; one_core_ms_est = summed process CPU time of the same run")}
 
 
-def serving_bench(n_requests: int):
+def serving_bench(n_requests: int, warmup: int):
     """Eight resident scenes (0.2M..3M Gaussians), Poisson arrivals of
     forward-only renders at 800x800 / 1280x720 / 1920x1080 from random cameras
-    on a radius-6 sphere.  One-at-a-time capacity mu1 is measured first; the
-    continuous-batching server then runs at 0.8 and 1.5 x mu1, and the
-    one-at-a-time server at 0.8 x mu1 for comparison."""
+    on a radius-6 sphere.  The one-at-a-time capacity mu1 is measured first
+    (back-to-back submissions); then both the one-at-a-time server and the
+    continuous-batching server run at 0.5, 0.8, 1.0 and 1.5 x mu1, each with
+    `warmup` requests that are not counted followed by `n_requests` counted."""
     from paper_2411_12788_amd import raster as R
     from paper_2411_12788_amd.serve import GpuExecutor, Server, drive, poisson_arrivals
-    t_gen = time.perf_counter()
     scenes = {}
     for k, n in enumerate(gs_inputs.SERVING_SCENE_SIZES):
         scenes[k] = R.DeviceScene.from_numpy(gs_inputs.surface_scene(n, 500 + k))
     torch.cuda.synchronize()
-    t_gen = time.perf_counter() - t_gen
     resident = sum(s.nbytes() for s in scenes.values())
 
     def requests(count, seed):
@@ -279,30 +416,31 @@ def serving_bench(n_requests: int):
         return out
 
     budget = 24 << 30
-    # warm-up and one-at-a-time capacity (back-to-back submissions)
+    # one-at-a-time capacity (back-to-back submissions, after a warm-up)
     ex1 = GpuExecutor(scenes, slots=1)
     srv = Server(ex1, budget, slots=1, max_batch=1)
-    drive(srv, requests(24, 1), [0.0] * 24)
-    srv.close()
-    srv = Server(ex1, budget, slots=1, max_batch=1)
-    cap = drive(srv, requests(max(40, n_requests // 4), 2), [0.0] * max(40, n_requests // 4))
+    cap_n = max(40, n_requests // 4)
+    cap = drive(srv, requests(warmup + cap_n, 2), [0.0] * (warmup + cap_n), warmup=warmup)
     srv.close()
     mu1 = cap["views_per_s"]
     out = {"workload": "8 resident scenes 0.2M-3M Gaussians (13.7M total), resolutions "
                        "800x800/1280x720/1920x1080, Poisson arrivals",
            "resident_gb": round(resident / 1e9, 3), "one_at_a_time_capacity_views_per_s": round(mu1, 2),
-           "runs": []}
-    for mode, slots, mb, factor in (("one_at_a_time", 1, 1, 0.8), ("continuous_batching", 4, 8, 0.8),
-                                    ("continuous_batching", 4, 8, 1.5)):
-        ex = GpuExecutor(scenes, slots=slots)
-        srv = Server(ex, budget, slots=slots, max_batch=mb)
-        qps = factor * mu1
-        st = drive(srv, requests(n_requests, 10 + slots), poisson_arrivals(qps, n_requests, 20 + slots))
-        srv.close()
-        out["runs"].append({"mode": mode, "offered_qps": round(qps, 2), "views_per_s": round(st["views_per_s"], 2),
-                            "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3),
-                            "mean_batch": round(st["mean_batch"], 2),
-                            "peak_reserved_gb": round(st["peak_reserved_gb"], 3), "requests": st["completed"]})
+           "requests_per_point": n_requests, "warmup_per_point": warmup, "runs": []}
+    for mode, slots, mb in (("one_at_a_time", 1, 1), ("continuous_batching", 4, 8)):
+        for factor in (0.5, 0.8, 1.0, 1.5):
+            ex = GpuExecutor(scenes, slots=slots)
+            srv = Server(ex, budget, slots=slots, max_batch=mb)
+            qps = factor * mu1
+            total = warmup + n_requests
+            seed = int(10 * factor) + 100 * slots
+            st = drive(srv, requests(total, seed), poisson_arrivals(qps, total, seed + 1), warmup=warmup)
+            srv.close()
+            out["runs"].append({"mode": mode, "load": factor, "offered_qps": round(qps, 2),
+                                "views_per_s": round(st["views_per_s"], 2), "p50_ms": round(st["p50_ms"], 3),
+                                "p99_ms": round(st["p99_ms"], 3), "mean_ms": round(st["mean_ms"], 3),
+                                "mean_batch": round(st["mean_batch"], 3), "batch_size_counts": st["batch_size_counts"],
+                                "peak_reserved_gb": round(st["peak_reserved_gb"], 3), "requests": st["completed"]})
     return out
 
 
@@ -350,18 +488,22 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(kernel: str):
-    """HBM bytes per launch of `kernel` from the committed counter summary, or
-    None when there is none or the kernel sources changed since it was taken."""
-    path = os.path.join(ROOT, "profiles", f"{kernel}_counters.md")
-    if not os.path.exists(path):
-        return None
-    txt = open(path).read()
-    m = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+COUNTERS_MD = os.path.join(ROOT, "profiles", "counters_surfaces_3M_1920x1080.md")
+
+
+def profile_counters():
+    """Per-kernel counters of the committed summary (mean per dispatch), or {}
+    when there is none or the kernel sources changed since it was taken."""
+    if not os.path.exists(COUNTERS_MD):
+        return {}
+    txt = open(COUNTERS_MD).read()
     h = re.search(r"source_sha256:\s*([0-9a-f]+)", txt)
-    if not m or not h or h.group(1) != source_hash():
-        return None
-    return float(m.group(1))
+    if not h or h.group(1) != source_hash():
+        return {}
+    out = {}
+    for m in re.finditer(r"^counters\[(k_[a-z0-9_]+)\]: (\{.*\})$", txt, flags=re.M):
+        out[m.group(1)] = json.loads(m.group(2))
+    return out
 
 
 def profile_run(steps: int):
@@ -379,13 +521,24 @@ def profile_run(steps: int):
           flush=True)
 
 
-STAGE_KERNELS = {"render_fwd": "k_render_fwd", "render_bwd": "k_render_bwd", "project": "k_project",
-                 "project_bwd": "k_project_bwd", "sort_pass": "k_os_pass"}
+# rocprofv3 runs whose output `--summarize DIR` turns into profiles/ (one
+# counter pass per run, within the per-block limits of one pass)
 PROFILE_CMDS = {
     "kt": "rocprofv3 --kernel-trace --stats -d {d}/kt -o kt --output-format csv -- python3 bench.py --profile --steps 3",
-    "fetch": "rocprofv3 --pmc FETCH_SIZE -d {d}/fetch -o fetch --output-format csv -- python3 bench.py --profile --steps 2",
-    "write": "rocprofv3 --pmc WRITE_SIZE -d {d}/write -o write --output-format csv -- python3 bench.py --profile --steps 2",
+    "fetch": "rocprofv3 --pmc FETCH_SIZE -d {d}/fetch -o fetch --output-format csv -- "
+             "python3 bench.py --profile --steps 2",
+    "write": "rocprofv3 --pmc WRITE_SIZE -d {d}/write -o write --output-format csv -- "
+             "python3 bench.py --profile --steps 2",
+    "dram": "rocprofv3 --pmc TCC_EA0_RDREQ_DRAM_32B_sum TCC_EA0_WRREQ_WRITE_DRAM_32B_sum "
+            "TCC_EA0_WRREQ_ATOMIC_DRAM_32B_sum -d {d}/dram -o dram --output-format csv -- "
+            "python3 bench.py --profile --steps 2",
+    "sq": "rocprofv3 --pmc SQ_INSTS_VALU SQ_INSTS_LDS SQ_INSTS_SALU SQ_INSTS_VMEM_RD SQ_WAVES SQ_ACTIVE_INST_VALU "
+          "SQ_LDS_BANK_CONFLICT GRBM_GUI_ACTIVE -d {d}/sq -o sq --output-format csv -- "
+          "python3 bench.py --profile --steps 2",
+    "util": "rocprofv3 --pmc VALUBusy VALUUtilization LDSBankConflict MemUnitStalled -d {d}/util -o util "
+            "--output-format csv -- python3 bench.py --profile --steps 2",
 }
+COPY_KERNEL = "copyBuffer (hipMemcpy D2D)"
 
 
 def _short(name: str) -> str:
@@ -393,59 +546,86 @@ def _short(name: str) -> str:
     if m:
         return m.group(1)
     if "copyBuffer" in name:
-        return "copyBuffer (hipMemcpy D2D)"
+        return COPY_KERNEL
     return name.split("(")[0][:60]
 
 
 def summarize(d: str) -> None:
-    """Turn the three rocprofv3 runs of `bench.py --profile` into the text
-    summaries kept under profiles/ (kernel times; HBM bytes per launch from
-    FETCH_SIZE / WRITE_SIZE scaled by what the counters read for a 1 GiB copy)."""
+    """Turn the rocprofv3 runs of PROFILE_CMDS (sub-folders of d) into the text
+    summaries kept under profiles/: kernel times, and per kernel the mean per
+    dispatch of every counter collected.  HBM bytes per launch: FETCH_SIZE and
+    WRITE_SIZE scaled by what they read for a 1 GiB copy ('traffic'), and the
+    DRAM-bound 32-byte request counts times 32 ('dram')."""
     import csv
+    dd = d.rstrip("/")
+    # the sources the profiled runs were built from (written beside the runs'
+    # output), else the current ones
+    sha_file = os.path.join(d, "source_sha256.txt")
+    sha = open(sha_file).read().strip() if os.path.exists(sha_file) else source_hash()
     stats = list(csv.DictReader(open(os.path.join(d, "kt", "kt_kernel_stats.csv"))))
     lines = ["# Kernel times: 3M Gaussians, one 1920x1080 view, fwd+bwd step", "",
-             "Command (from the repository root): `" + PROFILE_CMDS["kt"].format(d=d.rstrip("/")) + "`", "",
-             f"source_sha256: {source_hash()}", "",
+             "Command (from the repository root): `" + PROFILE_CMDS["kt"].format(d=dd) + "`", "",
+             f"source_sha256: {sha}", "",
              "| kernel | calls | avg us | min us | max us | share % |", "|---|---|---|---|---|---|"]
     for r in stats:
         lines.append(f"| {_short(r['Name'])} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
                      f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.2f} |")
     os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
     open(os.path.join(ROOT, "profiles", "kernels_surfaces_3M_1920x1080.md"), "w").write("\n".join(lines) + "\n")
-
-    def counter(kind):
-        rows = list(csv.DictReader(open(os.path.join(d, kind, f"{kind}_counter_collection.csv"))))
-        per = {}
-        for r in rows:
-            per.setdefault(_short(r["Kernel_Name"]), []).append(float(r["Counter_Value"]))
-        return per
-
-    fetch, write = counter("fetch"), counter("write")
-    copy = "copyBuffer (hipMemcpy D2D)"
-    gib_kib = float(1 << 20)
-    f_fac = max(fetch.get(copy, [gib_kib])) / gib_kib
-    w_fac = max(write.get(copy, [gib_kib])) / gib_kib
     avg_us = {_short(r["Name"]): float(r["AverageNs"]) / 1e3 for r in stats}
-    for stage, k in STAGE_KERNELS.items():
-        if k not in fetch or k not in write:
+    calls = {_short(r["Name"]): int(r["Calls"]) for r in stats}
+
+    per = {}  # kernel -> counter -> [values per dispatch]
+    done = []
+    for kind in PROFILE_CMDS:
+        path = os.path.join(d, kind, f"{kind}_counter_collection.csv")
+        if kind == "kt" or not os.path.exists(path):
             continue
-        fk = sum(fetch[k]) / len(fetch[k])
-        wk = sum(write[k]) / len(write[k])
-        traffic = 1024.0 * (fk / f_fac + wk / w_fac)
-        txt = [f"# HBM traffic of {k}: 3M Gaussians, one 1920x1080 view", "",
-               "Commands (from the repository root):", "",
-               "- `" + PROFILE_CMDS["fetch"].format(d=d.rstrip("/")) + "`",
-               "- `" + PROFILE_CMDS["write"].format(d=d.rstrip("/")) + "`",
-               "- `" + PROFILE_CMDS["kt"].format(d=d.rstrip("/")) + "` (durations)", "",
-               f"- FETCH_SIZE per dispatch: {fk:.1f} KiB (mean of {len(fetch[k])} dispatches)",
-               f"- WRITE_SIZE per dispatch: {wk:.1f} KiB",
-               f"- calibration: a 1 GiB device copy reads {f_fac:.4f} GiB by FETCH_SIZE and writes "
-               f"{w_fac:.4f} GiB by WRITE_SIZE; the counters are divided by these factors",
-               f"- average duration: {avg_us.get(k, float('nan')):.1f} us",
-               f"- measured HBM rate: {traffic / (avg_us.get(k, float('nan')) * 1e-6) / 1e9:.1f} GB/s", "",
-               f"traffic_bytes_per_launch: {traffic:.6e}",
-               f"source_sha256: {source_hash()}", ""]
-        open(os.path.join(ROOT, "profiles", f"{stage}_counters.md"), "w").write("\n".join(txt))
+        done.append(kind)
+        for r in csv.DictReader(open(path)):
+            per.setdefault(_short(r["Kernel_Name"]), {}).setdefault(r["Counter_Name"], []).append(
+                float(r["Counter_Value"]))
+    mean = {k: {c: sum(v) / len(v) for c, v in cs.items()} for k, cs in per.items()}
+    gib_kib = float(1 << 20)
+    cp = mean.get(COPY_KERNEL, {})
+    f_fac = max(per.get(COPY_KERNEL, {}).get("FETCH_SIZE", [gib_kib])) / gib_kib
+    w_fac = max(per.get(COPY_KERNEL, {}).get("WRITE_SIZE", [gib_kib])) / gib_kib
+    txt = ["# Counters per kernel: 3M Gaussians, one 1920x1080 view, fwd+bwd step", "",
+           "Commands (from the repository root), one counter pass per run:", ""]
+    txt += ["- `" + PROFILE_CMDS[k].format(d=dd) + "`" for k in ["kt"] + done]
+    txt += ["", f"Calibration: a 1 GiB device copy reads {f_fac:.4f} GiB by FETCH_SIZE and writes {w_fac:.4f} GiB "
+                f"by WRITE_SIZE; 'traffic' divides the two counters by these factors.  'dram' is 32 B x the "
+                f"32-byte read, write and atomic requests the L2 sends to DRAM (no calibration; the copy reads "
+                f"{32 * cp.get('TCC_EA0_RDREQ_DRAM_32B_sum', 0) / 2 ** 30:.3f} GiB and writes "
+                f"{32 * cp.get('TCC_EA0_WRREQ_WRITE_DRAM_32B_sum', 0) / 2 ** 30:.3f} GiB by it).  VALU lane-ops "
+                f"= 64 x SQ_INSTS_VALU (wave64 instructions issued).", "",
+           "| kernel | calls | avg us | traffic MB | dram MB | GB/s (traffic) | VALU instr (M) | LDS instr (M) | "
+           "VALUBusy % | VALUUtil % | LDS bank conflict % | mem stalled % |",
+           "|---|---|---|---|---|---|---|---|---|---|---|---|"]
+    machine = []
+    for k in sorted(mean, key=lambda x: -avg_us.get(x, 0.0)):
+        c = mean[k]
+        rec = {"avg_us": avg_us.get(k), "calls": calls.get(k)}
+        if "FETCH_SIZE" in c and "WRITE_SIZE" in c:
+            rec["traffic_bytes"] = 1024.0 * (c["FETCH_SIZE"] / f_fac + c["WRITE_SIZE"] / w_fac)
+        if "TCC_EA0_RDREQ_DRAM_32B_sum" in c:
+            rec["dram_read_bytes"] = 32.0 * c["TCC_EA0_RDREQ_DRAM_32B_sum"]
+            rec["dram_write_bytes"] = 32.0 * (c.get("TCC_EA0_WRREQ_WRITE_DRAM_32B_sum", 0.0) +
+                                             c.get("TCC_EA0_WRREQ_ATOMIC_DRAM_32B_sum", 0.0))
+        rec.update({n: c[n] for n in c})
+        machine.append(f"counters[{k}]: " + json.dumps(rec, sort_keys=True))
+        us = avg_us.get(k, float("nan"))
+        tr = rec.get("traffic_bytes")
+        dr = (rec["dram_read_bytes"] + rec["dram_write_bytes"]) if "dram_read_bytes" in rec else None
+
+        def f(x, scale=1.0, fmt="{:.1f}"):
+            return fmt.format(x * scale) if x is not None else "-"
+        txt.append(f"| {k} | {calls.get(k, '-')} | {us:.1f} | {f(tr, 1e-6)} | {f(dr, 1e-6)} | "
+                   f"{f(tr / (us * 1e-6) / 1e9 if tr and us == us else None)} | {f(c.get('SQ_INSTS_VALU'), 1e-6, '{:.2f}')} | "
+                   f"{f(c.get('SQ_INSTS_LDS'), 1e-6, '{:.2f}')} | {f(c.get('VALUBusy'))} | {f(c.get('VALUUtilization'))} | "
+                   f"{f(c.get('LDSBankConflict'))} | {f(c.get('MemUnitStalled'))} |")
+    txt += ["", "Machine-readable (mean per dispatch):", ""] + machine + ["", f"source_sha256: {sha}", ""]
+    open(COUNTERS_MD, "w").write("\n".join(txt))
     print(f"wrote profiles/ from {d}")
 
 
@@ -475,6 +655,17 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_step = 1e3 * wall / args.steps
+    # the same step with the backward re-deriving projection and lists
+    for _ in range(2):
+        step.run(record=False, recompute=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        step.run(record=False, recompute=True)
+    torch.cuda.synchronize()
+    ms_recompute = 1e3 * (time.perf_counter() - t1) / args.steps
+    step.run(record=False)  # leave the kept-lists state for the figures below
+    torch.cuda.synchronize()
     med = {k: float(np.median(v)) for k, v in step.times.items()}
     avg = {k: float(np.mean(v)) for k, v in step.times.items()}
     st = step.stats
@@ -484,20 +675,73 @@ def main():
     n_vis = int(st.n_visible)
     n_act = int(step.active.sum().item()) if step.active is not None else n
     ev_fwd, ev_bwd = pair_evaluations(step)
-    work = {
-        "render_fwd": ("alu", ev_fwd * FLOPS_FWD_PER_EVAL / 1e12, "TFLOP/s", PEAK_FP32_TFLOPS),
-        "render_bwd": ("alu", ev_bwd * FLOPS_BWD_PER_EVAL / 1e12, "TFLOP/s", PEAK_FP32_TFLOPS),
-        "project": ("hbm", n * PROJECT_BYTES_PER_RECORD / 1e9, "GB/s", PEAK_HBM_GBS),
-        "project_bwd": ("hbm", (n_act * PROJECT_BWD_BYTES_PER_ACTIVE + (n - n_act) * PROJECT_BWD_BYTES_PER_INACTIVE)
-                        / 1e9, "GB/s", PEAK_HBM_GBS),
+    ni, nrec, tiles = int(st.n_isect), n * len(wl.cameras), int(st.tiles_total)
+    passes = (int(st.key_bits) + 7) // 8
+    ibits = max(1, (nrec - 1).bit_length())
+    pair_pass = 16 if int(st.key_bits) + ibits <= 64 else 24
+    # algorithmic bytes per step of each stage (kernels table)
+    alg = {
+        "project": n * PROJECT_BYTES_PER_RECORD,
+        "bin_count": nrec * 20,
+        "bin_sort": nrec * 20 + ni * 8 + ni * 8 + passes * pair_pass * ni + ni * 12 + tiles * 20,
+        "render_fwd": ni * RENDER_FWD_BYTES_PER_PAIR + P * RENDER_FWD_BYTES_PER_PIXEL,
+        "loss": P * 3 * 12,
+        "render_bwd": ni * RENDER_BWD_BYTES_PER_PAIR + P * RENDER_BWD_BYTES_PER_PIXEL + ni * act_frac * 36,
+        "project_bwd": n_act * PROJECT_BWD_BYTES_PER_ACTIVE + (n - n_act) * PROJECT_BWD_BYTES_PER_INACTIVE,
     }
-    dom = max(work.keys(), key=lambda k: avg[k])
-    bound, units, unit, peak = work[dom]
-    achieved = units / (avg[dom] * 1e-3)
-    stages = {k: {"ms": round(avg[k], 4)} for k in step.names}
-    for k, (b, u, un, pk) in work.items():
-        a = u / (avg[k] * 1e-3)
-        stages[k].update({"bound": b, "achieved": round(a, 3), "unit": un, "frac": round(a / pk, 4)})
+    cnt = profile_counters()
+    kt_steps = 3  # steps of the kernel-trace profile run (PROFILE_CMDS["kt"])
+    stages = {}
+    for k in step.names:
+        a = alg[k] / (avg[k] * 1e-3) / 1e9
+        e = {"ms": round(avg[k], 4), "bytes_algorithmic": int(alg[k]), "gbs_algorithmic": round(a, 1),
+             "frac_hbm_algorithmic": round(a / PEAK_HBM_GBS, 4)}
+        ks = [x for x in STAGE_KERNELS[k] if x in cnt]
+        if ks:
+            per_step = {x: (cnt[x].get("calls") or kt_steps) / kt_steps for x in ks}
+            kus = sum(cnt[x]["avg_us"] * per_step[x] for x in ks if cnt[x].get("avg_us"))
+            e["kernel_us_profiled"] = round(kus, 1)
+            tr = [cnt[x].get("traffic_bytes") for x in ks]
+            if all(t is not None for t in tr):
+                tb = sum(t * per_step[x] for t, x in zip(tr, ks))
+                e["traffic_bytes"] = int(tb)
+                e["traffic_over_algorithmic"] = round(tb / alg[k], 3)
+            dr = [cnt[x].get("dram_read_bytes") for x in ks]
+            if all(t is not None for t in dr):
+                e["dram_bytes"] = int(sum((cnt[x]["dram_read_bytes"] + cnt[x]["dram_write_bytes"]) * per_step[x]
+                                          for x in ks))
+            if k in ("render_fwd", "render_bwd") and "SQ_INSTS_VALU" in cnt[ks[0]]:
+                lane_ops = 64.0 * cnt[ks[0]]["SQ_INSTS_VALU"]
+                e["valu_lane_ops"] = lane_ops
+                e["valu_tops"] = round(lane_ops / (avg[k] * 1e-3) / 1e12, 3)
+                e["frac_valu"] = round(lane_ops / (avg[k] * 1e-3) / 1e12 / PEAK_VALU_TOPS, 4)
+                for m in ("VALUBusy", "VALUUtilization", "LDSBankConflict", "MemUnitStalled"):
+                    if m in cnt[ks[0]]:
+                        e[m] = round(cnt[ks[0]][m], 2)
+        stages[k] = e
+    both = avg["bin_count"] + avg["bin_sort"]
+    stages["bin_count_and_sort"] = {"ms": round(both, 4), "frac_hbm_algorithmic": round(
+        (alg["bin_count"] + alg["bin_sort"]) / (both * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
+    kus = [stages[k].get("kernel_us_profiled") for k in ("bin_count", "bin_sort")]
+    if all(x is not None for x in kus):
+        stages["bin_count_and_sort"]["kernel_us_profiled"] = round(sum(kus), 1)
+        stages["bin_count_and_sort"]["frac_hbm_algorithmic_kernel_time"] = round(
+            (alg["bin_count"] + alg["bin_sort"]) / (sum(kus) * 1e-6) / 1e9 / PEAK_HBM_GBS, 4)
+    dom = max(("project", "render_fwd", "render_bwd", "project_bwd"), key=lambda k: avg[k])
+    sd = stages[dom]
+    if dom in ("render_fwd", "render_bwd"):
+        roof = {"bound": "alu", "kernel": STAGE_KERNELS[dom][0], "achieved": sd.get("valu_tops"),
+                "peak": PEAK_VALU_TOPS, "unit": "T VALU lane-op/s", "frac": sd.get("frac_valu"),
+                "hbm_gbs_algorithmic": sd["gbs_algorithmic"], "hbm_frac_algorithmic": sd["frac_hbm_algorithmic"]}
+    else:
+        roof = {"bound": "hbm", "kernel": STAGE_KERNELS[dom][0], "achieved": sd["gbs_algorithmic"],
+                "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": sd["frac_hbm_algorithmic"]}
+    roof["traffic"] = sd.get("traffic_bytes")
+    roof["dram_bytes"] = sd.get("dram_bytes")
+    roof["traffic_over_algorithmic"] = sd.get("traffic_over_algorithmic")
+    for m in ("VALUBusy", "VALUUtilization", "LDSBankConflict", "MemUnitStalled"):
+        if m in sd:
+            roof[m] = sd[m]
     out = {
         "metric": "fwd+bwd ms/step @3M Gaussians 1080p; served views/s + p50/p99 latency",
         "value": round(ms_step, 4),
@@ -506,6 +750,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(ms_step, 4),
+        "ms_per_step_recompute": round(ms_recompute, 4),
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
@@ -516,8 +761,7 @@ def main():
                    "n_visible": n_vis, "n_isect": int(st.n_isect), "key_bits": int(st.key_bits),
                    "included_pairs": int(nc), "pair_evaluations_fwd": int(ev_fwd),
                    "pair_evaluations_bwd": int(ev_bwd)},
-        "roofline": {"bound": bound, "kernel": dom, "achieved": round(achieved, 3), "peak": peak, "unit": unit,
-                     "frac": round(achieved / peak, 5), "traffic": traffic_from_profiles(dom)},
+        "roofline": roof,
         "stages": stages,
     }
     if not args.no_criteria:
@@ -525,9 +769,9 @@ def main():
     if not args.no_multiview:
         out["multiview"] = multiview_bench(5, 2)
     if not args.no_serving:
-        out["serving"] = serving_bench(args.serving_requests)
+        out["serving"] = serving_bench(args.serving_requests, args.serving_warmup)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample_pixels)
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_cores)
     print(json.dumps(out), flush=True)
 
 

@@ -323,9 +323,13 @@ def poisson_arrivals(qps: float, count: int, seed: int) -> List[float]:
     return list(np.cumsum(g.exponential(1.0 / qps, size=count)))
 
 
-def drive(server: Server, requests: Sequence, arrivals: Sequence[float]) -> Dict[str, float]:
+def drive(server: Server, requests: Sequence, arrivals: Sequence[float], warmup: int = 0) -> Dict[str, Any]:
     """Submit ``requests`` [(scene_id, camera)] at the given offsets (seconds)
-    from now, wait for all, and return the server's latency / throughput stats."""
+    from now, wait for all, and return latency / throughput statistics of the
+    requests after the first ``warmup`` (which run but are not counted):
+    p50 / p99 / mean latency, views/s from the first counted arrival to the
+    last counted completion, the offered rate, and the distribution of the
+    batch sizes the counted requests were rendered in."""
     t0 = server.clock()
     futs = []
     for (sid, cam), a in zip(requests, arrivals):
@@ -333,9 +337,24 @@ def drive(server: Server, requests: Sequence, arrivals: Sequence[float]) -> Dict
         if a > now:
             time.sleep(a - now)
         futs.append(server.submit(sid, cam, arrival=t0 + a))
-    for f in futs:
-        f.result(timeout=600)
-    t1 = server.clock()
-    st = server.stats(t0, t1)
-    st["offered_qps"] = len(arrivals) / max(arrivals[-1], 1e-9)
+    res = [f.result(timeout=600) for f in futs]
+    w = max(0, min(int(warmup), len(res) - 1))
+    meas, arr = res[w:], list(arrivals[w:])
+    lat = sorted(r.latency for r in meas)
+    n = len(lat)
+
+    def pct(p):
+        return lat[min(n - 1, int(round(p / 100.0 * (n - 1))))]
+
+    done = max(a + r.latency for a, r in zip(arr, meas))
+    span = done - arr[0]
+    sizes: Dict[int, int] = {}
+    for r in meas:
+        sizes[r.batch_size] = sizes.get(r.batch_size, 0) + 1
+    st: Dict[str, Any] = {"completed": n, "warmup": w, "p50_ms": 1e3 * pct(50), "p99_ms": 1e3 * pct(99),
+                          "mean_ms": 1e3 * sum(lat) / n, "mean_batch": sum(r.batch_size for r in meas) / n,
+                          "batch_size_counts": {str(k): sizes[k] for k in sorted(sizes)},
+                          "peak_reserved_gb": server.peak_reserved / 1e9,
+                          "views_per_s": n / span if span > 0 else float("inf")}
+    st["offered_qps"] = (len(arr) - 1) / max(arr[-1] - arr[0], 1e-9) if len(arr) > 1 else 0.0
     return st
