@@ -16,12 +16,13 @@
  *    `stream` completes; host pointers (marked [host]) are read before the
  *    call returns.  The library keeps no pointer after return and allocates
  *    nothing: scratch memory arrives as (ws, ws_bytes), sized by the matching
- *    *_workspace_size() query, 256-byte aligned.
+ *    *_workspace_size() query, 256-byte aligned.  (The one exception,
+ *    gs_sort_pairs_static, uses a library-owned device array instead.)
  *  - Asynchrony: work is enqueued on `stream` (a hipStream_t; NULL = the null
  *    stream).  Only gs_bin_count synchronises (it returns the pair count).
  *  - Reentrancy: no global mutable state (apart from the diagnostic
- *    gs_sort_set_spin_limit); concurrent calls on different streams with
- *    disjoint buffers are safe.
+ *    gs_sort_set_spin_limit and the scratch array of gs_sort_pairs_static);
+ *    concurrent calls on different streams with disjoint buffers are safe.
  *  - Views: V cameras (1 <= V <= GS_MAX_VIEWS) are rendered in one launch per
  *    stage.  A record is one (view, Gaussian) pair, index r = v * n + i.
  *    Per-pixel arrays are indexed by the global pixel id
@@ -263,6 +264,22 @@ int32_t gs_sort_status(const void* ws, void* stream);
  * the error path above without any wait).  Process-wide; affects sorts
  * enqueued after the call. */
 void gs_sort_set_spin_limit(uint32_t polls);
+
+/* Allocation-free sort, for callers that cannot allocate device memory (code
+ * under graph capture, tight serving loops, harnesses that forbid allocation).
+ * Same result as gs_sort_pairs: in-place stable ascending sort of (keys, vals)
+ * [dev, n] on key bits [0, key_bits) (1..64).  The scratch memory is a
+ * library-owned device array of fixed size per GPU (sort workspace for
+ * GS_SORT_STATIC_MAX_PAIRS pairs, about 14 MB), held until the process ends:
+ * n <= GS_SORT_STATIC_MAX_PAIRS, GS_ERR_CAPACITY otherwise.  Runs on the
+ * current device; `stream` must belong to it.  All calls on one GPU share the
+ * array, so calls that overlap on one GPU (other streams or threads) race.
+ * status [dev, u32, may be NULL] receives the sort's status flag once the sort
+ * completes on the stream: 0 for a valid order, nonzero when a look-back gave
+ * up (see gs_sort_status).  Allocates nothing and does not synchronise. */
+#define GS_SORT_STATIC_MAX_PAIRS (1 << 20)
+int32_t gs_sort_pairs_static(uint64_t* keys, uint32_t* vals, int64_t n, int32_t key_bits, uint32_t* status,
+                             void* stream);
 
 /* a5 (+a6) -- forward compositing, Eq. (1): per pixel, front to back over its
  * tile's list: alpha = min(alpha_max, opacity * G2D); skip when alpha <

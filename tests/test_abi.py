@@ -130,3 +130,13 @@ def test_criteria_argument_errors_on_host(L):
     assert lib.gs_densify_select(fake, fake, fake, 10, 1e-4, 0.1, None, None, None) == L.GS_ERR_NULL
     assert lib.gs_densify_select(None, fake, fake, 10, 1e-4, 0.1, fake, None, None) == L.GS_ERR_NULL
     assert lib.gs_densify_select(None, None, None, 0, 1e-4, 0.1, None, None, None) == L.GS_OK  # nothing to do
+
+
+def test_static_sort_capacity_on_host(L):
+    """Sizes beyond the allocation-free sort's fixed scratch are rejected
+    before any device work."""
+    lib = L.lib()
+    fake = ctypes.c_void_p(0x1000)
+    assert lib.gs_sort_pairs_static(fake, fake, L.GS_SORT_STATIC_MAX_PAIRS + 1, 40, None, None) == L.GS_ERR_CAPACITY
+    assert lib.gs_sort_pairs_static(fake, fake, 10, 0, None, None) == L.GS_ERR_SHAPE
+    assert lib.gs_sort_pairs_static(None, None, 10, 40, None, None) == L.GS_ERR_NULL
