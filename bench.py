@@ -189,6 +189,34 @@ def pair_evaluations(step):
     return float(fwd), float(last.sum().item())
 
 
+def deterministic_backward_ms(step, reps: int = 10) -> float:
+    """Time of the pixel backward of the last timed step with the ordered,
+    atomic-free reduction (bitwise-reproducible gradients), workspace reused."""
+    from paper_2411_12788_amd import _lib as L
+    R = step.R
+    ni = int(step.binned.stats.n_isect)
+    ws = torch.empty(max(L.lib().gs_render_backward_det_workspace_size(ni), 1), dtype=torch.uint8, device="cuda")
+
+    def one():
+        step.grad2d.zero_()
+        R.render_backward_pixels(step.proj, step.binned, step.cams, step.n, step.opts, step.frame, step.dldc,
+                                 step.active, step.grad2d, deterministic=True, det_ws=ws)
+
+    one()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    total = 0.0
+    for _ in range(reps):
+        step.grad2d.zero_()
+        e0.record()
+        R.render_backward_pixels(step.proj, step.binned, step.cams, step.n, step.opts, step.frame, step.dldc,
+                                 step.active, step.grad2d, deterministic=True, det_ws=ws)
+        e1.record()
+        torch.cuda.synchronize()
+        total += e0.elapsed_time(e1)
+    return total / reps
+
+
 def criteria_bench(step, reps: int = 10):
     """Time the culling/densification criteria on the accumulations of the last
     timed step: per-view visibility and critical set (both threshold readings),
@@ -764,6 +792,7 @@ def main():
         "roofline": roof,
         "stages": stages,
     }
+    out["stages"]["render_bwd_deterministic"] = {"ms": round(deterministic_backward_ms(step), 4)}
     if not args.no_criteria:
         out["criteria"] = criteria_bench(step)
     if not args.no_multiview:

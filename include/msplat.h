@@ -225,10 +225,13 @@ int32_t gs_bin_sort(const gs_projected_t* proj, const gs_camera_t* cams, int32_t
 
 /* Processing order of the tiles for the compositing kernels: tile ids
  * [dev, u32 tiles_total] grouped by the bit length of their list length,
- * longest lists first (order inside a group unspecified).  Work per tile
- * varies by orders of magnitude; starting the long lists first keeps them off
- * the critical path and spreads them over all XCDs.  Results do not depend on
- * the order.  Also produced by gs_bin_sort when tile_order is non-NULL. */
+ * longest lists first, ascending tile id inside a group (so the order is a
+ * function of the ranges alone).  Work per tile varies by orders of
+ * magnitude; starting the long lists first keeps them off the critical path
+ * and spreads them over all XCDs.  The compositing kernels also take from the
+ * order which tiles to share between four workgroups; that changes results
+ * only by float32 rounding, and the same order gives bitwise the same
+ * results.  Also produced by gs_bin_sort when tile_order is non-NULL. */
 size_t gs_tile_order_workspace_size(void);
 int32_t gs_tile_order(const uint32_t* ranges, int32_t tiles_total, uint32_t* tile_order, void* ws, size_t ws_bytes,
                       void* stream);
@@ -320,6 +323,27 @@ int32_t gs_render_backward_pixels(const gs_projected_t* proj, const uint32_t* va
                                   const uint32_t* tile_order, const gs_camera_t* cams, int32_t V, int64_t n,
                                   const gs_opts_t* opts, const float* t_final, const uint32_t* last,
                                   const float* dl_dcolor, const uint8_t* active, float* grad2d, void* stream);
+
+/* a7 with a deterministic reduction (Sec. 2.3 surveys how rasterizers reduce
+ * the backward's gradient atomics; this variant orders the reduction instead
+ * of only shortening it): the same result as gs_render_backward_pixels up to
+ * float32 summation order, added into grad2d, but bitwise the same from run to
+ * run for the same inputs and tile_order.  Each 4x4 pixel group's summed
+ * partials of an entry are stored in that (entry, group) slot instead of being
+ * added with float atomics; then per (tile, entry) the sixteen groups' slots
+ * are added in group order, and per record its pairs' sums in emission order
+ * (the tiles of its box, row-major, as gs_emit_keys emits them).  offsets
+ * [dev, u32 V*n] and n_isect are those of the gs_bin_count call whose pairs
+ * vals / ranges hold; ws [dev] sized by gs_render_backward_det_workspace_size
+ * (n_isect) (616 bytes per pair: slot masks, sixteen 9-float slots, one
+ * 9-float sum); n_isect < 2^32. */
+size_t gs_render_backward_det_workspace_size(int64_t n_isect);
+int32_t gs_render_backward_pixels_det(const gs_projected_t* proj, const uint32_t* vals, const uint32_t* ranges,
+                                      const uint32_t* tile_order, const uint32_t* offsets, const gs_camera_t* cams,
+                                      int32_t V, int64_t n, int64_t n_isect, const gs_opts_t* opts,
+                                      const float* t_final, const uint32_t* last, const float* dl_dcolor,
+                                      const uint8_t* active, float* grad2d, void* ws, size_t ws_bytes,
+                                      void* stream);
 
 /* a8 alone: chain rule of gs_project from grad2d to the parameters (written,
  * summed over views; rows with active[i] == 0 written as 0; records with

@@ -99,6 +99,9 @@ _SIGS = {
                                    c_p, c_p, P(Grads), c_p]),
     "gs_render_backward_pixels": (c_i32, [P(Projected), c_p, c_p, c_p, P(Camera), c_i32, c_i64, P(Opts), c_p, c_p,
                                           c_p, c_p, c_p, c_p]),
+    "gs_render_backward_det_workspace_size": (c_sz, [c_i64]),
+    "gs_render_backward_pixels_det": (c_i32, [P(Projected), c_p, c_p, c_p, c_p, P(Camera), c_i32, c_i64, c_i64,
+                                              P(Opts), c_p, c_p, c_p, c_p, c_p, c_p, c_sz, c_p]),
     "gs_project_backward": (c_i32, [P(Scene), P(Projected), P(Camera), c_i32, P(Opts), c_p, c_p, P(Grads), c_p]),
     "gs_l1_loss_grad": (c_i32, [c_p, c_p, c_i64, c_p, c_p, c_p]),
     "gs_fill_u32": (c_i32, [c_p, c_u32, c_i64, c_p]),

@@ -9,7 +9,8 @@ the projection backward.  With ``save_lists=True`` the forward's records and
 lists are kept instead (more memory, no recompute); both modes run the same
 kernels on bit-identical lists, so their gradients differ only by the
 summation order of the float atomics that gather per-pixel partials
-(~1e-6 relative).
+(~1e-6 relative); with ``deterministic=True`` the pixel backward uses the
+library's ordered reduction instead and the two modes agree bitwise.
 
 Differentiable output: colour [3, P].  Depth and the argmax index are marked
 non-differentiable; per-Gaussian accumulations, when requested, are returned
@@ -26,7 +27,8 @@ from . import raster as R
 
 class RasterizeFn(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, means, scales, quats, opacity, sh, cams, opts, sh_degree, active, save_lists, accum):
+    def forward(ctx, means, scales, quats, opacity, sh, cams, opts, sh_degree, active, save_lists, accum,
+                deterministic):
         scene = R.DeviceScene(means.contiguous(), scales.contiguous(), quats.contiguous(), opacity.contiguous(),
                               sh.contiguous(), int(sh_degree))
         proj = R.project(scene, cams, opts)
@@ -34,6 +36,7 @@ class RasterizeFn(torch.autograd.Function):
         frame = R.render_forward(scene, proj, binned, cams, opts, accum=accum, extras=False)
         ctx.cams, ctx.opts, ctx.sh_degree = cams, opts, int(sh_degree)
         ctx.active = active
+        ctx.deterministic = bool(deterministic)
         ctx.lists = (proj, binned) if save_lists else None
         ctx.save_for_backward(scene.means, scene.scales, scene.quats, scene.opacity, scene.sh, frame.t_final,
                               frame.last)
@@ -51,23 +54,23 @@ class RasterizeFn(torch.autograd.Function):
             binned = R.bin(proj, ctx.cams, scene.n)
         frame = R.Frame(None, None, None, t_final, last, None, None)
         grads, _ = R.render_backward(scene, proj, binned, ctx.cams, ctx.opts, frame, dcolor.contiguous(),
-                                     ctx.active)
+                                     ctx.active, deterministic=ctx.deterministic)
         ctx.lists = None
         return (grads["means"], grads["scales"], grads["quats"], grads["opacity"], grads["sh"],
-                None, None, None, None, None, None)
+                None, None, None, None, None, None, None)
 
 
 def rasterize(means: torch.Tensor, scales: torch.Tensor, quats: torch.Tensor, opacity: torch.Tensor,
               sh: torch.Tensor, cams: Sequence, opts: Optional[R.RasterOpts] = None, sh_degree: int = 3,
               active: Optional[torch.Tensor] = None, save_lists: bool = False,
-              accum: Optional[Dict[str, torch.Tensor]] = None):
+              accum: Optional[Dict[str, torch.Tensor]] = None, deterministic: bool = False):
     """Differentiable render of V views.  Layouts as in ``raster.DeviceScene``
     (means [3,n], scales [3,n], quats [4,n], opacity [n], sh [16,3,n]; activated
     scales and opacity).  Returns colour [3, P], depth [P], imax [P] with P the
     total pixel count (views concatenated, row-major within a view)."""
     opts = opts or R.RasterOpts()
     return RasterizeFn.apply(means, scales, quats, opacity, sh, list(cams), opts, sh_degree, active, save_lists,
-                             accum)
+                             accum, deterministic)
 
 
 def split_views(x: torch.Tensor, cams: Sequence):

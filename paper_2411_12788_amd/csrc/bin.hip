@@ -265,9 +265,9 @@ __global__ __launch_bounds__(kBlock) void k_ranges(const uint64_t* __restrict__ 
 }
 
 // ---------------------------------------------------------------------------
-// tile processing order: counting sort of tiles by the bit length of their
-// list length, longest first (bucket 0 = lists of 2^31.. entries, bucket 32 =
-// empty tiles)
+// tile processing order: stable counting sort of tiles by the bit length of
+// their list length, longest first (bucket 0 = lists of 2^31.. entries,
+// bucket 32 = empty tiles), ties in ascending tile id
 // ---------------------------------------------------------------------------
 constexpr int kOrderBuckets = 33;
 
@@ -298,22 +298,41 @@ __global__ void k_order_scan(uint32_t* __restrict__ hist) {
   }
 }
 
-// Positions are taken per workgroup: LDS counters rank the tiles of each
-// bucket, then one global atomic per (workgroup, bucket) reserves the run.
-// (Per-tile global atomics on ~16 cursors serialise in the L2.)
+// Stable scatter: inside a bucket the tiles keep ascending tile id, so the
+// order (and with it every per-tile decision the compositing kernels take
+// from it) is the same from run to run.  A tile's position is its bucket's
+// base, plus the tiles of that bucket in earlier workgroups (each workgroup
+// counts them itself: a re-read of the ranges before its chunk, a few
+// thousand tiles per view), plus its rank in its own workgroup (per-wave
+// ballot match of the bucket, then the counts of the earlier waves).
 __global__ __launch_bounds__(kBlock) void k_order_scatter(const uint32_t* __restrict__ ranges, int32_t tiles,
-                                                          uint32_t* __restrict__ cursor, uint32_t* __restrict__ order) {
-  __shared__ uint32_t cnt[kOrderBuckets], base[kOrderBuckets];
-  if (threadIdx.x < kOrderBuckets) cnt[threadIdx.x] = 0;
+                                                          const uint32_t* __restrict__ bucket_base,
+                                                          uint32_t* __restrict__ order) {
+  __shared__ uint32_t before[kOrderBuckets];
+  __shared__ uint32_t wcnt[kBlock / kWave][kOrderBuckets];
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+  if (threadIdx.x < kOrderBuckets) before[threadIdx.x] = 0;
+  for (int k = threadIdx.x; k < (kBlock / kWave) * kOrderBuckets; k += kBlock) (&wcnt[0][0])[k] = 0;
   __syncthreads();
-  const int32_t t = blockIdx.x * kBlock + threadIdx.x;
-  const int b = t < tiles ? order_bucket(ranges, t) : 0;
-  const uint32_t local = t < tiles ? atomicAdd(&cnt[b], 1u) : 0u;
+  const int32_t chunk0 = blockIdx.x * kBlock;
+  for (int32_t t = threadIdx.x; t < chunk0; t += kBlock) atomicAdd(&before[order_bucket(ranges, t)], 1u);
+  const int32_t t = chunk0 + threadIdx.x;
+  const bool in = t < tiles;
+  const uint32_t b = in ? (uint32_t)order_bucket(ranges, t) : 63u;
+  // lanes of this wave with the same bucket (6 bits cover buckets 0..32 and 63)
+  uint64_t m = ~0ull;
+#pragma unroll
+  for (int bit = 0; bit < 6; ++bit) {
+    const uint64_t bb = __ballot((b >> bit) & 1u);
+    m &= ((b >> bit) & 1u) ? bb : ~bb;
+  }
+  const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (kWave - lane));
+  const uint32_t rank = (uint32_t)__popcll(m & lt);
+  if (in && rank == 0) wcnt[w][b] = (uint32_t)__popcll(m);
   __syncthreads();
-  if (threadIdx.x < kOrderBuckets && cnt[threadIdx.x]) base[threadIdx.x] = atomicAdd(cursor + threadIdx.x, cnt[threadIdx.x]);
-  __syncthreads();
-  if (t >= tiles) return;
-  const uint32_t pos = base[b] + local;
+  if (!in) return;
+  uint32_t pos = bucket_base[b] + before[b] + rank;
+  for (int k = 0; k < w; ++k) pos += wcnt[k][b];
   if (pos < (uint32_t)tiles) order[pos] = (uint32_t)t;
 }
 
@@ -369,7 +388,8 @@ static int32_t launch_tile_order(const uint32_t* ranges, int32_t tiles, uint32_t
   if (r != GS_OK) return r;
   hipLaunchKernelGGL(k_order_hist, dim3(grid_1d(tiles)), dim3(kBlock), 0, st, ranges, tiles, hist);
   hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(64), 0, st, hist);
-  hipLaunchKernelGGL(k_order_scatter, dim3(grid_1d(tiles)), dim3(kBlock), 0, st, ranges, tiles, hist, order);
+  hipLaunchKernelGGL(k_order_scatter, dim3(grid_1d(tiles)), dim3(kBlock), 0, st, ranges, tiles,
+                     (const uint32_t*)hist, order);
   MS_CHECK_LAUNCH("tile_order");
   return GS_OK;
 }

@@ -689,6 +689,26 @@ __device__ __forceinline__ Sum9 row_sum9(const float (&p)[9], int lane) {
   return r;
 }
 
+// One group's summed partials of one entry leave the row: nine lanes add them
+// to the record's 2D gradient with float atomics, or (deterministic
+// reduction) store them in the entry's slot for this group (list position j,
+// group g16 of the tile's sixteen 4x4 groups) and mark the slot in the
+// entry's mask.  A slot is written at most once: each group walks an entry at
+// most once.
+template <bool DET>
+__device__ __forceinline__ void emit_partial(float* __restrict__ g2d, float* __restrict__ part,
+                                             uint32_t* __restrict__ pmask, uint32_t tag, uint32_t j, int g16,
+                                             int slot, uint64_t cm, int grp, const Sum9& r) {
+  if (slot < 0 || ((cm >> (16 * grp)) & 0xffffull) == 0) return;
+  const float val = slot == 8 ? r.v8 : r.v;
+  if (DET) {
+    part[((int64_t)j * 16 + g16) * kG2d + slot] = val;
+    if (slot == 8) atomicOr(pmask + j, 1u << g16);
+  } else {
+    atomicAdd(g2d + (int64_t)(tag & 0x7fffffffu) * kG2d + slot, val);
+  }
+}
+
 // Same lane layout and group streams as the forward, walking rounds and
 // entries back to front from the largest `last` of the workgroup.  Per pixel:
 // restore the transmittance in front of the Gaussian (T /= 1 - alpha), form
@@ -697,7 +717,7 @@ __device__ __forceinline__ Sum9 row_sum9(const float (&p)[9], int lane) {
 // per-pixel state but emit no gradient.  The nine partials of a group's entry
 // are summed over its 16 lanes in registers and added by nine of its lanes
 // to the record's 2D gradient.
-template <bool MASKED>
+template <bool MASKED, bool DET>
 __global__ __launch_bounds__(kBlock) void k_render_bwd(const float* __restrict__ rec, const int32_t* __restrict__ bin,
                                                        const uint32_t* __restrict__ vals,
                                                        const uint32_t* __restrict__ ranges,
@@ -706,6 +726,7 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(const float* __restrict__
                                                        const uint32_t* __restrict__ last,
                                                        const float* __restrict__ dldc,
                                                        const uint8_t* __restrict__ active, float* __restrict__ g2d,
+                                                       float* __restrict__ part, uint32_t* __restrict__ pmask,
                                                        KOpts op, ViewSet vs) {
   __shared__ float4 s_r0[kBatch], s_r1[kBatch], s_r2[kBatch], s_r3[kBatch];
   __shared__ int2 s_box[kBatch];
@@ -728,6 +749,9 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(const float* __restrict__
   const uint32_t start = uload(ranges + 2 * tile), end = uload(ranges + 2 * tile + 1);
   const int64_t vbase = (int64_t)v * n;
   const int64_t nrec = (int64_t)vs.count * n;
+  // the row's 4x4 group among the tile's sixteen (8x8 quarter, then 4x4 group
+  // inside it), the same pixels whether or not the tile is split
+  const int g16 = rp ? wi.quarter * 4 + wv : wv * 4 + grp;
   set_wave_priority(end - start);
   const int64_t P = vs.pixels_total;
   const int64_t gp = cam.pixel_base + (int64_t)py * cam.width + px;
@@ -850,8 +874,7 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(const float* __restrict__
         const uint64_t cm = __ballot(act);
         if (cm != 0) {
           const Sum9 r = row_sum9(pv, lane);
-          if (slot >= 0 && ((cm >> (16 * grp)) & 0xffffull) != 0)
-            atomicAdd(g2d + (int64_t)(tag & 0x7fffffffu) * kG2d + slot, slot == 8 ? r.v8 : r.v);
+          emit_partial<DET>(g2d, part, pmask, tag, base + (uint32_t)kr, g16, slot, cm, grp, r);
         }
       }
       // kBwdUnroll entries of the group's stream per iteration, latest first:
@@ -923,8 +946,7 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(const float* __restrict__
           if (cm != 0) {
             const Sum9 r = row_sum9(pv[u], lane);
             // the row's entries are shared by its 16 lanes, so the tags are row-uniform
-            if (slot >= 0 && ((cm >> (16 * grp)) & 0xffffull) != 0)
-              atomicAdd(g2d + (int64_t)(tag[u] & 0x7fffffffu) * kG2d + slot, slot == 8 ? r.v8 : r.v);
+            emit_partial<DET>(g2d, part, pmask, tag[u], base + (uint32_t)kk[u], g16, slot, cm, grp, r);
           }
         }
       }
@@ -940,6 +962,85 @@ __global__ void k_zero_f32(float* __restrict__ p, int64_t count) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (; i < count; i += stride) p[i] = 0.f;
+}
+
+// Deterministic gradient reduction.  Step 1, one workgroup per tile: for each
+// entry of the tile's list, the sum of the sixteen groups' slots in group
+// order, stored at the pair's emission index e = offsets[r] + the tile's rank
+// among the tiles the record was emitted for (row-major over its box, only the
+// kept tiles under tile culling), so every record's pairs sit side by side.
+__global__ __launch_bounds__(kBlock) void k_det_tile(const uint32_t* __restrict__ vals,
+                                                     const uint32_t* __restrict__ ranges,
+                                                     const int32_t* __restrict__ bin, const float* __restrict__ rec,
+                                                     float tile_cull, const uint32_t* __restrict__ offsets,
+                                                     const float* __restrict__ part,
+                                                     const uint32_t* __restrict__ pmask, float* __restrict__ tpart,
+                                                     int64_t nrec, int64_t n_isect, ViewSet vs) {
+  const int32_t tile = (int32_t)blockIdx.x;
+  const int32_t v = view_of_tile(vs, tile);
+  const int32_t lt = tile - vs.v[v].tile_base;
+  const int32_t tx = lt % vs.v[v].tiles_x, ty = lt / vs.v[v].tiles_x;
+  const uint32_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
+  for (uint32_t j = start + threadIdx.x; j < end; j += kBlock) {
+    const uint32_t r = vals[j];
+    if ((int64_t)r >= nrec) continue;
+    const int4 b = reinterpret_cast<const int4*>(bin)[r];
+    const int32_t x0 = b.x & 0xffff, x1 = (int32_t)((uint32_t)b.x >> 16);
+    const int32_t y0 = b.y & 0xffff, y1 = (int32_t)((uint32_t)b.y >> 16);
+    const int32_t tx0 = x0 >> 4, tx1 = x1 >> 4, ty0 = y0 >> 4;
+    uint32_t k;
+    if (b.w < (tx1 - tx0 + 1) * ((y1 >> 4) - ty0 + 1)) {
+      // tile culling emitted only the kept tiles: rank among those
+      const float4* R4 = reinterpret_cast<const float4*>(rec + (int64_t)r * kRecFloats);
+      const float4 r0 = R4[0], r1 = R4[1];
+      k = 0;
+      for (int32_t yy = ty0; yy <= ty; ++yy)
+        for (int32_t xx = tx0; xx <= tx1 && (yy < ty || xx < tx); ++xx)
+          k += tile_kept(r0, r1, xx, yy, x0, x1, y0, y1, tile_cull) ? 1u : 0u;
+    } else {
+      k = (uint32_t)((ty - ty0) * (tx1 - tx0 + 1) + (tx - tx0));
+    }
+    const int64_t e = (int64_t)offsets[r] + k;
+    if (e >= n_isect) continue;
+    float acc[kG2d];
+#pragma unroll
+    for (int c = 0; c < kG2d; ++c) acc[c] = 0.f;
+    for (uint32_t m = pmask[j]; m != 0u; m &= m - 1u) {
+      const float* sp = part + ((int64_t)j * 16 + (__builtin_ctz(m))) * kG2d;
+#pragma unroll
+      for (int c = 0; c < kG2d; ++c) acc[c] += sp[c];
+    }
+#pragma unroll
+    for (int c = 0; c < kG2d; ++c) tpart[e * kG2d + c] = acc[c];
+  }
+}
+
+// Step 2, one thread per record: its pairs' sums in emission order (tiles of
+// its box row-major), added to the record's 2D gradient.
+__global__ __launch_bounds__(kBlock) void k_det_record(const int32_t* __restrict__ bin,
+                                                       const uint32_t* __restrict__ offsets,
+                                                       const float* __restrict__ tpart, float* __restrict__ g2d,
+                                                       int64_t nrec, int64_t n_isect) {
+  const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (r >= nrec) return;
+  const int32_t tt = bin[4 * r + 3];
+  if (tt <= 0) return;
+  const int64_t e0 = offsets[r];
+  if (e0 + tt > n_isect) return;
+  float acc[kG2d];
+#pragma unroll
+  for (int c = 0; c < kG2d; ++c) acc[c] = 0.f;
+  for (int32_t k = 0; k < tt; ++k) {
+#pragma unroll
+    for (int c = 0; c < kG2d; ++c) acc[c] += tpart[(e0 + k) * kG2d + c];
+  }
+#pragma unroll
+  for (int c = 0; c < kG2d; ++c) g2d[r * kG2d + c] += acc[c];
+}
+
+size_t det_ws_bytes(int64_t n_isect) {
+  const int64_t ni = n_isect > 0 ? n_isect : 1;
+  return align256((size_t)ni * 4) + align256((size_t)ni * 16 * kG2d * 4) + align256((size_t)ni * kG2d * 4);
 }
 
 template <bool ACC, bool OUT>
@@ -1037,14 +1138,58 @@ int32_t gs_render_backward_pixels(const gs_projected_t* proj, const uint32_t* va
   hipStream_t s = (hipStream_t)stream;
   const dim3 grid(vs.tiles_total + 3 * split_tiles(tile_order, vs.tiles_total));
   if (active)
-    hipLaunchKernelGGL(k_render_bwd<true>, grid, dim3(kBlock), 0, s, proj->rec, proj->bin, vals,
+    hipLaunchKernelGGL((k_render_bwd<true, false>), grid, dim3(kBlock), 0, s, proj->rec, proj->bin, vals,
                        ranges, tile_order, split_tiles(tile_order, vs.tiles_total), n, t_final, last, dl_dcolor,
-                       active, grad2d, op, vs);
+                       active, grad2d, nullptr, nullptr, op, vs);
   else
-    hipLaunchKernelGGL(k_render_bwd<false>, grid, dim3(kBlock), 0, s, proj->rec, proj->bin, vals,
+    hipLaunchKernelGGL((k_render_bwd<false, false>), grid, dim3(kBlock), 0, s, proj->rec, proj->bin, vals,
                        ranges, tile_order, split_tiles(tile_order, vs.tiles_total), n, t_final, last, dl_dcolor,
-                       active, grad2d, op, vs);
+                       active, grad2d, nullptr, nullptr, op, vs);
   MS_CHECK_LAUNCH("render_backward_pixels");
+  return GS_OK;
+}
+
+size_t gs_render_backward_det_workspace_size(int64_t n_isect) { return det_ws_bytes(n_isect); }
+
+int32_t gs_render_backward_pixels_det(const gs_projected_t* proj, const uint32_t* vals, const uint32_t* ranges,
+                                      const uint32_t* tile_order, const uint32_t* offsets, const gs_camera_t* cams,
+                                      int32_t V, int64_t n, int64_t n_isect, const gs_opts_t* opts,
+                                      const float* t_final, const uint32_t* last, const float* dl_dcolor,
+                                      const uint8_t* active, float* grad2d, void* ws, size_t ws_bytes,
+                                      void* stream) {
+  if (!proj || !opts || !ranges || !t_final || !last || !dl_dcolor) { set_error("argument NULL"); return GS_ERR_NULL; }
+  if (n < 0 || n_isect < 0) { set_error("n < 0 or n_isect < 0"); return GS_ERR_SHAPE; }
+  ViewSet vs;
+  int32_t st = build_views(cams, V, &vs);
+  if (st != GS_OK) return st;
+  if ((st = check_records(V, n)) != GS_OK) return st;
+  if (n == 0 || n_isect == 0) return GS_OK;
+  if (!proj->rec || !proj->bin || !grad2d || !vals || !offsets || !ws) { set_error("buffer NULL"); return GS_ERR_NULL; }
+  if (n_isect >= (int64_t(1) << 32)) { set_error("n_isect of 2^32 or more"); return GS_ERR_CAPACITY; }
+  if (ws_bytes < det_ws_bytes(n_isect)) { set_error("deterministic backward workspace too small"); return GS_ERR_CAPACITY; }
+  char* p = (char*)ws;
+  uint32_t* pmask = (uint32_t*)p; p += align256((size_t)n_isect * 4);
+  float* part = (float*)p; p += align256((size_t)n_isect * 16 * kG2d * 4);
+  float* tpart = (float*)p;
+  const KOpts op = make_kopts(opts);
+  hipStream_t s = (hipStream_t)stream;
+  if ((st = launch_fill(pmask, 0u, n_isect, s)) != GS_OK) return st;
+  const dim3 grid(vs.tiles_total + 3 * split_tiles(tile_order, vs.tiles_total));
+  if (active)
+    hipLaunchKernelGGL((k_render_bwd<true, true>), grid, dim3(kBlock), 0, s, proj->rec, proj->bin, vals,
+                       ranges, tile_order, split_tiles(tile_order, vs.tiles_total), n, t_final, last, dl_dcolor,
+                       active, grad2d, part, pmask, op, vs);
+  else
+    hipLaunchKernelGGL((k_render_bwd<false, true>), grid, dim3(kBlock), 0, s, proj->rec, proj->bin, vals,
+                       ranges, tile_order, split_tiles(tile_order, vs.tiles_total), n, t_final, last, dl_dcolor,
+                       active, grad2d, part, pmask, op, vs);
+  MS_CHECK_LAUNCH("render_backward_pixels_det");
+  const int64_t nrec = (int64_t)V * n;
+  hipLaunchKernelGGL(k_det_tile, dim3((unsigned)vs.tiles_total), dim3(kBlock), 0, s, vals, ranges, proj->bin,
+                     proj->rec, proj->tile_cull_log2_alpha, offsets, part, pmask, tpart, nrec, n_isect, vs);
+  hipLaunchKernelGGL(k_det_record, dim3(grid_1d(nrec)), dim3(kBlock), 0, s, proj->bin, offsets, tpart, grad2d, nrec,
+                     n_isect);
+  MS_CHECK_LAUNCH("deterministic reduction");
   return GS_OK;
 }
 

@@ -301,13 +301,24 @@ def _grads_c(g):
 def render_backward(scene: DeviceScene, proj: Projected, binned: Binned, cams, opts: RasterOpts, frame: Frame,
                     dl_dcolor: torch.Tensor, active: Optional[torch.Tensor] = None,
                     grads: Optional[Dict[str, torch.Tensor]] = None, grad2d: Optional[torch.Tensor] = None,
-                    stream=None):
+                    stream=None, deterministic: bool = False):
+    """Pixel backward then projection backward.  With `deterministic` the
+    pixel stage uses the ordered reduction (gradients bitwise the same from
+    run to run); the projection backward is per Gaussian and always is."""
     V, n = len(cams), scene.n
     dev = proj.rec.device
     if grads is None:
         grads = alloc_grads(max(n, 1), dev)
     if grad2d is None:
         grad2d = torch.empty((max(V * n, 1), L.GS_GRAD2D_FLOATS), device=dev)
+    if deterministic:
+        fill_u32(grad2d, 0, stream)
+        render_backward_pixels(proj, binned, cams, n, opts, frame, dl_dcolor, active, grad2d, stream,
+                               deterministic=True)
+        L.check(L.lib().gs_project_backward(ctypes.byref(scene.c()), ctypes.byref(proj.c()), cameras(cams), V,
+                                            ctypes.byref(opts.c()), _ptr(grad2d), _ptr(active),
+                                            ctypes.byref(_grads_c(grads)), _stream(stream)), "gs_project_backward")
+        return grads, grad2d
     L.check(L.lib().gs_render_backward(ctypes.byref(scene.c()), ctypes.byref(proj.c()), _ptr(binned.vals),
                                        _ptr(binned.ranges), _ptr(binned.order), cameras(cams), V,
                                        ctypes.byref(opts.c()),
@@ -318,16 +329,37 @@ def render_backward(scene: DeviceScene, proj: Projected, binned: Binned, cams, o
 
 
 def render_backward_pixels(proj: Projected, binned: Binned, cams, n: int, opts: RasterOpts, frame: Frame,
-                           dl_dcolor: torch.Tensor, active=None, grad2d=None, stream=None) -> torch.Tensor:
+                           dl_dcolor: torch.Tensor, active=None, grad2d=None, stream=None,
+                           deterministic: bool = False, det_ws: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Per-record 2D gradients (added into grad2d).  With `deterministic` the
+    library's ordered reduction runs instead of float atomics (bitwise the same
+    from run to run); `det_ws` may hold a reusable workspace for it."""
     V = len(cams)
     if grad2d is None:
         grad2d = torch.zeros((max(V * n, 1), L.GS_GRAD2D_FLOATS), device=proj.rec.device)
+    if deterministic:
+        ni = int(binned.stats.n_isect)
+        need = max(L.lib().gs_render_backward_det_workspace_size(ni), 1)
+        ws = det_ws if det_ws is not None and det_ws.numel() >= need else torch.empty(
+            need, dtype=torch.uint8, device=proj.rec.device)
+        L.check(L.lib().gs_render_backward_pixels_det(
+            ctypes.byref(proj.c()), _ptr(binned.vals), _ptr(binned.ranges), _ptr(binned.order),
+            _ptr(binned.offsets), cameras(cams), V, n, ni, ctypes.byref(opts.c()), _ptr(frame.t_final),
+            _ptr(frame.last), _ptr(dl_dcolor.contiguous()), _ptr(active), _ptr(grad2d), _ptr(ws), ws.numel(),
+            _stream(stream)), "gs_render_backward_pixels_det")
+        return grad2d
     L.check(L.lib().gs_render_backward_pixels(ctypes.byref(proj.c()), _ptr(binned.vals), _ptr(binned.ranges),
                                               _ptr(binned.order), cameras(cams), V, n, ctypes.byref(opts.c()),
                                               _ptr(frame.t_final),
                                               _ptr(frame.last), _ptr(dl_dcolor.contiguous()), _ptr(active),
                                               _ptr(grad2d), _stream(stream)), "gs_render_backward_pixels")
     return grad2d
+
+
+def fill_u32(t: torch.Tensor, value: int = 0, stream=None) -> None:
+    """Fill a contiguous tensor of 4-byte elements with a 32-bit pattern
+    (a kernel, not a memset: safe inside captured graphs)."""
+    L.check(L.lib().gs_fill_u32(_ptr(t), value, t.numel() * t.element_size() // 4, _stream(stream)), "gs_fill_u32")
 
 
 def l1_loss_grad(color: torch.Tensor, target: torch.Tensor, dl_dcolor: torch.Tensor, loss: Optional[torch.Tensor],
