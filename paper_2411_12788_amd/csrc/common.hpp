@@ -147,8 +147,9 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t x) {
 // 1D vertex) against lo - log2(alpha_min), with a margin far above float
 // rounding.  Conservative, so culling with it never changes a result; it
 // drops the entries whose bounding box meets the rectangle but whose
-// (elongated, tilted) ellipse does not.
-__device__ __forceinline__ bool ellipse_meets(float4 r0, float4 r1, int32_t x0, int32_t x1, int32_t y0, int32_t y1,
+// (elongated, tilted) ellipse does not.  Host-callable so that a CPU test can
+// check it against brute-force enumeration of pixel centres.
+__host__ __device__ __forceinline__ bool ellipse_meets(float4 r0, float4 r1, int32_t x0, int32_t x1, int32_t y0, int32_t y1,
                                               float log2_alpha_min) {
   const float lx = ((float)x0 + 0.5f - r0.x) - r0.z, hx = ((float)x1 + 0.5f - r0.x) - r0.z;
   const float ly = ((float)y0 + 0.5f - r0.y) - r0.w, hy = ((float)y1 + 0.5f - r0.y) - r0.w;
@@ -168,7 +169,7 @@ __device__ __forceinline__ bool ellipse_meets(float4 r0, float4 r1, int32_t x0, 
 // can reach the culling alpha in the part of tile (tx, ty) inside its pixel
 // box [x0, x1] x [y0, y1].  Shared by the projection (which counts the kept
 // tiles) and the key emission (which emits them), so the two agree exactly.
-__device__ __forceinline__ bool tile_kept(float4 r0, float4 r1, int32_t tx, int32_t ty, int32_t x0, int32_t x1,
+__host__ __device__ __forceinline__ bool tile_kept(float4 r0, float4 r1, int32_t tx, int32_t ty, int32_t x0, int32_t x1,
                                           int32_t y0, int32_t y1, float log2_alpha) {
   const int32_t px0 = tx * kTile > x0 ? tx * kTile : x0, px1 = tx * kTile + kTile - 1 < x1 ? tx * kTile + kTile - 1 : x1;
   const int32_t py0 = ty * kTile > y0 ? ty * kTile : y0, py1 = ty * kTile + kTile - 1 < y1 ? ty * kTile + kTile - 1 : y1;
