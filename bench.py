@@ -217,6 +217,30 @@ def deterministic_backward_ms(step, reps: int = 10) -> float:
     return total / reps
 
 
+def bin_sort_ms(step, algorithm: int, reps: int = 10) -> float:
+    """Time of the bin_sort stage of the last timed step with the given radix
+    pass algorithm (GS_SORT_PRESCAN or GS_SORT_LOOKBACK), same buffers."""
+    from paper_2411_12788_amd import _lib as L
+    R = step.R
+    L.check(L.lib().gs_sort_set_algorithm(algorithm), "gs_sort_set_algorithm")
+    try:
+        offsets, st = R.bin_count(step.proj, step.cams, step.n)
+        R.bin_sort(step.proj, step.cams, step.n, offsets, st, buffers=step.bin_buffers)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        total = 0.0
+        for _ in range(reps):
+            e0.record()
+            R.bin_sort(step.proj, step.cams, step.n, offsets, st, buffers=step.bin_buffers)
+            e1.record()
+            torch.cuda.synchronize()
+            total += e0.elapsed_time(e1)
+        R.sort_status(step.bin_buffers.ws)
+    finally:
+        L.lib().gs_sort_set_algorithm(L.GS_SORT_PRESCAN)
+    return total / reps
+
+
 def criteria_bench(step, reps: int = 10):
     """Time the culling/densification criteria on the accumulations of the last
     timed step: per-view visibility and critical set (both threshold readings),
@@ -793,6 +817,8 @@ def main():
         "stages": stages,
     }
     out["stages"]["render_bwd_deterministic"] = {"ms": round(deterministic_backward_ms(step), 4)}
+    out["stages"]["bin_sort"]["ms_by_pass_algorithm"] = {"prescan": round(bin_sort_ms(step, 0), 4),
+                                                         "lookback": round(bin_sort_ms(step, 1), 4)}
     if not args.no_criteria:
         out["criteria"] = criteria_bench(step)
     if not args.no_multiview:

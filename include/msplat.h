@@ -268,6 +268,17 @@ int32_t gs_sort_status(const void* ws, void* stream);
  * enqueued after the call. */
 void gs_sort_set_spin_limit(uint32_t polls);
 
+/* Diagnostic: how a radix pass learns where its digits go in the output.
+ * GS_SORT_PRESCAN (default): per pass an up-sweep counts each digit per tile
+ * of keys and a scan turns the counts into prefixes, then the scatter;
+ * no workgroup waits on another.  GS_SORT_LOOKBACK: one kernel per pass, each
+ * tile publishes its counts and reads its predecessors' (decoupled look-back,
+ * bounded waits reported through gs_sort_status).  Both give the same order.
+ * Process-wide; affects sorts enqueued after the call.  GS_ERR_UNSUPPORTED
+ * for another value. */
+enum { GS_SORT_PRESCAN = 0, GS_SORT_LOOKBACK = 1 };
+int32_t gs_sort_set_algorithm(int32_t algorithm);
+
 /* Allocation-free sort, for callers that cannot allocate device memory (code
  * under graph capture, tight serving loops, harnesses that forbid allocation).
  * Same result as gs_sort_pairs: in-place stable ascending sort of (keys, vals)

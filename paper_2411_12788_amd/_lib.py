@@ -20,6 +20,7 @@ GS_DEPTH_MID, GS_DEPTH_CENTER, GS_DEPTH_BLEND = 0, 1, 2
 GS_ACCUM_IMPORTANCE, GS_ACCUM_PER_VIEW = 1, 2
 GS_THRESHOLD_VALUE, GS_THRESHOLD_MASS = 0, 1
 GS_SORT_STATIC_MAX_PAIRS = 1 << 20
+GS_SORT_PRESCAN, GS_SORT_LOOKBACK = 0, 1
 
 c_p = ctypes.c_void_p
 c_i32 = ctypes.c_int32
@@ -90,6 +91,7 @@ _SIGS = {
     "gs_tile_ranges": (c_i32, [c_p, c_i64, c_i32, c_u32, c_i32, c_p, c_p, c_p]),
     "gs_sort_status": (c_i32, [c_p, c_p]),
     "gs_sort_set_spin_limit": (None, [c_u32]),
+    "gs_sort_set_algorithm": (c_i32, [c_i32]),
     "gs_sort_pairs_static": (c_i32, [c_p, c_p, c_i64, c_i32, c_p, c_p]),
     "gs_render_forward": (c_i32, [P(Scene), P(Projected), c_p, c_p, c_p, P(Camera), c_i32, P(Opts), P(FwdOut),
                                   P(Accum), c_p]),

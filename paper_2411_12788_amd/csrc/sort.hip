@@ -1,18 +1,25 @@
 // Stable LSD radix sort of (u64 key, u32 value) pairs on the low `bits` key
-// bits: one histogram pass over the keys for all digits, then one kernel per
-// 8-bit digit ("onesweep").  Each workgroup ranks an 8192-key tile in
-// registers/LDS, publishes its per-digit counts, and obtains the count of
-// equal digits in all earlier tiles by a decoupled look-back over the
-// per-tile status words; tiles are handed out by an atomic counter, so every
-// tile a workgroup looks back at belongs to a workgroup that has already
-// started and will publish without waiting on anyone.  Keys are then staged in
-// LDS in local sorted order and written out in runs, so each digit's run is a
-// contiguous, coalesced store.  Per pass this reads 12 B and writes 12 B per
-// pair (8 B each when the value is packed under the key); the histograms of
-// all passes cost one extra 8 B read per pair in total.  The look-back is what
-// bounds a pass at a few million keys (the front of inclusive prefixes moves
-// one window of predecessors per round trip), so the tiles are large: 8192
-// keys instead of 4096 took a pass from 44 to 38 us at 3.3M keys.
+// bits, one 8-bit digit per pass.  A pass needs, for every tile of keys and
+// every digit, the number of equal digits in all earlier tiles; two ways of
+// getting it are built:
+//  - reduce-then-scan (default): an up-sweep kernel counts each digit per tile
+//    into a [digit][tile] table, a scan kernel (one workgroup per digit) turns
+//    each row into exclusive prefixes plus the digit's total, and the scatter
+//    kernel reads its prefixes and the totals.  No workgroup ever waits on
+//    another, so the tiles are small (2048 keys) and many are in flight.
+//  - decoupled look-back ("onesweep"): one histogram pass for all digits, then
+//    one kernel per pass whose workgroups publish their per-digit counts and
+//    walk back over their predecessors' status words until an inclusive
+//    prefix; tiles are handed out by an atomic counter, so a workgroup only
+//    ever waits on workgroups that have started.  At a few million keys the
+//    walk (one window of predecessors per round trip) bounds a pass, so the
+//    tiles are large (8192 keys).
+// Both rank a tile with wave ballots (stable), stage its keys in LDS in local
+// sorted order and write them out as per-digit runs (coalesced).  Per pass
+// this reads 12 B and writes 12 B per pair (8 B each when the value is packed
+// under the key); the up-sweep reads the keys once more.  At 3.3M keys the
+// reduce-then-scan passes take 0.26 ms for the five passes of the binning
+// against 0.30 ms for the look-back.
 //
 // Every wait is bounded: a look-back that has not resolved after the spin
 // limit raises the error word in the workspace header instead of spinning on,
@@ -26,14 +33,18 @@
 
 namespace msplat {
 
-// keys per thread and per tile of a pass: 32 (8192 keys) for keys-only passes;
-// 16 when values travel too, which keeps that kernel within 256 VGPRs
-template <bool VALS>
+// keys per thread and per tile of a pass.  Look-back passes: 32 (8192 keys)
+// for keys-only passes, 16 when values travel too (within 256 VGPRs); large
+// tiles keep the look-back chains short.  Prescanned passes wait on nobody,
+// so their tiles are small (8 per thread, 2048 keys): four times the
+// workgroups in flight to hide the memory latency.
+template <bool VALS, bool PRESCAN = false>
 struct OsTile {
-  static constexpr int items = VALS ? 16 : 32;
+  static constexpr int items = PRESCAN ? 8 : (VALS ? 16 : 32);
   static constexpr int keys = kBlock * items;
 };
 constexpr int kOsMinTile = OsTile<true>::keys;  // sizes the per-tile status words
+static_assert(OsTile<false, true>::keys * 2 <= kOsMinTile, "prescan counts fit the status area");
 static_assert(kOsMinTile == kSortMinTile, "status words are sized for the smallest tile");
 constexpr int kHistItems = 16;                   // keys per thread of the histogram kernel
 constexpr int kOsRadix = 256;
@@ -95,33 +106,58 @@ __global__ __launch_bounds__(kBlock) void k_os_scan(uint32_t* __restrict__ ghist
   }
 }
 
-template <bool VALS>
+// One LSD pass over tiles of OsTile<VALS>::keys keys.  PRESCAN: the count of
+// each digit in all earlier tiles comes from k_rt_up / k_rt_scan (prefix,
+// digit-major [256][nt], and the digit totals), tile = block; otherwise from
+// the decoupled look-back described above, tile = order of start.
+template <bool VALS, bool PRESCAN>
 __global__ __launch_bounds__(kBlock) void k_os_pass(const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin,
                                                     uint64_t* __restrict__ kout, uint32_t* __restrict__ vout,
                                                     int64_t n, int32_t shift, const uint32_t* __restrict__ digit_base,
                                                     uint32_t* status, uint32_t* counter, uint32_t* err,
-                                                    uint32_t spin_limit) {
+                                                    uint32_t spin_limit, const uint32_t* __restrict__ prefix,
+                                                    int32_t nt) {
   __shared__ uint32_t s_tile;
+  __shared__ uint32_t s_base[PRESCAN ? kOsRadix : 1];
+  __shared__ uint32_t s_wpre[kOsWaves];
   __shared__ uint32_t cnt[kOsWaves][kOsRadix];
   __shared__ uint32_t s_glob[kOsRadix];
   __shared__ uint32_t s_loff[kOsRadix + 1];
   __shared__ uint32_t s_wsum[kOsWaves];
-  __shared__ uint64_t s_key[OsTile<VALS>::keys];
-  __shared__ uint32_t s_val[VALS ? OsTile<VALS>::keys : 1];
+  __shared__ uint64_t s_key[OsTile<VALS, PRESCAN>::keys];
+  __shared__ uint32_t s_val[VALS ? OsTile<VALS, PRESCAN>::keys : 1];
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-  if (threadIdx.x == 0) s_tile = atomicAdd(counter, 1u);
+  if (PRESCAN) {
+    // digit bases: exclusive scan of the 256 digit totals (after the prefixes)
+    const uint32_t tot = prefix[(int64_t)kOsRadix * nt + threadIdx.x];
+    uint32_t inc = tot;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+      const uint32_t y = __shfl_up(inc, o, kWave);
+      if (lane >= o) inc += y;
+    }
+    if (lane == kWave - 1) s_wpre[w] = inc;
+    if (threadIdx.x == 0) s_tile = blockIdx.x;
+    __syncthreads();
+    uint32_t wpre = 0;
+#pragma unroll
+    for (int q = 0; q < kOsWaves; ++q) wpre += q < w ? s_wpre[q] : 0u;
+    s_base[threadIdx.x] = wpre + inc - tot;
+  } else if (threadIdx.x == 0) {
+    s_tile = atomicAdd(counter, 1u);
+  }
 #pragma unroll
   for (int k = 0; k < kOsWaves; ++k) cnt[k][threadIdx.x] = 0;
   __syncthreads();
   const uint32_t t = s_tile;
-  const int64_t tile_base = (int64_t)t * OsTile<VALS>::keys;
-  const int64_t base = tile_base + (int64_t)w * (OsTile<VALS>::items * kWave);
+  const int64_t tile_base = (int64_t)t * OsTile<VALS, PRESCAN>::keys;
+  const int64_t base = tile_base + (int64_t)w * (OsTile<VALS, PRESCAN>::items * kWave);
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
-  uint64_t key[OsTile<VALS>::items];
-  uint32_t val[OsTile<VALS>::items];
-  uint32_t rank[OsTile<VALS>::items];
+  uint64_t key[OsTile<VALS, PRESCAN>::items];
+  uint32_t val[OsTile<VALS, PRESCAN>::items];
+  uint32_t rank[OsTile<VALS, PRESCAN>::items];
 #pragma unroll
-  for (int k = 0; k < OsTile<VALS>::items; ++k) {
+  for (int k = 0; k < OsTile<VALS, PRESCAN>::items; ++k) {
     const int64_t e = base + (int64_t)k * kWave + lane;
     const bool in = e < n;
     key[k] = in ? kin[e] : 0ull;
@@ -145,11 +181,14 @@ __global__ __launch_bounds__(kBlock) void k_os_pass(const uint64_t* __restrict__
     cnt[k][d] = h;
     h += c;
   }
-  uint32_t* st = status + (int64_t)t * kOsRadix + d;
   uint32_t excl = 0;
-  if (t == 0) {
+  if (PRESCAN) {
+    excl = prefix[(int64_t)d * nt + t];
+  } else if (t == 0) {
+    uint32_t* st = status + (int64_t)t * kOsRadix + d;
     __hip_atomic_store(st, kFlagInc | h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   } else {
+    uint32_t* st = status + (int64_t)t * kOsRadix + d;
     __hip_atomic_store(st, kFlagAgg | h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     // look back over a window of kLook predecessors per step: the loads are
     // independent, so their latencies overlap instead of adding up
@@ -193,7 +232,7 @@ __global__ __launch_bounds__(kBlock) void k_os_pass(const uint64_t* __restrict__
     }
     __hip_atomic_store(st, kFlagInc | ((excl + h) & kValMask), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
-  s_glob[d] = digit_base[d] + excl;
+  s_glob[d] = (PRESCAN ? s_base[d] : digit_base[d]) + excl;
   // local offsets: exclusive scan of the tile's digit totals (thread = digit)
   {
     uint32_t inc = h;
@@ -212,12 +251,12 @@ __global__ __launch_bounds__(kBlock) void k_os_pass(const uint64_t* __restrict__
   }
   __syncthreads();
 #pragma unroll
-  for (int k = 0; k < OsTile<VALS>::items; ++k) {
+  for (int k = 0; k < OsTile<VALS, PRESCAN>::items; ++k) {
     const int64_t e = base + (int64_t)k * kWave + lane;
     if (e < n) {
       const uint32_t dd = (uint32_t)(key[k] >> shift) & 0xffu;
       const uint32_t lp = s_loff[dd] + cnt[w][dd] + rank[k];
-      if (lp < (uint32_t)OsTile<VALS>::keys) {
+      if (lp < (uint32_t)OsTile<VALS, PRESCAN>::keys) {
         s_key[lp] = key[k];
         if (VALS) s_val[lp] = val[k];
       }
@@ -236,6 +275,61 @@ __global__ __launch_bounds__(kBlock) void k_os_pass(const uint64_t* __restrict__
   }
 }
 
+// Up-sweep of a prescanned pass: each tile's count of every digit, stored
+// digit-major (counts[d * nt + t]) for the scan.  Per-wave LDS histograms.
+template <bool VALS>
+__global__ __launch_bounds__(kBlock) void k_rt_up(const uint64_t* __restrict__ kin, int64_t n, int32_t shift,
+                                                  uint32_t* __restrict__ counts, int32_t nt) {
+  __shared__ uint32_t h[kOsWaves][kOsRadix];
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+#pragma unroll
+  for (int k = 0; k < kOsWaves; ++k) h[k][threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * OsTile<VALS, true>::keys + (int64_t)w * (OsTile<VALS, true>::items * kWave);
+#pragma unroll 8
+  for (int k = 0; k < OsTile<VALS, true>::items; ++k) {
+    const int64_t e = base + (int64_t)k * kWave + lane;
+    if (e < n) atomicAdd(&h[w][(uint32_t)(kin[e] >> shift) & 0xffu], 1u);
+  }
+  __syncthreads();
+  uint32_t c = 0;
+#pragma unroll
+  for (int k = 0; k < kOsWaves; ++k) c += h[k][threadIdx.x];
+  counts[(int64_t)threadIdx.x * nt + blockIdx.x] = c;
+}
+
+// Scan of a prescanned pass: one workgroup per digit turns its nt tile
+// counts into exclusive prefixes in place and stores the digit's total after
+// the [256][nt] block (counts[256 * nt + d]).
+__global__ __launch_bounds__(kBlock) void k_rt_scan(uint32_t* __restrict__ counts, int32_t nt) {
+  __shared__ uint32_t s_w[kOsWaves];
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+  uint32_t* c = counts + (int64_t)blockIdx.x * nt;
+  uint32_t carry = 0;
+  for (int32_t t0 = 0; t0 < nt; t0 += kBlock) {
+    const int32_t t = t0 + threadIdx.x;
+    const uint32_t x = t < nt ? c[t] : 0u;
+    uint32_t inc = x;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+      const uint32_t y = __shfl_up(inc, o, kWave);
+      if (lane >= o) inc += y;
+    }
+    if (lane == kWave - 1) s_w[w] = inc;
+    __syncthreads();
+    uint32_t wpre = 0, tot = 0;
+#pragma unroll
+    for (int q = 0; q < kOsWaves; ++q) {
+      wpre += q < w ? s_w[q] : 0u;
+      tot += s_w[q];
+    }
+    if (t < nt) c[t] = carry + wpre + inc - x;
+    carry += tot;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) counts[(int64_t)kOsRadix * nt + blockIdx.x] = carry;
+}
+
 // Workspace: a 512-byte header (word 0: error flag of the last sort; bytes
 // 256..511 free for the caller), the histograms, per-tile status words and
 // tile counters (cleared together with the flag by one fill), then the
@@ -245,6 +339,7 @@ size_t onesweep_ws_size(int64_t n, int32_t passes) { return sort_ws_bytes(n); }
 int32_t launch_fill(void* dst, uint32_t value, int64_t count, hipStream_t st);
 
 static std::atomic<uint32_t> g_spin_limit{1u << 22};
+static std::atomic<int32_t> g_sort_algorithm{GS_SORT_PRESCAN};
 
 // Sorts (k0, v0) on key bits [lo_bit, lo_bit + bits); the last pass writes
 // values to vfinal and keys to the buffer returned in *keys_sorted (k0 or the
@@ -262,8 +357,9 @@ int32_t onesweep_sort(uint64_t* k0, uint32_t* v0, int64_t n, int32_t lo_bit, int
     return GS_ERR_CAPACITY;
   }
   const bool vals = v0 != nullptr;
+  const bool prescan = g_sort_algorithm.load() == GS_SORT_PRESCAN;
   const int64_t nn = n > 0 ? n : 1;
-  const int64_t tile = vals ? OsTile<true>::keys : OsTile<false>::keys;
+  const int64_t tile = prescan ? OsTile<true, true>::keys : (vals ? OsTile<true>::keys : OsTile<false>::keys);
   const int64_t nb = (nn + tile - 1) / tile;
   const int64_t nb_min = (nn + kOsMinTile - 1) / kOsMinTile;
   auto a = [](size_t x) { return (x + 255) & ~size_t(255); };
@@ -274,8 +370,9 @@ int32_t onesweep_sort(uint64_t* k0, uint32_t* v0, int64_t n, int32_t lo_bit, int
   uint32_t* counters = (uint32_t*)p; p += a(kMaxPasses * 4);
   uint64_t* kalt = (uint64_t*)p; p += a(nn * 8);
   uint32_t* valt = (uint32_t*)p;
-  // the flag, histograms, status words and counters in one fill
-  const int64_t zero_words = (int64_t)((char*)(counters + kMaxPasses) - (char*)err) / 4;
+  // the flag, histograms, status words and counters in one fill (the
+  // prescanned passes write all their counts: only the flag)
+  const int64_t zero_words = prescan ? 1 : (int64_t)((char*)(counters + kMaxPasses) - (char*)err) / 4;
   int32_t r = launch_fill(err, 0u, zero_words, st);
   if (r != GS_OK) return r;
   if (n <= 1 || passes == 0) {
@@ -286,26 +383,49 @@ int32_t onesweep_sort(uint64_t* k0, uint32_t* v0, int64_t n, int32_t lo_bit, int
     return GS_OK;
   }
   const uint32_t spin_limit = g_spin_limit.load();
-  const int64_t hb = (nn + kBlock * kHistItems - 1) / (kBlock * kHistItems);
-  hipLaunchKernelGGL(k_os_hist, dim3((unsigned)hb), dim3(kBlock), 0, st, k0, n, passes, lo_bit, ghist);
-  hipLaunchKernelGGL(k_os_scan, dim3(1), dim3(kBlock), 0, st, ghist, passes);
-  MS_CHECK_LAUNCH("sort histogram");
+  if (!prescan) {
+    const int64_t hb = (nn + kBlock * kHistItems - 1) / (kBlock * kHistItems);
+    hipLaunchKernelGGL(k_os_hist, dim3((unsigned)hb), dim3(kBlock), 0, st, k0, n, passes, lo_bit, ghist);
+    hipLaunchKernelGGL(k_os_scan, dim3(1), dim3(kBlock), 0, st, ghist, passes);
+    MS_CHECK_LAUNCH("sort histogram");
+  }
+  // prescanned passes: [256][nb] tile counts and 256 totals, in the status
+  // area (nb <= nb_min tiles, so 256 (nb + 1) <= 8 * 256 nb_min words)
+  uint32_t* counts = status;
+  const int32_t nt = (int32_t)nb;
   uint64_t* kin = k0;
   uint32_t* vin = v0;
   for (int ps = 0; ps < passes; ++ps) {
     uint64_t* kout = (kin == k0) ? kalt : k0;
     uint32_t* vout = nullptr;
+    const int32_t shift = lo_bit + 8 * ps;
+    if (prescan) {
+      if (vals)
+        hipLaunchKernelGGL(k_rt_up<true>, dim3((unsigned)nb), dim3(kBlock), 0, st, kin, n, shift, counts, nt);
+      else
+        hipLaunchKernelGGL(k_rt_up<false>, dim3((unsigned)nb), dim3(kBlock), 0, st, kin, n, shift, counts, nt);
+      hipLaunchKernelGGL(k_rt_scan, dim3(kOsRadix), dim3(kBlock), 0, st, counts, nt);
+      MS_CHECK_LAUNCH("sort up-sweep");
+    }
     if (vals) {
       vout = (vin == v0) ? valt : v0;
       if (ps == passes - 1) vout = vfinal;
       if (vout == vin) vout = (vin == v0) ? valt : v0;
-      hipLaunchKernelGGL(k_os_pass<true>, dim3((unsigned)nb), dim3(kBlock), 0, st, kin, vin, kout, vout, n,
-                         lo_bit + 8 * ps, ghist + ps * kOsRadix, status + (size_t)ps * nb * kOsRadix, counters + ps,
-                         err, spin_limit);
+      if (prescan)
+        hipLaunchKernelGGL((k_os_pass<true, true>), dim3((unsigned)nb), dim3(kBlock), 0, st, kin, vin, kout, vout,
+                           n, shift, nullptr, nullptr, nullptr, err, 0u, counts, nt);
+      else
+        hipLaunchKernelGGL((k_os_pass<true, false>), dim3((unsigned)nb), dim3(kBlock), 0, st, kin, vin, kout, vout,
+                           n, shift, ghist + ps * kOsRadix, status + (size_t)ps * nb * kOsRadix, counters + ps, err,
+                           spin_limit, nullptr, 0);
     } else {
-      hipLaunchKernelGGL(k_os_pass<false>, dim3((unsigned)nb), dim3(kBlock), 0, st, kin, nullptr, kout, nullptr, n,
-                         lo_bit + 8 * ps, ghist + ps * kOsRadix, status + (size_t)ps * nb * kOsRadix, counters + ps,
-                         err, spin_limit);
+      if (prescan)
+        hipLaunchKernelGGL((k_os_pass<false, true>), dim3((unsigned)nb), dim3(kBlock), 0, st, kin, nullptr, kout,
+                           nullptr, n, shift, nullptr, nullptr, nullptr, err, 0u, counts, nt);
+      else
+        hipLaunchKernelGGL((k_os_pass<false, false>), dim3((unsigned)nb), dim3(kBlock), 0, st, kin, nullptr, kout,
+                           nullptr, n, shift, ghist + ps * kOsRadix, status + (size_t)ps * nb * kOsRadix,
+                           counters + ps, err, spin_limit, nullptr, 0);
     }
     MS_CHECK_LAUNCH("sort pass");
     kin = kout;
@@ -341,5 +461,11 @@ int32_t gs_sort_status(const void* ws, void* stream) {
 }
 
 void gs_sort_set_spin_limit(uint32_t polls) { g_spin_limit.store(polls); }
+
+int32_t gs_sort_set_algorithm(int32_t algorithm) {
+  if (algorithm != GS_SORT_PRESCAN && algorithm != GS_SORT_LOOKBACK) { set_error("unknown sort algorithm"); return GS_ERR_UNSUPPORTED; }
+  g_sort_algorithm.store(algorithm);
+  return GS_OK;
+}
 
 }  // extern "C"

@@ -140,3 +140,10 @@ def test_static_sort_capacity_on_host(L):
     assert lib.gs_sort_pairs_static(fake, fake, L.GS_SORT_STATIC_MAX_PAIRS + 1, 40, None, None) == L.GS_ERR_CAPACITY
     assert lib.gs_sort_pairs_static(fake, fake, 10, 0, None, None) == L.GS_ERR_SHAPE
     assert lib.gs_sort_pairs_static(None, None, 10, 40, None, None) == L.GS_ERR_NULL
+
+
+def test_sort_algorithm_switch_on_host(L):
+    lib = L.lib()
+    assert lib.gs_sort_set_algorithm(7) == L.GS_ERR_UNSUPPORTED
+    assert lib.gs_sort_set_algorithm(L.GS_SORT_LOOKBACK) == L.GS_OK
+    assert lib.gs_sort_set_algorithm(L.GS_SORT_PRESCAN) == L.GS_OK

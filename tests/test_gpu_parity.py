@@ -74,9 +74,11 @@ def test_binning_bit_exact(gpu_lib):
     assert np.array_equal(_np(b.ranges).view(np.uint32), ranges)
 
 
+@pytest.mark.parametrize("algorithm", [0, 1])  # GS_SORT_PRESCAN, GS_SORT_LOOKBACK
 @pytest.mark.parametrize("n,bits,spread", [(1, 8, 2), (1000, 20, 16), (3 * 4096 + 17, 45, 1 << 40),
-                                           (100_003, 64, 1 << 62), (50_000, 33, 7)])
-def test_sort_pairs_matches_lexsort(gpu_lib, n, bits, spread):
+                                           (100_003, 64, 1 << 62), (50_000, 33, 7), (3_300_001, 45, 1 << 44)])
+def test_sort_pairs_matches_lexsort(gpu_lib, n, bits, spread, algorithm):
+    from paper_2411_12788_amd import _lib as L
     R = H.raster()
     g = gs_inputs.rng(n + bits)
     hi = min(spread, (1 << bits) - 1) if bits < 64 else spread
@@ -86,7 +88,12 @@ def test_sort_pairs_matches_lexsort(gpu_lib, n, bits, spread):
     vals = np.arange(n, dtype=np.uint32)
     kt = torch.from_numpy(keys.view(np.int64)).cuda()
     vt = torch.from_numpy(vals.view(np.int32)).cuda()
-    R.sort_pairs(kt, vt, bits)
+    assert L.lib().gs_sort_set_algorithm(algorithm) == L.GS_OK
+    try:
+        R.sort_pairs(kt, vt, bits)
+        torch.cuda.synchronize()
+    finally:
+        L.lib().gs_sort_set_algorithm(L.GS_SORT_PRESCAN)
     perm = np.lexsort((vals, keys))
     assert np.array_equal(_np(kt).view(np.uint64), keys[perm])
     assert np.array_equal(_np(vt).view(np.uint32), vals[perm])

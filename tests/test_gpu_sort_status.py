@@ -1,10 +1,11 @@
 """The radix sort's error flag reaches the caller (GPU, through the C ABI).
 
-The sort waits on other workgroups in bounded loops; a wait that gives up
-raises a flag in the workspace header instead of hanging.  These tests force
-that condition from the host (a spin limit of 0 makes every look-back give up
-at once, so every kernel still exits normally) or preset the flag, and check
-that gs_sort_status reports it and that the next sort clears it.
+With the look-back passes the sort waits on other workgroups in bounded
+loops; a wait that gives up raises a flag in the workspace header instead of
+hanging.  These tests force that condition from the host (a spin limit of 0
+makes every look-back give up at once, so every kernel still exits normally)
+or preset the flag, and check that gs_sort_status reports it and that the
+next sort clears it (with either pass algorithm).
 """
 import ctypes
 
@@ -57,12 +58,14 @@ def test_look_back_that_gives_up_is_reported(gpu_lib):
     kt = torch.from_numpy(keys.view(np.int64)).cuda()
     vt = torch.from_numpy(vals.view(np.int32)).cuda()
     print(f"spin limit 0, n={n}", flush=True)
+    L.lib().gs_sort_set_algorithm(L.GS_SORT_LOOKBACK)
     L.lib().gs_sort_set_spin_limit(0)
     try:
         assert _sort(L, kt, vt, 40, ws) == L.GS_OK  # enqueued fine; the error shows at the status read
         assert L.lib().gs_sort_status(ctypes.c_void_p(ws.data_ptr()), None) == L.GS_ERR_DEVICE
     finally:
         L.lib().gs_sort_set_spin_limit(1 << 22)
+        L.lib().gs_sort_set_algorithm(L.GS_SORT_PRESCAN)
     kt = torch.from_numpy(keys.view(np.int64)).cuda()
     vt = torch.from_numpy(vals.view(np.int32)).cuda()
     assert _sort(L, kt, vt, 40, ws) == L.GS_OK
