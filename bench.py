@@ -492,7 +492,8 @@ def serving_bench(n_requests: int, warmup: int):
                                 "views_per_s": round(st["views_per_s"], 2), "p50_ms": round(st["p50_ms"], 3),
                                 "p99_ms": round(st["p99_ms"], 3), "mean_ms": round(st["mean_ms"], 3),
                                 "mean_batch": round(st["mean_batch"], 3), "batch_size_counts": st["batch_size_counts"],
-                                "peak_reserved_gb": round(st["peak_reserved_gb"], 3), "requests": st["completed"]})
+                                "peak_reserved_gb": round(st["peak_reserved_gb"], 3), "requests": st["completed"],
+                                "service_ms_by_batch": st["service_ms_by_batch"]})
     return out
 
 

@@ -129,13 +129,36 @@ class Projected:
         return p
 
 
+class StepBuffers:
+    """Reusable device buffers of one stream's projection records, pair count
+    and sorted lists, grown when a call needs more (a serving slot or a
+    training loop then stops allocating after its first few calls)."""
+
+    def __init__(self):
+        self.store: Dict[str, torch.Tensor] = {}
+        self.bins = BinBuffers()
+
+    def take(self, name, count, dtype, dev, shape_tail=()):
+        per = int(np.prod(shape_tail)) if shape_tail else 1
+        base = self.store.get(name)
+        if base is None or base.numel() < count * per or base.dtype != dtype:
+            base = torch.empty(((count + count // 8) * per,), device=dev, dtype=dtype)
+            self.store[name] = base
+        return base[: count * per].view((count,) + tuple(shape_tail))
+
+
 def project(scene: DeviceScene, cams, opts: RasterOpts, cull_mask: Optional[torch.Tensor] = None,
-            stream=None) -> Projected:
+            stream=None, buffers: Optional[StepBuffers] = None) -> Projected:
     V, n = len(cams), scene.n
     dev = scene.opacity.device
-    out = Projected(torch.empty((max(V * n, 1), L.GS_REC_FLOATS), device=dev, dtype=torch.float32),
-                    torch.empty((max(V * n, 1), 4), device=dev, dtype=torch.int32),
-                    float(np.log2(opts.alpha_min)) if opts.tile_cull else 0.0)
+    m = max(V * n, 1)
+    if buffers is not None:
+        rec = buffers.take("rec", m, torch.float32, dev, (L.GS_REC_FLOATS,))
+        binr = buffers.take("bin", m, torch.int32, dev, (4,))
+    else:
+        rec = torch.empty((m, L.GS_REC_FLOATS), device=dev, dtype=torch.float32)
+        binr = torch.empty((m, 4), device=dev, dtype=torch.int32)
+    out = Projected(rec, binr, float(np.log2(opts.alpha_min)) if opts.tile_cull else 0.0)
     L.check(L.lib().gs_project(ctypes.byref(scene.c()), cameras(cams), V, _ptr(cull_mask), ctypes.byref(opts.c()),
                                ctypes.byref(out.c()), _stream(stream)), "gs_project")
     return out
@@ -151,11 +174,16 @@ class Binned:
     order: Optional[torch.Tensor] = None  # [tiles_total] tile processing order (longest lists first)
 
 
-def bin_count(proj: Projected, cams, n: int, stream=None):
+def bin_count(proj: Projected, cams, n: int, stream=None, buffers: Optional[StepBuffers] = None):
     V = len(cams)
     dev = proj.rec.device
-    offsets = torch.empty(max(V * n, 1), device=dev, dtype=torch.int32)
-    ws = torch.empty(L.lib().gs_bin_count_workspace_size(V * n), device=dev, dtype=torch.uint8)
+    need = L.lib().gs_bin_count_workspace_size(V * n)
+    if buffers is not None:
+        offsets = buffers.take("offsets", max(V * n, 1), torch.int32, dev)
+        ws = buffers.take("count_ws", max(need, 1), torch.uint8, dev)
+    else:
+        offsets = torch.empty(max(V * n, 1), device=dev, dtype=torch.int32)
+        ws = torch.empty(need, device=dev, dtype=torch.uint8)
     st = L.BinStats()
     L.check(L.lib().gs_bin_count(ctypes.byref(proj.c()), cameras(cams), V, n, _ptr(offsets), ctypes.byref(st),
                                  _ptr(ws), ws.numel(), _stream(stream)), "gs_bin_count")

@@ -65,6 +65,7 @@ class Server:
         self.growing = 0
         self.slot_extra: Dict[int, int] = {}  # second-phase adjustment of each running batch
         self.completed: List[Result] = []
+        self.service: List[Any] = []  # (batch size, seconds from admission to completion)
         self.admitted_batches: List[int] = []
         self.running = True
         self.seq = 0
@@ -174,6 +175,7 @@ class Server:
                 t.start()
 
     def _work(self, batch: List[Request], slot: int, reserved: int) -> None:
+        start = self.clock()
         try:
             outs = self.ex.run(batch, slot, self)
             done = self.clock()
@@ -184,11 +186,15 @@ class Server:
             err = None
         except BaseException as e:  # noqa: BLE001 - propagate to the futures
             err, results = e, []
+            done = self.clock()
         with self.cv:
             self.reserved -= reserved + self.slot_extra.pop(slot, 0)
             self.in_flight -= 1
             self.free_slots.append(slot)
-            self.completed.extend(results)
+            # the server keeps the timing only: the frames are the clients'
+            # (holding them here would keep every served frame on the device)
+            self.completed.extend(Result(None, None, r.latency, r.batch_size, r.slot) for r in results)
+            self.service.append((len(batch), done - start))
             self.cv.notify_all()
         if err is not None:
             for r in batch:
@@ -231,6 +237,11 @@ class GpuExecutor:
         # drops the pairs that cannot composite (~12 % on dense scenes)
         self.opts = opts or R.RasterOpts(tile_cull=True)
         self.streams = [torch.cuda.Stream(device=device) for _ in range(slots)]
+        # per slot: projection records, pair count and lists are reused from
+        # batch to batch (a slot runs one batch at a time), so the allocator
+        # is not asked for gigabytes of new blocks per batch; only the frames
+        # handed to clients are allocated per batch
+        self.buffers = [R.StepBuffers() for _ in range(slots)]
         self.pairs_per_record: Dict[Any, float] = {}
         self.lock = threading.Lock()
 
@@ -256,8 +267,9 @@ class GpuExecutor:
         cams = [r.camera for r in batch]
         st = self.streams[slot]
         with torch.cuda.stream(st):
-            proj = R.project(scene, cams, self.opts, stream=st)
-            offsets, stats = R.bin_count(proj, cams, scene.n, stream=st)
+            buf = self.buffers[slot]
+            proj = R.project(scene, cams, self.opts, stream=st, buffers=buf)
+            offsets, stats = R.bin_count(proj, cams, scene.n, stream=st, buffers=buf)
             real = self._bytes(scene.n, len(cams), sum(c.width * c.height for c in cams), int(stats.n_isect))
             est = self.footprint(batch)
             if real != est:
@@ -266,7 +278,7 @@ class GpuExecutor:
                 ppr = stats.n_isect / max(1, len(cams) * scene.n)
                 old = self.pairs_per_record.get(sid)
                 self.pairs_per_record[sid] = ppr if old is None else max(ppr, 0.5 * (old + ppr))
-            binned = R.bin_sort(proj, cams, scene.n, offsets, stats, stream=st)
+            binned = R.bin_sort(proj, cams, scene.n, offsets, stats, stream=st, buffers=buf.bins)
             frame = R.render_forward(scene, proj, binned, cams, self.opts, extras=False, stream=st)
             ev = torch.cuda.Event()
             ev.record(st)
@@ -331,13 +343,43 @@ def drive(server: Server, requests: Sequence, arrivals: Sequence[float], warmup:
     last counted completion, the offered rate, and the distribution of the
     batch sizes the counted requests were rendered in."""
     t0 = server.clock()
-    futs = []
-    for (sid, cam), a in zip(requests, arrivals):
+    # Results are read as they complete and not kept (a served frame is the
+    # client's to consume; holding every frame until the end of a run would
+    # keep the device memory of all of them alive).
+    total = len(arrivals)
+    recs: List[Any] = [None] * total
+    lock = threading.Condition()
+    left = [total]
+
+    def collect(k):
+        def done(f):
+            try:
+                r = f.result()
+                rec = (r.latency, r.batch_size)
+            except BaseException as e:  # noqa: BLE001 - reported below
+                rec = e
+            with lock:
+                recs[k] = rec
+                left[0] -= 1
+                lock.notify_all()
+        return done
+
+    for k, ((sid, cam), a) in enumerate(zip(requests, arrivals)):
         now = server.clock() - t0
         if a > now:
             time.sleep(a - now)
-        futs.append(server.submit(sid, cam, arrival=t0 + a))
-    res = [f.result(timeout=600) for f in futs]
+        server.submit(sid, cam, arrival=t0 + a).add_done_callback(collect(k))
+    with lock:
+        end_wait = time.monotonic() + 600.0
+        while left[0] > 0:
+            rem = end_wait - time.monotonic()
+            if rem <= 0:
+                raise TimeoutError("requests did not complete")
+            lock.wait(timeout=min(rem, 1.0))
+    for r in recs:
+        if isinstance(r, BaseException):
+            raise r
+    res = [Result(None, None, lat, bs, -1) for lat, bs in recs]
     w = max(0, min(int(warmup), len(res) - 1))
     meas, arr = res[w:], list(arrivals[w:])
     lat = sorted(r.latency for r in meas)
@@ -357,4 +399,12 @@ def drive(server: Server, requests: Sequence, arrivals: Sequence[float], warmup:
                           "peak_reserved_gb": server.peak_reserved / 1e9,
                           "views_per_s": n / span if span > 0 else float("inf")}
     st["offered_qps"] = (len(arr) - 1) / max(arr[-1] - arr[0], 1e-9) if len(arr) > 1 else 0.0
+    # admission-to-completion time of a batch, by its size (every batch of the
+    # run, warm-up included): with several slots it includes the time the
+    # batch shared the device with the others
+    by: Dict[int, List[float]] = {}
+    with server.cv:
+        for bs, sec in server.service:
+            by.setdefault(bs, []).append(sec)
+    st["service_ms_by_batch"] = {str(k): round(1e3 * sum(v) / len(v), 3) for k, v in sorted(by.items())}
     return st

@@ -117,3 +117,37 @@ def test_latency_percentiles_reported():
     st = drive(srv, _reqs(60, 5), poisson_arrivals(400.0, 60, 5))
     srv.close()
     assert st["completed"] == 60 and 0 < st["p50_ms"] <= st["p99_ms"] and st["views_per_s"] > 0
+
+
+def test_server_keeps_timing_not_frames_and_reports_service_times():
+    """Served frames belong to the clients: the server's record of a completed
+    request holds its latency and batch size only (holding the frames would
+    keep every served frame in device memory for the life of the server)."""
+    ex = FakeExecutor(SIZES, per_view_s=0.002, per_batch_s=0.002)
+    srv = Server(ex, hbm_budget=10 ** 9, slots=2, max_batch=4)
+    futs = [srv.submit(s, c) for s, c in _reqs(12, 3)]
+    got = [f.result(timeout=30) for f in futs]
+    srv.drain()
+    assert all(r.color is not None for r in got)  # the client gets its frame
+    assert len(srv.completed) == 12
+    assert all(r.color is None and r.depth is None for r in srv.completed)
+    assert sum(bs for bs, _ in srv.service) == 12
+    st = drive(srv, _reqs(8, 4), [0.0] * 8)
+    srv.close()
+    assert set(st["service_ms_by_batch"]) <= {"1", "2", "3", "4"}
+    assert all(v > 0 for v in st["service_ms_by_batch"].values())
+
+
+def test_step_buffers_grow_and_reuse():
+    import torch
+
+    from paper_2411_12788_amd.raster import StepBuffers
+    b = StepBuffers()
+    x = b.take("rec", 100, torch.float32, "cpu", (16,))
+    assert x.shape == (100, 16)
+    y = b.take("rec", 80, torch.float32, "cpu", (16,))
+    assert y.shape == (80, 16) and y.data_ptr() == x.data_ptr()  # reused
+    z = b.take("rec", 1000, torch.float32, "cpu", (16,))
+    assert z.shape == (1000, 16) and z.data_ptr() != x.data_ptr()  # grown
+    w = b.take("rec", 10, torch.int32, "cpu", (16,))
+    assert w.dtype == torch.int32
