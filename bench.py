@@ -45,10 +45,10 @@ RENDER_FWD_BYTES_PER_PIXEL = 12 + 4 + 4 + 4 + 4 + 4 + 1  # colour, depth, imax, 
 RENDER_BWD_BYTES_PER_PAIR = 4 + 8 + 64 + 1      # list index, box, full record, active flag
 RENDER_BWD_BYTES_PER_PIXEL = 12 + 4 + 4         # dL/dC, T, last
 STAGE_KERNELS = {"project": ["k_project"], "bin_count": ["k_count_reduce", "k_count_top", "k_count_down"],
-                 "bin_sort": ["k_emit", "k_os_hist", "k_os_scan", "k_os_pass", "k_ranges", "k_order_hist",
-                              "k_order_scan", "k_order_scatter"],
+                 "bin_sort": ["k_emit", "k_rt_up", "k_rt_scan", "k_os_hist", "k_os_scan", "k_os_pass", "k_ranges",
+                              "k_order_hist", "k_order_scan", "k_order_scatter"],
                  "render_fwd": ["k_render_fwd"], "loss": ["k_l1_loss_grad"], "render_bwd": ["k_render_bwd"],
-                 "project_bwd": ["k_project_bwd"]}
+                 "project_bwd": ["k_project_bwd1", "k_project_bwd"]}
 
 
 def parse():

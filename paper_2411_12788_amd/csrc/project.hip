@@ -234,77 +234,94 @@ struct ProjBwdArgs {
 
 // Geometry part of the chain rule for one view, accumulated into gm (means),
 // gs (scales), gq (raw quaternion).  Worked in the camera frame: with A = W R
-// diag(s) (camera-frame ellipsoid axes a_k s_k), Sigma_c = A A^T and
+// diag(s) (camera-frame ellipsoid axes u_k s_k), Sigma_c = A A^T and
 // Sigma' = J Sigma_c J^T + lowpass, the gradient dL/dSigma_c = J^T G J is never
-// formed; only its products with the axes, h_k = J^T G (J a_k), are.
+// formed; only its products with the axes are.  G, the gradient with respect
+// to Sigma', is -Q M Q for the conic Q = Sigma'^-1 and M the symmetric
+// gradient of the conic; it is applied as G J u_k = -Q (M v_k) with
+// v_k = Q J u_k, never formed either: for a needle-like Gaussian Q's
+// eigenvalues differ by the square of its elongation, and forming G first
+// cancels by that square, forming v_k first only by the elongation.  The
+// geometry is recomputed in double (the forward's values); the chain rule
+// runs in float, which with this ordering is as accurate as the float
+// 2D gradient it starts from, and which halves the registers it holds.
 __device__ __forceinline__ void geometry_backward(const KView& cam, const KOpts& op, const SceneArgs& sc, int64_t i,
-                                                  const float* gr, double* gm, double* gs, double* gq) {
-  Geo g;
-  geometry(cam, op, sc, i, g);
-  const double gu = gr[0], gv = gr[1], ga = gr[2], gb = gr[3], gc = gr[4];
-  // conic -> 2D covariance (per-entry gradient G of the symmetric matrix)
-  const double a = g.a, b = g.b, c = g.c;
-  const double g00 = -(a * a * ga + a * b * gb + b * b * gc);
-  const double g11 = -(b * b * ga + b * c * gb + c * c * gc);
-  const double g01 = -(a * b * ga + 0.5 * (a * c + b * b) * gb + b * c * gc);
-  double W[9];
-  for (int k = 0; k < 9; ++k) W[k] = cam.R[k];
-  // camera-frame unit axes u_k = W r_k (r_k = column k of R(q))
-  double ax[3][3];  // ax[k][row]
-  for (int k = 0; k < 3; ++k)
+                                                  const float* gr, float* gm, float* gs, float* gq) {
+  float Rq[3][3], s[3], J00, J02, J11, J12, a, b, c, tx, ty, tz, xr, yr, qh[4], qnorm;
+  bool clx, cly;
+  {
+    Geo g;
+    geometry(cam, op, sc, i, g);
     for (int r = 0; r < 3; ++r)
-      ax[k][r] = W[3 * r + 0] * g.Rq[0][k] + W[3 * r + 1] * g.Rq[1][k] + W[3 * r + 2] * g.Rq[2][k];
-  // J u_k (2-vectors) and G J u_k
-  double gJ00 = 0.0, gJ02 = 0.0, gJ11 = 0.0, gJ12 = 0.0;
-  double GR[3][3];  // dL/dR(q), row p, column k
+      for (int k = 0; k < 3; ++k) Rq[r][k] = (float)g.Rq[r][k];
+    for (int k = 0; k < 3; ++k) s[k] = (float)g.s[k];
+    J00 = (float)g.J00; J02 = (float)g.J02; J11 = (float)g.J11; J12 = (float)g.J12;
+    a = (float)g.a; b = (float)g.b; c = (float)g.c;
+    tx = (float)g.t[0]; ty = (float)g.t[1]; tz = (float)g.t[2];
+    xr = (float)g.xr; yr = (float)g.yr;
+    for (int k = 0; k < 4; ++k) qh[k] = (float)g.qh[k];
+    qnorm = (float)g.qnorm;
+    clx = g.clx; cly = g.cly;
+  }
+  // M = [[ga, gb / 2], [gb / 2, gc]]: the exponent's B multiplies dx dy once
+  const float gu = gr[0], gv = gr[1], ga = gr[2], hb = 0.5f * gr[3], gc = gr[4];
+  const float* W = cam.R;
+  float gJ00 = 0.f, gJ02 = 0.f, gJ11 = 0.f, gJ12 = 0.f;
+  float GR[3][3];  // dL/dR(q), row p, column k
   for (int k = 0; k < 3; ++k) {
-    const double j0 = g.J00 * ax[k][0] + g.J02 * ax[k][2];
-    const double j1 = g.J11 * ax[k][1] + g.J12 * ax[k][2];
-    const double m0 = g00 * j0 + g01 * j1, m1 = g01 * j0 + g11 * j1;
+    // camera-frame unit axis u_k = W r_k (r_k = column k of R(q)), j = J u_k
+    const float u0 = W[0] * Rq[0][k] + W[1] * Rq[1][k] + W[2] * Rq[2][k];
+    const float u1 = W[3] * Rq[0][k] + W[4] * Rq[1][k] + W[5] * Rq[2][k];
+    const float u2 = W[6] * Rq[0][k] + W[7] * Rq[1][k] + W[8] * Rq[2][k];
+    const float j0 = J00 * u0 + J02 * u2, j1 = J11 * u1 + J12 * u2;
+    const float v0 = a * j0 + b * j1, v1 = b * j0 + c * j1;      // v = Q j
+    const float w0 = ga * v0 + hb * v1, w1 = hb * v0 + gc * v1;  // M v
+    const float m0 = -(a * w0 + b * w1), m1 = -(b * w0 + c * w1);  // G j = -Q M v
     // h = J^T m: the camera-frame gradient applied to u_k
-    const double h0 = g.J00 * m0, h1 = g.J11 * m1, h2 = g.J02 * m0 + g.J12 * m1;
-    const double sk = g.s[k], s2 = sk * sk;
-    // Sigma_c = sum_k s_k^2 u_k u_k^T:  dL/ds_k = 2 s_k u_k^T G_c u_k,  dL/du_k = 2 s_k^2 G_c u_k
-    gs[k] += 2.0 * sk * (ax[k][0] * h0 + ax[k][1] * h1 + ax[k][2] * h2);
-    for (int pr = 0; pr < 3; ++pr) GR[pr][k] = 2.0 * s2 * (W[0 + pr] * h0 + W[3 + pr] * h1 + W[6 + pr] * h2);
+    const float h0 = J00 * m0, h1 = J11 * m1, h2 = J02 * m0 + J12 * m1;
+    const float sk = s[k], s2 = sk * sk;
+    // Sigma_c = sum_k s_k^2 u_k u_k^T:  dL/ds_k = 2 s_k u_k^T G_c u_k = -2 s_k v^T M v,
+    // dL/du_k = 2 s_k^2 G_c u_k
+    gs[k] += -2.f * sk * (v0 * w0 + v1 * w1);
+    for (int pr = 0; pr < 3; ++pr) GR[pr][k] = 2.f * s2 * (W[0 + pr] * h0 + W[3 + pr] * h1 + W[6 + pr] * h2);
     // dL/dJ = 2 G J Sigma_c, with J Sigma_c = sum_k s_k^2 (J u_k) u_k^T
-    gJ00 += 2.0 * s2 * m0 * ax[k][0];
-    gJ02 += 2.0 * s2 * m0 * ax[k][2];
-    gJ11 += 2.0 * s2 * m1 * ax[k][1];
-    gJ12 += 2.0 * s2 * m1 * ax[k][2];
+    gJ00 += 2.f * s2 * m0 * u0;
+    gJ02 += 2.f * s2 * m0 * u2;
+    gJ11 += 2.f * s2 * m1 * u1;
+    gJ12 += 2.f * s2 * m1 * u2;
   }
-  const double tx = g.t[0], ty = g.t[1], tz = g.t[2];
-  const double fx = cam.fx, fy = cam.fy;
-  double gt0 = gu * fx / tz, gt1 = gv * fy / tz;
-  double gt2 = -(gu * fx * tx + gv * fy * ty) / (tz * tz);
-  gt2 += -(gJ00 * g.J00 + gJ11 * g.J11) / tz;
-  if (g.clx) {
-    gt2 += gJ02 * (fx * g.xr / (tz * tz));
+  const float fx = cam.fx, fy = cam.fy;
+  const float itz = 1.f / tz, itz2 = itz * itz;
+  float gt0 = gu * fx * itz, gt1 = gv * fy * itz;
+  float gt2 = -(gu * fx * tx + gv * fy * ty) * itz2;
+  gt2 += -(gJ00 * J00 + gJ11 * J11) * itz;
+  if (clx) {
+    gt2 += gJ02 * (fx * xr * itz2);
   } else {
-    gt0 += -gJ02 * fx / (tz * tz);
-    gt2 += gJ02 * 2.0 * fx * tx / (tz * tz * tz);
+    gt0 += -gJ02 * fx * itz2;
+    gt2 += gJ02 * 2.f * fx * tx * itz2 * itz;
   }
-  if (g.cly) {
-    gt2 += gJ12 * (fy * g.yr / (tz * tz));
+  if (cly) {
+    gt2 += gJ12 * (fy * yr * itz2);
   } else {
-    gt1 += -gJ12 * fy / (tz * tz);
-    gt2 += gJ12 * 2.0 * fy * ty / (tz * tz * tz);
+    gt1 += -gJ12 * fy * itz2;
+    gt2 += gJ12 * 2.f * fy * ty * itz2 * itz;
   }
   // t = W p + tau
   gm[0] += W[0] * gt0 + W[3] * gt1 + W[6] * gt2;
   gm[1] += W[1] * gt0 + W[4] * gt1 + W[7] * gt2;
   gm[2] += W[2] * gt0 + W[5] * gt1 + W[8] * gt2;
   // rotation -> normalised quaternion (w, x, y, z) -> raw quaternion
-  const double w = g.qh[0], x = g.qh[1], y = g.qh[2], z = g.qh[3];
-  const double dw = 2.0 * (z * (GR[1][0] - GR[0][1]) + y * (GR[0][2] - GR[2][0]) + x * (GR[2][1] - GR[1][2]));
-  const double dx = 2.0 * (y * (GR[0][1] + GR[1][0]) + z * (GR[0][2] + GR[2][0]) + w * (GR[2][1] - GR[1][2])) -
-                    4.0 * x * (GR[1][1] + GR[2][2]);
-  const double dy = 2.0 * (x * (GR[0][1] + GR[1][0]) + w * (GR[0][2] - GR[2][0]) + z * (GR[1][2] + GR[2][1])) -
-                    4.0 * y * (GR[0][0] + GR[2][2]);
-  const double dz = 2.0 * (w * (GR[1][0] - GR[0][1]) + x * (GR[0][2] + GR[2][0]) + y * (GR[1][2] + GR[2][1])) -
-                    4.0 * z * (GR[0][0] + GR[1][1]);
-  const double proj = dw * w + dx * x + dy * y + dz * z;
-  const double iq = 1.0 / g.qnorm;
+  const float w = qh[0], x = qh[1], y = qh[2], z = qh[3];
+  const float dw = 2.f * (z * (GR[1][0] - GR[0][1]) + y * (GR[0][2] - GR[2][0]) + x * (GR[2][1] - GR[1][2]));
+  const float dx = 2.f * (y * (GR[0][1] + GR[1][0]) + z * (GR[0][2] + GR[2][0]) + w * (GR[2][1] - GR[1][2])) -
+                   4.f * x * (GR[1][1] + GR[2][2]);
+  const float dy = 2.f * (x * (GR[0][1] + GR[1][0]) + w * (GR[0][2] - GR[2][0]) + z * (GR[1][2] + GR[2][1])) -
+                   4.f * y * (GR[0][0] + GR[2][2]);
+  const float dz = 2.f * (w * (GR[1][0] - GR[0][1]) + x * (GR[0][2] + GR[2][0]) + y * (GR[1][2] + GR[2][1])) -
+                   4.f * z * (GR[0][0] + GR[1][1]);
+  const float proj = dw * w + dx * x + dy * y + dz * z;
+  const float iq = 1.f / qnorm;
   gq[0] += (dw - w * proj) * iq;
   gq[1] += (dx - x * proj) * iq;
   gq[2] += (dy - y * proj) * iq;
@@ -322,17 +339,60 @@ __device__ __forceinline__ bool record_live(const ProjBwdArgs& pa, int64_t r) {
   return nz;
 }
 
-// One thread per Gaussian: rows without gradient (inactive, or live in no
-// view) are written as zeros; the others run the chain rule, geometry in
-// double and colour in float.  Every gradient plane is written with
-// coalesced stores.  Register use (about 200 VGPRs, two waves per SIMD) sets
-// the speed here: holding the 48 SH coefficients as values instead of as 48
-// hoisted 64-bit addresses, and the colour pass in float, took the kernel from
-// one wave per SIMD to two and from ~0.9 ms to ~0.35 ms at 3M Gaussians.
-constexpr int kGradPlanes = 3 + 3 + 4 + 1 + 48;  // means, scales, quats, opacity, sh
+// Colour part of one view, first half: the raw colour per channel (it
+// decides the clamp at 0) and its gradient with respect to the viewing
+// direction, in one sweep over the coefficients; returns the clamped colour
+// gradient gc and the direction d, and adds the mean's gradient through the
+// direction to gm.  The SH gradient of coefficient k is then gc_ch Y_k(d).
+template <int DEG, typename C>
+__device__ __forceinline__ void colour_backward(const KView& cam, const SceneArgs& sc, int64_t i, const float* gr,
+                                                C&& coef, float* gc, float* d, float* gm) {
+  const int64_t n = sc.n;
+  double cc[3];
+  camera_centre(cam, cc);
+  const double e0 = sc.means[i] - cc[0], e1 = sc.means[n + i] - cc[1], e2 = sc.means[2 * n + i] - cc[2];
+  const double ild = 1.0 / sqrt(e0 * e0 + e1 * e1 + e2 * e2);
+  const float il = (float)ild;
+  d[0] = (float)(e0 * ild);
+  d[1] = (float)(e1 * ild);
+  d[2] = (float)(e2 * ild);
+  float raw[3] = {0.5f, 0.5f, 0.5f}, grx[3] = {0.f, 0.f, 0.f}, gry[3] = {0.f, 0.f, 0.f}, grz[3] = {0.f, 0.f, 0.f};
+  sh_terms<DEG>(d[0], d[1], d[2], [&](int k, float Yk, float Gx, float Gy, float Gz) {
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+      const float ck = coef(k, ch);
+      raw[ch] += ck * Yk;
+      grx[ch] += ck * Gx;
+      gry[ch] += ck * Gy;
+      grz[ch] += ck * Gz;
+    }
+  });
+  for (int ch = 0; ch < 3; ++ch) gc[ch] = raw[ch] < 0.f ? 0.f : gr[6 + ch];
+  // the direction gradient is sum_ch gc_ch grad(raw_ch)
+  const float gd0 = gc[0] * grx[0] + gc[1] * grx[1] + gc[2] * grx[2];
+  const float gd1 = gc[0] * gry[0] + gc[1] * gry[1] + gc[2] * gry[2];
+  const float gd2 = gc[0] * grz[0] + gc[1] * grz[1] + gc[2] * grz[2];
+  // dir = e / |e|: project out the radial part
+  const float dd = gd0 * d[0] + gd1 * d[1] + gd2 * d[2];
+  gm[0] += (gd0 - d[0] * dd) * il;
+  gm[1] += (gd1 - d[1] * dd) * il;
+  gm[2] += (gd2 - d[2] * dd) * il;
+}
 
-template <int DEG>
-__global__ __launch_bounds__(kBlock) void k_project_bwd(ProjBwdArgs pa, ViewSet vs) {
+// One thread per Gaussian: rows without gradient (inactive, or live in no
+// view) are written as zeros; the others run the chain rule.  Every gradient
+// plane is written with coalesced stores, each group as soon as it is known,
+// so no thread holds all 59 values.  Every store is issued by all lanes of
+// the wave (zeros where the row has no gradient), so each store writes whole
+// lines: stores of the same lines split between the lanes with and without
+// gradient (tried) arrive far apart and made partial-line writes, 0.34 ->
+// 0.38 ms, and leaving the rows without gradient unwritten 0.46 ms.  Register
+// use sets the speed here (the kernel is bound by how many loads are in
+// flight): the chain rule in float and, for one view, SH gradients stored as
+// they are computed instead of summed over views keep it at ~126 VGPRs.
+
+template <int DEG, bool ONE_VIEW>
+__device__ __forceinline__ void project_bwd_row(const ProjBwdArgs& pa, const ViewSet& vs) {
   const int64_t n = pa.sc.n;
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
@@ -342,90 +402,84 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd(ProjBwdArgs pa, ViewSet 
     for (int v = 0; v < vs.count && !any; ++v) any = record_live(pa, (int64_t)v * n + i);
     work = any;
   }
-  float outv[kGradPlanes];
-  for (int p = 0; p < kGradPlanes; ++p) outv[p] = 0.f;
-  if (work) {
-    constexpr int K = (DEG + 1) * (DEG + 1);
-    double gm[3] = {0, 0, 0}, gs[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, go = 0.0;
-    // pass 1: geometry (mean through u, v and J; covariance; opacity)
-    for (int v = 0; v < vs.count; ++v) {
-      const int64_t r = (int64_t)v * n + i;
-      if (!record_live(pa, r)) continue;
-      const float* gr = pa.g2d + r * kG2d;
-      go += gr[5];
-      geometry_backward(vs.v[v], pa.op, pa.sc, i, gr, gm, gs, gq);
+  constexpr int K = (DEG + 1) * (DEG + 1);
+  float gm[3] = {0.f, 0.f, 0.f};
+  {
+    // geometry (mean through u, v and J; covariance; opacity)
+    float gs[3] = {0.f, 0.f, 0.f}, gq[4] = {0.f, 0.f, 0.f, 0.f}, go = 0.f;
+    if (work) {
+      for (int v = 0; v < vs.count; ++v) {
+        const int64_t r = (int64_t)v * n + i;
+        if (!record_live(pa, r)) continue;
+        const float* gr = pa.g2d + r * kG2d;
+        go += gr[5];
+        geometry_backward(vs.v[v], pa.op, pa.sc, i, gr, gm, gs, gq);
+      }
     }
-    for (int k = 0; k < 3; ++k) outv[3 + k] = (float)gs[k];
-    for (int k = 0; k < 4; ++k) outv[6 + k] = (float)gq[k];
-    outv[10] = (float)go;
-    // pass 2: colour (SH coefficients, and the mean through the viewing
-    // direction), in float: a colour gradient needs no more, and the 48
-    // coefficients and 48 accumulators then fit in half the registers
+    for (int k = 0; k < 3; ++k) pa.gscales[k * n + i] = gs[k];
+    for (int k = 0; k < 4; ++k) pa.gquats[k * n + i] = gq[k];
+    pa.gopac[i] = go;
+  }
+  // colour (SH coefficients, and the mean through the viewing direction)
+  if (ONE_VIEW) {
+    // the one record is live when the row has gradient: each SH gradient is
+    // final when computed (zero for a row without gradient: gc = 0)
+    float gc[3] = {0.f, 0.f, 0.f}, d[3] = {0.f, 0.f, 1.f};
+    if (work)
+      colour_backward<DEG>(
+          vs.v[0], pa.sc, i, pa.g2d + i * kG2d,
+          [&](int k, int ch) { return pa.sc.sh[(int64_t)(k * 3 + ch) * n + i]; }, gc, d, gm);
+    sh_terms<DEG>(d[0], d[1], d[2], [&](int k, float Yk, float, float, float) {
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) pa.gsh[(int64_t)(k * 3 + ch) * n + i] = gc[ch] * Yk;
+    });
+  } else {
     float gsh[K][3];
 #pragma unroll
     for (int k = 0; k < K; ++k) gsh[k][0] = gsh[k][1] = gsh[k][2] = 0.f;
-    // the coefficients are loaded once, before the view loop (held as values,
-    // not as 48 hoisted 64-bit addresses)
-    float coef[K][3];
+    if (work) {
+      // the coefficients are loaded once, before the view loop (held as
+      // values, not as 48 hoisted 64-bit addresses)
+      float coef[K][3];
+#pragma unroll
+      for (int k = 0; k < K; ++k)
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) coef[k][ch] = pa.sc.sh[(int64_t)(k * 3 + ch) * n + i];
+      for (int v = 0; v < vs.count; ++v) {
+        const int64_t r = (int64_t)v * n + i;
+        if (!record_live(pa, r)) continue;
+        float gc[3], d[3];
+        colour_backward<DEG>(
+            vs.v[v], pa.sc, i, pa.g2d + r * kG2d, [&](int k, int ch) { return coef[k][ch]; }, gc, d, gm);
+        sh_terms<DEG>(d[0], d[1], d[2], [&](int k, float Yk, float, float, float) {
+#pragma unroll
+          for (int ch = 0; ch < 3; ++ch) gsh[k][ch] += gc[ch] * Yk;
+        });
+      }
+    }
 #pragma unroll
     for (int k = 0; k < K; ++k)
 #pragma unroll
-      for (int ch = 0; ch < 3; ++ch) coef[k][ch] = pa.sc.sh[(int64_t)(k * 3 + ch) * n + i];
-    for (int v = 0; v < vs.count; ++v) {
-      const int64_t r = (int64_t)v * n + i;
-      if (!record_live(pa, r)) continue;
-      const float* gr = pa.g2d + r * kG2d;
-      const KView& cam = vs.v[v];
-      double cc[3];
-      camera_centre(cam, cc);
-      const double e0 = pa.sc.means[i] - cc[0], e1 = pa.sc.means[n + i] - cc[1], e2 = pa.sc.means[2 * n + i] - cc[2];
-      const double ild = 1.0 / sqrt(e0 * e0 + e1 * e1 + e2 * e2);
-      const float il = (float)ild;
-      const float d0 = (float)(e0 * ild), d1 = (float)(e1 * ild), d2 = (float)(e2 * ild);
-      // raw colour per channel (decides the clamp at 0) and its gradient with
-      // respect to the direction, in one sweep over the coefficients; the
-      // direction gradient is then sum_ch gc_ch grad(raw_ch), so the
-      // coefficients are read once and never held across sweeps
-      float raw[3] = {0.5f, 0.5f, 0.5f}, grx[3] = {0.f, 0.f, 0.f}, gry[3] = {0.f, 0.f, 0.f},
-            grz[3] = {0.f, 0.f, 0.f};
-      sh_terms<DEG>(d0, d1, d2, [&](int k, float Yk, float Gx, float Gy, float Gz) {
-#pragma unroll
-        for (int ch = 0; ch < 3; ++ch) {
-          const float ck = coef[k][ch];
-          raw[ch] += ck * Yk;
-          grx[ch] += ck * Gx;
-          gry[ch] += ck * Gy;
-          grz[ch] += ck * Gz;
-        }
-      });
-      const float gc0 = raw[0] < 0.f ? 0.f : gr[6], gc1 = raw[1] < 0.f ? 0.f : gr[7];
-      const float gc2 = raw[2] < 0.f ? 0.f : gr[8];
-      const float gd0 = gc0 * grx[0] + gc1 * grx[1] + gc2 * grx[2];
-      const float gd1 = gc0 * gry[0] + gc1 * gry[1] + gc2 * gry[2];
-      const float gd2 = gc0 * grz[0] + gc1 * grz[1] + gc2 * grz[2];
-      sh_terms<DEG>(d0, d1, d2, [&](int k, float Yk, float, float, float) {
-        gsh[k][0] += gc0 * Yk;
-        gsh[k][1] += gc1 * Yk;
-        gsh[k][2] += gc2 * Yk;
-      });
-      // dir = e / |e|: project out the radial part
-      const float dd = gd0 * d0 + gd1 * d1 + gd2 * d2;
-      gm[0] += (double)((gd0 - d0 * dd) * il);
-      gm[1] += (double)((gd1 - d1 * dd) * il);
-      gm[2] += (double)((gd2 - d2 * dd) * il);
-    }
-    for (int k = 0; k < 3; ++k) outv[k] = (float)gm[k];
-#pragma unroll
-    for (int k = 0; k < 16; ++k)
-#pragma unroll
-      for (int ch = 0; ch < 3; ++ch) outv[11 + k * 3 + ch] = k < K ? gsh[k < K ? k : 0][ch] : 0.f;
+      for (int ch = 0; ch < 3; ++ch) pa.gsh[(int64_t)(k * 3 + ch) * n + i] = gsh[k][ch];
   }
-  float* const planes[5] = {pa.gmeans, pa.gscales, pa.gquats, pa.gopac, pa.gsh};
-  const int first[6] = {0, 3, 6, 10, 11, kGradPlanes};
-#pragma unroll
-  for (int g = 0; g < 5; ++g)
-#pragma unroll
-    for (int p = first[g]; p < first[g + 1]; ++p) planes[g][(int64_t)(p - first[g]) * n + i] = outv[p];
+  for (int k = K * 3; k < 48; ++k) pa.gsh[(int64_t)k * n + i] = 0.f;
+  for (int k = 0; k < 3; ++k) pa.gmeans[k * n + i] = gm[k];
+}
+
+// One view: held to 128 VGPRs (four waves per SIMD), which it fits without
+// spilling.
+template <int DEG>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_project_bwd1(ProjBwdArgs pa,
+                                                                                                 ViewSet vs) {
+  project_bwd_row<DEG, true>(pa, vs);
+}
+
+// Several views: the SH gradients are summed over views in registers; held to
+// 168 VGPRs (three waves per SIMD), which degree 3 fits without spilling.
+template <int DEG>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void k_project_bwd(
+    ProjBwdArgs pa, ViewSet vs) {
+  project_bwd_row<DEG, false>(pa, vs);
 }
 
 }  // namespace msplat
@@ -484,11 +538,20 @@ extern "C" int32_t gs_project_backward(const gs_scene_t* scene, const gs_project
   pa.op = make_kopts(opts);
   dim3 grid(grid_1d(scene->n));
   hipStream_t s = (hipStream_t)stream;
-  switch (scene->sh_degree) {
-    case 0: hipLaunchKernelGGL(k_project_bwd<0>, grid, dim3(kBlock), 0, s, pa, vs); break;
-    case 1: hipLaunchKernelGGL(k_project_bwd<1>, grid, dim3(kBlock), 0, s, pa, vs); break;
-    case 2: hipLaunchKernelGGL(k_project_bwd<2>, grid, dim3(kBlock), 0, s, pa, vs); break;
-    default: hipLaunchKernelGGL(k_project_bwd<3>, grid, dim3(kBlock), 0, s, pa, vs); break;
+  if (V == 1) {
+    switch (scene->sh_degree) {
+      case 0: hipLaunchKernelGGL(k_project_bwd1<0>, grid, dim3(kBlock), 0, s, pa, vs); break;
+      case 1: hipLaunchKernelGGL(k_project_bwd1<1>, grid, dim3(kBlock), 0, s, pa, vs); break;
+      case 2: hipLaunchKernelGGL(k_project_bwd1<2>, grid, dim3(kBlock), 0, s, pa, vs); break;
+      default: hipLaunchKernelGGL(k_project_bwd1<3>, grid, dim3(kBlock), 0, s, pa, vs); break;
+    }
+  } else {
+    switch (scene->sh_degree) {
+      case 0: hipLaunchKernelGGL(k_project_bwd<0>, grid, dim3(kBlock), 0, s, pa, vs); break;
+      case 1: hipLaunchKernelGGL(k_project_bwd<1>, grid, dim3(kBlock), 0, s, pa, vs); break;
+      case 2: hipLaunchKernelGGL(k_project_bwd<2>, grid, dim3(kBlock), 0, s, pa, vs); break;
+      default: hipLaunchKernelGGL(k_project_bwd<3>, grid, dim3(kBlock), 0, s, pa, vs); break;
+    }
   }
   MS_CHECK_LAUNCH("project_backward");
   return GS_OK;

@@ -23,6 +23,11 @@ from oracle import F
 # Tolerances.
 COLOR_ATOL = 1e-4        # colour, depth, transmittance: max abs
 GRAD_REL_L2 = 1e-3       # per parameter group
+# The projection backward alone (parameters from the per-record 2D gradient):
+# its chain rule runs in float, ordered so that no intermediate cancels by
+# more than the elongation of a Gaussian; emulated in float32 against float64
+# on needles of elongation 12 its largest error is 4.2e-5 (scales).
+A8_REL_L2 = 1e-4
 # Relative widths inside which a decision is evaluated both ways.  Wider than
 # the float32 error of the decision's operands (parity bar):
 # alpha is exp2 of a float32 exponent (error ~1e-6 relative); a transmittance
@@ -211,3 +216,26 @@ def rel_l2(a, b):
     a = np.asarray(a, dtype=np.float64)
     b = np.asarray(b, dtype=np.float64)
     return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+
+
+def check_projection_backward(p, cams, opts, g2d, grads, n, active=None, what=""):
+    """The GPU's parameter gradients against the oracle's projection backward
+    applied to the GPU's own per-record 2D gradient g2d [V n, 9] (the
+    projection backward alone, a8), group by group at A8_REL_L2."""
+    g2d = np.asarray(g2d, dtype=np.float64)
+    og = None
+    for v, cam in enumerate(cams):
+        proj = oracle.project(p, cam, opts)
+        og = oracle.project_backward(p, cam, opts, proj, g2d[v * n:(v + 1) * n], og)
+    if active is not None:
+        msk = np.asarray(active).astype(bool)
+        for g in og.values():
+            g[..., ~msk] = 0.0
+    errs = {}
+    for k in ("means", "scales", "quats", "opacity", "sh"):
+        got = np.asarray(grads[k], dtype=np.float64)[..., :n]
+        errs[k] = rel_l2(got, og[k])
+    report(f"projection backward alone {what}", **errs)
+    for k, e in errs.items():
+        assert e <= A8_REL_L2, (what, k, e)
+    return errs

@@ -169,6 +169,33 @@ def test_backward_small_cube(gpu_lib, masked):
         assert np.all(g2[active == 0] == 0)
 
 
+@pytest.mark.parametrize("case", ["needles", "cube masked", "needles two views"])
+def test_projection_backward_alone(gpu_lib, case):
+    """a8 by itself: parameters from the GPU's own per-record 2D gradient,
+    against the oracle's chain rule of that same gradient.  Needle-like
+    Gaussians (one axis 12x the others) are where an unfortunate order of the
+    float chain rule loses most (forming the 2D covariance gradient first
+    cancels by the elongation squared); two views take the multi-view kernel."""
+    R = H.raster()
+    if case == "cube masked":
+        wl = _small(seed=25, n=3000, W=112, H=96)
+        cams = wl.cameras
+        active = gs_inputs.bernoulli_mask(wl.scene.n, 0.25, 26)
+    else:
+        wl = gs_inputs.elongated_cube(seed=27)
+        cams = wl.cameras if case == "needles" else [wl.cameras[0], gs_inputs.look_at((1.5, 0.5, 3.5), (0, 0, 0),
+                                                                                       144, 112)]
+        active = None
+    lay = R.view_layout(cams)
+    out = H.run_gpu_forward(wl.scene, cams, accumulate=False)
+    dldc = torch.from_numpy(gs_inputs.normal_image(3, lay.pixels_total, 28, scale=1.0 / lay.pixels_total)).cuda()
+    grads, g2d = R.render_backward(out["scene"], out["proj"], out["binned"], cams, R.RasterOpts(), out["frame"],
+                                   dldc, None if active is None else torch.from_numpy(active).cuda())
+    torch.cuda.synchronize()
+    H.check_projection_backward(oracle.Params.of(wl.scene), cams, oracle.Opts(), _np(g2d),
+                                _grads_np(grads, wl.scene.n), wl.scene.n, active=active, what=case)
+
+
 def test_multiview_mixed_resolution(gpu_lib):
     R = H.raster()
     sc = gs_inputs.uniform_cube_scene(2500, 9)

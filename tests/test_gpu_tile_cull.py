@@ -95,7 +95,12 @@ def test_outputs_unchanged_by_culling(gpu_lib, k):
     assert torch.equal(a["acc"]["wmax"], b["acc"]["wmax"])
     assert H.rel_l2(_np(b["acc"]["importance"]), _np(a["acc"]["importance"])) <= 1e-6
     assert H.rel_l2(_np(g2b), _np(g2a)) <= 1e-5
-    # the chain rule to scales and rotations cancels, so the atomics' summation
-    # order shows at the parity tolerance's scale there (same bound as vs the oracle)
-    for name in ("means", "scales", "quats", "opacity", "sh"):
-        assert H.rel_l2(_np(gb[name]), _np(ga[name])) <= H.GRAD_REL_L2, name
+    # The parameter gradients are the projection backward of g2d, which reads
+    # no list: each run's equals the oracle's chain rule of that run's g2d.
+    # (Compared with each other directly they would differ by the atomics'
+    # order in g2d amplified by the chain rule's conditioning, ~1e-3 on
+    # needles for scales even in exact arithmetic.)
+    p = oracle.Params.of(wl.scene)
+    for tag, g, g2 in (("unculled", ga, g2a), ("culled", gb, g2b)):
+        H.check_projection_backward(p, wl.cameras, oracle.Opts(), _np(g2), {k: _np(v) for k, v in g.items()},
+                                    wl.scene.n, active=active, what=f"tile cull {k} {tag}")
