@@ -136,6 +136,10 @@ def _d(a) -> np.ndarray:
 
 
 def _p(a: np.ndarray):
+    # the C side indexes plain row-major arrays: a strided view (a column slice
+    # of a [k][n] plane array, say) would be read with the wrong layout
+    if not a.flags["C_CONTIGUOUS"]:
+        raise ValueError("oracle: arrays passed to the C oracle must be C-contiguous")
     return a.ctypes.data_as(ctypes.c_void_p)
 
 
@@ -148,6 +152,11 @@ class Params:
     opacity: np.ndarray
     sh: np.ndarray
     sh_degree: int
+
+    def __post_init__(self):
+        # contiguous float64 planes (slices of another Params are copied)
+        for k in ("means", "scales", "quats", "opacity", "sh"):
+            setattr(self, k, _d(getattr(self, k)))
 
     @property
     def n(self) -> int:

@@ -222,3 +222,18 @@ def test_colour_clamps_at_zero():
     P = oracle.project(_params(sc), cam, OPTS)[0]
     assert P[F["R"]] == 0 and P[F["RAW_R"]] == pytest.approx(-0.3, abs=1e-7)
     assert P[F["B"]] == pytest.approx(1.7, abs=1e-6)
+
+
+def test_params_of_slices_and_strided_arrays():
+    """A Params built from column slices of another projects like the slice of
+    the whole projection (the planes are copied contiguous); a strided array
+    handed to the C oracle directly is refused rather than misread."""
+    wl = gs_inputs.small_cube(seed=5, n=3000, width=112, height=96)
+    p = oracle.Params.of(wl.scene)
+    cam, opts = wl.cameras[0], oracle.Opts()
+    full = oracle.project(p, cam, opts)
+    sl = slice(1000, 2000)
+    sub = oracle.Params(p.means[:, sl], p.scales[:, sl], p.quats[:, sl], p.opacity[sl], p.sh[:, :, sl], p.sh_degree)
+    assert np.array_equal(oracle.project(sub, cam, opts), full[sl])
+    with pytest.raises(ValueError):
+        oracle._p(p.means[:, sl])
