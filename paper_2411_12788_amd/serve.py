@@ -339,9 +339,10 @@ def drive(server: Server, requests: Sequence, arrivals: Sequence[float], warmup:
     """Submit ``requests`` [(scene_id, camera)] at the given offsets (seconds)
     from now, wait for all, and return latency / throughput statistics of the
     requests after the first ``warmup`` (which run but are not counted):
-    p50 / p99 / mean latency, views/s from the first counted arrival to the
-    last counted completion, the offered rate, and the distribution of the
-    batch sizes the counted requests were rendered in."""
+    p50 / p99 / mean latency, views/s over the window from the first counted
+    arrival (or the last warm-up completion, if later) to the last counted
+    completion, the offered rate, and the distribution of the batch sizes the
+    counted requests were rendered in."""
     t0 = server.clock()
     # Results are read as they complete and not kept (a served frame is the
     # client's to consume; holding every frame until the end of a run would
@@ -388,8 +389,15 @@ def drive(server: Server, requests: Sequence, arrivals: Sequence[float], warmup:
     def pct(p):
         return lat[min(n - 1, int(round(p / 100.0 * (n - 1))))]
 
+    # throughput window: from the first counted arrival, or from the last
+    # warm-up completion if that is later (with every request submitted at
+    # once, the counted ones wait for the warm-up to be served), to the last
+    # counted completion
     done = max(a + r.latency for a, r in zip(arr, meas))
-    span = done - arr[0]
+    start = arr[0]
+    if w > 0:
+        start = max(start, max(a + r.latency for a, r in zip(arrivals[:w], res[:w])))
+    span = done - start
     sizes: Dict[int, int] = {}
     for r in meas:
         sizes[r.batch_size] = sizes.get(r.batch_size, 0) + 1

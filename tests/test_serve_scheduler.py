@@ -151,3 +151,15 @@ def test_step_buffers_grow_and_reuse():
     assert z.shape == (1000, 16) and z.data_ptr() != x.data_ptr()  # grown
     w = b.take("rec", 10, torch.int32, "cpu", (16,))
     assert w.dtype == torch.int32
+
+
+def test_back_to_back_capacity_excludes_warmup():
+    """All requests submitted at once: the counted requests' throughput is
+    their own service rate, not diluted by the time the warm-up took."""
+    ex = FakeExecutor(SIZES, per_view_s=0.004, per_batch_s=0.0)
+    srv = Server(ex, hbm_budget=10 ** 9, slots=1, max_batch=1)
+    st = drive(srv, _reqs(40, 5), [0.0] * 40, warmup=20)
+    srv.close()
+    assert st["completed"] == 20
+    # 20 requests at ~4 ms each: ~250/s (the old window, from t = 0, gave ~125/s)
+    assert 150 < st["views_per_s"] < 260, st["views_per_s"]
