@@ -36,7 +36,7 @@ PEAK_HBM_GBS = 8000.0
 # 4 SIMDs x 16 lanes per clock x 2.4 GHz = 39.3 T lane-ops/s
 PEAK_VALU_TOPS = 256 * 64 * 2.4e9 / 1e12
 STOP_T = 0.01  # a pixel with final transmittance >= 1e-4 / (1 - 0.99) never stopped
-# algorithmic bytes per unit (kernels table)
+# algorithmic bytes per unit: what each kernel must read and write at least
 PROJECT_BYTES_PER_RECORD = 59 * 4 + 64 + 16     # params read, record + bin written
 PROJECT_BWD_BYTES_PER_ACTIVE = 59 * 4 + 59 * 4 + 36 + 16  # params read, grads written, 2D grad + bin read
 PROJECT_BWD_BYTES_PER_INACTIVE = 59 * 4 + 1     # zero rows written, mask read
@@ -732,7 +732,7 @@ def main():
     passes = (int(st.key_bits) + 7) // 8
     ibits = max(1, (nrec - 1).bit_length())
     pair_pass = 16 if int(st.key_bits) + ibits <= 64 else 24
-    # algorithmic bytes per step of each stage (kernels table)
+    # algorithmic bytes per step of each stage (the per-unit figures above times the units)
     alg = {
         "project": n * PROJECT_BYTES_PER_RECORD,
         "bin_count": nrec * 20,

@@ -29,7 +29,7 @@ GRAD_REL_L2 = 1e-3       # per parameter group
 # on needles of elongation 12 its largest error is 4.2e-5 (scales).
 A8_REL_L2 = 1e-4
 # Relative widths inside which a decision is evaluated both ways.  Wider than
-# the float32 error of the decision's operands (parity bar):
+# the float32 error of the decision's operands:
 # alpha is exp2 of a float32 exponent (error ~1e-6 relative); a transmittance
 # after k factors carries ~k ulp plus up to 100x the alpha error of a factor
 # with alpha near 0.99; weights carry the transmittance's error.
