@@ -44,9 +44,10 @@ RENDER_FWD_BYTES_PER_PAIR = 4 + 8 + 48          # list index, pixel box, the 48 
 RENDER_FWD_BYTES_PER_PIXEL = 12 + 4 + 4 + 4 + 4 + 4 + 1  # colour, depth, imax, T, last, count, hit
 RENDER_BWD_BYTES_PER_PAIR = 4 + 8 + 64 + 1      # list index, box, full record, active flag
 RENDER_BWD_BYTES_PER_PIXEL = 12 + 4 + 4         # dL/dC, T, last
-STAGE_KERNELS = {"project": ["k_project"], "bin_count": ["k_count_reduce", "k_count_top", "k_count_down"],
-                 "bin_sort": ["k_emit", "k_rt_up", "k_rt_scan", "k_os_hist", "k_os_scan", "k_os_pass", "k_ranges",
-                              "k_order_hist", "k_order_scan", "k_order_scatter"],
+BIN_PARTS = {"count": ["k_count_reduce", "k_count_top", "k_count_down"],
+             "sort": ["k_emit", "k_rt_up", "k_rt_scan", "k_os_hist", "k_os_scan", "k_os_pass", "k_ranges",
+                      "k_order_hist", "k_order_scan", "k_order_scatter"]}
+STAGE_KERNELS = {"project": ["k_project"], "bin": BIN_PARTS["count"] + BIN_PARTS["sort"],
                  "render_fwd": ["k_render_fwd"], "loss": ["k_l1_loss_grad"], "render_bwd": ["k_render_bwd"],
                  "project_bwd": ["k_project_bwd1", "k_project_bwd"]}
 
@@ -102,38 +103,44 @@ class Step:
         self.acc = R.alloc_accum(self.n)
         self.grads = R.alloc_grads(self.n)
         self.grad2d = torch.empty((self.n * len(self.cams), 9), device="cuda")
-        self.names = ["project", "bin_count", "bin_sort", "render_fwd", "loss", "render_bwd", "project_bwd"]
-        self.ev = {k: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-                   for k in self.names}
+        self.names = ["project", "bin", "render_fwd", "loss", "render_bwd", "project_bwd"]
+        self.ev = None  # this step's stage events (start, end) when recording
+        self.pending = []  # recorded steps whose events are read after the timed region
         self.times = {k: [] for k in self.names}
         self.frame = None
-        self.bin_buffers = R.BinBuffers()
+        self.buffers = R.StepBuffers()  # pair count, lists and sort workspace, reused
 
     def run(self, record: bool, recompute: bool = False):
         """One step.  With `recompute` the backward re-derives the projection
         and the sorted lists instead of keeping the forward's (the memory-lean
         mode of the autograd wrapper)."""
-        R, ev = self.R, self.ev
+        R = self.R
+        if record:
+            # fresh events per step, read once after the timed region: no
+            # synchronisation between steps
+            ev = {k: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                  for k in self.names}
+            self.pending.append(ev)
 
         def mark(k, i):
             if record:
                 ev[k][i].record()
 
-        mark("project", 0)
-        proj = R.project(self.scene, self.cams, self.opts)
-        mark("project", 1)
-        mark("bin_count", 0)
-        offsets, st = R.bin_count(proj, self.cams, self.n)
-        mark("bin_count", 1)
-        # clears that the step needs anyway, queued while the host prepares the
-        # sort launches (the pair count above is read back by the host)
+        # Clears the step needs (accumulators, loss, the per-record 2D
+        # gradient the backward adds into), queued first: the device is still
+        # busy with the previous step's backward, so they cost no idle time.
+        # Queued after the pair count instead, each would be a gap: the host
+        # launches them one by one while nothing else is queued.
         for t in self.acc.values():
             t.zero_()
         self.loss.zero_()
         self.grad2d.zero_()
-        mark("bin_sort", 0)
-        binned = R.bin_sort(proj, self.cams, self.n, offsets, st, buffers=self.bin_buffers)
-        mark("bin_sort", 1)
+        mark("project", 0)
+        proj = R.project(self.scene, self.cams, self.opts)
+        mark("project", 1)
+        mark("bin", 0)
+        binned = R.bin_step(proj, self.cams, self.n, self.buffers)
+        mark("bin", 1)
         mark("render_fwd", 0)
         self.frame = R.render_forward(self.scene, proj, binned, self.cams, self.opts, accum=self.acc,
                                       extras=True, out=self.frame)
@@ -143,8 +150,7 @@ class Step:
         mark("loss", 1)
         if recompute:
             proj = R.project(self.scene, self.cams, self.opts)
-            offsets, st = R.bin_count(proj, self.cams, self.n)
-            binned = R.bin_sort(proj, self.cams, self.n, offsets, st, buffers=self.bin_buffers)
+            binned = R.bin_step(proj, self.cams, self.n, self.buffers)
         mark("render_bwd", 0)
         R.render_backward_pixels(proj, binned, self.cams, self.n, self.opts, self.frame, self.dldc, self.active,
                                  self.grad2d)
@@ -158,14 +164,17 @@ class Step:
                                             None if self.active is None else ctypes.c_void_p(self.active.data_ptr()),
                                             ctypes.byref(R._grads_c(self.grads)), R._stream()), "project_backward")
         mark("project_bwd", 1)
-        self.stats = st
+        self.stats = binned.stats
         self.proj = proj
         self.binned = binned
 
     def collect(self):
+        """Stage times of the recorded steps (after a synchronisation)."""
         torch.cuda.synchronize()
-        for k in self.names:
-            self.times[k].append(self.ev[k][0].elapsed_time(self.ev[k][1]))
+        for ev in self.pending:
+            for k in self.names:
+                self.times[k].append(ev[k][0].elapsed_time(ev[k][1]))
+        self.pending = []
 
 
 def pair_evaluations(step):
@@ -225,17 +234,17 @@ def bin_sort_ms(step, algorithm: int, reps: int = 10) -> float:
     L.check(L.lib().gs_sort_set_algorithm(algorithm), "gs_sort_set_algorithm")
     try:
         offsets, st = R.bin_count(step.proj, step.cams, step.n)
-        R.bin_sort(step.proj, step.cams, step.n, offsets, st, buffers=step.bin_buffers)
+        R.bin_sort(step.proj, step.cams, step.n, offsets, st, buffers=step.buffers.bins)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         total = 0.0
         for _ in range(reps):
             e0.record()
-            R.bin_sort(step.proj, step.cams, step.n, offsets, st, buffers=step.bin_buffers)
+            R.bin_sort(step.proj, step.cams, step.n, offsets, st, buffers=step.buffers.bins)
             e1.record()
             torch.cuda.synchronize()
             total += e0.elapsed_time(e1)
-        R.sort_status(step.bin_buffers.ws)
+        R.sort_status(step.buffers.bins.ws)
     finally:
         L.lib().gs_sort_set_algorithm(L.GS_SORT_PRESCAN)
     return total / reps
@@ -704,9 +713,9 @@ def main():
     t0 = time.perf_counter()
     for _ in range(args.steps):
         step.run(record=True)
-        step.collect()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    step.collect()
     ms_step = 1e3 * wall / args.steps
     # the same step with the backward re-deriving projection and lists
     for _ in range(2):
@@ -735,8 +744,7 @@ def main():
     # algorithmic bytes per step of each stage (the per-unit figures above times the units)
     alg = {
         "project": n * PROJECT_BYTES_PER_RECORD,
-        "bin_count": nrec * 20,
-        "bin_sort": nrec * 20 + ni * 8 + ni * 8 + passes * pair_pass * ni + ni * 12 + tiles * 20,
+        "bin": nrec * 20 + (nrec * 20 + ni * 8 + ni * 8 + passes * pair_pass * ni + ni * 12 + tiles * 20),
         "render_fwd": ni * RENDER_FWD_BYTES_PER_PAIR + P * RENDER_FWD_BYTES_PER_PIXEL,
         "loss": P * 3 * 12,
         "render_bwd": ni * RENDER_BWD_BYTES_PER_PAIR + P * RENDER_BWD_BYTES_PER_PIXEL + ni * act_frac * 36,
@@ -772,14 +780,16 @@ def main():
                     if m in cnt[ks[0]]:
                         e[m] = round(cnt[ks[0]][m], 2)
         stages[k] = e
-    both = avg["bin_count"] + avg["bin_sort"]
-    stages["bin_count_and_sort"] = {"ms": round(both, 4), "frac_hbm_algorithmic": round(
-        (alg["bin_count"] + alg["bin_sort"]) / (both * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
-    kus = [stages[k].get("kernel_us_profiled") for k in ("bin_count", "bin_sort")]
-    if all(x is not None for x in kus):
-        stages["bin_count_and_sort"]["kernel_us_profiled"] = round(sum(kus), 1)
-        stages["bin_count_and_sort"]["frac_hbm_algorithmic_kernel_time"] = round(
-            (alg["bin_count"] + alg["bin_sort"]) / (sum(kus) * 1e-6) / 1e9 / PEAK_HBM_GBS, 4)
+    # the binning stage (pair count, its read-back, key emission, sort, ranges,
+    # tile order): its algorithmic bytes over the profiled kernel time too, and
+    # the profiled time of the count and the sort kernels apart
+    kb = stages["bin"].get("kernel_us_profiled")
+    if kb:
+        stages["bin"]["frac_hbm_algorithmic_kernel_time"] = round(alg["bin"] / (kb * 1e-6) / 1e9 / PEAK_HBM_GBS, 4)
+        for part, ks in BIN_PARTS.items():
+            ks = [x for x in ks if x in cnt]
+            stages["bin"][f"{part}_kernel_us_profiled"] = round(
+                sum(cnt[x]["avg_us"] * (cnt[x].get("calls") or kt_steps) / kt_steps for x in ks), 1)
     dom = max(("project", "render_fwd", "render_bwd", "project_bwd"), key=lambda k: avg[k])
     sd = stages[dom]
     if dom in ("render_fwd", "render_bwd"):
@@ -818,7 +828,7 @@ def main():
         "stages": stages,
     }
     out["stages"]["render_bwd_deterministic"] = {"ms": round(deterministic_backward_ms(step), 4)}
-    out["stages"]["bin_sort"]["ms_by_pass_algorithm"] = {"prescan": round(bin_sort_ms(step, 0), 4),
+    out["stages"]["bin"]["sort_ms_by_pass_algorithm"] = {"prescan": round(bin_sort_ms(step, 0), 4),
                                                          "lookback": round(bin_sort_ms(step, 1), 4)}
     if not args.no_criteria:
         out["criteria"] = criteria_bench(step)

@@ -19,7 +19,8 @@
  *    *_workspace_size() query, 256-byte aligned.  (The one exception,
  *    gs_sort_pairs_static, uses a library-owned device array instead.)
  *  - Asynchrony: work is enqueued on `stream` (a hipStream_t; NULL = the null
- *    stream).  Only gs_bin_count synchronises (it returns the pair count).
+ *    stream).  Only gs_bin_count and gs_bin synchronise (they return the pair
+ *    count).
  *  - Reentrancy: no global mutable state (apart from the diagnostic
  *    gs_sort_set_spin_limit and the scratch array of gs_sort_pairs_static);
  *    concurrent calls on different streams with disjoint buffers are safe.
@@ -222,6 +223,23 @@ size_t gs_bin_sort_workspace_size(int64_t n_isect);
 int32_t gs_bin_sort(const gs_projected_t* proj, const gs_camera_t* cams, int32_t V, int64_t n,
                     const uint32_t* offsets, const gs_bin_stats_t* stats, uint64_t* keys, uint32_t* vals,
                     uint32_t* ranges, uint32_t* tile_order, void* ws, size_t ws_bytes, void* stream);
+
+/* a2-a4 in one call: gs_bin_count, then gs_bin_sort when the pairs fit the
+ * caller's buffers, with nothing between the pair count's read-back and the
+ * sort's first launch (a caller that keeps its buffers from step to step
+ * then pays one host round trip per binning).  Arguments as in the two calls;
+ * pair_capacity = entries of vals (and of keys, when not NULL); ranges and
+ * tile_order hold tiles_total entries (fixed by the cameras); count_ws /
+ * sort_ws are the two calls' workspaces.  Returns the first failing call's
+ * status, with one addition: GS_ERR_CAPACITY with *stats and offsets valid
+ * and stats->n_isect < 2^30 means the pairs did not fit (n_isect >
+ * pair_capacity, or sort_ws_bytes < gs_bin_sort_workspace_size(n_isect));
+ * nothing was sorted, and the caller grows its buffers and calls gs_bin_sort
+ * with the same stats and offsets.  Synchronises `stream` (the pair count). */
+int32_t gs_bin(const gs_projected_t* proj, const gs_camera_t* cams, int32_t V, int64_t n, uint32_t* offsets,
+               gs_bin_stats_t* stats, uint64_t* keys, uint32_t* vals, int64_t pair_capacity, uint32_t* ranges,
+               uint32_t* tile_order, void* count_ws, size_t count_ws_bytes, void* sort_ws, size_t sort_ws_bytes,
+               void* stream);
 
 /* Processing order of the tiles for the compositing kernels: tile ids
  * [dev, u32 tiles_total] grouped by the bit length of their list length,

@@ -83,6 +83,8 @@ _SIGS = {
     "gs_bin_sort_workspace_size": (c_sz, [c_i64]),
     "gs_bin_sort": (c_i32, [P(Projected), P(Camera), c_i32, c_i64, c_p, P(BinStats), c_p, c_p, c_p, c_p, c_p, c_sz,
                             c_p]),
+    "gs_bin": (c_i32, [P(Projected), P(Camera), c_i32, c_i64, c_p, P(BinStats), c_p, c_p, c_i64, c_p, c_p, c_p, c_sz,
+                       c_p, c_sz, c_p]),
     "gs_tile_order_workspace_size": (c_sz, []),
     "gs_tile_order": (c_i32, [c_p, c_i32, c_p, c_p, c_sz, c_p]),
     "gs_emit_keys": (c_i32, [P(Projected), P(Camera), c_i32, c_i64, c_p, c_i32, c_u32, c_p, c_p, c_p]),

@@ -553,6 +553,21 @@ int32_t gs_bin_sort(const gs_projected_t* proj, const gs_camera_t* cams, int32_t
   if (ws_bytes < gs_bin_sort_workspace_size(ni)) { set_error("bin_sort workspace too small"); return GS_ERR_CAPACITY; }
   return bin_sort_on_ws(proj, vs, V, n, offsets, stats, keys, vals, ranges, tile_order, ws, s);
 }
+int32_t gs_bin(const gs_projected_t* proj, const gs_camera_t* cams, int32_t V, int64_t n, uint32_t* offsets,
+               gs_bin_stats_t* stats, uint64_t* keys, uint32_t* vals, int64_t pair_capacity, uint32_t* ranges,
+               uint32_t* tile_order, void* count_ws, size_t count_ws_bytes, void* sort_ws, size_t sort_ws_bytes,
+               void* stream) {
+  if (pair_capacity < 0) { set_error("pair_capacity < 0"); return GS_ERR_SHAPE; }
+  int32_t st = gs_bin_count(proj, cams, V, n, offsets, stats, count_ws, count_ws_bytes, stream);
+  if (st != GS_OK) return st;
+  if (stats->n_isect > pair_capacity || sort_ws_bytes < gs_bin_sort_workspace_size(stats->n_isect)) {
+    set_error("the pairs do not fit the buffers: grow them to stats->n_isect and call gs_bin_sort");
+    return GS_ERR_CAPACITY;
+  }
+  return gs_bin_sort(proj, cams, V, n, offsets, stats, keys, vals, ranges, tile_order, sort_ws, sort_ws_bytes,
+                     stream);
+}
+
 size_t gs_tile_order_workspace_size(void) { return 256; }
 
 int32_t gs_tile_order(const uint32_t* ranges, int32_t tiles_total, uint32_t* tile_order, void* ws, size_t ws_bytes,

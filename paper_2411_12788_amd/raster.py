@@ -231,6 +231,54 @@ def bin_sort(proj: Projected, cams, n: int, offsets: torch.Tensor, st: L.BinStat
                   order[:tiles])
 
 
+def tiles_total(cams) -> int:
+    return sum(((int(c.width) + L.GS_TILE - 1) // L.GS_TILE) * ((int(c.height) + L.GS_TILE - 1) // L.GS_TILE)
+               for c in cams)
+
+
+def bin_step(proj: Projected, cams, n: int, buffers: StepBuffers, want_keys: bool = False, stream=None,
+             on_count=None) -> Binned:
+    """Pair count, emission, sort, ranges and tile order in one library call
+    (gs_bin) into the reusable buffers, so nothing runs on the host between
+    the pair count's read-back and the sort's launch; when the pairs outgrow
+    the buffers they grow and the sort runs as a second call.  on_count(stats),
+    if given, runs once the pair count is known and before any buffer grows
+    (a caller that accounts for device memory adjusts its reservation there)."""
+    V = len(cams)
+    dev = proj.rec.device
+    lib = L.lib()
+    offsets = buffers.take("offsets", max(V * n, 1), torch.int32, dev)
+    cws = buffers.take("count_ws", max(lib.gs_bin_count_workspace_size(V * n), 1), torch.uint8, dev)
+    bb = buffers.bins
+    tiles = tiles_total(cams)
+    bb.ranges = bb._fit(bb.ranges, 2 * max(tiles, 1), torch.int32, dev)
+    bb.order = bb._fit(bb.order, max(tiles, 1), torch.int32, dev)
+    cap = 0 if bb.vals is None else bb.vals.numel()
+    if want_keys:
+        cap = min(cap, 0 if bb.keys is None else bb.keys.numel())
+    ws_bytes = 0 if bb.ws is None else bb.ws.numel()
+    st = L.BinStats()
+    pc = proj.c()
+    cc = cameras(cams)
+    sp = _stream(stream)
+    rc = lib.gs_bin(ctypes.byref(pc), cc, V, n, _ptr(offsets), ctypes.byref(st), _ptr(bb.keys if want_keys else None),
+                    _ptr(bb.vals), cap, _ptr(bb.ranges), _ptr(bb.order), _ptr(cws), cws.numel(), _ptr(bb.ws), ws_bytes,
+                    sp)
+    ni = int(st.n_isect)
+    grow = rc == L.GS_ERR_CAPACITY and 0 <= ni < (1 << 30) and (ni > cap or
+                                                                ws_bytes < lib.gs_bin_sort_workspace_size(ni))
+    if on_count is not None and (rc == L.GS_OK or grow):
+        on_count(st)
+    if grow:
+        vals, keys, ranges, order, ws = bb.get(ni, tiles, want_keys, dev)
+        L.check(lib.gs_bin_sort(ctypes.byref(pc), cc, V, n, _ptr(offsets), ctypes.byref(st), _ptr(keys), _ptr(vals),
+                                _ptr(ranges), _ptr(order), _ptr(ws), ws.numel(), sp), "gs_bin_sort")
+    else:
+        L.check(rc, "gs_bin")
+    return Binned(bb.vals[:ni], bb.ranges[: 2 * tiles].view(tiles, 2), bb.keys[:ni] if want_keys else None, st,
+                  offsets, bb.order[:tiles])
+
+
 def sort_status(ws: torch.Tensor, stream=None) -> None:
     """Raises if the last sort on workspace `ws` raised its error flag (synchronises)."""
     L.check(L.lib().gs_sort_status(_ptr(ws), _stream(stream)), "gs_sort_status")

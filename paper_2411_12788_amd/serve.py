@@ -8,8 +8,9 @@ waiting requests for the same scene (up to ``max_batch`` views, any mix of
 resolutions): they render in one multi-view launch per stage.  Work on
 different slots overlaps on the GPU.  Admission is two-phase because the pair
 count is only known after projection: a request first reserves an estimate,
-and after the binning count the executor grows (or shrinks) the reservation to
-the real figure, waiting if the budget is momentarily full.
+and once the pairs are counted the executor grows (or shrinks) the reservation
+to the real figure, waiting if the budget is momentarily full, before any of
+the slot's buffers grow.
 
 Latency is measured from arrival to completion of the request's last kernel
 (host copy excluded).  ``Server`` is independent of the GPU; ``GpuExecutor``
@@ -269,16 +270,21 @@ class GpuExecutor:
         with torch.cuda.stream(st):
             buf = self.buffers[slot]
             proj = R.project(scene, cams, self.opts, stream=st, buffers=buf)
-            offsets, stats = R.bin_count(proj, cams, scene.n, stream=st, buffers=buf)
-            real = self._bytes(scene.n, len(cams), sum(c.width * c.height for c in cams), int(stats.n_isect))
             est = self.footprint(batch)
-            if real != est:
-                server.grow(real - est, slot)
-            with self.lock:
-                ppr = stats.n_isect / max(1, len(cams) * scene.n)
-                old = self.pairs_per_record.get(sid)
-                self.pairs_per_record[sid] = ppr if old is None else max(ppr, 0.5 * (old + ppr))
-            binned = R.bin_sort(proj, cams, scene.n, offsets, stats, stream=st, buffers=buf.bins)
+
+            def counted(stats):
+                # second admission phase, before any buffer of the slot grows
+                real = self._bytes(scene.n, len(cams), sum(c.width * c.height for c in cams), int(stats.n_isect))
+                if real != est:
+                    server.grow(real - est, slot)
+                with self.lock:
+                    ppr = stats.n_isect / max(1, len(cams) * scene.n)
+                    old = self.pairs_per_record.get(sid)
+                    self.pairs_per_record[sid] = ppr if old is None else max(ppr, 0.5 * (old + ppr))
+
+            # count and sort in one library call when the slot's buffers hold
+            # the pairs
+            binned = R.bin_step(proj, cams, scene.n, buf, stream=st, on_count=counted)
             frame = R.render_forward(scene, proj, binned, cams, self.opts, extras=False, stream=st)
             ev = torch.cuda.Event()
             ev.record(st)

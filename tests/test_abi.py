@@ -147,3 +147,20 @@ def test_sort_algorithm_switch_on_host(L):
     assert lib.gs_sort_set_algorithm(7) == L.GS_ERR_UNSUPPORTED
     assert lib.gs_sort_set_algorithm(L.GS_SORT_LOOKBACK) == L.GS_OK
     assert lib.gs_sort_set_algorithm(L.GS_SORT_PRESCAN) == L.GS_OK
+
+
+def test_fused_binning_argument_errors_on_host(L):
+    """gs_bin refuses a negative capacity before anything runs, and passes the
+    pair count's argument errors through."""
+    from paper_2411_12788_amd import raster as R
+    lib = L.lib()
+    cams = R.cameras([gs_inputs.look_at((0, 0, 4), (0, 0, 0), 16, 16)])
+    fake = ctypes.c_void_p(0x1000)
+    st = L.BinStats()
+    proj = L.Projected(fake, fake, 0.0)
+    assert lib.gs_bin(ctypes.byref(proj), cams, 1, 10, fake, ctypes.byref(st), None, fake, -1, fake, None, fake,
+                      1 << 20, fake, 1 << 20, None) == L.GS_ERR_SHAPE
+    assert lib.gs_bin(None, cams, 1, 10, fake, ctypes.byref(st), None, fake, 10, fake, None, fake, 1 << 20, fake,
+                      1 << 20, None) == L.GS_ERR_NULL
+    assert lib.gs_bin(ctypes.byref(proj), cams, 1, 10, fake, None, None, fake, 10, fake, None, fake, 1 << 20, fake,
+                      1 << 20, None) == L.GS_ERR_NULL

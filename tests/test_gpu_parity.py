@@ -291,6 +291,34 @@ def test_tile_order_is_longest_first_permutation(gpu_lib):
     assert np.all(np.diff(bits) <= 0)
 
 
+def test_fused_binning_equals_two_calls(gpu_lib):
+    """gs_bin through raster.bin_step: the first call (empty buffers: the
+    sort runs as a second call after they grow), a repeat (everything in one
+    call), a larger workload (growth again) and a smaller one (one call into
+    larger buffers) give the lists of the separate count and sort; an empty
+    scene gives empty ranges."""
+    R = H.raster()
+    bufs = R.StepBuffers()
+    for seed, n in ((21, 4096), (21, 4096), (22, 9000), (23, 1000), (24, 0)):
+        wl = _small(seed=seed, n=max(n, 1))
+        if n == 0:
+            wl.scene.opacity[:] = 0.0  # nothing reaches alpha_min: no pairs
+        opts = R.RasterOpts()
+        ds = R.DeviceScene.from_numpy(wl.scene)
+        proj = R.project(ds, wl.cameras, opts)
+        fused = R.bin_step(proj, wl.cameras, ds.n, bufs, want_keys=True)
+        fresh = R.bin(proj, wl.cameras, ds.n, want_keys=True)
+        torch.cuda.synchronize()
+        assert fused.stats.n_isect == fresh.stats.n_isect
+        assert torch.equal(fused.keys, fresh.keys)
+        assert torch.equal(fused.vals, fresh.vals)
+        assert torch.equal(fused.ranges, fresh.ranges)
+        assert torch.equal(fused.order, fresh.order)
+        assert torch.equal(fused.offsets, fresh.offsets)
+        if n == 0:
+            assert fused.stats.n_isect == 0 and int(fused.ranges.abs().sum()) == 0
+
+
 def test_bin_buffers_reused_across_sizes(gpu_lib):
     """Binning into reused buffers (larger, then smaller, then larger again)
     gives the same lists as fresh buffers."""
