@@ -106,14 +106,28 @@ class Layout:
     pixels_total: int
 
 
+_LAYOUTS: Dict[tuple, Layout] = {}
+
+
 def view_layout(cams) -> Layout:
+    """Per-view tile and pixel bases of a multi-view launch (from the library).
+    It depends only on the views' sizes and is memoised on them: every
+    render call asks for it, and building the camera array costs more than
+    the lookup (the returned object is shared; do not modify it)."""
+    key = tuple((int(c.width), int(c.height)) for c in cams)
+    hit = _LAYOUTS.get(key)
+    if hit is not None:
+        return hit
     V = len(cams)
     ca = cameras(cams)
     tx, ty, tb = (ctypes.c_int32 * V)(), (ctypes.c_int32 * V)(), (ctypes.c_int32 * V)()
     pb = (ctypes.c_int64 * V)()
     tt, pt = ctypes.c_int32(), ctypes.c_int64()
     L.check(L.lib().gs_view_layout(ca, V, tx, ty, tb, pb, ctypes.byref(tt), ctypes.byref(pt)), "gs_view_layout")
-    return Layout(list(tx), list(ty), list(tb), list(pb), tt.value, pt.value)
+    lay = Layout(list(tx), list(ty), list(tb), list(pb), tt.value, pt.value)
+    if len(_LAYOUTS) < 1024:
+        _LAYOUTS[key] = lay
+    return lay
 
 
 @dataclasses.dataclass
