@@ -65,6 +65,8 @@ def parse():
     ap.add_argument("--serving-warmup", type=int, default=200)
     ap.add_argument("--no-multiview", action="store_true")
     ap.add_argument("--no-criteria", action="store_true")
+    ap.add_argument("--input-order", action="store_true",
+                    help="time the Gaussians in their generated order instead of the library's spatial order")
     ap.add_argument("--profile", action="store_true",
                     help="short run for rocprofv3: a few steps plus a 1 GiB copy kernel for counter calibration")
     ap.add_argument("--summarize", metavar="DIR",
@@ -87,7 +89,7 @@ def workload(name):
 class Step:
     """Buffers and launches of one training step (all on torch's current stream)."""
 
-    def __init__(self, wl):
+    def __init__(self, wl, spatial: bool = True):
         from paper_2411_12788_amd import raster as R
         self.R = R
         self.cams = wl.cameras
@@ -98,14 +100,21 @@ class Step:
         P = self.lay.pixels_total
         self.target = torch.from_numpy(gs_inputs.uniform_image(3, P, 4242)).cuda()
         self.active = torch.from_numpy(wl.active).cuda() if wl.active is not None else None
+        self.perm = None
+        if spatial:
+            # the layout the library keeps Gaussians in: the same set, stored
+            # along the Morton curve of the means; the mask moves with them
+            self.scene, self.perm = self.scene.in_spatial_order()
+            if self.active is not None:
+                self.active = R.permute(self.active, self.perm)
         self.dldc = torch.empty((3, P), device="cuda")
         self.loss = torch.zeros(1, device="cuda")
         self.acc = R.alloc_accum(self.n)
         self.grads = R.alloc_grads(self.n)
         self.grad2d = torch.empty((self.n * len(self.cams), 9), device="cuda")
         self.names = ["project", "bin", "render_fwd", "loss", "render_bwd", "project_bwd"]
-        self.ev = None  # this step's stage events (start, end) when recording
         self.pending = []  # recorded steps whose events are read after the timed region
+        self.prepared = []  # event sets made ahead of the timed region
         self.times = {k: [] for k in self.names}
         self.frame = None
         self.buffers = R.StepBuffers()  # pair count, lists and sort workspace, reused
@@ -116,10 +125,11 @@ class Step:
         mode of the autograd wrapper)."""
         R = self.R
         if record:
-            # fresh events per step, read once after the timed region: no
-            # synchronisation between steps
-            ev = {k: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-                  for k in self.names}
+            # one set of events per step, read once after the timed region (no
+            # synchronisation between steps), created beforehand by
+            # prepare_events (creating them here made a rare host stall of
+            # ~1 ms inside the timed region)
+            ev = self.prepared.pop() if self.prepared else self._new_events()
             self.pending.append(ev)
 
         def mark(k, i):
@@ -136,7 +146,7 @@ class Step:
         self.loss.zero_()
         self.grad2d.zero_()
         mark("project", 0)
-        proj = R.project(self.scene, self.cams, self.opts)
+        proj = R.project(self.scene, self.cams, self.opts, buffers=self.buffers)
         mark("project", 1)
         mark("bin", 0)
         binned = R.bin_step(proj, self.cams, self.n, self.buffers)
@@ -149,7 +159,7 @@ class Step:
         R.l1_loss_grad(self.frame.color, self.target, self.dldc, self.loss)
         mark("loss", 1)
         if recompute:
-            proj = R.project(self.scene, self.cams, self.opts)
+            proj = R.project(self.scene, self.cams, self.opts, buffers=self.buffers)
             binned = R.bin_step(proj, self.cams, self.n, self.buffers)
         mark("render_bwd", 0)
         R.render_backward_pixels(proj, binned, self.cams, self.n, self.opts, self.frame, self.dldc, self.active,
@@ -168,6 +178,19 @@ class Step:
         self.proj = proj
         self.binned = binned
 
+    def _new_events(self):
+        return {k: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for k in self.names}
+
+    def prepare_events(self, steps: int):
+        """Create (and record once, so the device events exist) the event sets
+        of `steps` recorded steps."""
+        self.prepared = [self._new_events() for _ in range(steps)]
+        for ev in self.prepared:
+            for a, b in ev.values():
+                a.record()
+                b.record()
+        torch.cuda.synchronize()
+
     def collect(self):
         """Stage times of the recorded steps (after a synchronisation)."""
         torch.cuda.synchronize()
@@ -175,6 +198,28 @@ class Step:
             for k in self.names:
                 self.times[k].append(ev[k][0].elapsed_time(ev[k][1]))
         self.pending = []
+
+
+def spatial_order_ms(step, reps: int = 5) -> float:
+    """One-off cost of moving the step's scene (generated order) and mask into
+    the spatial order: Morton codes, their sort, and the planar gathers."""
+    R = step.R
+
+    def one():
+        sc, perm = step.scene.in_spatial_order()
+        if step.active is not None:
+            R.permute(step.active, perm)
+        return sc
+
+    one()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        one()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
 
 
 def pair_evaluations(step):
@@ -461,7 +506,8 @@ def serving_bench(n_requests: int, warmup: int):
     from paper_2411_12788_amd.serve import GpuExecutor, Server, drive, poisson_arrivals
     scenes = {}
     for k, n in enumerate(gs_inputs.SERVING_SCENE_SIZES):
-        scenes[k] = R.DeviceScene.from_numpy(gs_inputs.surface_scene(n, 500 + k))
+        # resident in the library's spatial order (served images do not depend on it)
+        scenes[k] = R.DeviceScene.from_numpy(gs_inputs.surface_scene(n, 500 + k)).in_spatial_order()[0]
     torch.cuda.synchronize()
     resident = sum(s.nbytes() for s in scenes.values())
 
@@ -514,7 +560,7 @@ def multiview_bench(steps: int, warmup: int):
     from paper_2411_12788_amd import raster as R
     from paper_2411_12788_amd.autograd import rasterize
     wl = gs_inputs.multiview()
-    sc = R.DeviceScene.from_numpy(wl.scene)
+    sc = R.DeviceScene.from_numpy(wl.scene).in_spatial_order()[0]
     leaves = [t.clone().requires_grad_(True) for t in (sc.means, sc.scales, sc.quats, sc.opacity, sc.sh)]
     lay = R.view_layout(wl.cameras)
     target = torch.from_numpy(gs_inputs.uniform_image(3, lay.pixels_total, 777)).cuda()
@@ -706,9 +752,10 @@ def main():
         profile_run(max(2, args.steps))
         return
     wl = workload(args.workload)
-    step = Step(wl)
+    step = Step(wl, spatial=not args.input_order)
     for _ in range(args.warmup):
         step.run(record=False)
+    step.prepare_events(args.steps)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -728,6 +775,20 @@ def main():
     ms_recompute = 1e3 * (time.perf_counter() - t1) / args.steps
     step.run(record=False)  # leave the kept-lists state for the figures below
     torch.cuda.synchronize()
+    # the same workload with the Gaussians in their generated order, and the
+    # one-off cost of the reorder
+    other = Step(wl, spatial=args.input_order)
+    for _ in range(args.warmup):
+        other.run(record=False)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for _ in range(args.steps):
+        other.run(record=False)
+    torch.cuda.synchronize()
+    ms_other = 1e3 * (time.perf_counter() - t2) / args.steps
+    reorder_ms = spatial_order_ms(step if args.input_order else other)
+    del other
+    torch.cuda.empty_cache()
     med = {k: float(np.median(v)) for k, v in step.times.items()}
     avg = {k: float(np.mean(v)) for k, v in step.times.items()}
     st = step.stats
@@ -814,6 +875,8 @@ def main():
         "warmup": args.warmup,
         "ms_per_step": round(ms_step, 4),
         "ms_per_step_recompute": round(ms_recompute, 4),
+        ("ms_per_step_spatial_order" if args.input_order else "ms_per_step_input_order"): round(ms_other, 4),
+        "spatial_order_ms": round(reorder_ms, 4),
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
@@ -821,6 +884,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl.name, "gaussians": n, "views": len(wl.cameras),
                    "resolution": f"{wl.cameras[0].width}x{wl.cameras[0].height}", "active_fraction": act_frac,
+                   "layout": ("generated order" if args.input_order else
+                              "spatial order (gs_spatial_order: the same Gaussians along the Morton curve)"),
                    "n_visible": n_vis, "n_isect": int(st.n_isect), "key_bits": int(st.key_bits),
                    "included_pairs": int(nc), "pair_evaluations_fwd": int(ev_fwd),
                    "pair_evaluations_bwd": int(ev_bwd)},

@@ -16,8 +16,11 @@
  *    `stream` completes; host pointers (marked [host]) are read before the
  *    call returns.  The library keeps no pointer after return and allocates
  *    nothing: scratch memory arrives as (ws, ws_bytes), sized by the matching
- *    *_workspace_size() query, 256-byte aligned.  (The one exception,
- *    gs_sort_pairs_static, uses a library-owned device array instead.)
+ *    *_workspace_size() query, 256-byte aligned.  (The exceptions:
+ *    gs_sort_pairs_static uses a library-owned device array instead, and
+ *    gs_bin_count keeps, per host thread and device, a 64-byte pinned host
+ *    buffer and an event for its read-back, made on first use and kept until
+ *    the process ends.)
  *  - Asynchrony: work is enqueued on `stream` (a hipStream_t; NULL = the null
  *    stream).  Only gs_bin_count and gs_bin synchronise (they return the pair
  *    count).
@@ -204,8 +207,11 @@ int32_t gs_project(const gs_scene_t* scene, const gs_camera_t* cams, int32_t V, 
                    const gs_opts_t* opts, const gs_projected_t* out, void* stream);
 
 /* a2 -- binning count: exclusive scan of tiles_touched into offsets [dev, u32
- * V*n] and the statistics above.  Synchronises `stream` to return *stats.
- * GS_ERR_CAPACITY if the pair count is 2^30 or more (the sort's limit). */
+ * V*n] and the statistics above.  Synchronises `stream` to return *stats: the
+ * counting kernel also writes the totals to host-mapped memory and the calling
+ * thread polls an event (it spins, holding one core, for the few microseconds
+ * of the count).  GS_ERR_CAPACITY if the pair count is 2^30 or more (the
+ * sort's limit). */
 size_t gs_bin_count_workspace_size(int64_t n_records);
 int32_t gs_bin_count(const gs_projected_t* proj, const gs_camera_t* cams, int32_t V, int64_t n,
                      uint32_t* offsets, gs_bin_stats_t* stats, void* ws, size_t ws_bytes, void* stream);
@@ -312,6 +318,34 @@ int32_t gs_sort_set_algorithm(int32_t algorithm);
 #define GS_SORT_STATIC_MAX_PAIRS (1 << 20)
 int32_t gs_sort_pairs_static(uint64_t* keys, uint32_t* vals, int64_t n, int32_t key_bits, uint32_t* status,
                              void* stream);
+
+/* Spatial order: a memory layout of this library, not a step of the method.
+ * The Gaussians' index order is free (every result is the same up to a
+ * permutation, except that list entries of exactly equal depth keep ascending
+ * index order); stored along a Morton (Z-order) curve of their means, the
+ * Gaussians a tile's list names sit close together in memory, and the
+ * compositing and projection kernels read fewer cache lines.
+ * gs_spatial_order: perm [dev, u32 n] receives the stable ascending order of
+ * the 30-bit codes of the means [dev, f32 3 x n, planar]; codes [dev, u32 n]
+ * may be NULL, else receives the code of Gaussian i at i.  The code, in
+ * float32: per axis, lo and hi are the min and max over the Gaussians whose
+ * three coordinates are finite, s = 1024 / (hi - lo) (0 when hi = lo), the
+ * cell is floor((x - lo) * s), or 1023 when that product is 1023 or more or
+ * not a number; bits 3b + 2, 3b + 1 and 3b of the code are bit b of the x, y
+ * and z cells.  A Gaussian with a non-finite coordinate gets 2^30 - 1 (it
+ * sorts last).  ws [dev] sized by gs_spatial_order_workspace_size(n); its
+ * start is a sort workspace (gs_sort_status applies); n < 2^30
+ * (GS_ERR_CAPACITY otherwise).  Does not synchronise.
+ * gs_permute: dst[p n + i] = src[p n + perm[i]] for planes p < planes and
+ * i < n, elements of elem_bytes (1, 2, 4, 8 or 16) bytes [dev, both planar
+ * with plane stride n; they may not overlap (GS_ERR_SHAPE)].  An entry
+ * perm[i] >= n writes zero bytes at i.  Moves the scene, optimizer state and
+ * any other per-Gaussian array into the order perm gives. */
+size_t gs_spatial_order_workspace_size(int64_t n);
+int32_t gs_spatial_order(const float* means, int64_t n, uint32_t* perm, uint32_t* codes, void* ws, size_t ws_bytes,
+                         void* stream);
+int32_t gs_permute(const void* src, void* dst, int64_t planes, int64_t n, int32_t elem_bytes, const uint32_t* perm,
+                   void* stream);
 
 /* a5 (+a6) -- forward compositing, Eq. (1): per pixel, front to back over its
  * tile's list: alpha = min(alpha_max, opacity * G2D); skip when alpha <

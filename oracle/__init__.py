@@ -34,6 +34,10 @@ other than itself live in ``tests/test_oracle_*.py``:
   tile_alpha_max    Eq. (1) alpha over a tile's pixel centres (tile culling checks)
                                                             pinned: isotropic closed form,
                     centre inside the tile
+  spatial_order     not a step of the method: the GPU library's memory layout
+                    (Morton order of the means), checked so that its permutation
+                    is exact                                pinned: octree descent in
+                    double, Z-order of grid points, numpy stable argsort, special cases
 """
 from __future__ import annotations
 
@@ -581,3 +585,17 @@ def sample(importance, expo, k: int, area=None):
     out = np.zeros(max(n, 1), dtype=np.uint8)
     lib().orc_sample(ctypes.c_int64(n), _p(imp), None if a is None else _p(a), _p(e), ctypes.c_int64(k), _p(out))
     return out[:n]
+
+
+def spatial_order(means):
+    """(codes[n] uint32, perm[n] int64): 30-bit Morton codes of the means
+    [3, n] on a 1024^3 grid over the bounding box of the finite means, in
+    float32, and the Gaussians in ascending code (ties: ascending index).  Not
+    a step of the method: the memory order the GPU library keeps Gaussians in."""
+    m = np.ascontiguousarray(means, dtype=np.float32)
+    assert m.ndim == 2 and m.shape[0] == 3
+    n = m.shape[1]
+    codes = np.zeros(max(n, 1), dtype=np.uint32)
+    perm = np.zeros(max(n, 1), dtype=np.int64)
+    lib().orc_spatial_order(ctypes.c_int64(n), _p(m), _p(codes), _p(perm))
+    return codes[:n], perm[:n]

@@ -1132,3 +1132,78 @@ int64_t orc_split(int64_t n, const double* means, const double* scales, const do
   }
   return count;
 }
+
+/* ------------------------------------------------------------------------ */
+/* spatial order of the Gaussians (not a step of the method: a memory layout */
+/* of the GPU library, checked here so that its permutation is exact)       */
+/* ------------------------------------------------------------------------ */
+/* Morton (Z-order) code on a 1024^3 grid over the bounding box of the finite
+ * means, taken in float32 (the precision the layout is defined in): per axis
+ * lo/hi = min/max over the Gaussians whose three coordinates are finite,
+ * s = 1024 / (hi - lo) (0 when hi = lo), cell = floor((x - lo) * s), or 1023
+ * when that product is not below 1023 or is not a number.  Reading the code
+ * from its top: ten levels of octant digits, each the (x, y, z) bits of the
+ * cells at that level, x most significant.  A Gaussian with a non-finite
+ * coordinate gets 2^30 - 1.  perm = the Gaussians in ascending code, equal
+ * codes in ascending index. */
+static int finite_f(float v) { return isfinite(v) != 0; }
+
+typedef struct {
+  uint32_t code;
+  int64_t idx;
+} codeidx_t;
+
+static int cmp_codeidx(const void* a, const void* b) {
+  const codeidx_t* x = (const codeidx_t*)a;
+  const codeidx_t* y = (const codeidx_t*)b;
+  if (x->code != y->code) return x->code < y->code ? -1 : 1;
+  return x->idx < y->idx ? -1 : (x->idx > y->idx ? 1 : 0);
+}
+
+static uint32_t morton_cell_f(float x, float lo, float s) {
+  volatile float d = x - lo;
+  volatile float t = d * s;
+  if (t < 1023.0f) return (uint32_t)floorf(t);
+  return 1023u;
+}
+
+void orc_spatial_order(int64_t n, const float* means, uint32_t* codes, int64_t* perm) {
+  float lo[3] = {0.0f, 0.0f, 0.0f}, hi[3] = {0.0f, 0.0f, 0.0f};
+  int any = 0;
+  for (int64_t i = 0; i < n; i++) {
+    const float p[3] = {means[i], means[n + i], means[2 * n + i]};
+    if (!(finite_f(p[0]) && finite_f(p[1]) && finite_f(p[2]))) continue;
+    for (int a = 0; a < 3; a++) {
+      if (!any || p[a] < lo[a]) lo[a] = p[a];
+      if (!any || p[a] > hi[a]) hi[a] = p[a];
+    }
+    any = 1;
+  }
+  float s[3];
+  for (int a = 0; a < 3; a++) {
+    volatile float ext = hi[a] - lo[a];
+    volatile float q = ext > 0.0f ? 1024.0f / ext : 0.0f;
+    s[a] = q;
+  }
+  codeidx_t* c = (codeidx_t*)malloc(sizeof(codeidx_t) * (n > 0 ? n : 1));
+  for (int64_t i = 0; i < n; i++) {
+    const float p[3] = {means[i], means[n + i], means[2 * n + i]};
+    uint32_t code = (1u << 30) - 1u;
+    if (finite_f(p[0]) && finite_f(p[1]) && finite_f(p[2])) {
+      uint32_t cell[3];
+      for (int a = 0; a < 3; a++) cell[a] = morton_cell_f(p[a], lo[a], s[a]);
+      code = 0;
+      for (int level = 9; level >= 0; level--) {
+        const uint32_t digit = (((cell[0] >> level) & 1u) << 2) | (((cell[1] >> level) & 1u) << 1) |
+                               ((cell[2] >> level) & 1u);
+        code = (code << 3) | digit;
+      }
+    }
+    codes[i] = code;
+    c[i].code = code;
+    c[i].idx = i;
+  }
+  qsort(c, (size_t)n, sizeof(codeidx_t), cmp_codeidx);
+  for (int64_t i = 0; i < n; i++) perm[i] = c[i].idx;
+  free(c);
+}

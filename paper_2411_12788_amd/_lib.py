@@ -95,6 +95,9 @@ _SIGS = {
     "gs_sort_set_spin_limit": (None, [c_u32]),
     "gs_sort_set_algorithm": (c_i32, [c_i32]),
     "gs_sort_pairs_static": (c_i32, [c_p, c_p, c_i64, c_i32, c_p, c_p]),
+    "gs_spatial_order_workspace_size": (c_sz, [c_i64]),
+    "gs_spatial_order": (c_i32, [c_p, c_i64, c_p, c_p, c_p, c_sz, c_p]),
+    "gs_permute": (c_i32, [c_p, c_p, c_i64, c_i64, c_i32, c_p, c_p]),
     "gs_render_forward": (c_i32, [P(Scene), P(Projected), c_p, c_p, c_p, P(Camera), c_i32, P(Opts), P(FwdOut),
                                   P(Accum), c_p]),
     "gs_accumulate_importance": (c_i32, [P(Projected), c_p, c_p, c_p, P(Camera), c_i32, c_i64, P(Opts), P(Accum),

@@ -10,6 +10,8 @@
 // positive depths is the float order.
 #include "common.hpp"
 
+#include <immintrin.h>
+
 namespace msplat {
 
 constexpr int kScanItems = 16;
@@ -51,6 +53,7 @@ struct CountWs {
   uint32_t* block_zmax;  // [nb]
   uint32_t* block_vis;   // [nb]
   uint64_t* stats;       // [4]: n_isect, n_visible, zmin, zmax
+  uint64_t* host_stats;  // [4] in host-mapped pinned memory: the same, for the read-back (or NULL)
 };
 
 // Block = 4096 records; wave w owns the 1024 records from 1024 w, read 64 at
@@ -152,6 +155,12 @@ __global__ __launch_bounds__(kBlock) void k_count_top(int64_t nb, CountWs ws) {
     ws.stats[1] = c;
     ws.stats[2] = a;
     ws.stats[3] = b;
+    if (ws.host_stats) {
+      ws.host_stats[0] = carry;
+      ws.host_stats[1] = c;
+      ws.host_stats[2] = a;
+      ws.host_stats[3] = b;
+    }
   }
 }
 
@@ -365,6 +374,7 @@ static CountWs carve_count(void* ws, int64_t nrec) {
   c.block_zmax = (uint32_t*)p; p += align256(nb * 4);
   c.block_vis = (uint32_t*)p; p += align256(nb * 4);
   c.stats = (uint64_t*)p;
+  c.host_stats = nullptr;
   return c;
 }
 
@@ -438,6 +448,43 @@ using namespace msplat;
 
 extern "C" {
 
+// The pair count's read-back.  k_count_top also writes the four totals into
+// a small host-mapped pinned buffer (one per host thread and device, made on
+// first use and kept until the process ends), and the host polls an event
+// recorded after the count instead of waiting in the runtime: a copy to
+// pageable memory goes through a staging kernel with a wait of its own, and
+// the runtime's wait turns into an interrupt-driven sleep after a short spin;
+// both added tens of microseconds to a read-back that sits on the step's
+// critical path.
+struct CountReadback {
+  hipEvent_t ev = nullptr;
+  uint64_t* host = nullptr;  // [4], host-mapped
+  uint64_t* dev = nullptr;   // the same memory, as the device sees it
+};
+
+static int32_t count_readback(CountReadback** out) {
+  constexpr int kMaxDevices = 64;
+  static thread_local CountReadback rb[kMaxDevices];
+  int dev = 0;
+  int32_t st = check_hip(hipGetDevice(&dev), "bin_count device");
+  if (st != GS_OK) return st;
+  if (dev < 0 || dev >= kMaxDevices) { set_error("device index out of range"); return GS_ERR_UNSUPPORTED; }
+  CountReadback& r = rb[dev];
+  if (!r.ev) {
+    void* h = nullptr;
+    void* d = nullptr;
+    if ((st = check_hip(hipHostMalloc(&h, 64, hipHostMallocDefault), "bin_count read-back buffer")) != GS_OK) return st;
+    if ((st = check_hip(hipHostGetDevicePointer(&d, h, 0), "bin_count read-back buffer")) != GS_OK) return st;
+    hipEvent_t e = nullptr;
+    if ((st = check_hip(hipEventCreateWithFlags(&e, hipEventDisableTiming), "bin_count event")) != GS_OK) return st;
+    r.host = static_cast<uint64_t*>(h);
+    r.dev = static_cast<uint64_t*>(d);
+    r.ev = e;
+  }
+  *out = &r;
+  return GS_OK;
+}
+
 size_t gs_bin_count_workspace_size(int64_t n_records) { return count_ws_size(n_records); }
 
 int32_t gs_bin_count(const gs_projected_t* proj, const gs_camera_t* cams, int32_t V, int64_t n, uint32_t* offsets,
@@ -456,18 +503,34 @@ int32_t gs_bin_count(const gs_projected_t* proj, const gs_camera_t* cams, int32_
   if (!proj->bin || !offsets || !ws) { set_error("buffer NULL"); return GS_ERR_NULL; }
   if (ws_bytes < count_ws_size(nrec)) { set_error("count workspace too small"); return GS_ERR_CAPACITY; }
   hipStream_t s = (hipStream_t)stream;
+  CountReadback* rb = nullptr;
+  if ((st = count_readback(&rb)) != GS_OK) return st;
   CountWs c = carve_count(ws, nrec);
+  c.host_stats = rb->dev;
+  // a value no count can produce: if it were still there after the wait, the
+  // totals come from the device copy instead
+  constexpr uint64_t kUnset = ~0ull;
+  __atomic_store_n(rb->host, kUnset, __ATOMIC_RELEASE);
   const int64_t nb = count_blocks(nrec);
   const int4* bin = reinterpret_cast<const int4*>(proj->bin);
   hipLaunchKernelGGL(k_count_reduce, dim3((unsigned)nb), dim3(kBlock), 0, s, bin, nrec, c);
   hipLaunchKernelGGL(k_count_top, dim3(1), dim3(kBlock), 0, s, nb, c);
   hipLaunchKernelGGL(k_count_down, dim3((unsigned)nb), dim3(kBlock), 0, s, bin, nrec, c, offsets);
   MS_CHECK_LAUNCH("bin_count");
+  if ((st = check_hip(hipEventRecord(rb->ev, s), "bin_count event")) != GS_OK) return st;
+  for (;;) {
+    const hipError_t e = hipEventQuery(rb->ev);
+    if (e == hipSuccess) break;
+    if (e != hipErrorNotReady) return check_hip(e, "bin_count wait");
+    _mm_pause();
+  }
   uint64_t h[4];
-  st = check_hip(hipMemcpyAsync(h, c.stats, sizeof(h), hipMemcpyDeviceToHost, s), "bin_count copy");
-  if (st != GS_OK) return st;
-  st = check_hip(hipStreamSynchronize(s), "bin_count sync");
-  if (st != GS_OK) return st;
+  for (int k = 0; k < 4; ++k) h[k] = __atomic_load_n(rb->host + k, __ATOMIC_ACQUIRE);
+  if (h[0] == kUnset) {
+    st = check_hip(hipMemcpyAsync(h, c.stats, sizeof(h), hipMemcpyDeviceToHost, s), "bin_count copy");
+    if (st != GS_OK) return st;
+    if ((st = check_hip(hipStreamSynchronize(s), "bin_count sync")) != GS_OK) return st;
+  }
   stats->n_isect = (int64_t)h[0];
   stats->n_visible = (int64_t)h[1];
   stats->zbits_min = (uint32_t)h[2];

@@ -8,7 +8,7 @@ from typing import Optional, Tuple
 import torch
 
 from . import _lib as L
-from .raster import DeviceScene, Projected, _ptr, _stream, cameras
+from .raster import DeviceScene, Projected, _ptr, _stream, cameras, permute
 
 KEEP_QUANTILE = 0.99   # Sec. 5.1 and Sec. 5.2
 THETA_BLUR = 2e-4      # Eq. (3)
@@ -78,6 +78,17 @@ def clone(scene: DeviceScene, select: torch.Tensor, capacity: Optional[int] = No
     L.check(L.lib().gs_clone(ctypes.byref(scene.c()), _ptr(select), ctypes.byref(so), _ptr(count), _ptr(ws),
                              ws.numel(), _stream(stream)), "gs_clone")
     return out, count
+
+
+def reorder(scene: DeviceScene, *rows: torch.Tensor, stream=None):
+    """(scene, [rows], perm): the scene and any per-Gaussian arrays (contiguous,
+    last dimension n: optimizer moments, accumulated statistics, masks) moved
+    into the library's spatial order, Gaussian i of the results being
+    Gaussian perm[i] of the inputs.  For use after the set of Gaussians
+    changes (clone, split, pruning), when appended rows have broken the
+    order; a memory layout only, every result is the same up to perm."""
+    out, perm = scene.in_spatial_order(stream)
+    return out, [permute(t, perm, stream) for t in rows], perm
 
 
 SPLIT_FACTOR = 1.6  # 3DGS: children take the parent's scales divided by 1.6

@@ -7,7 +7,7 @@ from __future__ import annotations
 
 import ctypes
 import dataclasses
-from typing import Dict, List, Optional, Sequence
+from typing import Dict, List, Optional, Sequence, Tuple
 
 import numpy as np
 import torch
@@ -80,6 +80,19 @@ class DeviceScene:
 
     def nbytes(self) -> int:
         return sum(a.numel() * 4 for a in (self.means, self.scales, self.quats, self.opacity, self.sh))
+
+    def in_spatial_order(self, stream=None) -> Tuple["DeviceScene", torch.Tensor]:
+        """(the scene along the Morton curve of its means, the permutation):
+        the layout the compositing kernels read fastest (see spatial_order)."""
+        perm = spatial_order(self.means, stream)
+        return self.permuted(perm, stream), perm
+
+    def permuted(self, perm: torch.Tensor, stream=None) -> "DeviceScene":
+        """The same Gaussians in the order `perm` gives (Gaussian i of the
+        result is Gaussian perm[i] of this scene)."""
+        return DeviceScene(permute(self.means, perm, stream), permute(self.scales, perm, stream),
+                           permute(self.quats, perm, stream), permute(self.opacity, perm, stream),
+                           permute(self.sh, perm, stream), self.sh_degree)
 
 
 def cameras(cams) -> "ctypes.Array[L.Camera]":
@@ -316,6 +329,35 @@ def sort_pairs(keys: torch.Tensor, vals: torch.Tensor, key_bits: int, stream=Non
             "gs_sort_pairs")
     if check and n > 0:
         sort_status(ws, stream)
+
+
+def spatial_order(means: torch.Tensor, stream=None, codes: bool = False):
+    """Permutation [n] (int32 holding the library's u32) that stores the
+    Gaussians along the Morton curve of their means [3, n]; with `codes` also
+    the 30-bit code of each Gaussian.  A memory layout, not a step of the
+    method: every result is the same up to the permutation."""
+    assert means.dim() == 2 and means.shape[0] == 3 and means.is_contiguous() and means.dtype == torch.float32
+    n = int(means.shape[1])
+    perm = torch.empty(n, device=means.device, dtype=torch.int32)
+    c = torch.empty(n, device=means.device, dtype=torch.int32) if codes else None
+    ws = torch.empty(max(L.lib().gs_spatial_order_workspace_size(n), 1), device=means.device, dtype=torch.uint8)
+    L.check(L.lib().gs_spatial_order(_ptr(means), n, _ptr(perm), _ptr(c), _ptr(ws), ws.numel(), _stream(stream)),
+            "gs_spatial_order")
+    return (perm, c) if codes else perm
+
+
+def permute(t: torch.Tensor, perm: torch.Tensor, stream=None) -> torch.Tensor:
+    """New tensor r with r[..., i] = t[..., perm[i]]: the planes of a
+    contiguous per-Gaussian array (last dimension n) moved into the order perm
+    gives; entries of perm outside [0, n) give zeros."""
+    assert t.is_contiguous() and perm.is_contiguous() and perm.dtype == torch.int32
+    n = int(t.shape[-1]) if t.dim() > 0 else 0
+    assert perm.numel() == n
+    out = torch.empty_like(t)
+    planes = t.numel() // n if n > 0 else 0
+    L.check(L.lib().gs_permute(_ptr(t), _ptr(out), planes, n, t.element_size(), _ptr(perm), _stream(stream)),
+            "gs_permute")
+    return out
 
 
 @dataclasses.dataclass
