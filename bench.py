@@ -615,17 +615,23 @@ def profile_counters():
 
 
 def profile_run(steps: int):
+    """The profiled program: set-up (scene upload and its spatial order), then
+    three 1 GiB device copies (the counters' calibration, and the marker after
+    which every dispatch belongs to the steps), then `steps` steps."""
     wl = workload("large")
     step = Step(wl)
-    for _ in range(steps):
-        step.run(record=False)
     torch.cuda.synchronize()
     a = torch.empty(1 << 28, device="cuda")
     b = torch.empty_like(a)
     for _ in range(3):
         b.copy_(a)  # 1 GiB read + 1 GiB written: calibration for the HBM counters
     torch.cuda.synchronize()
-    print(json.dumps({"profile_steps": steps, "copy_bytes_each_way": a.numel() * 4, "source_sha256": source_hash()}),
+    copy_bytes = a.numel() * a.element_size()
+    del a, b
+    for _ in range(steps):
+        step.run(record=False)
+    torch.cuda.synchronize()
+    print(json.dumps({"profile_steps": steps, "copy_bytes_each_way": copy_bytes, "source_sha256": source_hash()}),
           flush=True)
 
 
@@ -670,18 +676,40 @@ def summarize(d: str) -> None:
     # output), else the current ones
     sha_file = os.path.join(d, "source_sha256.txt")
     sha = open(sha_file).read().strip() if os.path.exists(sha_file) else source_hash()
-    stats = list(csv.DictReader(open(os.path.join(d, "kt", "kt_kernel_stats.csv"))))
+
+    def of_steps(rows, name_key):
+        # the calibration copies (1 GiB each, the only copies of 100 us or
+        # more) and every dispatch after the last of them (the steps); the
+        # set-up before them (upload, spatial order) is left out
+        rows = list(rows)
+
+        def calib(r):
+            return (_short(r[name_key]) == COPY_KERNEL and
+                    int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) >= 100_000)
+        marks = [int(r["Dispatch_Id"]) for r in rows if calib(r)]
+        last = max(marks) if marks else -1
+        return [r for r in rows if int(r["Dispatch_Id"]) > last or calib(r)]
+
+    trace = of_steps(csv.DictReader(open(os.path.join(d, "kt", "kt_kernel_trace.csv"))), "Kernel_Name")
+    durs = {}
+    for r in trace:
+        durs.setdefault(_short(r["Kernel_Name"]), []).append(
+            (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    total = sum(sum(v) for v in durs.values()) or 1.0
     lines = ["# Kernel times: 3M Gaussians, one 1920x1080 view, fwd+bwd step", "",
              "Command (from the repository root): `" + PROFILE_CMDS["kt"].format(d=dd) + "`", "",
+             "From the kernel trace: the three calibration copies and every dispatch after them "
+             "(the steps); the set-up before them (scene upload and spatial order) is left out.", "",
              f"source_sha256: {sha}", "",
              "| kernel | calls | avg us | min us | max us | share % |", "|---|---|---|---|---|---|"]
-    for r in stats:
-        lines.append(f"| {_short(r['Name'])} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
-                     f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.2f} |")
+    for k in sorted(durs, key=lambda x: -sum(durs[x])):
+        v = durs[k]
+        lines.append(f"| {k} | {len(v)} | {sum(v) / len(v):.1f} | {min(v):.1f} | {max(v):.1f} | "
+                     f"{100.0 * sum(v) / total:.2f} |")
     os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
     open(os.path.join(ROOT, "profiles", "kernels_surfaces_3M_1920x1080.md"), "w").write("\n".join(lines) + "\n")
-    avg_us = {_short(r["Name"]): float(r["AverageNs"]) / 1e3 for r in stats}
-    calls = {_short(r["Name"]): int(r["Calls"]) for r in stats}
+    avg_us = {k: sum(v) / len(v) for k, v in durs.items()}
+    calls = {k: len(v) for k, v in durs.items()}
 
     per = {}  # kernel -> counter -> [values per dispatch]
     done = []
@@ -690,7 +718,7 @@ def summarize(d: str) -> None:
         if kind == "kt" or not os.path.exists(path):
             continue
         done.append(kind)
-        for r in csv.DictReader(open(path)):
+        for r in of_steps(csv.DictReader(open(path)), "Kernel_Name"):
             per.setdefault(_short(r["Kernel_Name"]), {}).setdefault(r["Counter_Name"], []).append(
                 float(r["Counter_Value"]))
     mean = {k: {c: sum(v) / len(v) for c, v in cs.items()} for k, cs in per.items()}
