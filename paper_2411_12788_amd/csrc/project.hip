@@ -153,28 +153,11 @@ __global__ __launch_bounds__(kBlock) void k_project(ProjArgs pa, ViewSet vs) {
   const double o = pa.sc.opacity[i];
   bool ok = g.ok && o >= (double)op.alpha_min;
   if (pa.cull && pa.cull[i] == 0) ok = false;
-  // colour from SH along the viewing direction
-  double cc[3];
-  camera_centre(cam, cc);
-  double dx = pa.sc.means[i] - cc[0], dy = pa.sc.means[n + i] - cc[1], dz = pa.sc.means[2 * n + i] - cc[2];
-  const double il = 1.0 / sqrt(dx * dx + dy * dy + dz * dz);
-  dx *= il; dy *= il; dz *= il;
-  double rgb[3] = {0.5, 0.5, 0.5};
-  const float* shp = pa.sc.sh;
-  sh_terms<DEG>(dx, dy, dz, [&](int k, double Yk, double, double, double) {
-#pragma unroll
-    for (int ch = 0; ch < 3; ++ch) rgb[ch] += (double)shp[(int64_t)(k * 3 + ch) * n + i] * Yk;
-  });
-  // a colour that is not finite before the clamp (NaN or infinite SH terms)
-  // makes the record invalid; the clamp must not turn NaN into black
-  const bool rgb_finite = isfinite(rgb[0]) && isfinite(rgb[1]) && isfinite(rgb[2]);
-#pragma unroll
-  for (int ch = 0; ch < 3; ++ch) rgb[ch] = rgb[ch] > 0.0 ? rgb[ch] : 0.0;
   // extent of the ellipse where opacity * G2D >= alpha_min
   const double kk = 2.0 * log(o / (double)op.alpha_min);
   const double ex = sqrt(kk * g.S00), ey = sqrt(kk * g.S11);
   ok = ok && isfinite(g.u) && isfinite(g.v) && isfinite(ex) && isfinite(ey) && isfinite(g.a) && isfinite(g.b) &&
-       isfinite(g.c) && rgb_finite && isfinite(g.t[2]);
+       isfinite(g.c) && isfinite(g.t[2]);
   int32_t xlo = 1, xhi = 0, ylo = 1, yhi = 0, tiles = 0;
   if (ok) {
     const double W1 = cam.width - 1, H1 = cam.height - 1;
@@ -186,6 +169,32 @@ __global__ __launch_bounds__(kBlock) void k_project(ProjArgs pa, ViewSet vs) {
     } else {
       ok = false;
     }
+  }
+  // Colour from SH along the viewing direction, evaluated only for a record
+  // that is drawn: the SH planes are 48 of the 59 floats a Gaussian holds, and
+  // lanes that skip them issue no loads, so lines of Gaussians that no view
+  // draws (off-screen or behind the camera, which the spatial order keeps
+  // together) are not read at all.
+  double rgb[3] = {0.5, 0.5, 0.5};
+  if (ok) {
+    double cc[3];
+    camera_centre(cam, cc);
+    double dx = pa.sc.means[i] - cc[0], dy = pa.sc.means[n + i] - cc[1], dz = pa.sc.means[2 * n + i] - cc[2];
+    const double il = 1.0 / sqrt(dx * dx + dy * dy + dz * dz);
+    dx *= il; dy *= il; dz *= il;
+    const float* shp = pa.sc.sh;
+    sh_terms<DEG>(dx, dy, dz, [&](int k, double Yk, double, double, double) {
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) rgb[ch] += (double)shp[(int64_t)(k * 3 + ch) * n + i] * Yk;
+    });
+    // a colour that is not finite before the clamp (NaN or infinite SH terms)
+    // makes the record invalid; the clamp must not turn NaN into black
+    if (!(isfinite(rgb[0]) && isfinite(rgb[1]) && isfinite(rgb[2]))) {
+      ok = false;
+      xlo = 1; xhi = 0; ylo = 1; yhi = 0; tiles = 0;
+    }
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) rgb[ch] = rgb[ch] > 0.0 ? rgb[ch] : 0.0;
   }
   const float zf = (float)g.t[2];
   float4* out = reinterpret_cast<float4*>(pa.rec + r * kRecFloats);
