@@ -147,3 +147,25 @@ def test_results_follow_the_permutation(gpu_lib, which):
     torch.testing.assert_close(a1["importance"][pl], a2["importance"], rtol=1e-6, atol=1e-7)
     for k in g1:
         assert torch.equal(g1[k][..., pl], g2[k]), k
+
+
+def test_densify_reorder_moves_rows_with_the_scene(gpu_lib):
+    """densify.reorder: the scene and per-Gaussian arrays of any shape and
+    element size move by the same permutation, the spatial order of the means."""
+    R = raster()
+    from paper_2411_12788_amd import densify as D
+    sc = gs_inputs.surface_scene(50_000, 45)
+    ds = R.DeviceScene.from_numpy(sc)
+    n = ds.n
+    g = torch.Generator(device="cuda").manual_seed(46)
+    adam = torch.randn((2, 59, n), device="cuda", generator=g)      # optimizer moments, planar
+    count = torch.randint(0, 100, (n,), device="cuda", dtype=torch.int32, generator=g)
+    flags = torch.randint(0, 2, (n,), device="cuda", dtype=torch.uint8, generator=g)
+    out, (a2, c2, f2), perm = D.reorder(ds, adam, count, flags)
+    torch.cuda.synchronize()
+    assert torch.equal(perm, R.spatial_order(ds.means))
+    p = perm.long()
+    assert torch.equal(out.means, ds.means[:, p]) and torch.equal(out.scales, ds.scales[:, p])
+    assert torch.equal(out.quats, ds.quats[:, p]) and torch.equal(out.opacity, ds.opacity[p])
+    assert torch.equal(out.sh, ds.sh[..., p]) and out.sh_degree == ds.sh_degree
+    assert torch.equal(a2, adam[..., p]) and torch.equal(c2, count[p]) and torch.equal(f2, flags[p])
