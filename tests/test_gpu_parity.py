@@ -265,7 +265,8 @@ def test_argument_errors(gpu_lib):
 
 def test_l1_loss_grad_matches_definition(gpu_lib):
     R = H.raster()
-    for count in (1, 7, 4099, 3 * 128 * 96 + 2):
+    # up to a 1080p frame and beyond one pass of the capped grid (4096 x 256 x 4 float4)
+    for count in (1, 7, 4099, 3 * 128 * 96 + 2, 3 * 1920 * 1080, 4 * 4096 * 256 * 4 + 4 * 999 + 3):
         g = gs_inputs.rng(count)
         c = torch.from_numpy(g.uniform(size=count).astype(np.float32)).cuda()
         t = torch.from_numpy(g.uniform(size=count).astype(np.float32)).cuda()
