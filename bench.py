@@ -45,9 +45,9 @@ RENDER_FWD_BYTES_PER_PAIR = 4 + 8 + 48          # list index, pixel box, the 48 
 RENDER_FWD_BYTES_PER_PIXEL = 12 + 4 + 4 + 4 + 4 + 4 + 1  # colour, depth, imax, T, last, count, hit
 RENDER_BWD_BYTES_PER_PAIR = 4 + 8 + 64 + 1      # list index, box, full record, active flag
 RENDER_BWD_BYTES_PER_PIXEL = 12 + 4 + 4         # dL/dC, T, last
-BIN_PARTS = {"count": ["k_count_reduce", "k_count_top", "k_count_down"],
+BIN_PARTS = {"count": ["k_count_reduce", "k_count_down"],
              "sort": ["k_emit", "k_rt_up", "k_rt_scan", "k_os_hist", "k_os_scan", "k_os_pass", "k_ranges",
-                      "k_order_hist", "k_order_scan", "k_order_scatter"]}
+                      "k_tile_order", "k_order_hist", "k_order_scan", "k_order_scatter"]}
 STAGE_KERNELS = {"project": ["k_project"], "bin": BIN_PARTS["count"] + BIN_PARTS["sort"],
                  "render_fwd": ["k_render_fwd"], "loss": ["k_l1_loss_grad"], "render_bwd": ["k_render_bwd"],
                  "project_bwd": ["k_project_bwd1", "k_project_bwd"]}
@@ -109,10 +109,20 @@ class Step:
             if self.active is not None:
                 self.active = R.permute(self.active, self.perm)
         self.dldc = torch.empty((3, P), device="cuda")
-        self.loss = torch.zeros(1, device="cuda")
-        self.acc = R.alloc_accum(self.n)
+        # what the step clears (accumulators, loss, the per-record 2D gradient
+        # the backward adds into) lives in one arena: one fill clears it
+        n, V = self.n, len(self.cams)
+        pieces = {"importance": n, "wmax": n, "area": n, "loss": 1, "grad2d": 9 * n * V}
+        at, offs = 0, {}
+        for k, c in pieces.items():
+            offs[k] = at
+            at += (c + 63) // 64 * 64  # 256-byte aligned pieces
+        self.arena = torch.zeros(at, device="cuda")
+        cut = {k: self.arena[offs[k]: offs[k] + c] for k, c in pieces.items()}
+        self.acc = dict(importance=cut["importance"], wmax=cut["wmax"], area=cut["area"].view(torch.int32))
+        self.loss = cut["loss"]
+        self.grad2d = cut["grad2d"].view(n * V, 9)
         self.grads = R.alloc_grads(self.n)
-        self.grad2d = torch.empty((self.n * len(self.cams), 9), device="cuda")
         self.names = ["project", "bin", "render_fwd", "loss", "render_bwd", "project_bwd"]
         self.pending = []  # recorded steps whose events are read after the timed region
         self.prepared = []  # event sets made ahead of the timed region
@@ -137,15 +147,12 @@ class Step:
             if record:
                 ev[k][i].record()
 
-        # Clears the step needs (accumulators, loss, the per-record 2D
-        # gradient the backward adds into), queued first: the device is still
-        # busy with the previous step's backward, so they cost no idle time.
-        # Queued after the pair count instead, each would be a gap: the host
-        # launches them one by one while nothing else is queued.
-        for t in self.acc.values():
-            t.zero_()
-        self.loss.zero_()
-        self.grad2d.zero_()
+        # The clears the step needs (accumulators, loss, the per-record 2D
+        # gradient the backward adds into), one fill over their arena, queued
+        # first: the device is still busy with the previous step's backward,
+        # so the launch costs no idle time.  Queued after the pair count
+        # instead, it would be a gap: nothing else is queued then.
+        R.fill_u32(self.arena, 0)
         mark("project", 0)
         proj = R.project(self.scene, self.cams, self.opts, buffers=self.buffers)
         mark("project", 1)

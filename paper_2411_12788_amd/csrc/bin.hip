@@ -68,18 +68,22 @@ __global__ __launch_bounds__(kBlock) void k_count_reduce(const int4* __restrict_
   __shared__ uint32_t lz[2 * kWaves + kWaves];
   uint64_t sum = 0;
   uint32_t zmin = 0xffffffffu, zmax = 0u, vis = 0;
-#pragma unroll 4
+  // the block's 16 loads per thread all in flight before the first is used
+  int2 zw[kScanItems];
+#pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
     const int64_t r = count_record(k);
-    if (r < nrec) {
-      int4 b = bin[r];
-      if (b.w > 0) {
-        sum += (uint32_t)b.w;
-        uint32_t z = (uint32_t)b.z;
-        zmin = z < zmin ? z : zmin;
-        zmax = z > zmax ? z : zmax;
-        vis++;
-      }
+    const int4 b = r < nrec ? bin[r] : make_int4(0, 0, 0, 0);
+    zw[k] = make_int2(b.z, b.w);
+  }
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    if (zw[k].y > 0) {
+      sum += (uint32_t)zw[k].y;
+      const uint32_t z = (uint32_t)zw[k].x;
+      zmin = z < zmin ? z : zmin;
+      zmax = z > zmax ? z : zmax;
+      vis++;
     }
   }
   uint64_t tot;
@@ -109,64 +113,28 @@ __global__ __launch_bounds__(kBlock) void k_count_reduce(const int4* __restrict_
   }
 }
 
-// one block: exclusive scan of block sums in place, and the global statistics
-__global__ __launch_bounds__(kBlock) void k_count_top(int64_t nb, CountWs ws) {
-  __shared__ uint64_t lds[kWaves + 1];
-  __shared__ uint32_t lz[3 * kWaves];
-  uint64_t carry = 0;
-  uint32_t zmin = 0xffffffffu, zmax = 0u;
-  uint64_t vis = 0;
-  for (int64_t c0 = 0; c0 < nb; c0 += kBlock) {
-    const int64_t k = c0 + threadIdx.x;
-    uint64_t x = k < nb ? ws.block_sum[k] : 0;
-    if (k < nb) {
-      uint32_t a = ws.block_zmin[k], b = ws.block_zmax[k];
-      zmin = a < zmin ? a : zmin;
-      zmax = b > zmax ? b : zmax;
-      vis += ws.block_vis[k];
-    }
-    uint64_t tot;
-    uint64_t ex = block_exclusive_scan<uint64_t>(x, lds, &tot);
-    if (k < nb) ws.block_sum[k] = carry + ex;
-    carry += tot;
-  }
+// Sum over the block of one value per thread (every thread gets it).
+template <typename T>
+__device__ __forceinline__ T block_total(T x, T* lds /*kWaves*/) {
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    uint32_t a = __shfl_xor(zmin, o, kWave), b = __shfl_xor(zmax, o, kWave);
-    uint64_t c = __shfl_xor(vis, o, kWave);
-    zmin = a < zmin ? a : zmin;
-    zmax = b > zmax ? b : zmax;
-    vis += c;
-  }
-  __shared__ uint64_t lv[kWaves];
-  const int w = threadIdx.x / kWave;
-  if ((threadIdx.x & (kWave - 1)) == 0) { lz[w] = zmin; lz[kWaves + w] = zmax; lv[w] = vis; }
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, kWave);
+  if ((threadIdx.x & (kWave - 1)) == 0) lds[threadIdx.x / kWave] = x;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t a = lz[0], b = lz[kWaves];
-    uint64_t c = 0;
-    for (int k = 0; k < kWaves; ++k) {
-      a = lz[k] < a ? lz[k] : a;
-      b = lz[kWaves + k] > b ? lz[kWaves + k] : b;
-      c += lv[k];
-    }
-    if (c == 0) { a = 0; b = 0; }
-    ws.stats[0] = carry;
-    ws.stats[1] = c;
-    ws.stats[2] = a;
-    ws.stats[3] = b;
-    if (ws.host_stats) {
-      ws.host_stats[0] = carry;
-      ws.host_stats[1] = c;
-      ws.host_stats[2] = a;
-      ws.host_stats[3] = b;
-    }
-  }
+  T s = 0;
+#pragma unroll
+  for (int k = 0; k < kWaves; ++k) s += lds[k];
+  __syncthreads();
+  return s;
 }
 
+// Offsets of one block of records.  The block's start is the sum of the
+// totals of the blocks before it, which each block adds itself (at most a few
+// thousand values, read from L2), so no separate scan of the totals runs.  The
+// last block also reduces the statistics of all blocks and publishes them.
 __global__ __launch_bounds__(kBlock) void k_count_down(const int4* __restrict__ bin, int64_t nrec, CountWs ws,
                                                        uint32_t* __restrict__ offsets) {
   __shared__ uint64_t lds[kWaves + 1];
+  __shared__ uint64_t lsum[kWaves];
   const int lane = threadIdx.x & (kWave - 1);
   uint32_t t[kScanItems];
   uint64_t sum = 0;
@@ -177,6 +145,9 @@ __global__ __launch_bounds__(kBlock) void k_count_down(const int4* __restrict__ 
     t[k] = w > 0 ? (uint32_t)w : 0u;
     sum += t[k];
   }
+  uint64_t before = 0;
+  for (int64_t k = threadIdx.x; k < (int64_t)blockIdx.x; k += kBlock) before += ws.block_sum[k];
+  before = block_total<uint64_t>(before, lsum);
   // the wave's records precede those of later waves: exclusive scan of the
   // lane sums over the block gives each wave's start (lanes' sums are added in
   // wave order, and within a wave k-major below)
@@ -184,9 +155,47 @@ __global__ __launch_bounds__(kBlock) void k_count_down(const int4* __restrict__ 
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) wsum += __shfl_xor(wsum, o, kWave);
   uint64_t tot;
-  uint64_t run = ws.block_sum[blockIdx.x] +
-                 block_exclusive_scan<uint64_t>(lane == 0 ? wsum : 0ull, lds, &tot);
+  uint64_t run = before + block_exclusive_scan<uint64_t>(lane == 0 ? wsum : 0ull, lds, &tot);
   run = __shfl(run, 0, kWave);
+  if (blockIdx.x == gridDim.x - 1) {
+    // every block's statistics, written by the reduce kernel before this one
+    uint32_t zmin = 0xffffffffu, zmax = 0u;
+    uint64_t vis = 0;
+    for (int64_t k = threadIdx.x; k < (int64_t)gridDim.x; k += kBlock) {
+      const uint32_t a = ws.block_zmin[k], b = ws.block_zmax[k];
+      zmin = a < zmin ? a : zmin;
+      zmax = b > zmax ? b : zmax;
+      vis += ws.block_vis[k];
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const uint32_t a = __shfl_xor(zmin, o, kWave), b = __shfl_xor(zmax, o, kWave);
+      zmin = a < zmin ? a : zmin;
+      zmax = b > zmax ? b : zmax;
+    }
+    __shared__ uint32_t lz[2 * kWaves];
+    if (lane == 0) { lz[threadIdx.x / kWave] = zmin; lz[kWaves + threadIdx.x / kWave] = zmax; }
+    vis = block_total<uint64_t>(vis, lsum);  // its barriers also order the lz stores
+    if (threadIdx.x == 0) {
+      uint32_t a = lz[0], b = lz[kWaves];
+      for (int k = 1; k < kWaves; ++k) {
+        a = lz[k] < a ? lz[k] : a;
+        b = lz[kWaves + k] > b ? lz[kWaves + k] : b;
+      }
+      if (vis == 0) { a = 0; b = 0; }
+      const uint64_t total = before + tot;
+      ws.stats[0] = total;
+      ws.stats[1] = vis;
+      ws.stats[2] = a;
+      ws.stats[3] = b;
+      if (ws.host_stats) {
+        ws.host_stats[0] = total;
+        ws.host_stats[1] = vis;
+        ws.host_stats[2] = a;
+        ws.host_stats[3] = b;
+      }
+    }
+  }
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
     uint32_t inc = t[k];
@@ -211,8 +220,10 @@ __global__ __launch_bounds__(kBlock) void k_emit(const int4* __restrict__ bin, c
                                                  float tile_cull, const uint32_t* __restrict__ offsets,
                                                  int64_t n, int64_t nrec, int32_t shift, uint32_t zmin, int32_t ibits,
                                                  uint64_t* __restrict__ keys, uint32_t* __restrict__ vals,
-                                                 ViewSet vs) {
+                                                 ViewSet vs, uint32_t* __restrict__ clear, int64_t clear_words) {
   const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  // the tile ranges start empty ([0, 0)); k_ranges writes the listed tiles'
+  for (int64_t k = r; k < clear_words; k += (int64_t)gridDim.x * kBlock) clear[k] = 0u;
   if (r >= nrec) return;
   const int4 b = bin[r];
   if (b.w <= 0) return;
@@ -345,6 +356,76 @@ __global__ __launch_bounds__(kBlock) void k_order_scatter(const uint32_t* __rest
   if (pos < (uint32_t)tiles) order[pos] = (uint32_t)t;
 }
 
+// The same order from one workgroup, for up to kOrderLdsTiles tiles: each
+// tile's bucket is read once into LDS; wave w takes the w-th of sixteen
+// consecutive runs of tiles and counts its buckets (ballot match, one add per
+// bucket present in 64 tiles); the counts give every (wave, bucket) its first
+// position (tiles of earlier buckets, then the bucket's tiles in earlier
+// waves), and each wave places its run in ascending id from there.  One launch
+// and three barriers instead of four launches.
+constexpr int kOrderThreads = 1024;
+constexpr int kOrderLdsTiles = 32768;
+constexpr int kOrderWaves = kOrderThreads / kWave;
+
+__device__ __forceinline__ uint64_t same_bucket_lanes(uint32_t b) {
+  uint64_t m = ~0ull;  // 6 bits cover buckets 0..32 and 63 (no tile)
+#pragma unroll
+  for (int bit = 0; bit < 6; ++bit) {
+    const uint64_t bb = __ballot((b >> bit) & 1u);
+    m &= ((b >> bit) & 1u) ? bb : ~bb;
+  }
+  return m;
+}
+
+__global__ __launch_bounds__(kOrderThreads) void k_tile_order(const uint32_t* __restrict__ ranges, int32_t tiles,
+                                                              uint32_t* __restrict__ order) {
+  __shared__ uint8_t s_b[kOrderLdsTiles];
+  __shared__ uint32_t wc[kOrderWaves][kOrderBuckets];  // a wave's count of a bucket, then its next position
+  __shared__ uint32_t tot[kOrderBuckets];
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+  const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (kWave - lane));
+  for (int k = threadIdx.x; k < kOrderWaves * kOrderBuckets; k += kOrderThreads) (&wc[0][0])[k] = 0;
+#pragma unroll 4
+  for (int32_t t = threadIdx.x; t < tiles; t += kOrderThreads) s_b[t] = (uint8_t)order_bucket(ranges, t);
+  __syncthreads();
+  const int32_t per = (tiles + kOrderWaves - 1) / kOrderWaves;
+  const int32_t t_lo = w * per, t_hi = t_lo + per < tiles ? t_lo + per : tiles;
+  for (int32_t t0 = t_lo; t0 < t_hi; t0 += kWave) {
+    const int32_t t = t0 + lane;
+    const uint32_t b = t < t_hi ? s_b[t] : 63u;
+    const uint64_t m = same_bucket_lanes(b);
+    if (b != 63u && (m & lt) == 0ull) wc[w][b] += (uint32_t)__popcll(m);
+  }
+  __syncthreads();
+  if (threadIdx.x < kOrderBuckets) {
+    uint32_t c = 0;
+    for (int k = 0; k < kOrderWaves; ++k) c += wc[k][threadIdx.x];
+    tot[threadIdx.x] = c;
+  }
+  __syncthreads();
+  if (threadIdx.x < kOrderBuckets) {
+    uint32_t run = 0;
+    for (int k = 0; k < (int)threadIdx.x; ++k) run += tot[k];
+    for (int k = 0; k < kOrderWaves; ++k) {  // this thread's column only
+      const uint32_t c = wc[k][threadIdx.x];
+      wc[k][threadIdx.x] = run;
+      run += c;
+    }
+  }
+  __syncthreads();
+  for (int32_t t0 = t_lo; t0 < t_hi; t0 += kWave) {
+    const int32_t t = t0 + lane;
+    const uint32_t b = t < t_hi ? s_b[t] : 63u;
+    const uint64_t m = same_bucket_lanes(b);
+    if (b != 63u) {
+      const uint32_t pos = wc[w][b] + (uint32_t)__popcll(m & lt);
+      if (pos < (uint32_t)tiles) order[pos] = (uint32_t)t;
+    }
+    // the group's lanes read the position above before its first lane moves it
+    if (b != 63u && (m & lt) == 0ull) wc[w][b] += (uint32_t)__popcll(m);
+  }
+}
+
 __global__ void k_copy_u64(const uint64_t* __restrict__ a, uint64_t* __restrict__ b, int64_t n) {
   const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (k < n) b[k] = a[k];
@@ -394,6 +475,11 @@ static int32_t bits_for(uint64_t maxval) {
 static int32_t launch_tile_order(const uint32_t* ranges, int32_t tiles, uint32_t* order, uint32_t* hist,
                                  hipStream_t st) {
   if (tiles <= 0) return GS_OK;
+  if (tiles <= kOrderLdsTiles) {
+    hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(kOrderThreads), 0, st, ranges, tiles, order);
+    MS_CHECK_LAUNCH("tile_order");
+    return GS_OK;
+  }
   int32_t r = launch_fill(hist, 0u, kOrderBuckets, st);
   if (r != GS_OK) return r;
   hipLaunchKernelGGL(k_order_hist, dim3(grid_1d(tiles)), dim3(kBlock), 0, st, ranges, tiles, hist);
@@ -410,10 +496,11 @@ int32_t bin_sort_on_ws(const gs_projected_t* proj, const ViewSet& vs, int32_t V,
                            uint32_t* ranges, uint32_t* tile_order, void* ws, hipStream_t s) {
   const int64_t ni = stats->n_isect;
   int32_t st;
-  if ((st = launch_fill(ranges, 0u, 2 * (int64_t)vs.tiles_total, s)) != GS_OK) return st;
   uint32_t* order_hist = (uint32_t*)((char*)ws + 256);
   if (ni == 0) {
-    // no sort runs: clear the status flag it would have cleared
+    // no emission or sort runs: clear the ranges, and the status flag the
+    // sort would have cleared
+    if ((st = launch_fill(ranges, 0u, 2 * (int64_t)vs.tiles_total, s)) != GS_OK) return st;
     if ((st = launch_fill(ws, 0u, 1, s)) != GS_OK) return st;
     return tile_order ? launch_tile_order(ranges, vs.tiles_total, tile_order, order_hist, s) : GS_OK;
   }
@@ -430,7 +517,7 @@ int32_t bin_sort_on_ws(const gs_projected_t* proj, const ViewSet& vs, int32_t V,
   if (stats->key_bits + ibits > 64) ibits = 0;
   hipLaunchKernelGGL(k_emit, dim3(grid_1d(nrec)), dim3(kBlock), 0, s, reinterpret_cast<const int4*>(proj->bin),
                      proj->rec, proj->tile_cull_log2_alpha, offsets, n, nrec, shift, stats->zbits_min, ibits, k0, v0,
-                     vs);
+                     vs, ranges, 2 * (int64_t)vs.tiles_total);
   MS_CHECK_LAUNCH("emit");
   uint64_t* ks = nullptr;
   if ((st = onesweep_sort(k0, ibits > 0 ? nullptr : v0, ni, ibits, stats->key_bits, ws, vals, &ks, s)) != GS_OK)
@@ -448,11 +535,11 @@ using namespace msplat;
 
 extern "C" {
 
-// The pair count's read-back.  k_count_top also writes the four totals into
-// a small host-mapped pinned buffer (one per host thread and device, made on
-// first use and kept until the process ends), and the host polls an event
-// recorded after the count instead of waiting in the runtime: a copy to
-// pageable memory goes through a staging kernel with a wait of its own, and
+// The pair count's read-back.  The last block of k_count_down also writes the
+// four totals into a small host-mapped pinned buffer (one per host thread and
+// device, made on first use and kept until the process ends), and the host
+// polls an event recorded after the count instead of waiting in the runtime: a
+// copy to pageable memory goes through a staging kernel with a wait of its own, and
 // the runtime's wait turns into an interrupt-driven sleep after a short spin;
 // both added tens of microseconds to a read-back that sits on the step's
 // critical path.
@@ -514,7 +601,6 @@ int32_t gs_bin_count(const gs_projected_t* proj, const gs_camera_t* cams, int32_
   const int64_t nb = count_blocks(nrec);
   const int4* bin = reinterpret_cast<const int4*>(proj->bin);
   hipLaunchKernelGGL(k_count_reduce, dim3((unsigned)nb), dim3(kBlock), 0, s, bin, nrec, c);
-  hipLaunchKernelGGL(k_count_top, dim3(1), dim3(kBlock), 0, s, nb, c);
   hipLaunchKernelGGL(k_count_down, dim3((unsigned)nb), dim3(kBlock), 0, s, bin, nrec, c, offsets);
   MS_CHECK_LAUNCH("bin_count");
   if ((st = check_hip(hipEventRecord(rb->ev, s), "bin_count event")) != GS_OK) return st;
@@ -560,7 +646,7 @@ int32_t gs_emit_keys(const gs_projected_t* proj, const gs_camera_t* cams, int32_
   if (proj->tile_cull_log2_alpha < 0.f && !proj->rec) { set_error("tile culling needs proj->rec"); return GS_ERR_NULL; }
   hipLaunchKernelGGL(k_emit, dim3(grid_1d(nrec)), dim3(kBlock), 0, (hipStream_t)stream,
                      reinterpret_cast<const int4*>(proj->bin), proj->rec, proj->tile_cull_log2_alpha, offsets, n, nrec,
-                     depth_shift, zbits_min, 0, keys, vals, vs);
+                     depth_shift, zbits_min, 0, keys, vals, vs, nullptr, 0);
   MS_CHECK_LAUNCH("emit");
   return GS_OK;
 }

@@ -277,11 +277,15 @@ __global__ __launch_bounds__(kBlock) void k_os_pass(const uint64_t* __restrict__
 
 // Up-sweep of a prescanned pass: each tile's count of every digit, stored
 // digit-major (counts[d * nt + t]) for the scan.  Per-wave LDS histograms.
+// The first pass also clears the error flag (`clear`, else NULL): prescanned
+// passes never raise it, so nothing reads it before this store lands.
 template <bool VALS>
 __global__ __launch_bounds__(kBlock) void k_rt_up(const uint64_t* __restrict__ kin, int64_t n, int32_t shift,
-                                                  uint32_t* __restrict__ counts, int32_t nt) {
+                                                  uint32_t* __restrict__ counts, int32_t nt,
+                                                  uint32_t* __restrict__ clear) {
   __shared__ uint32_t h[kOsWaves][kOsRadix];
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+  if (clear && blockIdx.x == 0 && threadIdx.x == 0) *clear = 0u;
 #pragma unroll
   for (int k = 0; k < kOsWaves; ++k) h[k][threadIdx.x] = 0;
   __syncthreads();
@@ -370,12 +374,13 @@ int32_t onesweep_sort(uint64_t* k0, uint32_t* v0, int64_t n, int32_t lo_bit, int
   uint32_t* counters = (uint32_t*)p; p += a(kMaxPasses * 4);
   uint64_t* kalt = (uint64_t*)p; p += a(nn * 8);
   uint32_t* valt = (uint32_t*)p;
-  // the flag, histograms, status words and counters in one fill (the
-  // prescanned passes write all their counts: only the flag)
+  // the flag, histograms, status words and counters in one fill; prescanned
+  // passes write all their counts, and the first up-sweep clears the flag
+  const bool runs = n > 1 && passes > 0;
   const int64_t zero_words = prescan ? 1 : (int64_t)((char*)(counters + kMaxPasses) - (char*)err) / 4;
-  int32_t r = launch_fill(err, 0u, zero_words, st);
-  if (r != GS_OK) return r;
-  if (n <= 1 || passes == 0) {
+  int32_t r = GS_OK;
+  if (!(prescan && runs) && (r = launch_fill(err, 0u, zero_words, st)) != GS_OK) return r;
+  if (!runs) {
     if (vals && vfinal != v0 && n > 0) {
       r = check_hip(hipMemcpyAsync(vfinal, v0, n * 4, hipMemcpyDeviceToDevice, st), "sort copy");
       if (r != GS_OK) return r;
@@ -400,10 +405,11 @@ int32_t onesweep_sort(uint64_t* k0, uint32_t* v0, int64_t n, int32_t lo_bit, int
     uint32_t* vout = nullptr;
     const int32_t shift = lo_bit + 8 * ps;
     if (prescan) {
+      uint32_t* clear = ps == 0 ? err : nullptr;
       if (vals)
-        hipLaunchKernelGGL(k_rt_up<true>, dim3((unsigned)nb), dim3(kBlock), 0, st, kin, n, shift, counts, nt);
+        hipLaunchKernelGGL(k_rt_up<true>, dim3((unsigned)nb), dim3(kBlock), 0, st, kin, n, shift, counts, nt, clear);
       else
-        hipLaunchKernelGGL(k_rt_up<false>, dim3((unsigned)nb), dim3(kBlock), 0, st, kin, n, shift, counts, nt);
+        hipLaunchKernelGGL(k_rt_up<false>, dim3((unsigned)nb), dim3(kBlock), 0, st, kin, n, shift, counts, nt, clear);
       hipLaunchKernelGGL(k_rt_scan, dim3(kOsRadix), dim3(kBlock), 0, st, counts, nt);
       MS_CHECK_LAUNCH("sort up-sweep");
     }

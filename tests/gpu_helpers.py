@@ -239,3 +239,35 @@ def check_projection_backward(p, cams, opts, g2d, grads, n, active=None, what=""
     for k, e in errs.items():
         assert e <= A8_REL_L2, (what, k, e)
     return errs
+
+
+def check_bin_extras(b, rects, zb, n_views, tiles_total, ranges, what=""):
+    """The count's side outputs and the tile order against their definitions
+    over the oracle's tile rectangles and depth bits: offsets = exclusive scan
+    of the tiles each record touches; n_visible = records touching a tile;
+    zbits_min / max over those; depth_bits = bit length of their spread;
+    key_bits = depth_bits + bit length of (tiles_total - 1); the tile order =
+    lists by descending bit length of their length, ascending tile id inside
+    one bit length (`ranges` are the oracle's [tiles_total, 2])."""
+    r = np.asarray(rects, dtype=np.int64)
+    cnt = np.where((r[:, 0] <= r[:, 1]) & (r[:, 2] <= r[:, 3]), (r[:, 1] - r[:, 0] + 1) * (r[:, 3] - r[:, 2] + 1), 0)
+    assert cnt.sum() < 2 ** 32
+    want_off = (np.cumsum(cnt) - cnt).astype(np.uint32)
+    got_off = b.offsets.cpu().numpy().view(np.uint32)[: len(cnt)]
+    bad = np.flatnonzero(got_off != want_off)
+    assert bad.size == 0, (what, "offsets", bad[:8].tolist())
+    st = b.stats
+    vis = cnt > 0
+    assert st.n_isect == int(cnt.sum()), what
+    assert st.n_visible == int(vis.sum()), (what, st.n_visible, int(vis.sum()))
+    zv = np.asarray(zb, dtype=np.uint32)[vis]
+    zmin, zmax = (int(zv.min()), int(zv.max())) if zv.size else (0, 0)
+    assert (st.zbits_min, st.zbits_max) == (zmin, zmax), (what, st.zbits_min, st.zbits_max, zmin, zmax)
+    assert st.depth_bits == (zmax - zmin).bit_length(), what
+    assert st.key_bits == st.depth_bits + (tiles_total - 1).bit_length(), what
+    if b.order is not None:
+        L = (ranges[:, 1].astype(np.int64) - ranges[:, 0].astype(np.int64))
+        bits = np.array([int(x).bit_length() for x in L])
+        want = np.lexsort((np.arange(len(L)), -bits))
+        got = b.order.cpu().numpy().view(np.uint32).astype(np.int64)
+        assert np.array_equal(got, want), (what, "tile order", int((got != want).sum()))

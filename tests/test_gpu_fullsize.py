@@ -129,6 +129,7 @@ def test_full_size_sampled_parity(gpu_lib, which):
     assert np.array_equal(_np(b.keys).view(np.uint64), keys)
     assert np.array_equal(_np(b.vals).view(np.uint32), vals)
     assert np.array_equal(_np(b.ranges).view(np.uint32), ranges)
+    H.check_bin_extras(b, oracle.tile_rects(proj), oracle.zbits(proj), 1, total, ranges, which)
     del keys
     # sampled pixels, every one checked: 64 over every Gaussian (untiled, so the
     # tiling itself is under test) and 2000 over their tile's list
@@ -182,13 +183,16 @@ def test_multiview_full_size_sampled_parity(gpu_lib):
     projs = [oracle.project(p, c, opts) for c in cams]
     # binning of all views, bit-exact in full (records of view v are v * n + i)
     tx, ty, base, total = oracle.view_layout(cams)
-    keys, vals, ranges = oracle.bin(np.concatenate([oracle.tile_rects(q) for q in projs]),
-                                    np.concatenate([oracle.zbits(q) for q in projs]), V, n, base, tx, total)
+    rects = np.concatenate([oracle.tile_rects(q) for q in projs])
+    zb = np.concatenate([oracle.zbits(q) for q in projs])
+    keys, vals, ranges = oracle.bin(rects, zb, V, n, base, tx, total)
     b = out["binned"]
     assert b.stats.n_isect == len(keys) > 10 ** 7
     assert np.array_equal(_np(b.keys).view(np.uint64), keys)
     assert np.array_equal(_np(b.vals).view(np.uint32), vals)
     assert np.array_equal(_np(b.ranges).view(np.uint32), ranges)
+    H.check_bin_extras(b, rects, zb, V, total, ranges, f"{V} views")
+    del rects, zb
     del keys
     fr = out["frame"]
     acc = {k: _np(t) for k, t in out["acc"].items()}

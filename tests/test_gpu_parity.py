@@ -72,6 +72,7 @@ def test_binning_bit_exact(gpu_lib):
     assert np.array_equal(_np(b.keys).view(np.uint64), keys)
     assert np.array_equal(_np(b.vals).view(np.uint32), vals)
     assert np.array_equal(_np(b.ranges).view(np.uint32), ranges)
+    H.check_bin_extras(b, oracle.tile_rects(P), oracle.zbits(P), 1, total, ranges, "small")
 
 
 @pytest.mark.parametrize("algorithm", [0, 1])  # GS_SORT_PRESCAN, GS_SORT_LOOKBACK
@@ -265,19 +266,36 @@ def test_argument_errors(gpu_lib):
 
 def test_l1_loss_grad_matches_definition(gpu_lib):
     R = H.raster()
-    # up to a 1080p frame and beyond one pass of the capped grid (4096 x 256 x 4 float4)
-    for count in (1, 7, 4099, 3 * 128 * 96 + 2, 3 * 1920 * 1080, 4 * 4096 * 256 * 4 + 4 * 999 + 3):
+    # up to a 1080p frame and many passes of the capped grid (256 x 1024
+    # threads, one float4 each per pass); `skew` offsets the buffers by one
+    # float, off the 16-byte alignment of the float4 path
+    for count, skew in ((1, 0), (7, 0), (4099, 0), (3 * 128 * 96 + 2, 0), (3 * 1920 * 1080, 0),
+                        (4 * 4096 * 256 * 4 + 4 * 999 + 3, 0), (3 * 1920 * 1080 - 5, 1)):
         g = gs_inputs.rng(count)
-        c = torch.from_numpy(g.uniform(size=count).astype(np.float32)).cuda()
-        t = torch.from_numpy(g.uniform(size=count).astype(np.float32)).cuda()
+        c = torch.from_numpy(g.uniform(size=count + skew).astype(np.float32)).cuda()[skew:]
+        t = torch.from_numpy(g.uniform(size=count + skew).astype(np.float32)).cuda()[skew:]
         t[: count // 5] = c[: count // 5]  # exact ties give a zero gradient
-        dl = torch.empty_like(c)
+        dl = torch.empty(count + skew, device="cuda")[skew:]
         loss = torch.zeros(1, device="cuda")
         R.l1_loss_grad(c, t, dl, loss)
         torch.cuda.synchronize()
         d = (c - t).double().cpu().numpy()
         assert np.array_equal(_np(dl), (np.sign(d) / count).astype(np.float32))
         assert loss.item() == pytest.approx(np.abs(d).mean(), rel=1e-5)
+
+
+def test_fill_u32_writes_exactly_its_words(gpu_lib):
+    """16-byte stores over the aligned part, word stores elsewhere: every word
+    of the range takes the value, the words around it keep theirs."""
+    R = H.raster()
+    for count, skew in ((1, 0), (3, 1), (4, 0), (5, 3), (4099, 2), (8192 * 256 * 4 * 3 + 7, 1),
+                        (36 * 10 ** 6 + 1, 0)):
+        buf = torch.full((count + skew + 4,), 0x5A5A5A5A, dtype=torch.int32, device="cuda")
+        R.fill_u32(buf[skew: skew + count], 0xC0FFEE)
+        torch.cuda.synchronize()
+        b = _np(buf).view(np.uint32)
+        assert np.all(b[skew: skew + count] == 0xC0FFEE), (count, skew)
+        assert np.all(b[:skew] == 0x5A5A5A5A) and np.all(b[skew + count:] == 0x5A5A5A5A), (count, skew)
 
 
 def test_tile_order_is_longest_first_permutation(gpu_lib):
