@@ -38,7 +38,7 @@ PEAK_VALU_TOPS = 256 * 64 * 2.4e9 / 1e12
 STOP_T = 0.01  # a pixel with final transmittance >= 1e-4 / (1 - 0.99) never stopped
 # algorithmic bytes per unit: what each kernel must read and write at least
 PROJECT_BYTES_PER_RECORD = 59 * 4 + 64 + 16     # drawn: params read, record + bin written
-PROJECT_BYTES_PER_UNDRAWN = 11 * 4 + 64 + 16     # not drawn: no SH read (mean, scale, rotation, opacity)
+PROJECT_BYTES_PER_UNDRAWN = 11 * 4 + 16          # not drawn: no SH read (mean, scale, rotation, opacity), no record
 PROJECT_BWD_BYTES_PER_ACTIVE = 59 * 4 + 59 * 4 + 36 + 16  # params read, grads written, 2D grad + bin read
 PROJECT_BWD_BYTES_PER_INACTIVE = 59 * 4 + 1     # zero rows written, mask read
 RENDER_FWD_BYTES_PER_PAIR = 4 + 8 + 48          # list index, pixel box, the 48 record bytes compositing reads

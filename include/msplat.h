@@ -118,7 +118,8 @@ typedef struct {
  *   u = u_hi + u_lo), A, B, C, lo (exponent form of the conic: the 2D Gaussian
  *   times opacity is exp2(lo - A dx^2 - B dx dy - C dy^2), lo = log2 opacity),
  *   r, g, b, opacity, z (camera depth of the centre), a, b, c (conic
- *   [[a, b], [b, c]] = inverse of the 2D covariance with low-pass).
+ *   [[a, b], [b, c]] = inverse of the 2D covariance with low-pass).  Written
+ *   for drawn records only (tiles_touched > 0); other rows keep their bytes.
  * bin[V * n][4] int32: x box (x_lo | x_hi << 16), y box (y_lo | y_hi << 16) in
  *   pixels, clipped to the image; float32 bits of z; tiles_touched (0 = not
  *   drawn: culled, behind the near plane, off-image, or opacity < alpha_min). */
@@ -266,7 +267,8 @@ int32_t gs_tile_order(const uint32_t* ranges, int32_t tiles_total, uint32_t* til
  *   [0, key_bits) (1..64); ws sized by gs_sort_workspace_size(n); n < 2^30
  *   (GS_ERR_CAPACITY otherwise).
  * gs_tile_ranges: ranges from sorted keys whose tile id is key >> depth_shift;
- *   keys_out (may be NULL) receives (tile << 32) | (low bits + zbits_min). */
+ *   keys_out (may be NULL; not keys itself: GS_ERR_SHAPE) receives
+ *   (tile << 32) | (low bits + zbits_min). */
 int32_t gs_emit_keys(const gs_projected_t* proj, const gs_camera_t* cams, int32_t V, int64_t n,
                      const uint32_t* offsets, int32_t depth_shift, uint32_t zbits_min, uint64_t* keys,
                      uint32_t* vals, void* stream);

@@ -263,24 +263,48 @@ __global__ __launch_bounds__(kBlock) void k_emit(const int4* __restrict__ bin, c
 // tile ranges
 // ---------------------------------------------------------------------------
 // Packed keys (ibits > 0) also give the sorted record indices to vals.
+// kRangeKeys consecutive keys per thread: their neighbours come from the
+// same six loads, and their record indices leave in one 16-byte store.
+constexpr int kRangeKeys = 4;
+static_assert(kRangeKeys == 4, "the record indices leave as one uint4");
+
 __global__ __launch_bounds__(kBlock) void k_ranges(const uint64_t* __restrict__ keys, int64_t n, int32_t shift,
                                                    uint32_t zmin, int32_t ibits, int64_t tiles_total,
                                                    uint32_t* __restrict__ ranges, uint64_t* __restrict__ keys_out,
                                                    uint32_t* __restrict__ vals) {
-  const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (k >= n) return;
-  const uint64_t packed = keys[k];
-  const uint64_t key = packed >> ibits;
+  const int64_t k0 = ((int64_t)blockIdx.x * kBlock + threadIdx.x) * kRangeKeys;
+  if (k0 >= n) return;
+  uint64_t p[kRangeKeys + 2];  // keys k0 - 1 .. k0 + kRangeKeys
+  p[0] = k0 > 0 ? keys[k0 - 1] : 0ull;
+#pragma unroll
+  for (int j = 0; j <= kRangeKeys; ++j) p[j + 1] = k0 + j < n ? keys[k0 + j] : 0ull;
   const int32_t ts = shift + ibits;
-  const uint64_t tile = packed >> ts;
-  if (ibits > 0) vals[k] = (uint32_t)(packed & ((1ull << ibits) - 1ull));
-  if (tile < (uint64_t)tiles_total) {
-    if (k == 0 || (keys[k - 1] >> ts) != tile) ranges[2 * tile] = (uint32_t)k;
-    if (k == n - 1 || (keys[k + 1] >> ts) != tile) ranges[2 * tile + 1] = (uint32_t)(k + 1);
+  const uint64_t imask = ibits > 0 ? (1ull << ibits) - 1ull : 0ull;
+  uint32_t v[kRangeKeys];
+#pragma unroll
+  for (int j = 0; j < kRangeKeys; ++j) {
+    const int64_t k = k0 + j;
+    const uint64_t packed = p[j + 1];
+    const uint64_t tile = packed >> ts;
+    v[j] = (uint32_t)(packed & imask);
+    if (k < n && tile < (uint64_t)tiles_total) {
+      if (k == 0 || (p[j] >> ts) != tile) ranges[2 * tile] = (uint32_t)k;
+      if (k == n - 1 || (p[j + 2] >> ts) != tile) ranges[2 * tile + 1] = (uint32_t)(k + 1);
+    }
+    if (keys_out && k < n) {
+      const uint64_t key = packed >> ibits;
+      const uint64_t lowmask = shift >= 64 ? ~0ull : ((1ull << shift) - 1ull);
+      keys_out[k] = (tile << 32) | (uint64_t)((uint32_t)(key & lowmask) + zmin);
+    }
   }
-  if (keys_out) {
-    const uint64_t lowmask = shift >= 64 ? ~0ull : ((1ull << shift) - 1ull);
-    keys_out[k] = (tile << 32) | (uint64_t)((uint32_t)(key & lowmask) + zmin);
+  if (ibits > 0) {
+    if (k0 + kRangeKeys <= n && (reinterpret_cast<uintptr_t>(vals) & 15) == 0) {
+      *reinterpret_cast<uint4*>(vals + k0) = make_uint4(v[0], v[1], v[2], v[3]);
+    } else {
+#pragma unroll
+      for (int j = 0; j < kRangeKeys; ++j)
+        if (k0 + j < n) vals[k0 + j] = v[j];
+    }
   }
 }
 
@@ -522,7 +546,8 @@ int32_t bin_sort_on_ws(const gs_projected_t* proj, const ViewSet& vs, int32_t V,
   uint64_t* ks = nullptr;
   if ((st = onesweep_sort(k0, ibits > 0 ? nullptr : v0, ni, ibits, stats->key_bits, ws, vals, &ks, s)) != GS_OK)
     return st;
-  hipLaunchKernelGGL(k_ranges, dim3(grid_1d(ni)), dim3(kBlock), 0, s, ks, ni, shift, stats->zbits_min, ibits,
+  hipLaunchKernelGGL(k_ranges, dim3(grid_1d((ni + kRangeKeys - 1) / kRangeKeys)), dim3(kBlock), 0, s, ks, ni, shift,
+                     stats->zbits_min, ibits,
                      (int64_t)vs.tiles_total, ranges, keys, vals);
   MS_CHECK_LAUNCH("ranges");
   if (tile_order) return launch_tile_order(ranges, vs.tiles_total, tile_order, order_hist, s);
@@ -672,15 +697,21 @@ int32_t gs_sort_pairs(uint64_t* keys, uint32_t* vals, int64_t n, int32_t key_bit
 int32_t gs_tile_ranges(const uint64_t* keys, int64_t n, int32_t depth_shift, uint32_t zbits_min, int32_t tiles_total,
                        uint32_t* ranges, uint64_t* keys_out, void* stream) {
   if (n < 0 || tiles_total < 0 || depth_shift < 0 || depth_shift > 63) { set_error("bad args"); return GS_ERR_SHAPE; }
+  // every argument checked before anything is queued
+  if (n > 0 && !keys) { set_error("keys NULL"); return GS_ERR_NULL; }
+  if (n > 0 && keys_out == keys) {
+    set_error("keys_out must not be keys (neighbouring keys are read)");
+    return GS_ERR_SHAPE;
+  }
+  if (tiles_total > 0 && !ranges) { set_error("ranges NULL"); return GS_ERR_NULL; }
   hipStream_t s = (hipStream_t)stream;
   if (tiles_total > 0) {
-    if (!ranges) { set_error("ranges NULL"); return GS_ERR_NULL; }
     int32_t st = launch_fill(ranges, 0u, 2 * (int64_t)tiles_total, s);
     if (st != GS_OK) return st;
   }
   if (n == 0) return GS_OK;
-  if (!keys) { set_error("keys NULL"); return GS_ERR_NULL; }
-  hipLaunchKernelGGL(k_ranges, dim3(grid_1d(n)), dim3(kBlock), 0, s, keys, n, depth_shift, zbits_min, 0,
+  hipLaunchKernelGGL(k_ranges, dim3(grid_1d((n + kRangeKeys - 1) / kRangeKeys)), dim3(kBlock), 0, s, keys, n,
+                     depth_shift, zbits_min, 0,
                      (int64_t)tiles_total, ranges, keys_out, nullptr);
   MS_CHECK_LAUNCH("ranges");
   return GS_OK;

@@ -216,11 +216,10 @@ __global__ __launch_bounds__(kBlock) void k_project(ProjArgs pa, ViewSet vs) {
     out[1] = r1;
     out[2] = make_float4((float)rgb[0], (float)rgb[1], (float)rgb[2], (float)o);
     out[3] = make_float4(zf, (float)g.a, (float)g.b, (float)g.c);
-  } else {
-    const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
-    out[0] = z4; out[1] = z4; out[2] = z4;
-    out[3] = make_float4(zf, 0.f, 0.f, 0.f);
   }
+  // a record that is not drawn keeps whatever its row held: no kernel reads
+  // it (lists hold drawn records only), and the rows of Gaussians no view
+  // draws, which the spatial order keeps together, are then not written at all
   int4 b4;
   b4.x = (xlo & 0xffff) | (xhi << 16);
   b4.y = (ylo & 0xffff) | (yhi << 16);

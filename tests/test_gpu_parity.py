@@ -75,6 +75,45 @@ def test_binning_bit_exact(gpu_lib):
     H.check_bin_extras(b, oracle.tile_rects(P), oracle.zbits(P), 1, total, ranges, "small")
 
 
+@pytest.mark.parametrize("which", ["cube 4096 128x128", "surfaces 500k 1245x825"])
+def test_split_binning_stages_match_oracle(gpu_lib, which):
+    """gs_emit_keys, gs_sort_pairs and gs_tile_ranges called one by one give
+    the oracle's sorted keys (as (tile << 32) | z bits), values and ranges;
+    keys_out may not be the keys themselves."""
+    import ctypes
+    from paper_2411_12788_amd import _lib as L
+    R = H.raster()
+    lib = L.lib()
+    wl = _small(seed=3) if which.startswith("cube") else gs_inputs.training_view()
+    cams = wl.cameras
+    ds = R.DeviceScene.from_numpy(wl.scene)
+    n = ds.n
+    proj = R.project(ds, cams, R.RasterOpts())
+    offsets, st = R.bin_count(proj, cams, n)
+    ni, tiles = int(st.n_isect), int(st.tiles_total)
+    print("split binning case:", which, ni, "pairs", flush=True)
+    keys = torch.empty(ni, dtype=torch.int64, device="cuda")
+    vals = torch.empty(ni, dtype=torch.int32, device="cuda")
+    assert lib.gs_emit_keys(ctypes.byref(proj.c()), R.cameras(cams), len(cams), n, R._ptr(offsets), st.depth_bits,
+                            st.zbits_min, R._ptr(keys), R._ptr(vals), None) == L.GS_OK
+    ws = torch.empty(lib.gs_sort_workspace_size(ni), dtype=torch.uint8, device="cuda")
+    assert lib.gs_sort_pairs(R._ptr(keys), R._ptr(vals), ni, st.key_bits, R._ptr(ws), ws.numel(), None) == L.GS_OK
+    ranges = torch.full((tiles, 2), 7, dtype=torch.int32, device="cuda")
+    kout = torch.empty(ni, dtype=torch.int64, device="cuda")
+    assert lib.gs_tile_ranges(R._ptr(keys), ni, st.depth_bits, st.zbits_min, tiles, R._ptr(ranges), R._ptr(kout),
+                              None) == L.GS_OK
+    assert lib.gs_tile_ranges(R._ptr(keys), ni, st.depth_bits, st.zbits_min, tiles, R._ptr(ranges), R._ptr(keys),
+                              None) == L.GS_ERR_SHAPE
+    torch.cuda.synchronize()
+    P = oracle.project(oracle.Params.of(wl.scene), cams[0], oracle.Opts())
+    tx, ty, base, total = oracle.view_layout(cams)
+    okeys, ovals, oranges = oracle.bin(oracle.tile_rects(P), oracle.zbits(P), 1, n, base, tx, total)
+    assert ni == len(okeys) and tiles == total
+    assert np.array_equal(_np(kout).view(np.uint64), okeys)
+    assert np.array_equal(_np(vals).view(np.uint32), ovals)
+    assert np.array_equal(_np(ranges).view(np.uint32), oranges)
+
+
 @pytest.mark.parametrize("algorithm", [0, 1])  # GS_SORT_PRESCAN, GS_SORT_LOOKBACK
 @pytest.mark.parametrize("n,bits,spread", [(1, 8, 2), (1000, 20, 16), (3 * 4096 + 17, 45, 1 << 40),
                                            (100_003, 64, 1 << 62), (50_000, 33, 7), (3_300_001, 45, 1 << 44)])
