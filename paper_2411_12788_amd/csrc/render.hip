@@ -288,7 +288,15 @@ __device__ __forceinline__ WorkItem work_item(const uint32_t* order, const uint3
       w.skip = q != ((b >> 5) & 3);
     }
   } else {
-    w.tile = (int32_t)uload(order + (b - 3 * nsplit));
+    // Workgroups go to the eight XCDs in turn.  Inside each aligned group of
+    // 64 workgroups, the eight of one XCD take eight consecutive entries of
+    // the order (neighbouring tiles of one length class, which share records,
+    // in one L2); every XCD still walks the order at the same pace.  Partial
+    // groups at either end keep the identity, so the map stays a bijection.
+    int32_t p = b;
+    const int32_t g0 = b & ~63, lo = 4 * nsplit, hi = (int32_t)gridDim.x;
+    if (g0 >= lo && g0 + 64 <= hi) p = g0 + ((b & 7) << 3) + ((b & 63) >> 3);
+    w.tile = (int32_t)uload(order + (p - 3 * nsplit));
   }
   return w;
 }
