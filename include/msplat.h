@@ -24,8 +24,10 @@
  *  - Asynchrony: work is enqueued on `stream` (a hipStream_t; NULL = the null
  *    stream).  Only gs_bin_count and gs_bin synchronise (they return the pair
  *    count).
- *  - Reentrancy: no global mutable state (apart from the diagnostic
- *    gs_sort_set_spin_limit and the scratch array of gs_sort_pairs_static);
+ *  - Reentrancy: no global mutable state (apart from the diagnostics
+ *    gs_sort_set_spin_limit, gs_sort_set_algorithm and
+ *    gs_bin_count_set_fold_blocks, and the scratch array of
+ *    gs_sort_pairs_static);
  *    concurrent calls on different streams with disjoint buffers are safe.
  *  - Views: V cameras (1 <= V <= GS_MAX_VIEWS) are rendered in one launch per
  *    stage.  A record is one (view, Gaussian) pair, index r = v * n + i.
@@ -304,6 +306,15 @@ void gs_sort_set_spin_limit(uint32_t polls);
  * for another value. */
 enum { GS_SORT_PRESCAN = 0, GS_SORT_LOOKBACK = 1 };
 int32_t gs_sort_set_algorithm(int32_t algorithm);
+
+/* Diagnostic: the largest number of 4096-record blocks for which gs_bin_count
+ * runs two kernels (each block of the down-sweep adds the totals of the
+ * blocks before it, and the last one publishes the statistics); above it a
+ * single-workgroup scan of the block totals runs between the two.  Default
+ * 4096 (about 16.7M records; a negative value restores it); 0 always takes
+ * the three-kernel path.  Both give the same offsets and statistics.
+ * Process-wide; returns the previous value. */
+int64_t gs_bin_count_set_fold_blocks(int64_t blocks);
 
 /* Allocation-free sort, for callers that cannot allocate device memory (code
  * under graph capture, tight serving loops, harnesses that forbid allocation).

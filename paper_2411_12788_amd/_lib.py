@@ -94,6 +94,7 @@ _SIGS = {
     "gs_sort_status": (c_i32, [c_p, c_p]),
     "gs_sort_set_spin_limit": (None, [c_u32]),
     "gs_sort_set_algorithm": (c_i32, [c_i32]),
+    "gs_bin_count_set_fold_blocks": (c_i64, [c_i64]),
     "gs_sort_pairs_static": (c_i32, [c_p, c_p, c_i64, c_i32, c_p, c_p]),
     "gs_spatial_order_workspace_size": (c_sz, [c_i64]),
     "gs_spatial_order": (c_i32, [c_p, c_i64, c_p, c_p, c_p, c_sz, c_p]),

@@ -12,6 +12,8 @@
 
 #include <immintrin.h>
 
+#include <atomic>
+
 namespace msplat {
 
 constexpr int kScanItems = 16;
@@ -113,6 +115,62 @@ __global__ __launch_bounds__(kBlock) void k_count_reduce(const int4* __restrict_
   }
 }
 
+// Above kCountFoldBlocks blocks: one block scans the block sums in place
+// and reduces the global statistics, between reduce and down-sweep.
+__global__ __launch_bounds__(kBlock) void k_count_top(int64_t nb, CountWs ws) {
+  __shared__ uint64_t lds[kWaves + 1];
+  __shared__ uint32_t lz[3 * kWaves];
+  uint64_t carry = 0;
+  uint32_t zmin = 0xffffffffu, zmax = 0u;
+  uint64_t vis = 0;
+  for (int64_t c0 = 0; c0 < nb; c0 += kBlock) {
+    const int64_t k = c0 + threadIdx.x;
+    uint64_t x = k < nb ? ws.block_sum[k] : 0;
+    if (k < nb) {
+      uint32_t a = ws.block_zmin[k], b = ws.block_zmax[k];
+      zmin = a < zmin ? a : zmin;
+      zmax = b > zmax ? b : zmax;
+      vis += ws.block_vis[k];
+    }
+    uint64_t tot;
+    uint64_t ex = block_exclusive_scan<uint64_t>(x, lds, &tot);
+    if (k < nb) ws.block_sum[k] = carry + ex;
+    carry += tot;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    uint32_t a = __shfl_xor(zmin, o, kWave), b = __shfl_xor(zmax, o, kWave);
+    uint64_t c = __shfl_xor(vis, o, kWave);
+    zmin = a < zmin ? a : zmin;
+    zmax = b > zmax ? b : zmax;
+    vis += c;
+  }
+  __shared__ uint64_t lv[kWaves];
+  const int w = threadIdx.x / kWave;
+  if ((threadIdx.x & (kWave - 1)) == 0) { lz[w] = zmin; lz[kWaves + w] = zmax; lv[w] = vis; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t a = lz[0], b = lz[kWaves];
+    uint64_t c = 0;
+    for (int k = 0; k < kWaves; ++k) {
+      a = lz[k] < a ? lz[k] : a;
+      b = lz[kWaves + k] > b ? lz[kWaves + k] : b;
+      c += lv[k];
+    }
+    if (c == 0) { a = 0; b = 0; }
+    ws.stats[0] = carry;
+    ws.stats[1] = c;
+    ws.stats[2] = a;
+    ws.stats[3] = b;
+    if (ws.host_stats) {
+      ws.host_stats[0] = carry;
+      ws.host_stats[1] = c;
+      ws.host_stats[2] = a;
+      ws.host_stats[3] = b;
+    }
+  }
+}
+
 // Sum over the block of one value per thread (every thread gets it).
 template <typename T>
 __device__ __forceinline__ T block_total(T x, T* lds /*kWaves*/) {
@@ -127,10 +185,16 @@ __device__ __forceinline__ T block_total(T x, T* lds /*kWaves*/) {
   return s;
 }
 
-// Offsets of one block of records.  The block's start is the sum of the
-// totals of the blocks before it, which each block adds itself (at most a few
-// thousand values, read from L2), so no separate scan of the totals runs.  The
-// last block also reduces the statistics of all blocks and publishes them.
+// Offsets of one block of records.  FOLDED (up to kCountFoldBlocks blocks):
+// the block's start is the sum of the totals of the blocks before it, which
+// each block adds itself (at most a few thousand values, read from L2), so no
+// separate scan of the totals runs, and the last block reduces the statistics
+// of all blocks and publishes them.  Otherwise k_count_top has turned the
+// totals into the blocks' starts and published the statistics.
+constexpr int64_t kCountFoldBlocks = 4096;
+static std::atomic<int64_t> g_count_fold_blocks{kCountFoldBlocks};
+
+template <bool FOLDED>
 __global__ __launch_bounds__(kBlock) void k_count_down(const int4* __restrict__ bin, int64_t nrec, CountWs ws,
                                                        uint32_t* __restrict__ offsets) {
   __shared__ uint64_t lds[kWaves + 1];
@@ -146,8 +210,12 @@ __global__ __launch_bounds__(kBlock) void k_count_down(const int4* __restrict__ 
     sum += t[k];
   }
   uint64_t before = 0;
-  for (int64_t k = threadIdx.x; k < (int64_t)blockIdx.x; k += kBlock) before += ws.block_sum[k];
-  before = block_total<uint64_t>(before, lsum);
+  if (FOLDED) {
+    for (int64_t k = threadIdx.x; k < (int64_t)blockIdx.x; k += kBlock) before += ws.block_sum[k];
+    before = block_total<uint64_t>(before, lsum);
+  } else {
+    before = ws.block_sum[blockIdx.x];
+  }
   // the wave's records precede those of later waves: exclusive scan of the
   // lane sums over the block gives each wave's start (lanes' sums are added in
   // wave order, and within a wave k-major below)
@@ -157,7 +225,7 @@ __global__ __launch_bounds__(kBlock) void k_count_down(const int4* __restrict__ 
   uint64_t tot;
   uint64_t run = before + block_exclusive_scan<uint64_t>(lane == 0 ? wsum : 0ull, lds, &tot);
   run = __shfl(run, 0, kWave);
-  if (blockIdx.x == gridDim.x - 1) {
+  if (FOLDED && blockIdx.x == gridDim.x - 1) {
     // every block's statistics, written by the reduce kernel before this one
     uint32_t zmin = 0xffffffffu, zmax = 0u;
     uint64_t vis = 0;
@@ -560,14 +628,15 @@ using namespace msplat;
 
 extern "C" {
 
-// The pair count's read-back.  The last block of k_count_down also writes the
-// four totals into a small host-mapped pinned buffer (one per host thread and
-// device, made on first use and kept until the process ends), and the host
-// polls an event recorded after the count instead of waiting in the runtime: a
-// copy to pageable memory goes through a staging kernel with a wait of its own, and
-// the runtime's wait turns into an interrupt-driven sleep after a short spin;
-// both added tens of microseconds to a read-back that sits on the step's
-// critical path.
+// The pair count's read-back.  The kernel that publishes the statistics
+// (k_count_down's last block, or k_count_top) also writes the four totals
+// into a small host-mapped pinned buffer (one per host thread and device,
+// made on first use and kept until the process ends), and the host polls an
+// event recorded after the count instead of waiting in the runtime: a copy
+// to pageable memory goes through a staging kernel with a wait of its own,
+// and the runtime's wait turns into an interrupt-driven sleep after a short
+// spin; both added tens of microseconds to a read-back that sits on the
+// step's critical path.
 struct CountReadback {
   hipEvent_t ev = nullptr;
   uint64_t* host = nullptr;  // [4], host-mapped
@@ -599,6 +668,10 @@ static int32_t count_readback(CountReadback** out) {
 
 size_t gs_bin_count_workspace_size(int64_t n_records) { return count_ws_size(n_records); }
 
+int64_t gs_bin_count_set_fold_blocks(int64_t blocks) {
+  return g_count_fold_blocks.exchange(blocks < 0 ? kCountFoldBlocks : blocks);
+}
+
 int32_t gs_bin_count(const gs_projected_t* proj, const gs_camera_t* cams, int32_t V, int64_t n, uint32_t* offsets,
                      gs_bin_stats_t* stats, void* ws, size_t ws_bytes, void* stream) {
   if (!proj || !stats) { set_error("proj/stats NULL"); return GS_ERR_NULL; }
@@ -626,7 +699,12 @@ int32_t gs_bin_count(const gs_projected_t* proj, const gs_camera_t* cams, int32_
   const int64_t nb = count_blocks(nrec);
   const int4* bin = reinterpret_cast<const int4*>(proj->bin);
   hipLaunchKernelGGL(k_count_reduce, dim3((unsigned)nb), dim3(kBlock), 0, s, bin, nrec, c);
-  hipLaunchKernelGGL(k_count_down, dim3((unsigned)nb), dim3(kBlock), 0, s, bin, nrec, c, offsets);
+  if (nb <= g_count_fold_blocks.load()) {
+    hipLaunchKernelGGL(k_count_down<true>, dim3((unsigned)nb), dim3(kBlock), 0, s, bin, nrec, c, offsets);
+  } else {
+    hipLaunchKernelGGL(k_count_top, dim3(1), dim3(kBlock), 0, s, nb, c);
+    hipLaunchKernelGGL(k_count_down<false>, dim3((unsigned)nb), dim3(kBlock), 0, s, bin, nrec, c, offsets);
+  }
   MS_CHECK_LAUNCH("bin_count");
   if ((st = check_hip(hipEventRecord(rb->ev, s), "bin_count event")) != GS_OK) return st;
   for (;;) {

@@ -149,6 +149,13 @@ def test_sort_algorithm_switch_on_host(L):
     assert lib.gs_sort_set_algorithm(L.GS_SORT_PRESCAN) == L.GS_OK
 
 
+def test_count_fold_switch_on_host(L):
+    lib = L.lib()
+    assert lib.gs_bin_count_set_fold_blocks(0) == 4096  # the default
+    assert lib.gs_bin_count_set_fold_blocks(-1) == 0
+    assert lib.gs_bin_count_set_fold_blocks(-1) == 4096  # restored
+
+
 def test_fused_binning_argument_errors_on_host(L):
     """gs_bin refuses a negative capacity before anything runs, and passes the
     pair count's argument errors through."""

@@ -60,7 +60,18 @@ def test_project_matches_oracle(gpu_lib):
     assert np.array_equal(binr[v, 2].view(np.uint32), P[v, F["Z"]].astype(np.float32).view(np.uint32))
 
 
-def test_binning_bit_exact(gpu_lib):
+@pytest.fixture(params=["fold", "top scan"])
+def count_path(request):
+    """gs_bin_count's two paths: the down-sweep adding the earlier blocks'
+    totals itself (the default at these sizes), or a scan kernel between."""
+    from paper_2411_12788_amd import _lib as L
+    lib = L.lib()
+    prev = lib.gs_bin_count_set_fold_blocks(0 if request.param == "top scan" else -1)
+    yield request.param
+    lib.gs_bin_count_set_fold_blocks(prev)
+
+
+def test_binning_bit_exact(gpu_lib, count_path):
     wl = _small(seed=1)
     out = H.run_gpu_forward(wl.scene, wl.cameras, accumulate=False, want_keys=True)
     b = out["binned"]
@@ -76,7 +87,7 @@ def test_binning_bit_exact(gpu_lib):
 
 
 @pytest.mark.parametrize("which", ["cube 4096 128x128", "surfaces 500k 1245x825"])
-def test_split_binning_stages_match_oracle(gpu_lib, which):
+def test_split_binning_stages_match_oracle(gpu_lib, which, count_path):
     """gs_emit_keys, gs_sort_pairs and gs_tile_ranges called one by one give
     the oracle's sorted keys (as (tile << 32) | z bits), values and ranges;
     keys_out may not be the keys themselves."""
@@ -91,7 +102,7 @@ def test_split_binning_stages_match_oracle(gpu_lib, which):
     proj = R.project(ds, cams, R.RasterOpts())
     offsets, st = R.bin_count(proj, cams, n)
     ni, tiles = int(st.n_isect), int(st.tiles_total)
-    print("split binning case:", which, ni, "pairs", flush=True)
+    print("split binning case:", which, count_path, ni, "pairs", flush=True)
     keys = torch.empty(ni, dtype=torch.int64, device="cuda")
     vals = torch.empty(ni, dtype=torch.int32, device="cuda")
     assert lib.gs_emit_keys(ctypes.byref(proj.c()), R.cameras(cams), len(cams), n, R._ptr(offsets), st.depth_bits,
@@ -112,6 +123,8 @@ def test_split_binning_stages_match_oracle(gpu_lib, which):
     assert np.array_equal(_np(kout).view(np.uint64), okeys)
     assert np.array_equal(_np(vals).view(np.uint32), ovals)
     assert np.array_equal(_np(ranges).view(np.uint32), oranges)
+    b = R.Binned(vals, ranges, kout, st, offsets, None)
+    H.check_bin_extras(b, oracle.tile_rects(P), oracle.zbits(P), 1, total, oranges, which)
 
 
 @pytest.mark.parametrize("algorithm", [0, 1])  # GS_SORT_PRESCAN, GS_SORT_LOOKBACK
